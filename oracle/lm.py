@@ -1,0 +1,270 @@
+"""FP64 Levenberg-Marquardt solver of the oracle (test infrastructure only).
+
+Follows Sec. 2.2 of the paper (eqs. linearized_prob, m-function, LMA-step) and
+the safeguard of Sec. 3.1 (eq. rho_agreement, Prop. 3.2, Alg. 2), with the
+readings where the paper is silent:
+
+* objective  Phi(u) = 0.5*||A(u) - y||^2 + 0.5*alpha_f*||grad f||^2
+                      + 0.5*alpha_mu*||grad mu||^2,  u = (f, mu);
+  its gradient g = J^T (A(u) - y) + R u with R = diag(alpha_f L, alpha_mu L),
+  L = grad^T grad.
+* step       CG with x0 = 0 and a fixed number of steps on
+             (J^T J + beta D + R) x = -g, D = diag(d_f I, d_mu I)
+             (eq. LMA-step solved through its normal equations).
+* trial      u' = clamp(u + x) to the box constraints, s = u' - u.
+* model      pred = m(0) - m(s) = -(g.s + 0.5*(||J s||^2 + s.R s))  (eq. m-function)
+* gain ratio rho = (Phi(u) - Phi(u')) / pred  (eq. rho_agreement), -inf if pred <= 0;
+             accept iff rho > eta.
+* damping    Nielsen's rule: accept -> beta *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
+             reject -> beta *= nu, nu *= 2.  beta0 = tau * ||J 1||^2 / ||1||^2
+             unless given.
+* hook       after an accepted step, u~ = G(u, s) replaces u' iff
+             rho(u~ - u) > eta and m(u~ - u) <= m(s)  (Prop. 3.2, Alg. 2).
+* continuation  alpha_k = alpha / decay**min(k, decay_until)  (Sec. 3.1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import Geometry, forward, jvp, reg_energy, reg_gradient, vjp
+
+
+@dataclass
+class LMParams:
+    max_outer: int = 15
+    n_cg: int = 20
+    alpha_f: float = 1e-2
+    alpha_mu: float = 1e-2
+    alpha_decay: float = 1.0
+    alpha_decay_until: int = 0
+    beta0: float = 0.0
+    tau: float = 1e-3
+    eta: float = 1e-3
+    d_f: float = 1.0
+    d_mu: float = 1.0
+    f_lo: float = 0.0
+    f_hi: float = np.inf
+    mu_lo: float = 0.0
+    mu_hi: float = np.inf
+    tol: float = 0.0
+
+
+@dataclass
+class LMReport:
+    phi: List[float] = field(default_factory=list)
+    rho: List[float] = field(default_factory=list)
+    beta: List[float] = field(default_factory=list)
+    pred: List[float] = field(default_factory=list)
+    ared: List[float] = field(default_factory=list)
+    gnorm: List[float] = field(default_factory=list)
+    accepted: List[int] = field(default_factory=list)
+    hook_accepted: List[int] = field(default_factory=list)
+    cg_rr: List[List[float]] = field(default_factory=list)
+    iters_run: int = 0
+    beta_final: float = 0.0
+    stop_reason: str = "max_outer"
+
+
+def alphas_at(p: LMParams, k: int):
+    decay = p.alpha_decay ** min(k, p.alpha_decay_until)
+    return p.alpha_f / decay, p.alpha_mu / decay
+
+
+def objective(g: Geometry, y, f, mu, af, am):
+    """Phi(u) and the data residual A(u) - y."""
+    r = forward(g, f, mu) - y
+    phi = 0.5 * float(np.dot(r.ravel(), r.ravel())) + reg_energy(af, f) + reg_energy(am, mu)
+    return phi, r
+
+
+def gradient(g: Geometry, f, mu, r, af, am):
+    gf, gm = vjp(g, f, mu, r)
+    return gf + reg_gradient(af, f), gm + reg_gradient(am, mu)
+
+
+def normal_matvec(g: Geometry, f, mu, pf, pm, beta, p: LMParams, af, am):
+    """(J^T J + beta D + R) [pf, pm]."""
+    jp = jvp(g, f, mu, pf, pm)
+    qf, qm = vjp(g, f, mu, jp)
+    qf = qf + beta * p.d_f * pf + reg_gradient(af, pf)
+    qm = qm + beta * p.d_mu * pm + reg_gradient(am, pm)
+    return qf, qm
+
+
+def cg(matvec: Callable, bf, bm, n_steps: int):
+    """Conjugate gradients from x0 = 0 for a fixed number of steps.
+
+    Returns (xf, xm, rr) where rr[m] is r^T r after step m (the recurrence
+    residual).  Stops early if p^T M p <= 0 or r^T r == 0; the remaining rr
+    entries then repeat the last value.
+    """
+    xf = np.zeros_like(bf)
+    xm = np.zeros_like(bm)
+    rf, rm = bf.copy(), bm.copy()
+    pf, pm = rf.copy(), rm.copy()
+    rr = float(np.sum(rf * rf) + np.sum(rm * rm))
+    trace = []
+    for _ in range(n_steps):
+        if rr == 0.0:
+            trace.append(rr)
+            continue
+        qf, qm = matvec(pf, pm)
+        gamma = float(np.sum(pf * qf) + np.sum(pm * qm))
+        if not gamma > 0.0:
+            trace.append(rr)
+            continue
+        a = rr / gamma
+        xf += a * pf
+        xm += a * pm
+        rf -= a * qf
+        rm -= a * qm
+        rr_new = float(np.sum(rf * rf) + np.sum(rm * rm))
+        pf = rf + (rr_new / rr) * pf
+        pm = rm + (rr_new / rr) * pm
+        rr = rr_new
+        trace.append(rr)
+    return xf, xm, trace
+
+
+def model_decrease(g: Geometry, f, mu, gf, gm, sf, sm, af, am) -> float:
+    """pred = m(0) - m(s) = -(g.s + 0.5*(||J s||^2 + s.R s))  (eq. m-function)."""
+    js = jvp(g, f, mu, sf, sm)
+    sRs = 2.0 * (reg_energy(af, sf) + reg_energy(am, sm))
+    gs = float(np.sum(gf * sf) + np.sum(gm * sm))
+    return -(gs + 0.5 * (float(np.sum(js * js)) + sRs))
+
+
+def nielsen_update(beta: float, nu: float, accepted: bool, rho: float):
+    """Nielsen's damping update (H.B. Nielsen, IMM-REP-1999-05)."""
+    if accepted:
+        return beta * max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3), 2.0
+    return beta * nu, 2.0 * nu
+
+
+def initial_damping(g: Geometry, f, mu, p: LMParams) -> float:
+    if p.beta0 > 0.0:
+        return float(p.beta0)
+    one = np.ones(g.image_shape)
+    j1 = jvp(g, f, mu, one, one)
+    return p.tau * float(np.sum(j1 * j1)) / (2.0 * g.n * g.n)
+
+
+def initial_guess(g: Geometry, y):
+    """mu0 = 0, f0 = c0 * 1 with c0 the least-squares fit of A(1, 0) to y."""
+    one = np.ones(g.image_shape)
+    a1 = forward(g, one, np.zeros(g.image_shape))
+    c0 = float(np.sum(a1 * y) / np.sum(a1 * a1))
+    return c0 * one, np.zeros(g.image_shape)
+
+
+@dataclass
+class Iterate:
+    """Everything one outer iteration produces (for step-by-step comparison)."""
+
+    phi: float
+    gf: np.ndarray
+    gm: np.ndarray
+    xf: np.ndarray
+    xm: np.ndarray
+    cg_rr: list
+    sf: np.ndarray
+    sm: np.ndarray
+    pred: float
+    ared: float
+    rho: float
+    phi_trial: float
+    f_trial: np.ndarray
+    mu_trial: np.ndarray
+
+
+def lm_iteration(g: Geometry, y, f, mu, beta, p: LMParams, k: int) -> Iterate:
+    """One outer iteration up to (not including) the accept decision."""
+    af, am = alphas_at(p, k)
+    phi, r = objective(g, y, f, mu, af, am)
+    gf, gm = gradient(g, f, mu, r, af, am)
+    xf, xm, rr = cg(
+        lambda a, b: normal_matvec(g, f, mu, a, b, beta, p, af, am), -gf, -gm, p.n_cg
+    )
+    ft = np.clip(f + xf, p.f_lo, p.f_hi)
+    mt = np.clip(mu + xm, p.mu_lo, p.mu_hi)
+    sf, sm = ft - f, mt - mu
+    pred = model_decrease(g, f, mu, gf, gm, sf, sm, af, am)
+    phi_t, _ = objective(g, y, ft, mt, af, am)
+    ared = phi - phi_t
+    rho = ared / pred if pred > 0.0 else -np.inf
+    return Iterate(phi, gf, gm, xf, xm, rr, sf, sm, pred, ared, rho, phi_t, ft, mt)
+
+
+HookFn = Callable[[np.ndarray, np.ndarray, np.ndarray, np.ndarray], tuple]
+
+
+def lm_solve(
+    g: Geometry,
+    y,
+    f0,
+    mu0,
+    p: LMParams,
+    hook: Optional[HookFn] = None,
+    replay: Optional[List[int]] = None,
+):
+    """Run the LM iteration; returns (f, mu, LMReport).
+
+    ``replay`` forces the accept decision of each outer iteration (1 accept,
+    0 reject) instead of the test rho > eta; everything else is unchanged.
+    ``hook(f, mu, s_f, s_mu) -> (f~, mu~)`` is the learned refinement.
+    """
+    f = np.array(f0, dtype=np.float64)
+    mu = np.array(mu0, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    rep = LMReport()
+    beta = initial_damping(g, f, mu, p)
+    beta_init = beta
+    nu = 2.0
+    for k in range(p.max_outer):
+        it = lm_iteration(g, y, f, mu, beta, p, k)
+        af, am = alphas_at(p, k)
+        rep.phi.append(it.phi)
+        rep.beta.append(beta)
+        rep.pred.append(it.pred)
+        rep.ared.append(it.ared)
+        rep.rho.append(it.rho)
+        rep.gnorm.append(float(np.sqrt(np.sum(it.gf ** 2) + np.sum(it.gm ** 2))))
+        rep.cg_rr.append(list(it.cg_rr))
+        acc = (it.rho > p.eta) if replay is None else bool(replay[k])
+        rep.accepted.append(int(acc))
+        hook_ok = 0
+        rep.iters_run = k + 1
+        if acc:
+            unorm = float(np.sqrt(np.sum(f ** 2) + np.sum(mu ** 2)))
+            snorm = float(np.sqrt(np.sum(it.sf ** 2) + np.sum(it.sm ** 2)))
+            f_old, mu_old = f, mu
+            f, mu = it.f_trial, it.mu_trial
+            beta, nu = nielsen_update(beta, nu, True, it.rho)
+            if hook is not None:
+                ft, mt = hook(f_old, mu_old, it.sf, it.sm)
+                ft = np.asarray(ft, dtype=np.float64)
+                mt = np.asarray(mt, dtype=np.float64)
+                stf, stm = ft - f_old, mt - mu_old
+                pred_t = model_decrease(g, f_old, mu_old, it.gf, it.gm, stf, stm, af, am)
+                phi_t, _ = objective(g, y, ft, mt, af, am)
+                rho_t = (it.phi - phi_t) / pred_t if pred_t > 0.0 else -np.inf
+                if rho_t > p.eta and pred_t >= it.pred:
+                    f, mu = ft, mt
+                    hook_ok = 1
+            rep.hook_accepted.append(hook_ok)
+            if p.tol > 0.0 and (it.ared <= p.tol * it.phi or snorm <= p.tol * unorm):
+                rep.stop_reason = "tol"
+                break
+        else:
+            beta, nu = nielsen_update(beta, nu, False, it.rho)
+            rep.hook_accepted.append(0)
+        if beta > 1e16 * beta_init:
+            rep.stop_reason = "beta_overflow"
+            break
+    af, am = alphas_at(p, rep.iters_run)
+    rep.phi.append(objective(g, y, f, mu, af, am)[0])
+    rep.beta_final = beta
+    return f, mu, rep

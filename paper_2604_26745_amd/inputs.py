@@ -1,0 +1,164 @@
+"""Seeded synthetic inputs: rod-lattice phantoms, count noise, request traces.
+
+This module holds no arithmetic of the reconstruction method.  It only draws
+the test objects (emission and attenuation maps of a fuel-assembly-like rod
+lattice, Sec. 3.3 of the paper describes the family it imitates), the
+counting noise applied to a clean sinogram someone else computed, and the
+arrival times of a request stream.  Both the CPU oracle's tests and the GPU
+path use it, so that both see the same inputs.
+
+Phantom recipe: a square can of coolant (background attenuation, no
+emission) holding an n_rods x n_rods square lattice of disk rods.  Rods are
+centred at ((k - (n_rods-1)/2) * pitch, (l - (n_rods-1)/2) * pitch); a few
+randomly chosen rods are empty (replaced by coolant: no emission, background
+attenuation).  Each pixel value is the mean over a 4 x 4 sub-pixel grid, so
+rod edges are area-weighted.  Random draws, in this order, from
+``numpy.random.default_rng([seed, 0])``: the empty rod indices (without
+replacement), the emission of each rod (row-major), the attenuation of each
+rod (row-major, when it is drawn).  Noise draws from ``default_rng([seed, 1])``;
+mixed-size configurations draw their size/lattice from ``default_rng([seed, 2])``
+and request arrivals from ``default_rng([seed, 3])``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class SliceConfig:
+    """One slice: geometry, phantom family and solver sizes."""
+
+    name: str
+    n: int
+    n_angles: int
+    n_bins: int
+    psf_sigma: float = 1.5
+    n_rods: int = 9
+    rod_radius: float = 2.0
+    pitch: float = 6.0
+    can_half: float = 27.0
+    rod_mu: Optional[float] = 0.05           # fixed rod attenuation, or None -> uniform draw
+    rod_mu_range: Tuple[float, float] = (0.03, 0.08)
+    bg_mu: float = 0.01
+    f_sigma: float = 0.3                     # rod emission ~ lognormal(0, f_sigma)
+    n_empty: int = 5
+    peak_counts: float = 1e4
+    max_outer: int = 15
+    n_cg: int = 20
+    alpha: float = 1e-2
+
+
+# The five workloads.  Sizes in pixels, angles over a full turn.
+SMALL_64 = SliceConfig("lattice9_n64_a120_b96", 64, 120, 96)
+MAIN_128 = SliceConfig(
+    "lattice9_n128_a360_b192", 128, 360, 192, rod_radius=4.0, pitch=12.0,
+    can_half=54.0, n_cg=30,
+)
+LARGE_256 = SliceConfig(
+    "lattice17_n256_a360_b256", 256, 360, 256, n_rods=17, rod_radius=3.0,
+    pitch=10.0, can_half=85.0, rod_mu=None, f_sigma=0.5, n_empty=29, n_cg=30,
+)
+MIX_SIZES = (64, 96, 128, 192, 256)
+
+
+def mixed_config(seed: int) -> Tuple[SliceConfig, float]:
+    """One slice of the mixed-size batch: size G in MIX_SIZES, 360 angles,
+    1.5 G bins, 9x9 or 17x17 lattice (even odds), can half-side 0.42 G,
+    pitch 2h/n_rods, rod radius pitch/3, 0..ceil(0.1 n^2) empty rods, peak
+    counts 10**U(3, 5).  Returns (config, peak)."""
+    rng = np.random.default_rng([seed, 2])
+    G = int(MIX_SIZES[rng.integers(0, len(MIX_SIZES))])
+    big = bool(rng.integers(0, 2))
+    n_rods = 17 if big else 9
+    h = 0.42 * G
+    pitch = 2.0 * h / n_rods
+    n_empty = int(rng.integers(0, math.ceil(0.1 * n_rods * n_rods) + 1))
+    peak = float(10.0 ** rng.uniform(3.0, 5.0))
+    cfg = SliceConfig(
+        "mix_n%d_r%d" % (G, n_rods), G, 360, int(round(1.5 * G)), n_rods=n_rods,
+        rod_radius=pitch / 3.0, pitch=pitch, can_half=h,
+        rod_mu=None if big else 0.05, f_sigma=0.5 if big else 0.3,
+        n_empty=n_empty, peak_counts=peak, n_cg=30,
+    )
+    return cfg, peak
+
+
+def rod_lattice(cfg: SliceConfig, seed: int = 0):
+    """Ground-truth emission f and attenuation mu (N x N, float64)."""
+    rng = np.random.default_rng([seed, 0])
+    nr = cfg.n_rods
+    n_rod_total = nr * nr
+    empty = set(int(i) for i in rng.choice(n_rod_total, size=cfg.n_empty, replace=False)) \
+        if cfg.n_empty > 0 else set()
+    rod_f = rng.lognormal(0.0, cfg.f_sigma, size=n_rod_total)
+    if cfg.rod_mu is None:
+        rod_mu = rng.uniform(cfg.rod_mu_range[0], cfg.rod_mu_range[1], size=n_rod_total)
+    else:
+        rod_mu = np.full(n_rod_total, cfg.rod_mu)
+
+    n = cfg.n
+    sub = 4
+    off = (np.arange(sub) + 0.5) / sub - 0.5
+    cc = np.arange(n) - 0.5 * (n - 1)
+    # sub-pixel sample coordinates, shape (n*sub,)
+    xs = (cc[:, None] + off[None, :]).reshape(-1)
+    X, Y = np.meshgrid(xs, xs)          # X: column coordinate, Y: row coordinate
+    f_hi = np.zeros_like(X)
+    in_can = (np.abs(X) <= cfg.can_half) & (np.abs(Y) <= cfg.can_half)
+    mu_hi = np.where(in_can, cfg.bg_mu, 0.0)
+    for idx in range(n_rod_total):
+        if idx in empty:
+            continue
+        l, k = divmod(idx, nr)          # row-major: l = lattice row, k = lattice column
+        cx = (k - 0.5 * (nr - 1)) * cfg.pitch
+        cy = (l - 0.5 * (nr - 1)) * cfg.pitch
+        # window of sub-samples that can lie inside this rod
+        lo_c = max(0, int(np.searchsorted(xs, cx - cfg.rod_radius - 1.0)))
+        hi_c = min(xs.size, int(np.searchsorted(xs, cx + cfg.rod_radius + 1.0)))
+        lo_r = max(0, int(np.searchsorted(xs, cy - cfg.rod_radius - 1.0)))
+        hi_r = min(xs.size, int(np.searchsorted(xs, cy + cfg.rod_radius + 1.0)))
+        Xw = X[lo_r:hi_r, lo_c:hi_c]
+        Yw = Y[lo_r:hi_r, lo_c:hi_c]
+        inside = (Xw - cx) ** 2 + (Yw - cy) ** 2 <= cfg.rod_radius ** 2
+        f_hi[lo_r:hi_r, lo_c:hi_c][inside] = rod_f[idx]
+        mu_hi[lo_r:hi_r, lo_c:hi_c][inside] = rod_mu[idx]
+    f = f_hi.reshape(n, sub, n, sub).mean(axis=(1, 3))
+    mu = mu_hi.reshape(n, sub, n, sub).mean(axis=(1, 3))
+    return f, mu
+
+
+def poisson_counts(y_clean: np.ndarray, peak: float, seed: int = 0) -> np.ndarray:
+    """y = Poisson(kappa * y_clean) / kappa with kappa = peak / max(y_clean)."""
+    rng = np.random.default_rng([seed, 1])
+    y_clean = np.asarray(y_clean, dtype=np.float64)
+    kappa = peak / float(np.max(y_clean))
+    return rng.poisson(np.maximum(kappa * y_clean, 0.0)).astype(np.float64) / kappa
+
+
+def random_like(shape, seed: int, scale: float = 1.0, kind: str = "normal") -> np.ndarray:
+    """Seeded test vectors (directions, cotangents)."""
+    rng = np.random.default_rng([seed, 7])
+    if kind == "normal":
+        return scale * rng.standard_normal(shape)
+    return scale * rng.uniform(0.0, 1.0, size=shape)
+
+
+def arrival_times(rate: float, duration: float, seed: int = 0) -> np.ndarray:
+    """Open-loop Poisson arrivals (seconds) at ``rate`` per second over ``duration``."""
+    rng = np.random.default_rng([seed, 3])
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        out.append(t)
+    return np.asarray(out)
+
+
+def scaled(cfg: SliceConfig, **kw) -> SliceConfig:
+    return replace(cfg, **kw)
