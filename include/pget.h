@@ -1,0 +1,232 @@
+/*
+ * pget.h — C ABI of the MI355X (gfx950) library for the Levenberg-Marquardt
+ * reconstruction of emission and attenuation maps in passive gamma emission
+ * tomography (arXiv 2604.26745, "Robust Model-Based Iteration for Passive
+ * Gamma Emission Tomography").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Maps (emission f, the paper's lambda; attenuation mu) are N x N,
+ *    row-major, pixel (r, c) centred at (c - (N-1)/2, r - (N-1)/2), pixel
+ *    size 1.  Sinograms are n_angles x n_bins, row-major.
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *    tensors), contiguous, 4-byte aligned, FP32 (IEEE binary32).  Inputs must
+ *    not alias outputs unless stated.
+ *  - Every call is asynchronous on `stream`; argument errors are returned
+ *    synchronously and nothing is enqueued.  Device-side failures of the
+ *    solver are reported in the report's `status` after the stream syncs.
+ *  - The caller owns every data buffer and the workspace; the library owns
+ *    only the plan's small tables (angle table, collimator taps, ray clip
+ *    bounds).  `ws` must be at least pget_workspace_bytes(plan, op, batch)
+ *    bytes of device memory, 256-byte aligned; its contents on entry are
+ *    ignored and on exit are unspecified.
+ *  - A plan may be used from several threads only with distinct workspaces
+ *    and streams.
+ *  - No entry point throws; every failure is a negative pget_status.
+ */
+#ifndef PGET_H
+#define PGET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PGET_OK = 0,
+    PGET_ERR_INVALID_ARG = -1, /* bad pointer, size or parameter            */
+    PGET_ERR_HIP = -2,         /* a HIP runtime call failed                  */
+    PGET_ERR_WORKSPACE = -3,   /* workspace missing or too small             */
+    PGET_ERR_NONFINITE = -4,   /* NaN/Inf met in the solver (report status)  */
+    PGET_ERR_UNSUPPORTED = -5  /* geometry outside what the kernels handle   */
+} pget_status;
+
+/* Storage type of maps and sinograms handed to the library. */
+typedef enum { PGET_FP32 = 0 } pget_storage;
+
+/*
+ * Parallel-beam geometry of one slice (Sec. 2.1, eq. fwd_model and its
+ * discrete form eq. d_fwd_model).  Angle a is theta_a = angle0 + a*arc/n_angles;
+ * omega = (cos theta, sin theta) points toward the detector, bin j sits at
+ * s_j = (j - (n_bins-1)/2)*bin_size along omega_perp = (-sin, cos), and each
+ * ray is sampled at t_i = (i - (n_t-1)/2)*step, n_t = 2*ceil((N/sqrt2+1)/step).
+ * The maps are sampled bilinearly (zero outside the grid), a sample is
+ * attenuated by half its own attenuation plus all samples nearer the detector,
+ * the ray sum is weighted by step, and the collimator response r_{m,n} is a
+ * Gaussian across bins with standard deviation psf_sigma bins, truncated at
+ * psf_radius bins (negative: ceil(3 sigma)), normalised, zero-padded.
+ * atten_scale is the constant correction c of eq. d_fwd_model.
+ */
+typedef struct {
+    int32_t n;          /* N, 2 <= N <= 1024                                 */
+    int32_t n_angles;   /* >= 1                                              */
+    int32_t n_bins;     /* >= 1                                              */
+    int32_t psf_radius; /* taps per side; < 0 -> ceil(3*psf_sigma); <= 32   */
+    double angle0;      /* radians                                           */
+    double arc;         /* radians, e.g. 2*pi for a full turn                */
+    double bin_size;    /* > 0, pixels                                       */
+    double step;        /* > 0, pixels                                       */
+    double psf_sigma;   /* >= 0, bins; 0 = no blur                           */
+    double atten_scale; /* > 0                                               */
+} pget_geometry;
+
+typedef struct pget_plan pget_plan;
+
+/* Operation codes for pget_workspace_bytes. */
+enum { PGET_OP_FORWARD = 0, PGET_OP_JVP = 1, PGET_OP_VJP = 2, PGET_OP_LM = 3 };
+
+/*
+ * Build the geometry tables of one slice shape on the current HIP device.
+ * *out receives an opaque plan to release with pget_plan_destroy.
+ * Errors: INVALID_ARG (null pointer, size out of range), UNSUPPORTED,
+ * HIP (device allocation of the tables failed).
+ */
+pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pget_plan** out);
+void pget_plan_destroy(pget_plan* plan);
+
+/* Derived sizes: samples per ray n_t, and the collimator half width. */
+int32_t pget_plan_n_samples(const pget_plan* plan);
+int32_t pget_plan_psf_half_width(const pget_plan* plan);
+
+/*
+ * Device workspace needed by `op` for `batch` slices of this plan's shape
+ * (batch >= 1; forward/jvp/vjp use batch 1).  0 on a bad argument.
+ */
+size_t pget_workspace_bytes(const pget_plan* plan, int32_t op, int32_t batch);
+
+/*
+ * y = A(f, mu): the attenuated ray transform with collimator response
+ * (Sec. 2.1, eq. fwd_model / eq. d_fwd_model).  f, mu: N x N; y: n_angles x
+ * n_bins.  ws: pget_workspace_bytes(plan, PGET_OP_FORWARD, 1).
+ */
+pget_status pget_forward(const pget_plan* plan, const float* f, const float* mu, float* y,
+                         void* ws, hipStream_t stream);
+
+/*
+ * jv = J(f, mu) [vf, vmu] = D_lambda F[vf] + D_mu F[vmu] with
+ * D_lambda F[v] = F(v, mu) and D_mu F[v] = -F(lambda * B v, mu) (Sec. 2.1,
+ * eq. frechet), in the same discretisation as pget_forward.  y_or_null, if
+ * not NULL, also receives A(f, mu).  ws: PGET_OP_JVP.
+ */
+pget_status pget_jvp(const pget_plan* plan, const float* f, const float* mu, const float* vf,
+                     const float* vmu, float* jv, float* y_or_null, void* ws, hipStream_t stream);
+
+/*
+ * [gf, gmu] = J(f, mu)^T w, the exact transpose of pget_jvp (the adjoint
+ * F'^* used for the gradient F'^*[r_k] in Sec. 3.1).  Computed as a gather
+ * per pixel over (angle, bin, sample); no atomics, deterministic.
+ * w: n_angles x n_bins; gf, gmu: N x N.  ws: PGET_OP_VJP.
+ */
+pget_status pget_vjp(const pget_plan* plan, const float* f, const float* mu, const float* w,
+                     float* gf, float* gmu, void* ws, hipStream_t stream);
+
+/*
+ * Solver parameters (Sec. 2.2, eqs. lma_objective, LMA-step; Sec. 3.1).
+ * Objective Phi(u) = 0.5 ||A(u) - y||^2 + 0.5 alpha_f ||grad f||^2
+ *                    + 0.5 alpha_mu ||grad mu||^2   (forward differences,
+ * Neumann boundary: the paper's priors P1, P2 are replaced by this gradient
+ * penalty).  Each outer iteration solves (J^T J + beta D + R) x = -g with
+ * n_cg conjugate-gradient steps from x = 0, D = diag(d_f I, d_mu I),
+ * R = diag(alpha_f L, alpha_mu L), L = grad^T grad; clamps u + x into the box
+ * [f_lo, f_hi] x [mu_lo, mu_hi]; accepts iff the gain ratio
+ * rho = (Phi(u) - Phi(u')) / (m(0) - m(s)) > eta (eq. rho_agreement; rho is
+ * -inf when the predicted decrease is <= 0); and updates beta by Nielsen's
+ * rule.  beta0 <= 0 selects beta0 = tau * ||J 1||^2 / ||1||^2.
+ * alpha_decay > 1 divides both alphas by alpha_decay^min(k, alpha_decay_until)
+ * at outer iteration k (the continuation of Sec. 3.1); 1 disables it.
+ * tol > 0 stops after an accepted step with ared <= tol*Phi or
+ * ||s|| <= tol*||u||.  replay (test use): per outer iteration 1 = accept,
+ * 0 = reject, instead of the rho test; NULL for the normal rule.
+ */
+typedef struct {
+    int32_t max_outer;        /* >= 1                                        */
+    int32_t n_cg;             /* >= 1                                        */
+    double alpha_f, alpha_mu; /* >= 0                                        */
+    double alpha_decay;       /* >= 1                                        */
+    int32_t alpha_decay_until;
+    double beta0, tau;
+    double eta;               /* acceptance threshold, e.g. 1e-3             */
+    double d_f, d_mu;         /* > 0                                         */
+    double f_lo, f_hi, mu_lo, mu_hi;
+    double tol;
+    const int8_t* replay;     /* host pointer, max_outer entries, or NULL    */
+} pget_lm_params;
+
+/*
+ * Per-solve report.  Every pointer is caller-owned and may be NULL (not
+ * written) or point to host or device memory of the given length; it is
+ * written asynchronously on the stream.  After the stream syncs:
+ *   status        PGET_OK, or PGET_ERR_NONFINITE if Phi or a step went
+ *                 non-finite (the iterate is left at its last finite value).
+ *   iters_run     outer iterations executed (<= max_outer).
+ *   phi[k]        Phi at the start of outer iteration k; phi[iters_run] is
+ *                 Phi of the returned maps.       [max_outer + 1]
+ *   rho, beta, pred, ared, gnorm [k]               [max_outer]
+ *   accepted[k], hook_accepted[k]                  [max_outer]
+ *   cg_rr[k * n_cg + m]  r^T r after CG step m     [max_outer * n_cg]
+ *   beta_final    damping after the last iteration.
+ * The scalar fields are written through `scalars` (device or host memory,
+ * 4 doubles: status, iters_run, beta_final, stop_reason) when not NULL;
+ * stop_reason: 0 max_outer, 1 tolerance, 2 damping overflow, 3 non-finite.
+ */
+typedef struct {
+    double* scalars;
+    double* phi;
+    double* rho;
+    double* beta;
+    double* pred;
+    double* ared;
+    double* gnorm;
+    int8_t* accepted;
+    int8_t* hook_accepted;
+    double* cg_rr;
+} pget_lm_report;
+
+/*
+ * The learned refinement of Alg. 2 (Deep Gauss-Newton step), called on the
+ * host after each ACCEPTED LM step with device pointers to the previous
+ * iterate u_k = (f, mu) and the LM step s_k = (s_f, s_mu); it must enqueue
+ * work on `stream` that writes its proposal u~ into (f_tilde, mu_tilde) and
+ * return 0, or return nonzero to skip.  The proposal is kept iff
+ * rho(u~ - u_k) > eta and m(u~ - u_k) <= m(s_k) (Prop. 3.2, Alg. 2).
+ */
+typedef int (*pget_refine_fn)(void* user, const float* f, const float* mu, const float* s_f,
+                              const float* s_mu, float* f_tilde, float* mu_tilde,
+                              hipStream_t stream);
+
+/*
+ * Levenberg-Marquardt reconstruction of one slice.  f_inout, mu_inout hold
+ * the initial guess on entry and the result on exit (N x N each); y is the
+ * measured sinogram.  Without a hook the whole solve is enqueued with no
+ * host synchronisation; with a hook the host waits for each accept decision.
+ * ws: PGET_OP_LM with batch 1.
+ */
+pget_status pget_lm_solve(const pget_plan* plan, const float* y, float* f_inout, float* mu_inout,
+                          const pget_lm_params* params, pget_refine_fn hook, void* hook_user,
+                          const pget_lm_report* report, void* ws, hipStream_t stream);
+
+/*
+ * n_slices independent reconstructions of the same plan shape solved
+ * together (every kernel launch covers all slices).  y, f_inout, mu_inout
+ * are arrays of n_slices device pointers (host arrays of pointers);
+ * params and reports are arrays of n_slices entries (reports may be NULL).
+ * Each slice's result is the one pget_lm_solve gives for it alone.
+ * ws: PGET_OP_LM with batch n_slices.
+ */
+pget_status pget_lm_solve_batched(const pget_plan* plan, int32_t n_slices, const float* const* y,
+                                  float* const* f_inout, float* const* mu_inout,
+                                  const pget_lm_params* params, const pget_lm_report* reports,
+                                  void* ws, hipStream_t stream);
+
+/* Human-readable name of a status code (static string). */
+const char* pget_status_string(pget_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGET_H */

@@ -1,0 +1,838 @@
+// Host runtime and C ABI of libpget: plans (geometry tables), workspace
+// layout, launch shapes, and the device-resident Levenberg-Marquardt loop.
+#include "pget.h"
+#include "pget_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+
+using namespace pget;
+
+struct pget_plan {
+    pget_geometry geom;
+    Geo g;
+    Tables t;
+    void* table_mem;     // one device allocation holding every table
+    bool lds_img;        // the bordered map pair fits in LDS
+    size_t op_lds_bytes; // dynamic LDS of k_march / k_jvp_lin
+    int op_threads;      // threads per block of k_march / k_jvp_lin
+    int tiles_x;         // VJP tiles per edge
+    int device;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e__ = (expr);                       \
+        if (e__ != hipSuccess) return PGET_ERR_HIP;    \
+    } while (0)
+
+bool geometry_ok(const pget_geometry* g)
+{
+    if (!g) return false;
+    // N <= 512 and n_angles <= 1024 keep every reducing launch within
+    // SLOT_WIDTH blocks per slice
+    if (g->n < 2 || g->n > 512) return false;
+    if (g->n_angles < 1 || g->n_angles > SLOT_WIDTH) return false;
+    if (g->n_bins < 1 || g->n_bins > 8192) return false;
+    if (!(g->bin_size >= 1.0) || !(g->step >= 1.0)) return false;   // <= 3 gather candidates per axis
+    if (!(g->psf_sigma >= 0.0) || !(g->atten_scale > 0.0)) return false;
+    if (!isfinite(g->angle0) || !isfinite(g->arc)) return false;
+    if (g->psf_radius > 32) return false;
+    if (g->psf_sigma > 0.0 && g->psf_radius < 0 && ceil(3.0 * g->psf_sigma) > 32.0) return false;
+    return true;
+}
+
+int half_width(const pget_geometry* g)
+{
+    if (g->psf_sigma <= 0.0) return 0;
+    if (g->psf_radius >= 0) return g->psf_radius;
+    return (int)ceil(3.0 * g->psf_sigma);
+}
+
+// Launch shapes for a batch of `batch` slices.
+struct Shapes {
+    int apb;          // angles per block of k_march / k_jvp_lin
+    int n_op_blocks;  // blocks per slice
+    int groups;       // angle groups of the adjoint gather
+    int n_vjp_blocks; // blocks per slice of k_vjp_lin
+    int n_ew_blocks;  // blocks per slice of the element-wise kernels
+};
+
+Shapes shapes_for(const pget_plan* P, int batch)
+{
+    Shapes s;
+    const int cus = 256;
+    // enough blocks to cover the chip twice; more angles per block when the
+    // batch already does (the staged map is then reused across angles)
+    int want = std::max(1, (P->g.n_angles * batch) / (4 * cus));
+    s.apb = std::min(4, want);
+    s.n_op_blocks = (P->g.n_angles + s.apb - 1) / s.apb;
+    const int tiles = P->tiles_x * P->tiles_x;
+    int g = (2 * cus + tiles * batch - 1) / (tiles * batch);
+    g = std::max(1, std::min(g, P->g.n_angles));
+    s.groups = g;
+    s.n_vjp_blocks = tiles * g;
+    s.n_ew_blocks = (P->g.n * P->g.n + EW_THREADS - 1) / EW_THREADS;
+    return s;
+}
+
+// Workspace layout.  Every buffer is 256-byte aligned.
+struct Layout {
+    size_t wts, tsum, sino_a, sino_b, ymeas, gpart_grad, gpart_cg, gimg, part;
+    size_t u, ut, s, x, r, p, q, grad, state, params, repdev, reparr;
+    size_t total;
+};
+
+Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int max_outer, int n_cg)
+{
+    const Geo& g = P->g;
+    Layout L = {};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    const size_t B = (size_t)batch;
+    const size_t n2 = (size_t)g.n * g.n;
+    const size_t sino = (size_t)g.n_angles * g.n_bins;
+    const size_t lat = (size_t)g.n_angles * g.n_t * g.n_bins;
+    if (op != PGET_OP_FORWARD) {
+        L.wts = take(B * lat * sizeof(float2));
+        L.tsum = take(B * sino * sizeof(float));
+    }
+    L.sino_a = take(B * sino * sizeof(float));
+    L.sino_b = take(B * sino * sizeof(float));
+    L.gimg = P->lds_img ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
+    L.part = take(B * (size_t)N_SLOTS * SLOT_WIDTH * sizeof(double));
+    if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.groups * B * 2 * n2 * sizeof(float));
+    if (op == PGET_OP_LM) {
+        L.gpart_grad = take((size_t)sh.groups * B * 2 * n2 * sizeof(float));
+        L.ymeas = take(B * sino * sizeof(float));
+        L.u = take(B * 2 * n2 * sizeof(float));
+        L.ut = take(B * 2 * n2 * sizeof(float));
+        L.s = take(B * 2 * n2 * sizeof(float));
+        L.x = take(B * 2 * n2 * sizeof(float));
+        L.r = take(B * 2 * n2 * sizeof(float));
+        L.p = take(B * 2 * n2 * sizeof(float));
+        L.q = take(B * 2 * n2 * sizeof(float));
+        L.grad = take(B * 2 * n2 * sizeof(float));
+        L.state = take(B * sizeof(LMState));
+        L.params = take(B * sizeof(LMParamsDev));
+        L.repdev = take(B * sizeof(ReportDev));
+        const size_t per = (size_t)(max_outer + 1) * 6 * sizeof(double) + 2 * (size_t)max_outer +
+                           (size_t)max_outer * n_cg * sizeof(double) + 4 * sizeof(double) + 64;
+        L.reparr = take(B * align_up(per));
+    }
+    L.total = off;
+    return L;
+}
+
+inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+Tables tables_of(const pget_plan* P) { return P->t; }
+
+template <bool LDS, int M>
+void launch_march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_march<LDS, M>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes, s, A);
+}
+template <int M>
+void march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStream_t s)
+{
+    if (P->lds_img) launch_march<true, M>(P, A, blocks, batch, s);
+    else launch_march<false, M>(P, A, blocks, batch, s);
+}
+template <bool LDS, int M>
+void launch_jvp(const pget_plan* P, const JvpArgs& A, int blocks, int batch, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_jvp_lin<LDS, M>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes, s, A);
+}
+template <int M>
+void jvp(const pget_plan* P, const JvpArgs& A, int blocks, int batch, hipStream_t s)
+{
+    if (P->lds_img) launch_jvp<true, M>(P, A, blocks, batch, s);
+    else launch_jvp<false, M>(P, A, blocks, batch, s);
+}
+
+void pack(const pget_plan* P, const PairSrc& src, const double* part, float2* out, int batch,
+          const LMState* st, hipStream_t s)
+{
+    const int total = P->g.pitch * P->g.pitch;
+    const int blocks = std::min(1024, (total + 255) / 256);
+    hipLaunchKernelGGL(k_pack, dim3(blocks, batch), dim3(256), 0, s, P->g, src, part, out,
+                       (long long)total, st);
+}
+
+PairSrc planar_src(const float* f, const float* mu, long long stride)
+{
+    PairSrc s = {};
+    s.af = f;
+    s.am = mu;
+    s.stride = stride;
+    s.kind = 0;
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pget_status_string(pget_status st)
+{
+    switch (st) {
+    case PGET_OK: return "ok";
+    case PGET_ERR_INVALID_ARG: return "invalid argument";
+    case PGET_ERR_HIP: return "HIP runtime error";
+    case PGET_ERR_WORKSPACE: return "workspace missing or too small";
+    case PGET_ERR_NONFINITE: return "non-finite value in the solver";
+    case PGET_ERR_UNSUPPORTED: return "unsupported geometry";
+    }
+    return "unknown status";
+}
+
+pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pget_plan** out)
+{
+    if (!out) return PGET_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!geometry_ok(geom)) return PGET_ERR_INVALID_ARG;
+    if (storage != PGET_FP32) return PGET_ERR_UNSUPPORTED;
+    pget_plan* P = new (std::nothrow) pget_plan();
+    if (!P) return PGET_ERR_HIP;
+    P->geom = *geom;
+    Geo& g = P->g;
+    g.n = geom->n;
+    g.n_angles = geom->n_angles;
+    g.n_bins = geom->n_bins;
+    g.n_t = 2 * (int)ceil(((double)geom->n / sqrt(2.0) + 1.0) / geom->step);
+    g.K = half_width(geom);
+    g.pitch = g.n + 2;
+    g.n_groups = (g.n_bins + RG - 1) / RG;
+    g.step = (float)geom->step;
+    g.bin_size = (float)geom->bin_size;
+    g.t_off = 0.5f * (float)(g.n_t - 1);
+    g.s_off = 0.5f * (float)(g.n_bins - 1);
+    g.half = 0.5f * (float)(g.n - 1);
+    g.c_att = (float)geom->atten_scale;
+    g.kq = (float)(-geom->atten_scale * geom->step * geom->step);
+    g.ln2_scale = (float)(geom->atten_scale * geom->step * 1.4426950408889634);
+
+    // ---- tables in double precision, stored rounded to float
+    const int na = g.n_angles, nb = g.n_bins, nt = g.n_t, ng = g.n_groups, K = g.K;
+    std::vector<float4> trig(na);
+    std::vector<float2> rbase((size_t)na * nb);
+    std::vector<int2> clip((size_t)na * nb);
+    std::vector<int2> grange((size_t)na * ng);
+    std::vector<float> taps(2 * K + 1);
+    const double half = 0.5 * (g.n - 1), soff = 0.5 * (nb - 1), toff = 0.5 * (nt - 1);
+    for (int a = 0; a < na; ++a) {
+        const double th = geom->angle0 + (double)a * geom->arc / (double)na;
+        const double cs = cos(th), sn = sin(th);
+        trig[a] = make_float4((float)(geom->step * cs), (float)(geom->step * sn), (float)cs, (float)sn);
+        for (int grp = 0; grp < ng; ++grp) grange[(size_t)a * ng + grp] = make_int2(1, 0);
+        for (int j = 0; j < nb; ++j) {
+            const double s = ((double)j - soff) * geom->bin_size;
+            const double cb = -s * sn + half, rbv = s * cs + half;
+            rbase[(size_t)a * nb + j] = make_float2((float)cb, (float)rbv);
+            int lo = nt, hi = -1;
+            for (int i = 0; i < nt; ++i) {
+                const double t = ((double)i - toff) * geom->step;
+                const double col = cb + t * cs, row = rbv + t * sn;
+                if (col > -1.0 && col < (double)g.n && row > -1.0 && row < (double)g.n) {
+                    lo = std::min(lo, i);
+                    hi = std::max(hi, i);
+                }
+            }
+            if (hi < lo) { lo = 1; hi = 0; }
+            clip[(size_t)a * nb + j] = make_int2(lo, hi);
+            if (hi >= lo) {
+                int2& gr = grange[(size_t)a * ng + j / RG];
+                if (gr.y < gr.x) gr = make_int2(lo, hi);
+                else gr = make_int2(std::min(gr.x, lo), std::max(gr.y, hi));
+            }
+        }
+    }
+    if (K == 0) taps[0] = 1.0f;
+    else {
+        std::vector<double> t(2 * K + 1);
+        double sum = 0.0;
+        for (int k = -K; k <= K; ++k) {
+            t[k + K] = exp(-(double)(k * k) / (2.0 * geom->psf_sigma * geom->psf_sigma));
+            sum += t[k + K];
+        }
+        for (int k = 0; k < 2 * K + 1; ++k) taps[k] = (float)(t[k] / sum);
+    }
+    size_t o_trig = 0;
+    size_t o_rbase = align_up(o_trig + trig.size() * sizeof(float4));
+    size_t o_clip = align_up(o_rbase + rbase.size() * sizeof(float2));
+    size_t o_gr = align_up(o_clip + clip.size() * sizeof(int2));
+    size_t o_taps = align_up(o_gr + grange.size() * sizeof(int2));
+    size_t total = align_up(o_taps + taps.size() * sizeof(float));
+    if (hipGetDevice(&P->device) != hipSuccess || hipMalloc(&P->table_mem, total) != hipSuccess) {
+        delete P;
+        return PGET_ERR_HIP;
+    }
+    char* base = static_cast<char*>(P->table_mem);
+    bool ok = hipMemcpy(base + o_trig, trig.data(), trig.size() * sizeof(float4), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + o_rbase, rbase.data(), rbase.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + o_clip, clip.data(), clip.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + o_gr, grange.data(), grange.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + o_taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        (void)hipFree(P->table_mem);
+        delete P;
+        return PGET_ERR_HIP;
+    }
+    P->t.trig = reinterpret_cast<const float4*>(base + o_trig);
+    P->t.rbase = reinterpret_cast<const float2*>(base + o_rbase);
+    P->t.clip = reinterpret_cast<const int2*>(base + o_clip);
+    P->t.grange = reinterpret_cast<const int2*>(base + o_gr);
+    P->t.taps = reinterpret_cast<const float*>(base + o_taps);
+
+    // ---- launch shapes
+    const size_t img_bytes = (size_t)g.pitch * g.pitch * sizeof(float2);
+    const size_t row_bytes = 2 * (size_t)nb * sizeof(float);
+    const size_t lds_budget = 160 * 1024 - 2048;   // static shared arrays take the rest
+    P->lds_img = img_bytes + row_bytes <= lds_budget;
+    P->op_lds_bytes = (P->lds_img ? img_bytes : 0) + row_bytes;
+    if (P->op_lds_bytes > lds_budget) {
+        (void)hipFree(P->table_mem);
+        delete P;
+        return PGET_ERR_UNSUPPORTED;
+    }
+    P->op_threads = std::min(ng, 16) * WAVE;
+    if (P->op_lds_bytes > 64 * 1024) {
+        const int bytes = (int)P->op_lds_bytes;
+        bool attr_ok = true;
+        if (P->lds_img) {
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_LIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_TRIAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_NORMAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_SQNORM>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+        }
+        if (!attr_ok) {
+            (void)hipFree(P->table_mem);
+            delete P;
+            return PGET_ERR_HIP;
+        }
+    }
+    P->tiles_x = (g.n + VT - 1) / VT;
+    *out = P;
+    return PGET_OK;
+}
+
+void pget_plan_destroy(pget_plan* plan)
+{
+    if (!plan) return;
+    (void)hipFree(plan->table_mem);
+    delete plan;
+}
+
+int32_t pget_plan_n_samples(const pget_plan* plan) { return plan ? plan->g.n_t : -1; }
+int32_t pget_plan_psf_half_width(const pget_plan* plan) { return plan ? plan->g.K : -1; }
+
+size_t pget_workspace_bytes(const pget_plan* plan, int32_t op, int32_t batch)
+{
+    if (!plan || batch < 1 || op < PGET_OP_FORWARD || op > PGET_OP_LM) return 0;
+    if (op != PGET_OP_LM && batch != 1) return 0;
+    Shapes sh = shapes_for(plan, batch);
+    // report arrays are sized for the largest supported solve
+    Layout L = layout_for(plan, op, batch, sh, 256, 256);
+    return L.total;
+}
+
+pget_status pget_forward(const pget_plan* P, const float* f, const float* mu, float* y, void* ws,
+                         hipStream_t stream)
+{
+    if (!P || !f || !mu || !y) return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    Shapes sh = shapes_for(P, 1);
+    Layout L = layout_for(P, PGET_OP_FORWARD, 1, sh, 256, 256);
+    MarchArgs A = {};
+    A.g = P->g;
+    A.t = P->t;
+    A.src = planar_src(f, mu, 0);
+    A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
+    A.yout = y;
+    A.angles_per_block = sh.apb;
+    if (!P->lds_img) {
+        A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
+        pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
+    }
+    march<MARCH_FWD>(P, A, sh.n_op_blocks, 1, stream);
+    return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+// Linearise at (f, mu): per-sample weights and ray totals into the workspace.
+static void linearise(const pget_plan* P, const float* f, const float* mu, float* y_or_null,
+                      void* ws, const Layout& L, const Shapes& sh, hipStream_t stream)
+{
+    MarchArgs A = {};
+    A.g = P->g;
+    A.t = P->t;
+    A.src = planar_src(f, mu, 0);
+    A.wts = reinterpret_cast<float2*>(at(ws, L.wts));
+    A.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
+    A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
+    A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
+    A.yout = y_or_null;
+    A.angles_per_block = sh.apb;
+    if (!P->lds_img) {
+        A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
+        pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
+    }
+    march<MARCH_LIN>(P, A, sh.n_op_blocks, 1, stream);
+}
+
+pget_status pget_jvp(const pget_plan* P, const float* f, const float* mu, const float* vf,
+                     const float* vmu, float* jv, float* y_or_null, void* ws, hipStream_t stream)
+{
+    if (!P || !f || !mu || !vf || !vmu || !jv) return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    Shapes sh = shapes_for(P, 1);
+    Layout L = layout_for(P, PGET_OP_JVP, 1, sh, 256, 256);
+    linearise(P, f, mu, y_or_null, ws, L, sh, stream);
+    JvpArgs A = {};
+    A.g = P->g;
+    A.t = P->t;
+    A.src = planar_src(vf, vmu, 0);
+    A.wts = reinterpret_cast<float2*>(at(ws, L.wts));
+    A.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
+    A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
+    A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
+    A.out = jv;
+    A.angles_per_block = sh.apb;
+    if (!P->lds_img) {
+        A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
+        pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
+    }
+    jvp<JVP_PLAIN>(P, A, sh.n_op_blocks, 1, stream);
+    return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const float* w, float* gf,
+                     float* gmu, void* ws, hipStream_t stream)
+{
+    if (!P || !f || !mu || !w || !gf || !gmu) return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    Shapes sh = shapes_for(P, 1);
+    Layout L = layout_for(P, PGET_OP_VJP, 1, sh, 256, 256);
+    linearise(P, f, mu, nullptr, ws, L, sh, stream);
+    float* wt = reinterpret_cast<float*>(at(ws, L.sino_a));
+    hipLaunchKernelGGL(k_psf, dim3(P->g.n_angles), dim3(256), P->g.n_bins * sizeof(float), stream, P->g,
+                       P->t.taps, w, wt);
+    VjpArgs V = {};
+    V.g = P->g;
+    V.t = P->t;
+    V.wts = reinterpret_cast<float2*>(at(ws, L.wts));
+    V.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
+    V.wt = wt;
+    V.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
+    V.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
+    const long long n2 = (long long)P->g.n * P->g.n;
+    V.gpart = reinterpret_cast<float*>(at(ws, L.gpart_cg));
+    V.gpart_group_stride = 2 * n2;
+    V.gpart_slice_stride = 0;
+    V.tiles_x = P->tiles_x;
+    V.groups = sh.groups;
+    hipLaunchKernelGGL(k_vjp_lin, dim3(sh.n_vjp_blocks, 1), dim3(VJP_THREADS), 0, stream, V);
+    hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, (int)n2,
+                       sh.groups, V.gpart, (long long)V.gpart_group_stride, gf, gmu);
+    return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ solver
+namespace {
+
+bool params_ok(const pget_lm_params* p)
+{
+    if (!p) return false;
+    if (p->max_outer < 1 || p->max_outer > 256 || p->n_cg < 1 || p->n_cg > 256) return false;
+    if (!(p->alpha_f >= 0) || !(p->alpha_mu >= 0) || !(p->alpha_decay >= 1.0)) return false;
+    if (!(p->d_f > 0) || !(p->d_mu > 0) || !(p->eta >= 0) || !(p->tau > 0)) return false;
+    if (!(p->f_lo <= p->f_hi) || !(p->mu_lo <= p->mu_hi)) return false;
+    if (!(p->tol >= 0)) return false;
+    return true;
+}
+
+LMParamsDev to_dev(const pget_lm_params& p)
+{
+    LMParamsDev d = {};
+    d.alpha_f = p.alpha_f;
+    d.alpha_mu = p.alpha_mu;
+    d.alpha_decay = p.alpha_decay;
+    d.alpha_decay_until = p.alpha_decay_until;
+    d.max_outer = p.max_outer;
+    d.n_cg = p.n_cg;
+    d.beta0 = p.beta0;
+    d.tau = p.tau;
+    d.eta = p.eta;
+    d.d_f = p.d_f;
+    d.d_mu = p.d_mu;
+    d.f_lo = p.f_lo;
+    d.f_hi = p.f_hi;
+    d.mu_lo = p.mu_lo;
+    d.mu_hi = p.mu_hi;
+    d.tol = p.tol;
+    d.has_replay = p.replay != nullptr;
+    if (p.replay)
+        for (int k = 0; k < p.max_outer; ++k) d.replay[k] = p.replay[k];
+    return d;
+}
+
+struct Solve {
+    const pget_plan* P;
+    int B;
+    Shapes sh;
+    Layout L;
+    void* ws;
+    hipStream_t stream;
+    MarchArgs lin, trial;
+    JvpArgs jcg, jpred, jones;
+    VjpArgs vgrad, vcg;
+    VecArgs V;
+    float2* gimg;
+};
+
+void setup(Solve& S)
+{
+    const pget_plan* P = S.P;
+    const Geo& g = P->g;
+    const long long n2 = (long long)g.n * g.n;
+    const long long sino = (long long)g.n_angles * g.n_bins;
+    const long long lat = (long long)g.n_angles * g.n_t * g.n_bins;
+    void* ws = S.ws;
+    double* part = reinterpret_cast<double*>(at(ws, S.L.part));
+    float* u = reinterpret_cast<float*>(at(ws, S.L.u));
+    float* ut = reinterpret_cast<float*>(at(ws, S.L.ut));
+    LMState* st = reinterpret_cast<LMState*>(at(ws, S.L.state));
+    float2* wts = reinterpret_cast<float2*>(at(ws, S.L.wts));
+    float* tsum = reinterpret_cast<float*>(at(ws, S.L.tsum));
+    float* wt_res = reinterpret_cast<float*>(at(ws, S.L.sino_a));   // K (A(u) - y)
+    float* wt_cg = reinterpret_cast<float*>(at(ws, S.L.sino_b));    // K K J p
+    const float* ymeas = reinterpret_cast<float*>(at(ws, S.L.ymeas));
+    S.gimg = P->lds_img ? nullptr : reinterpret_cast<float2*>(at(ws, S.L.gimg));
+
+    MarchArgs& M = S.lin;
+    M = MarchArgs{};
+    M.g = g;
+    M.t = P->t;
+    M.src = planar_src(u, u + n2, 2 * n2);
+    M.gimg = S.gimg;
+    M.gimg_stride = (long long)g.pitch * g.pitch;
+    M.wts = wts;
+    M.tsum = tsum;
+    M.wts_stride = lat;
+    M.sino_stride = sino;
+    M.ymeas = ymeas;
+    M.wout = wt_res;
+    M.part = part;
+    M.slot = SLOT_PHI_DATA_U;
+    M.st = st;
+    M.angles_per_block = S.sh.apb;
+
+    MarchArgs& T = S.trial;
+    T = M;
+    T.src = planar_src(ut, ut + n2, 2 * n2);
+    T.wts = nullptr;
+    T.tsum = nullptr;
+    T.wout = nullptr;
+    T.slot = SLOT_PHI_DATA_T;
+
+    JvpArgs& J = S.jcg;
+    J = JvpArgs{};
+    J.g = g;
+    J.t = P->t;
+    J.gimg = S.gimg;
+    J.gimg_stride = (long long)g.pitch * g.pitch;
+    J.wts = wts;
+    J.tsum = tsum;
+    J.wts_stride = lat;
+    J.sino_stride = sino;
+    J.out = wt_cg;
+    J.part = part;
+    J.st = st;
+    J.angles_per_block = S.sh.apb;
+    float* r = reinterpret_cast<float*>(at(ws, S.L.r));
+    float* p = reinterpret_cast<float*>(at(ws, S.L.p));
+    J.src = PairSrc{};
+    J.src.af = r;
+    J.src.am = r + n2;
+    J.src.bf = p;
+    J.src.bm = p + n2;
+    J.src.stride = 2 * n2;
+    J.src.kind = 1;
+    J.src.n_rr = S.sh.n_ew_blocks;
+
+    float* s = reinterpret_cast<float*>(at(ws, S.L.s));
+    S.jpred = J;
+    S.jpred.src = planar_src(s, s + n2, 2 * n2);
+    S.jpred.out = nullptr;
+    S.jpred.slot = SLOT_JS;
+    S.jones = S.jpred;
+    S.jones.src.kind = 2;
+    S.jones.slot = SLOT_J1;
+
+    VjpArgs& VG = S.vgrad;
+    VG = VjpArgs{};
+    VG.g = g;
+    VG.t = P->t;
+    VG.wts = wts;
+    VG.tsum = tsum;
+    VG.wt = wt_res;
+    VG.wts_stride = lat;
+    VG.sino_stride = sino;
+    VG.gpart = reinterpret_cast<float*>(at(ws, S.L.gpart_grad));
+    VG.gpart_group_stride = (long long)S.B * 2 * n2;
+    VG.gpart_slice_stride = 2 * n2;
+    VG.tiles_x = P->tiles_x;
+    VG.groups = S.sh.groups;
+    VG.st = st;
+    VG.skip_if_clean = 1;
+    S.vcg = VG;
+    S.vcg.wt = wt_cg;
+    S.vcg.gpart = reinterpret_cast<float*>(at(ws, S.L.gpart_cg));
+    S.vcg.skip_if_clean = 0;
+
+    VecArgs& V = S.V;
+    V = VecArgs{};
+    V.g = g;
+    V.vstride = 2 * n2;
+    V.u = u;
+    V.ut = ut;
+    V.s = s;
+    V.x = reinterpret_cast<float*>(at(ws, S.L.x));
+    V.r = r;
+    V.p = p;
+    V.q = reinterpret_cast<float*>(at(ws, S.L.q));
+    V.grad = reinterpret_cast<float*>(at(ws, S.L.grad));
+    V.gpart = S.vcg.gpart;
+    V.gpart_group_stride = S.vcg.gpart_group_stride;
+    V.gpart_slice_stride = S.vcg.gpart_slice_stride;
+    V.groups = S.sh.groups;
+    V.part = part;
+    V.n_jvp_blocks = S.sh.n_op_blocks;
+    V.n_ew_blocks = S.sh.n_ew_blocks;
+    V.n_march_blocks = S.sh.n_op_blocks;
+    V.st = st;
+    V.prm = reinterpret_cast<LMParamsDev*>(at(ws, S.L.params));
+    V.rep = reinterpret_cast<ReportDev*>(at(ws, S.L.repdev));
+}
+
+void enqueue_march(Solve& S, const MarchArgs& A, int mode)
+{
+    if (!S.P->lds_img) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream);
+    if (mode == MARCH_LIN) march<MARCH_LIN>(S.P, A, S.sh.n_op_blocks, S.B, S.stream);
+    else march<MARCH_TRIAL>(S.P, A, S.sh.n_op_blocks, S.B, S.stream);
+}
+
+void enqueue_jvp(Solve& S, const JvpArgs& A, int mode)
+{
+    if (!S.P->lds_img) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream);
+    if (mode == JVP_NORMAL) jvp<JVP_NORMAL>(S.P, A, S.sh.n_op_blocks, S.B, S.stream);
+    else jvp<JVP_SQNORM>(S.P, A, S.sh.n_op_blocks, S.B, S.stream);
+}
+
+// Model decrease and objective of the step held in ut (k_trial already run):
+// ||J s||^2 and Phi(u').
+void enqueue_step_eval(Solve& S)
+{
+    enqueue_jvp(S, S.jpred, JVP_SQNORM);
+    enqueue_march(S, S.trial, MARCH_TRIAL);
+}
+
+void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_present)
+{
+    const dim3 ew(S.sh.n_ew_blocks, S.B);
+    enqueue_march(S, S.lin, MARCH_LIN);
+    if (k == 0 && need_beta0) {
+        enqueue_jvp(S, S.jones, JVP_SQNORM);
+        hipLaunchKernelGGL(k_beta0, dim3(S.B), dim3(256), 0, S.stream, S.V);
+    }
+    hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vgrad);
+    VecArgs Vg = S.V;
+    Vg.gpart = S.vgrad.gpart;
+    hipLaunchKernelGGL(k_grad_init, ew, dim3(EW_THREADS), 0, S.stream, Vg);
+    for (int m = 0; m < n_cg; ++m) {
+        JvpArgs J = S.jcg;
+        J.src.rr_slot_cur = rr_slot(m);
+        J.src.rr_slot_prev = rr_slot(m + 2);
+        J.src.first = (m == 0);
+        enqueue_jvp(S, J, JVP_NORMAL);
+        hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vcg);
+        VecArgs V = S.V;
+        V.cg_step = m;
+        hipLaunchKernelGGL(k_cg_q, ew, dim3(EW_THREADS), 0, S.stream, V);
+        hipLaunchKernelGGL(k_cg_x, ew, dim3(EW_THREADS), 0, S.stream, V);
+    }
+    VecArgs Vt = S.V;
+    Vt.cg_step = n_cg;
+    hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vt);
+    enqueue_jvp(S, S.jpred, JVP_SQNORM);
+    enqueue_march(S, S.trial, MARCH_TRIAL);
+    hipLaunchKernelGGL(k_decide, dim3(S.B), dim3(256), 0, S.stream, S.V, hook_present ? 1 : 0);
+}
+
+void enqueue_commit(Solve& S)
+{
+    const dim3 ew(S.sh.n_ew_blocks, S.B);
+    hipLaunchKernelGGL(k_accept, ew, dim3(EW_THREADS), 0, S.stream, S.V);
+    hipLaunchKernelGGL(k_commit, dim3((S.B + 63) / 64), dim3(64), 0, S.stream, S.V.st, S.B);
+}
+
+// The hook path of Alg. 2 for slice 0 (batch 1): host round trip per
+// accepted step.
+pget_status run_hook(Solve& S, pget_refine_fn hook, void* user)
+{
+    LMState st;
+    if (hipMemcpyAsync(&st, S.V.st, sizeof(LMState), hipMemcpyDeviceToHost, S.stream) != hipSuccess ||
+        hipStreamSynchronize(S.stream) != hipSuccess)
+        return PGET_ERR_HIP;
+    if (st.done || !st.accepted) return PGET_OK;
+    const long long n2 = (long long)S.P->g.n * S.P->g.n;
+    float* prop = S.V.q;   // free after the CG solve: holds the proposal u~
+    int rc = hook(user, S.V.u, S.V.u + n2, S.V.s, S.V.s + n2, prop, prop + n2, S.stream);
+    if (rc != 0) return PGET_OK;
+    // evaluate the proposal: s~ = u~ - u, m(s~), Phi(u~)
+    VecArgs Vh = S.V;
+    Vh.ut = prop;
+    Vh.hook_mode = 1;
+    const dim3 ew(S.sh.n_ew_blocks, S.B);
+    hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vh);
+    enqueue_jvp(S, S.jpred, JVP_SQNORM);
+    MarchArgs T = S.trial;
+    T.src = planar_src(prop, prop + n2, 2 * n2);
+    T.slot = SLOT_PHI_DATA_H;
+    enqueue_march(S, T, MARCH_TRIAL);
+    hipLaunchKernelGGL(k_hook_decide, dim3(S.B), dim3(256), 0, S.stream, Vh);
+    return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+void copy_report(const ReportDev& R, const pget_lm_report* out, int max_outer, int n_cg, hipStream_t s)
+{
+    if (!out) return;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+        if (dst) (void)hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s);
+    };
+    cp(out->scalars, R.scalars, 4 * sizeof(double));
+    cp(out->phi, R.phi, (size_t)(max_outer + 1) * sizeof(double));
+    cp(out->rho, R.rho, (size_t)max_outer * sizeof(double));
+    cp(out->beta, R.beta, (size_t)max_outer * sizeof(double));
+    cp(out->pred, R.pred, (size_t)max_outer * sizeof(double));
+    cp(out->ared, R.ared, (size_t)max_outer * sizeof(double));
+    cp(out->gnorm, R.gnorm, (size_t)max_outer * sizeof(double));
+    cp(out->accepted, R.accepted, (size_t)max_outer);
+    cp(out->hook_accepted, R.hook_accepted, (size_t)max_outer);
+    cp(out->cg_rr, R.cg_rr, (size_t)max_outer * n_cg * sizeof(double));
+}
+
+pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* const* f,
+                       float* const* mu, const pget_lm_params* params, const pget_lm_report* reports,
+                       pget_refine_fn hook, void* hook_user, void* ws, hipStream_t stream)
+{
+    if (!P || B < 1 || !y || !f || !mu || !params) return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    const int max_outer = params[0].max_outer, n_cg = params[0].n_cg;
+    bool need_beta0 = false;
+    for (int b = 0; b < B; ++b) {
+        if (!params_ok(&params[b])) return PGET_ERR_INVALID_ARG;
+        if (params[b].max_outer != max_outer || params[b].n_cg != n_cg) return PGET_ERR_INVALID_ARG;
+        if (!y[b] || !f[b] || !mu[b]) return PGET_ERR_INVALID_ARG;
+        if (params[b].beta0 <= 0.0) need_beta0 = true;
+    }
+    if (hook && B != 1) return PGET_ERR_INVALID_ARG;
+    Solve S;
+    S.P = P;
+    S.B = B;
+    S.sh = shapes_for(P, B);
+    S.L = layout_for(P, PGET_OP_LM, B, S.sh, 256, 256);
+    S.ws = ws;
+    S.stream = stream;
+    setup(S);
+    const Geo& g = P->g;
+    const size_t n2 = (size_t)g.n * g.n, sino = (size_t)g.n_angles * g.n_bins;
+
+    // parameters and report descriptors (small host -> device uploads)
+    std::vector<LMParamsDev> prm(B);
+    std::vector<ReportDev> rep(B);
+    const size_t per = align_up((size_t)(max_outer + 1) * 6 * sizeof(double) + 2 * (size_t)max_outer +
+                                (size_t)max_outer * n_cg * sizeof(double) + 4 * sizeof(double) + 64);
+    for (int b = 0; b < B; ++b) {
+        prm[b] = to_dev(params[b]);
+        char* base = at(ws, S.L.reparr + (size_t)b * per);
+        size_t o = 0;
+        auto take = [&](size_t bytes) { char* p = base + o; o += (bytes + 7) / 8 * 8; return p; };
+        rep[b].phi = reinterpret_cast<double*>(take((max_outer + 1) * sizeof(double)));
+        rep[b].rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        rep[b].beta = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        rep[b].pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        rep[b].ared = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        rep[b].gnorm = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        rep[b].cg_rr = reinterpret_cast<double*>(take((size_t)max_outer * n_cg * sizeof(double)));
+        rep[b].scalars = reinterpret_cast<double*>(take(4 * sizeof(double)));
+        rep[b].accepted = reinterpret_cast<int8_t*>(take(max_outer));
+        rep[b].hook_accepted = reinterpret_cast<int8_t*>(take(max_outer));
+    }
+    HIP_TRY(hipMemcpyAsync(const_cast<LMParamsDev*>(S.V.prm), prm.data(), B * sizeof(LMParamsDev), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(S.V.rep, rep.data(), B * sizeof(ReportDev), hipMemcpyHostToDevice, stream));
+    float* ymeas = reinterpret_cast<float*>(at(ws, S.L.ymeas));
+    for (int b = 0; b < B; ++b) {
+        HIP_TRY(hipMemcpyAsync(ymeas + b * sino, y[b], sino * sizeof(float), hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(S.V.u + b * 2 * n2, f[b], n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(S.V.u + b * 2 * n2 + n2, mu[b], n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    }
+    // the host vectors above must outlive the uploads
+    HIP_TRY(hipStreamSynchronize(stream));
+    hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
+    for (int k = 0; k < max_outer; ++k) {
+        enqueue_iteration(S, k, n_cg, need_beta0, hook != nullptr);
+        if (hook) {
+            pget_status rc = run_hook(S, hook, hook_user);
+            if (rc != PGET_OK) return rc;
+        }
+        enqueue_commit(S);
+    }
+    hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, stream, S.V);
+    hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, stream, S.V);
+    for (int b = 0; b < B; ++b) {
+        HIP_TRY(hipMemcpyAsync(f[b], S.V.u + b * 2 * n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(mu[b], S.V.u + b * 2 * n2 + n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+        if (reports) copy_report(rep[b], &reports[b], max_outer, n_cg, stream);
+    }
+    return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+pget_status pget_lm_solve(const pget_plan* plan, const float* y, float* f_inout, float* mu_inout,
+                          const pget_lm_params* params, pget_refine_fn hook, void* hook_user,
+                          const pget_lm_report* report, void* ws, hipStream_t stream)
+{
+    const float* ys[1] = {y};
+    float* fs[1] = {f_inout};
+    float* ms[1] = {mu_inout};
+    return solve_impl(plan, 1, ys, fs, ms, params, report, hook, hook_user, ws, stream);
+}
+
+pget_status pget_lm_solve_batched(const pget_plan* plan, int32_t n_slices, const float* const* y,
+                                  float* const* f_inout, float* const* mu_inout,
+                                  const pget_lm_params* params, const pget_lm_report* reports,
+                                  void* ws, hipStream_t stream)
+{
+    return solve_impl(plan, n_slices, y, f_inout, mu_inout, params, reports, nullptr, nullptr, ws, stream);
+}
+
+}  // extern "C"

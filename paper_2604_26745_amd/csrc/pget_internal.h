@@ -1,0 +1,230 @@
+// Internal structures shared by the HIP kernels and the host runtime of
+// libpget.  Not part of the public ABI (include/pget.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pget {
+
+// One wave marches a group of RG consecutive detector bins of one angle;
+// its 64 lanes are RG rays x SPL consecutive samples (lane = ray*SPL + sample).
+constexpr int RG = 16;
+constexpr int SPL = 4;
+constexpr int WAVE = 64;
+// Pixel tile of the adjoint gather and its lattice footprint per angle.
+constexpr int VT = 32;            // tile edge in pixels
+constexpr int VFP = 52;           // staged footprint edge in lattice points (>= VT*sqrt2 + 6)
+constexpr int VJP_THREADS = 256;  // 4 pixels per thread
+constexpr int EW_THREADS = 256;   // element-wise kernels
+constexpr int MAX_TAPS = 65;      // 2*32 + 1
+
+// Geometry of one slice shape, as the kernels see it.
+struct Geo {
+    int n;          // N
+    int n_angles;
+    int n_bins;
+    int n_t;        // samples per ray
+    int K;          // collimator half width
+    int pitch;      // N + 2: row pitch of the zero-bordered image
+    int n_groups;   // ceil(n_bins / RG)
+    float step;     // sample spacing
+    float bin_size;
+    float t_off;    // (n_t - 1) / 2
+    float s_off;    // (n_bins - 1) / 2
+    float half;     // (N - 1) / 2
+    float c_att;    // attenuation scale c
+    float kq;       // -c * step^2: weight of the attenuation derivative
+    float ln2_scale;  // c * step * log2(e): exponent scale for exp2
+};
+
+// Device-resident tables of a plan.
+struct Tables {
+    const float4* trig;   // [n_angles]: (step*cos, step*sin, cos, sin)
+    const float2* rbase;  // [n_angles][n_bins]: (col, row) of the ray at t = 0
+    const int2* clip;     // [n_angles][n_bins]: samples [lo, hi] inside the support; lo > hi if none
+    const int2* grange;   // [n_angles][n_groups]: union of the group's clip ranges
+    const float* taps;    // [2K + 1]
+};
+
+// Per-slice LM parameters on the device.
+struct LMParamsDev {
+    double alpha_f, alpha_mu, alpha_decay;
+    int alpha_decay_until;
+    int max_outer, n_cg;
+    double beta0, tau, eta, d_f, d_mu;
+    double f_lo, f_hi, mu_lo, mu_hi, tol;
+    int has_replay;
+    int8_t replay[256];
+};
+
+// Per-slice LM state on the device.
+struct LMState {
+    double beta, nu, beta_init;
+    double phi_u;        // Phi at the current iterate (with this iteration's alphas)
+    double alpha_f, alpha_mu;  // alphas of the current outer iteration
+    int k;               // outer iterations done
+    int dirty;           // iterate changed since the last linearisation
+    int done;            // solve finished (early exit / non-finite)
+    int accepted;        // decision of the last outer iteration
+    int hook_keep;       // the hook's proposal replaces the LM trial point
+    int done_next;       // stop after this iteration's commit
+    int final_slot;      // slot holding ||A(u) - y||^2 of the current iterate
+    int stop_reason;
+    int status;
+    double pred, ared, rho;    // of the last LM step
+};
+
+// Reduction slots: each kernel that reduces writes one double per block.
+enum Slot {
+    SLOT_PHI_DATA_U = 0,   // ||A(u) - y||^2
+    SLOT_PHI_REG_U,        // alpha ||grad u||^2 (both blocks)
+    SLOT_PHI_DATA_T,       // ||A(u') - y||^2
+    SLOT_PHI_REG_T,        // alpha ||grad u'||^2
+    SLOT_GS,               // g . s
+    SLOT_SRS,              // s . R s
+    SLOT_JS,               // ||J s||^2
+    SLOT_SNORM,            // ||s||^2
+    SLOT_UNORM,            // ||u||^2
+    SLOT_GNORM,            // ||g||^2
+    SLOT_GAMMA,            // p . q
+    SLOT_RR0,              // r.r of CG step m lives in SLOT_RR0 + m % 3: a step reads
+    SLOT_RR1,              // the slots of m and m-1 while writing m+1, so three
+    SLOT_RR2,              // rotating slots keep readers and writers apart
+    SLOT_J1,               // ||J 1||^2 (initial damping)
+    SLOT_PHI_DATA_H,       // ||A(u~) - y||^2 of a hook proposal
+    N_SLOTS
+};
+constexpr int SLOT_WIDTH = 1024;   // max blocks per slice of any reducing launch
+__host__ __device__ constexpr int rr_slot(int m) { return SLOT_RR0 + (m % 3); }
+
+// Report arrays kept on the device during a solve (per slice).
+struct ReportDev {
+    double* phi;     // [max_outer + 1]
+    double* rho;     // [max_outer]
+    double* beta;
+    double* pred;
+    double* ared;
+    double* gnorm;
+    int8_t* accepted;
+    int8_t* hook_accepted;
+    double* cg_rr;   // [max_outer * n_cg]
+    double* scalars; // [4]
+};
+
+
+// Source of the map pair staged for an operator: a, a + beta*b (CG search
+// direction p = r + beta p_old, beta = rr_m / rr_{m-1}), or all ones.
+struct PairSrc {
+    const float* af;
+    const float* am;
+    const float* bf;
+    const float* bm;
+    long long stride;     // elements between slices
+    int kind;             // 0: a; 1: a + beta*b; 2: ones
+    int rr_slot_cur;      // kind 1: slots holding r.r of this and the previous CG step
+    int rr_slot_prev;
+    int n_rr;             // partials per rr slot
+    int first;            // kind 1: 1 on the first CG step (beta = 0)
+};
+
+enum MarchMode { MARCH_FWD = 0, MARCH_LIN = 1, MARCH_TRIAL = 2 };
+enum JvpMode { JVP_PLAIN = 0, JVP_NORMAL = 1, JVP_SQNORM = 2 };
+
+struct MarchArgs {
+    Geo g;
+    Tables t;
+    PairSrc src;            // (f, mu)
+    const float2* gimg;     // global bordered image when not staged in LDS
+    long long gimg_stride;
+    float2* wts;            // MARCH_LIN: [n_angles][n_t][n_bins] (step*E, R')
+    float* tsum;            // MARCH_LIN: [n_angles][n_bins] sum of lambda*E
+    long long wts_stride, sino_stride;
+    const float* ymeas;     // measured sinogram (residual modes) or null
+    float* yout;            // MARCH_FWD: A(f, mu); MARCH_LIN: optional
+    float* wout;            // K (A - y) (MARCH_LIN with ymeas)
+    double* part;           // reduction slots
+    int slot;               // slot of ||A - y||^2
+    const LMState* st;      // skip flags (null: always run)
+    int angles_per_block;
+};
+
+struct JvpArgs {
+    Geo g;
+    Tables t;
+    PairSrc src;            // the direction v (or the CG direction p)
+    const float2* gimg;
+    long long gimg_stride;
+    const float2* wts;
+    const float* tsum;
+    long long wts_stride, sino_stride;
+    float* out;             // PLAIN: K z;  NORMAL: K K z
+    double* part;
+    int slot;               // SQNORM: slot of ||K z||^2
+    const LMState* st;
+    int skip_if_clean;      // for the initial-damping probe: run only when dirty
+    int angles_per_block;
+};
+
+struct VjpArgs {
+    Geo g;
+    Tables t;
+    const float2* wts;
+    const float* tsum;
+    const float* wt;        // blurred cotangent per ray [n_angles][n_bins]
+    long long wts_stride, sino_stride;
+    float* gpart;           // [groups][slices][2][N][N]
+    long long gpart_group_stride, gpart_slice_stride;
+    int tiles_x;            // ceil(N / VT)
+    int groups;             // angle groups
+    const LMState* st;
+    int skip_if_clean;
+};
+
+struct VecArgs {
+    Geo g;
+    long long vstride;      // 2 N^2
+    float* u;               // current iterate (f, mu)
+    float* ut;              // trial iterate
+    float* s;               // step u' - u
+    float* x;               // CG solution
+    float* r;               // CG residual
+    float* p;               // CG direction (previous step's on entry to k_cg_x)
+    float* q;               // (J^T J + beta D + R) p
+    float* grad;            // gradient g
+    const float* gpart;     // angle-group partials of the adjoint
+    long long gpart_group_stride, gpart_slice_stride;
+    int groups;
+    double* part;
+    int n_jvp_blocks;       // partials of SLOT_JS / J1 / PHI_DATA_*
+    int n_ew_blocks;        // partials of element-wise slots
+    int n_march_blocks;
+    LMState* st;
+    const LMParamsDev* prm;
+    ReportDev* rep;
+    int cg_step;            // CG step index m (k_cg_q / k_cg_x / k_jvp source)
+    int hook_mode;          // k_trial: 1 -> ut holds the hook's proposal (no clamp)
+};
+
+template <bool LDS_IMG, int MODE> __global__ void k_march(MarchArgs A);
+template <bool LDS_IMG, int MODE> __global__ void k_jvp_lin(JvpArgs A);
+__global__ void k_pack(Geo g, PairSrc s, const double* part, float2* out, long long out_stride,
+                       const LMState* st);
+__global__ void k_psf(Geo g, const float* taps_g, const float* in, float* out);
+__global__ void k_vjp_lin(VjpArgs A);
+__global__ void k_sum_groups(int n2, int groups, const float* gpart, long long group_stride, float* gf,
+                             float* gm);
+__global__ void k_grad_init(VecArgs V);
+__global__ void k_cg_q(VecArgs V);
+__global__ void k_cg_x(VecArgs V);
+__global__ void k_trial(VecArgs V);
+__global__ void k_beta0(VecArgs V);
+__global__ void k_lm_init(LMState* st, const LMParamsDev* prm, int n_slices);
+__global__ void k_decide(VecArgs V, int hook_present);
+__global__ void k_hook_decide(VecArgs V);
+__global__ void k_accept(VecArgs V);
+__global__ void k_final_reg(VecArgs V);
+__global__ void k_finish(VecArgs V);
+__global__ void k_commit(LMState* st, int n_slices);
+
+}  // namespace pget

@@ -1,0 +1,971 @@
+// HIP kernels for gfx950 of the PGET Levenberg-Marquardt hot path.
+//
+// Operators (arXiv 2604.26745, Sec. 2.1, eq. fwd_model / eq. d_fwd_model /
+// eq. frechet):
+//   k_march     ray march of A(f, mu): bilinear samples of the rotated maps,
+//               suffix sum of attenuation toward the detector, exp, ray sum,
+//               collimator blur across bins.  In linearising mode it also
+//               stores, per lattice sample, step*E_i and the suffix sum R'_i of
+//               lambda*E (half of its own term included), from which every
+//               Jacobian product of the outer iteration follows without exp.
+//   k_jvp_lin   J v from the stored weights: per ray
+//               sum_i step*E_i vf_i + kq * (T - R'_i) vmu_i,  T = sum_i lambda_i E_i.
+//   k_vjp_lin   J^T w as a gather: for every pixel and angle the (at most 3x3)
+//               lattice samples whose bilinear footprint covers the pixel.
+// Solver (Sec. 2.2, eqs. m-function, LMA-step; Sec. 3.1, eq. rho_agreement):
+//   element-wise CG kernels, trial / model-decrease kernel, decision kernel.
+//
+// Work mapping: one wavefront = RG consecutive bins (rays) of one angle x
+// SPL consecutive samples per ray; lanes of a ray form a DPP quad.  A
+// workgroup owns a block of angles and stages the whole zero-bordered map
+// pair (interleaved float2) in LDS when it fits; otherwise the maps are read
+// from a global bordered copy through the caches.  Reductions are FP64 and
+// deterministic: every block writes one partial, consumers sum the partials
+// in index order.
+#include "pget_internal.h"
+
+#include <math.h>
+
+namespace pget {
+
+// ------------------------------------------------------------------ helpers
+template <int CTRL>
+__device__ __forceinline__ float qperm(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// quad_perm encodings: lane i of each quad reads lane p_i
+constexpr int QP_SHIFT1 = 0 | (0 << 2) | (1 << 4) | (2 << 6);  // [0,0,1,2]
+constexpr int QP_SHIFT2 = 0 | (0 << 2) | (0 << 4) | (1 << 6);  // [0,0,0,1]
+constexpr int QP_BCAST3 = 3 | (3 << 2) | (3 << 4) | (3 << 6);  // [3,3,3,3]
+constexpr int QP_SWAP1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);   // [1,0,3,2]
+constexpr int QP_SWAP2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);   // [2,3,0,1]
+
+// inclusive prefix sum over the 4 lanes of a quad (lane order = sample order
+// from the detector side), and the quad total
+__device__ __forceinline__ void quad_scan(float x, int q, float& incl, float& total)
+{
+    float s = x;
+    float t = qperm<QP_SHIFT1>(s);
+    s += (q >= 1) ? t : 0.0f;
+    t = qperm<QP_SHIFT2>(s);
+    s += (q >= 2) ? t : 0.0f;
+    incl = s;
+    total = qperm<QP_BCAST3>(s);
+}
+
+__device__ __forceinline__ float quad_sum(float x)
+{
+    x += qperm<QP_SWAP1>(x);
+    x += qperm<QP_SWAP2>(x);
+    return x;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum of v over the block, returned to every thread (fixed order).
+__device__ double block_sum(double v, double* sh)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+    __syncthreads();
+    return s;
+}
+
+// Sum of n partials (one per producing block) in fixed order; every thread
+// of the block gets the result.
+__device__ double sum_partials(const double* p, int n, double* sh)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    return block_sum(v, sh);
+}
+
+__device__ __forceinline__ double* slot_ptr(double* part, int slice, int slot)
+{
+    return part + ((size_t)slice * N_SLOTS + slot) * SLOT_WIDTH;
+}
+__device__ __forceinline__ const double* slot_ptr(const double* part, int slice, int slot)
+{
+    return part + ((size_t)slice * N_SLOTS + slot) * SLOT_WIDTH;
+}
+
+// Bilinear sample of the zero-bordered interleaved map pair at (col, row)
+// in pixel-index coordinates.  Index clamping keeps FP32 rounding at the
+// support edge inside the bordered array.
+__device__ __forceinline__ float2 bilerp(const float2* __restrict__ img, int pitch, int n, float col,
+                                         float row)
+{
+    float cf = floorf(col), rf = floorf(row);
+    int c0 = min(max((int)cf, -1), n - 1);
+    int r0 = min(max((int)rf, -1), n - 1);
+    float fc = col - (float)c0, fr = row - (float)r0;
+    const float2* p = img + (r0 + 1) * pitch + (c0 + 1);
+    float2 v00 = p[0], v01 = p[1], v10 = p[pitch], v11 = p[pitch + 1];
+    float tx = fmaf(fc, v01.x - v00.x, v00.x);
+    float ty = fmaf(fc, v01.y - v00.y, v00.y);
+    float bx = fmaf(fc, v11.x - v10.x, v10.x);
+    float by = fmaf(fc, v11.y - v10.y, v10.y);
+    return make_float2(fmaf(fr, bx - tx, tx), fmaf(fr, by - ty, ty));
+}
+
+// ------------------------------------------------------------ map sources
+
+__device__ float resolve_beta(const PairSrc& s, const double* part, int slice, double* sh)
+{
+    if (s.kind != 1 || s.first) return 0.0f;
+    double cur = sum_partials(slot_ptr(part, slice, s.rr_slot_cur), s.n_rr, sh);
+    double prev = sum_partials(slot_ptr(part, slice, s.rr_slot_prev), s.n_rr, sh);
+    return prev > 0.0 ? (float)(cur / prev) : 0.0f;
+}
+
+__device__ __forceinline__ float2 src_value(const PairSrc& s, int slice, int idx, float beta)
+{
+    if (s.kind == 2) return make_float2(1.0f, 1.0f);
+    size_t o = (size_t)slice * s.stride + idx;
+    float2 v = make_float2(s.af[o], s.am[o]);
+    if (s.kind == 1) {
+        v.x = fmaf(beta, s.bf[o], v.x);
+        v.y = fmaf(beta, s.bm[o], v.y);
+    }
+    return v;
+}
+
+// Stage the zero-bordered pair image ((N+2)^2 float2) into `dst`.
+__device__ void stage_image(float2* dst, const PairSrc& s, int slice, int n, int pitch, float beta)
+{
+    const int total = pitch * pitch;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int rr = idx / pitch - 1, cc = idx - (idx / pitch) * pitch - 1;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (rr >= 0 && rr < n && cc >= 0 && cc < n) v = src_value(s, slice, rr * n + cc, beta);
+        dst[idx] = v;
+    }
+}
+
+// Global bordered copy for maps too large for LDS.
+__global__ void __launch_bounds__(256) k_pack(Geo g, PairSrc s, const double* part, float2* out,
+                                              long long out_stride, const LMState* st)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.y;
+    if (st && st[slice].done) return;
+    float beta = resolve_beta(s, part, slice, sh);
+    const int pitch = g.pitch, total = pitch * pitch;
+    float2* dst = out + (size_t)slice * out_stride;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+        int rr = idx / pitch - 1, cc = idx - (idx / pitch) * pitch - 1;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (rr >= 0 && rr < g.n && cc >= 0 && cc < g.n) v = src_value(s, slice, rr * g.n + cc, beta);
+        dst[idx] = v;
+    }
+}
+
+// ------------------------------------------------------ collimator epilogue
+// y[j] = sum_k taps[k] * x[j - k + K], zero outside [0, n_bins).
+__device__ __forceinline__ float psf_at(const float* x, const float* taps, int K, int nb, int j)
+{
+    float acc = 0.0f;
+    for (int k = -K; k <= K; ++k) {
+        int jj = j - k;
+        if (jj >= 0 && jj < nb) acc = fmaf(taps[k + K], x[jj], acc);
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------ march
+
+
+template <bool LDS_IMG, int MODE>
+__global__ void __launch_bounds__(1024) k_march(MarchArgs A)
+{
+    extern __shared__ float4 smem_raw[];
+    __shared__ double sh[16];
+    __shared__ float taps[MAX_TAPS];
+    const Geo& g = A.g;
+    const int slice = blockIdx.y;
+    if (A.st) {
+        if (A.st[slice].done) return;
+        if (MODE == MARCH_LIN && !A.st[slice].dirty) return;
+    }
+    float2* simg = reinterpret_cast<float2*>(smem_raw);
+    const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
+    float* rowp = reinterpret_cast<float*>(simg + img_elems);   // raw ray sums  [n_bins]
+    float* rowr = rowp + g.n_bins;                              // residual      [n_bins]
+    for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = A.t.taps[k];
+    if (LDS_IMG) stage_image(simg, A.src, slice, g.n, g.pitch, 0.0f);
+    const float2* img = LDS_IMG ? simg : A.gimg + (size_t)slice * A.gimg_stride;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int q = lane & (SPL - 1), jj = lane >> 2;
+    double acc_r2 = 0.0;
+    const float hs = 0.5f;
+    for (int ab = 0; ab < A.angles_per_block; ++ab) {
+        const int a = blockIdx.x * A.angles_per_block + ab;
+        if (a >= g.n_angles) break;
+        const float4 tr = A.t.trig[a];
+        for (int grp = wave; grp < g.n_groups; grp += nwaves) {
+            const int j = grp * RG + jj;
+            const bool ray_ok = j < g.n_bins;
+            int2 cl = make_int2(1, 0);
+            float2 rb = make_float2(0.0f, 0.0f);
+            if (ray_ok) {
+                cl = A.t.clip[(size_t)a * g.n_bins + j];
+                rb = A.t.rbase[(size_t)a * g.n_bins + j];
+            }
+            const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
+            float carry_mu = 0.0f, carry_le = 0.0f;
+            float2* wrow = nullptr;
+            if (MODE == MARCH_LIN) wrow = A.wts + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
+            for (int i0 = gr.y; i0 >= gr.x; i0 -= SPL) {
+                const int i = i0 - q;
+                const bool act = (i >= cl.x) && (i <= cl.y);
+                float lam = 0.0f, mu = 0.0f;
+                if (act) {
+                    const float ti = (float)i - g.t_off;
+                    const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
+                    const float2 v = bilerp(img, g.pitch, g.n, col, row);
+                    lam = v.x;
+                    mu = v.y;
+                }
+                float incl, tot;
+                quad_scan(mu, q, incl, tot);
+                // B_i / step = carry + (samples nearer the detector) + mu_i / 2
+                const float bsum = carry_mu + (incl - hs * mu);
+                carry_mu += tot;
+                const float E = __builtin_amdgcn_exp2f(-g.ln2_scale * bsum);
+                const float le = lam * E;
+                float lincl, ltot;
+                quad_scan(le, q, lincl, ltot);
+                if (MODE == MARCH_LIN && act) {
+                    const float rprime = carry_le + (lincl - hs * le);
+                    wrow[(size_t)i * g.n_bins + j] = make_float2(g.step * E, rprime);
+                }
+                carry_le += ltot;
+            }
+            if (ray_ok && q == 0) {
+                rowp[j] = g.step * carry_le;
+                if (MODE == MARCH_LIN)
+                    A.tsum[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + j] = carry_le;
+            }
+        }
+        __syncthreads();
+        // collimator blur and epilogue over the bins of this angle
+        const size_t srow = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
+        for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) {
+            const float y = psf_at(rowp, taps, g.K, g.n_bins, j);
+            if (A.yout) A.yout[srow + j] = y;
+            if (A.ymeas) {
+                const float r = y - A.ymeas[srow + j];
+                rowr[j] = r;
+                acc_r2 += (double)r * (double)r;
+            }
+        }
+        if (A.wout) {
+            __syncthreads();
+            for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x)
+                A.wout[srow + j] = psf_at(rowr, taps, g.K, g.n_bins, j);
+        }
+        __syncthreads();
+    }
+    if (A.part && A.ymeas) {
+        double s = block_sum(acc_r2, sh);
+        if (threadIdx.x == 0) slot_ptr(A.part, slice, A.slot)[blockIdx.x] = s;
+    }
+}
+
+// ----------------------------------------------------------- linear JVP
+
+
+template <bool LDS_IMG, int MODE>
+__global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
+{
+    extern __shared__ float4 smem_raw[];
+    __shared__ double sh[16];
+    __shared__ float taps[MAX_TAPS];
+    const Geo& g = A.g;
+    const int slice = blockIdx.y;
+    if (A.st && A.st[slice].done) return;
+    float2* simg = reinterpret_cast<float2*>(smem_raw);
+    const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
+    float* rowz = reinterpret_cast<float*>(simg + img_elems);
+    float* rowy = rowz + g.n_bins;
+    for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = A.t.taps[k];
+    if (LDS_IMG) {
+        const float beta = resolve_beta(A.src, A.part, slice, sh);
+        stage_image(simg, A.src, slice, g.n, g.pitch, beta);
+    }
+    const float2* img = LDS_IMG ? simg : A.gimg + (size_t)slice * A.gimg_stride;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int q = lane & (SPL - 1), jj = lane >> 2;
+    double acc2 = 0.0;
+    for (int ab = 0; ab < A.angles_per_block; ++ab) {
+        const int a = blockIdx.x * A.angles_per_block + ab;
+        if (a >= g.n_angles) break;
+        const float4 tr = A.t.trig[a];
+        const float2* wrow = A.wts + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
+        for (int grp = wave; grp < g.n_groups; grp += nwaves) {
+            const int j = grp * RG + jj;
+            const bool ray_ok = j < g.n_bins;
+            int2 cl = make_int2(1, 0);
+            float2 rb = make_float2(0.0f, 0.0f);
+            float T = 0.0f;
+            if (ray_ok) {
+                cl = A.t.clip[(size_t)a * g.n_bins + j];
+                rb = A.t.rbase[(size_t)a * g.n_bins + j];
+                T = A.tsum[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + j];
+            }
+            const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
+            float accf = 0.0f, accq = 0.0f;
+            for (int i0 = gr.y; i0 >= gr.x; i0 -= SPL) {
+                const int i = i0 - q;
+                if (i >= cl.x && i <= cl.y) {
+                    const float ti = (float)i - g.t_off;
+                    const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
+                    const float2 v = bilerp(img, g.pitch, g.n, col, row);
+                    const float2 w = wrow[(size_t)i * g.n_bins + j];
+                    accf = fmaf(w.x, v.x, accf);
+                    accq = fmaf(T - w.y, v.y, accq);
+                }
+            }
+            accf = quad_sum(accf);
+            accq = quad_sum(accq);
+            if (ray_ok && q == 0) rowz[j] = fmaf(g.kq, accq, accf);
+        }
+        __syncthreads();
+        const size_t srow = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
+        for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) {
+            const float y = psf_at(rowz, taps, g.K, g.n_bins, j);
+            if (MODE == JVP_PLAIN) A.out[srow + j] = y;
+            if (MODE == JVP_NORMAL) rowy[j] = y;
+            if (MODE == JVP_SQNORM) acc2 += (double)y * (double)y;
+        }
+        if (MODE == JVP_NORMAL) {
+            __syncthreads();
+            for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x)
+                A.out[srow + j] = psf_at(rowy, taps, g.K, g.n_bins, j);
+        }
+        __syncthreads();
+    }
+    if (MODE == JVP_SQNORM) {
+        double s = block_sum(acc2, sh);
+        if (threadIdx.x == 0) slot_ptr(A.part, slice, A.slot)[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------- blur of a sinogram
+__global__ void __launch_bounds__(256) k_psf(Geo g, const float* taps_g, const float* in, float* out)
+{
+    __shared__ float taps[MAX_TAPS];
+    extern __shared__ float row[];
+    const int a = blockIdx.x;
+    for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = taps_g[k];
+    for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) row[j] = in[(size_t)a * g.n_bins + j];
+    __syncthreads();
+    for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x)
+        out[(size_t)a * g.n_bins + j] = psf_at(row, taps, g.K, g.n_bins, j);
+}
+
+// ------------------------------------------------------- adjoint (gather)
+
+__global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
+{
+    __shared__ float2 lat[VFP * VFP];
+    __shared__ int2 rclip[VFP];
+    __shared__ float2 rcoef[VFP];   // (step-free weight of a: wt_j, T_j)
+    const Geo& g = A.g;
+    const int slice = blockIdx.y;
+    if (A.st) {
+        if (A.st[slice].done) return;
+        if (A.skip_if_clean && !A.st[slice].dirty) return;
+    }
+    const int ntile = A.tiles_x * A.tiles_x;
+    const int tile = blockIdx.x % ntile, grp = blockIdx.x / ntile;
+    const int tr0 = (tile / A.tiles_x) * VT, tc0 = (tile % A.tiles_x) * VT;
+    const int apg = (g.n_angles + A.groups - 1) / A.groups;
+    const int a_begin = grp * apg, a_end = min(g.n_angles, a_begin + apg);
+
+    // this thread's pixels: one row, 4 consecutive columns
+    const int prow = tr0 + (threadIdx.x >> 3);
+    const int pcol = tc0 + (threadIdx.x & 7) * 4;
+    const float px0 = (float)pcol - g.half, py = (float)prow - g.half;
+    float accf[4] = {0.f, 0.f, 0.f, 0.f}, accm[4] = {0.f, 0.f, 0.f, 0.f};
+    const float SQ2 = 1.41421356f;
+    const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
+    const float2* wbase = A.wts + (size_t)slice * A.wts_stride;
+
+    for (int a = a_begin; a < a_end; ++a) {
+        const float4 tr = A.t.trig[a];
+        const float cs = tr.z, sn = tr.w;
+        // lattice coordinates of the tile corners -> staged window
+        const float xa = (float)tc0 - g.half, xb = (float)(tc0 + VT - 1) - g.half;
+        const float ya = (float)tr0 - g.half, yb = (float)(tr0 + VT - 1) - g.half;
+        float umin = 1e30f, umax = -1e30f, vmin = 1e30f, vmax = -1e30f;
+#pragma unroll
+        for (int cnr = 0; cnr < 4; ++cnr) {
+            const float x = (cnr & 1) ? xb : xa, y = (cnr & 2) ? yb : ya;
+            const float u = fmaf(-x * sn + y * cs, inv_ds, g.s_off);
+            const float v = fmaf(x * cs + y * sn, inv_dt, g.t_off);
+            umin = fminf(umin, u); umax = fmaxf(umax, u);
+            vmin = fminf(vmin, v); vmax = fmaxf(vmax, v);
+        }
+        const int jlo = (int)floorf(umin - SQ2);     // = first candidate - 1 (margin)
+        const int ilo = (int)floorf(vmin - SQ2);
+        const size_t sbase = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
+        __syncthreads();   // previous angle's gather is done with lat / rclip
+        for (int k = threadIdx.x; k < VFP; k += blockDim.x) {
+            const int j = jlo + k;
+            int2 cl = make_int2(1, 0);
+            float2 rc = make_float2(0.0f, 0.0f);
+            if (j >= 0 && j < g.n_bins) {
+                cl = A.t.clip[(size_t)a * g.n_bins + j];
+                rc = make_float2(A.wt[sbase + j], A.tsum[sbase + j]);
+            }
+            rclip[k] = cl;
+            rcoef[k] = rc;
+        }
+        __syncthreads();
+        const float2* wrow = wbase + (size_t)a * g.n_t * g.n_bins;
+        for (int idx = threadIdx.x; idx < VFP * VFP; idx += blockDim.x) {
+            const int ii = idx / VFP, jj = idx - ii * VFP;
+            const int i = ilo + ii, j = jlo + jj;
+            const int2 cl = rclip[jj];
+            float2 val = make_float2(0.0f, 0.0f);
+            if (i >= cl.x && i <= cl.y) {
+                const float2 w = wrow[(size_t)i * g.n_bins + j];
+                const float2 rc = rcoef[jj];
+                val = make_float2(w.x * rc.x, g.kq * (rc.y - w.y) * rc.x);
+            }
+            lat[idx] = val;
+        }
+        __syncthreads();
+        // displacement (pixel -> lattice point) per unit lattice step
+        const float A1 = -g.bin_size * sn, A2 = g.step * cs;   // dx
+        const float A3 = g.bin_size * cs, A4 = g.step * sn;    // dy
+#pragma unroll
+        for (int pxi = 0; pxi < 4; ++pxi) {
+            const float x = px0 + (float)pxi;
+            const float u = fmaf(-x * sn + py * cs, inv_ds, g.s_off);
+            const float v = fmaf(x * cs + py * sn, inv_dt, g.t_off);
+            const float ju = floorf(u - SQ2) + 1.0f, iv = floorf(v - SQ2) + 1.0f;
+            const float du0 = ju - u, dv0 = iv - v;
+            const float dx0 = fmaf(du0, A1, dv0 * A2), dy0 = fmaf(du0, A3, dv0 * A4);
+            const int jb = min(max((int)ju - jlo, 0), VFP - 3);
+            const int ib = min(max((int)iv - ilo, 0), VFP - 3);
+            const float2* L = lat + ib * VFP + jb;
+            float sf = 0.0f, sm = 0.0f;
+#pragma unroll
+            for (int di = 0; di < 3; ++di) {
+#pragma unroll
+                for (int dj = 0; dj < 3; ++dj) {
+                    const float dx = dx0 + ((float)dj * A1 + (float)di * A2);
+                    const float dy = dy0 + ((float)dj * A3 + (float)di * A4);
+                    const float w = fmaxf(0.0f, 1.0f - fabsf(dx)) * fmaxf(0.0f, 1.0f - fabsf(dy));
+                    const float2 c = L[di * VFP + dj];
+                    sf = fmaf(w, c.x, sf);
+                    sm = fmaf(w, c.y, sm);
+                }
+            }
+            accf[pxi] += sf;
+            accm[pxi] += sm;
+        }
+    }
+    if (prow < g.n) {
+        float* out = A.gpart + (size_t)grp * A.gpart_group_stride + (size_t)slice * A.gpart_slice_stride;
+        const int n2 = g.n * g.n;
+#pragma unroll
+        for (int pxi = 0; pxi < 4; ++pxi) {
+            const int c = pcol + pxi;
+            if (c < g.n) {
+                out[prow * g.n + c] = accf[pxi];
+                out[n2 + prow * g.n + c] = accm[pxi];
+            }
+        }
+    }
+}
+
+// Sum of the angle-group partial images (fixed order) into gf / gmu.
+__global__ void __launch_bounds__(256) k_sum_groups(int n2, int groups, const float* gpart,
+                                                    long long group_stride, float* gf, float* gm)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n2) return;
+    float sf = 0.0f, sm = 0.0f;
+    for (int k = 0; k < groups; ++k) {
+        sf += gpart[(size_t)k * group_stride + idx];
+        sm += gpart[(size_t)k * group_stride + n2 + idx];
+    }
+    gf[idx] = sf;
+    gm[idx] = sm;
+}
+
+// ----------------------------------------------------------- LM kernels
+// Vectors of one slice are [2][N][N] (f block, then mu block).
+
+__device__ __forceinline__ void alphas_at(const LMParamsDev& p, int k, float& af, float& am)
+{
+    int e = min(k, p.alpha_decay_until);
+    double d = pow(p.alpha_decay, (double)e);
+    af = (float)(p.alpha_f / d);
+    am = (float)(p.alpha_mu / d);
+}
+
+// L x at pixel (r, c): sum over in-grid 4-neighbours of (x[m] - x[m'])
+__device__ __forceinline__ float lap(const float* x, int n, int r, int c)
+{
+    const int m = r * n + c;
+    const float v = x[m];
+    float acc = 0.0f;
+    if (c > 0) acc += v - x[m - 1];
+    if (c + 1 < n) acc += v - x[m + 1];
+    if (r > 0) acc += v - x[m - n];
+    if (r + 1 < n) acc += v - x[m + n];
+    return acc;
+}
+
+// squared forward differences at pixel (r, c) (right and down edges)
+__device__ __forceinline__ float grad2(const float* x, int n, int r, int c)
+{
+    const int m = r * n + c;
+    float acc = 0.0f;
+    if (c + 1 < n) { float d = x[m + 1] - x[m]; acc += d * d; }
+    if (r + 1 < n) { float d = x[m + n] - x[m]; acc += d * d; }
+    return acc;
+}
+
+// Start of an outer iteration: g = J^T (A(u) - y) + R u;  CG state x = 0,
+// r = -g, p = 0;  partials of ||g||^2 (= r.r) and alpha ||grad u||^2.
+__global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.y;
+    LMState& st = V.st[slice];
+    if (st.done) return;
+    const Geo& g = V.g;
+    const int n = g.n, n2 = n * n;
+    float af, am;
+    alphas_at(V.prm[slice], st.k, af, am);
+    const size_t vo = (size_t)slice * V.vstride;
+    const float* gp = V.gpart + (size_t)slice * V.gpart_slice_stride;
+    double rr = 0.0, reg = 0.0;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n2) {
+        const int r = m / n, c = m - r * n;
+        const float* uf = V.u + vo;
+        const float* um = uf + n2;
+        float gf = 0.0f, gm = 0.0f;
+        for (int k = 0; k < V.groups; ++k) {
+            gf += gp[(size_t)k * V.gpart_group_stride + m];
+            gm += gp[(size_t)k * V.gpart_group_stride + n2 + m];
+        }
+        gf = fmaf(af, lap(uf, n, r, c), gf);
+        gm = fmaf(am, lap(um, n, r, c), gm);
+        V.grad[vo + m] = gf;
+        V.grad[vo + n2 + m] = gm;
+        V.r[vo + m] = -gf;
+        V.r[vo + n2 + m] = -gm;
+        V.x[vo + m] = 0.0f;
+        V.x[vo + n2 + m] = 0.0f;
+        V.p[vo + m] = 0.0f;
+        V.p[vo + n2 + m] = 0.0f;
+        rr = (double)gf * gf + (double)gm * gm;
+        reg = (double)af * grad2(uf, n, r, c) + (double)am * grad2(um, n, r, c);
+    }
+    double s1 = block_sum(rr, sh);
+    double s2 = block_sum(reg, sh);
+    if (threadIdx.x == 0) {
+        slot_ptr(V.part, slice, SLOT_RR0)[blockIdx.x] = s1;
+        slot_ptr(V.part, slice, SLOT_PHI_REG_U)[blockIdx.x] = s2;
+    }
+}
+
+// CG step, first half: p = r + beta_cg p_old (beta_cg = rr_m / rr_{m-1}),
+// q = J^T J p + beta D p + R p, partials of gamma = p.q.
+__global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.y;
+    LMState& st = V.st[slice];
+    if (st.done) return;
+    const Geo& g = V.g;
+    const int n = g.n, n2 = n * n;
+    const int m_step = V.cg_step;
+    float bcg = 0.0f;
+    double rr_cur = sum_partials(slot_ptr(V.part, slice, rr_slot(m_step)), V.n_ew_blocks, sh);
+    if (m_step > 0) {
+        double rr_prev = sum_partials(slot_ptr(V.part, slice, rr_slot(m_step + 2)), V.n_ew_blocks, sh);
+        bcg = rr_prev > 0.0 ? (float)(rr_cur / rr_prev) : 0.0f;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && V.rep)
+            V.rep[slice].cg_rr[(size_t)st.k * V.prm[slice].n_cg + (m_step - 1)] = rr_cur;
+    } else if (blockIdx.x == 0 && threadIdx.x == 0 && V.rep) {
+        V.rep[slice].gnorm[st.k] = sqrt(rr_cur);   // r = -g at the first step
+    }
+    float af, am;
+    alphas_at(V.prm[slice], st.k, af, am);
+    const float bdf = (float)(st.beta * V.prm[slice].d_f), bdm = (float)(st.beta * V.prm[slice].d_mu);
+    const size_t vo = (size_t)slice * V.vstride;
+    const float* gp = V.gpart + (size_t)slice * V.gpart_slice_stride;
+    double gam = 0.0;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n2) {
+        const int r = m / n, c = m - r * n;
+        const float* rf = V.r + vo;
+        const float* rm = rf + n2;
+        const float* pf = V.p + vo;
+        const float* pm = pf + n2;
+        // p at the pixel and its 4 neighbours
+        auto P = [&](const float* rr_, const float* pp_, int mm) { return fmaf(bcg, pp_[mm], rr_[mm]); };
+        const float pfc = P(rf, pf, m), pmc = P(rm, pm, m);
+        float lf = 0.0f, lm = 0.0f;
+        if (c > 0) { lf += pfc - P(rf, pf, m - 1); lm += pmc - P(rm, pm, m - 1); }
+        if (c + 1 < n) { lf += pfc - P(rf, pf, m + 1); lm += pmc - P(rm, pm, m + 1); }
+        if (r > 0) { lf += pfc - P(rf, pf, m - n); lm += pmc - P(rm, pm, m - n); }
+        if (r + 1 < n) { lf += pfc - P(rf, pf, m + n); lm += pmc - P(rm, pm, m + n); }
+        float gf = 0.0f, gm = 0.0f;
+        for (int k = 0; k < V.groups; ++k) {
+            gf += gp[(size_t)k * V.gpart_group_stride + m];
+            gm += gp[(size_t)k * V.gpart_group_stride + n2 + m];
+        }
+        const float qf = fmaf(af, lf, fmaf(bdf, pfc, gf));
+        const float qm = fmaf(am, lm, fmaf(bdm, pmc, gm));
+        V.q[vo + m] = qf;
+        V.q[vo + n2 + m] = qm;
+        gam = (double)pfc * qf + (double)pmc * qm;
+    }
+    double s = block_sum(gam, sh);
+    if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_GAMMA)[blockIdx.x] = s;
+}
+
+// CG step, second half: alpha = rr_m / gamma; x += alpha p; r -= alpha q;
+// p_old <- p; partials of rr_{m+1}.
+__global__ void __launch_bounds__(EW_THREADS) k_cg_x(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.y;
+    LMState& st = V.st[slice];
+    if (st.done) return;
+    const Geo& g = V.g;
+    const int n2 = g.n * g.n;
+    const int m_step = V.cg_step;
+    double rr_cur = sum_partials(slot_ptr(V.part, slice, rr_slot(m_step)), V.n_ew_blocks, sh);
+    float bcg = 0.0f;
+    if (m_step > 0) {
+        double rr_prev = sum_partials(slot_ptr(V.part, slice, rr_slot(m_step + 2)), V.n_ew_blocks, sh);
+        bcg = rr_prev > 0.0 ? (float)(rr_cur / rr_prev) : 0.0f;
+    }
+    double gam = sum_partials(slot_ptr(V.part, slice, SLOT_GAMMA), V.n_ew_blocks, sh);
+    const float alpha = (gam > 0.0 && rr_cur > 0.0) ? (float)(rr_cur / gam) : 0.0f;
+    const size_t vo = (size_t)slice * V.vstride;
+    double rr = 0.0;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n2) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const size_t o = vo + (size_t)b * n2 + m;
+            const float p = fmaf(bcg, V.p[o], V.r[o]);
+            V.x[o] = fmaf(alpha, p, V.x[o]);
+            const float rn = fmaf(-alpha, V.q[o], V.r[o]);
+            V.r[o] = rn;
+            V.p[o] = p;
+            rr += (double)rn * rn;
+        }
+    }
+    double s = block_sum(rr, sh);
+    if (threadIdx.x == 0) slot_ptr(V.part, slice, rr_slot(m_step + 1))[blockIdx.x] = s;
+}
+
+// Trial point u' = clamp(u + x) (or the hook's proposal), s = u' - u, and
+// partials of g.s, s.R s, ||s||^2, ||u||^2, alpha ||grad u'||^2.
+__global__ void __launch_bounds__(EW_THREADS) k_trial(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.y;
+    LMState& st = V.st[slice];
+    if (st.done) return;
+    const LMParamsDev& P = V.prm[slice];
+    const Geo& g = V.g;
+    const int n = g.n, n2 = n * n;
+    if (!V.hook_mode && V.rep && blockIdx.x == 0) {
+        double rr = sum_partials(slot_ptr(V.part, slice, rr_slot(P.n_cg)), V.n_ew_blocks, sh);
+        if (threadIdx.x == 0) V.rep[slice].cg_rr[(size_t)st.k * P.n_cg + (P.n_cg - 1)] = rr;
+    }
+    float af, am;
+    alphas_at(P, st.k, af, am);
+    const size_t vo = (size_t)slice * V.vstride;
+    const float* uf = V.u + vo;
+    const float* um = uf + n2;
+    const float lo_f = (float)P.f_lo, hi_f = (float)P.f_hi, lo_m = (float)P.mu_lo, hi_m = (float)P.mu_hi;
+    auto TF = [&](int mm) {
+        return V.hook_mode ? V.ut[vo + mm] : fminf(fmaxf(uf[mm] + V.x[vo + mm], lo_f), hi_f);
+    };
+    auto TM = [&](int mm) {
+        return V.hook_mode ? V.ut[vo + n2 + mm] : fminf(fmaxf(um[mm] + V.x[vo + n2 + mm], lo_m), hi_m);
+    };
+    double gs = 0.0, srs = 0.0, ss = 0.0, uu = 0.0, regt = 0.0;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n2) {
+        const int r = m / n, c = m - r * n;
+        const float tf = TF(m), tm = TM(m);
+        const float sf = tf - uf[m], sm = tm - um[m];
+        float gsf = 0.0f, gsm = 0.0f, gtf = 0.0f, gtm = 0.0f;
+        if (c + 1 < n) {
+            const float tf1 = TF(m + 1), tm1 = TM(m + 1);
+            const float df = (tf1 - uf[m + 1]) - sf, dm = (tm1 - um[m + 1]) - sm;
+            gsf += df * df; gsm += dm * dm;
+            const float ef = tf1 - tf, em = tm1 - tm;
+            gtf += ef * ef; gtm += em * em;
+        }
+        if (r + 1 < n) {
+            const float tf1 = TF(m + n), tm1 = TM(m + n);
+            const float df = (tf1 - uf[m + n]) - sf, dm = (tm1 - um[m + n]) - sm;
+            gsf += df * df; gsm += dm * dm;
+            const float ef = tf1 - tf, em = tm1 - tm;
+            gtf += ef * ef; gtm += em * em;
+        }
+        if (!V.hook_mode) {
+            V.ut[vo + m] = tf;
+            V.ut[vo + n2 + m] = tm;
+        }
+        V.s[vo + m] = sf;
+        V.s[vo + n2 + m] = sm;
+        gs = (double)V.grad[vo + m] * sf + (double)V.grad[vo + n2 + m] * sm;
+        srs = (double)af * gsf + (double)am * gsm;
+        ss = (double)sf * sf + (double)sm * sm;
+        uu = (double)uf[m] * uf[m] + (double)um[m] * um[m];
+        regt = (double)af * gtf + (double)am * gtm;
+    }
+    double v;
+    v = block_sum(gs, sh);   if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_GS)[blockIdx.x] = v;
+    v = block_sum(srs, sh);  if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SRS)[blockIdx.x] = v;
+    v = block_sum(ss, sh);   if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SNORM)[blockIdx.x] = v;
+    v = block_sum(uu, sh);   if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_UNORM)[blockIdx.x] = v;
+    v = block_sum(regt, sh); if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_PHI_REG_T)[blockIdx.x] = v;
+}
+
+// Initial damping: beta0 = tau ||J 1||^2 / (2 N^2) unless given.
+__global__ void __launch_bounds__(256) k_beta0(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.x;
+    LMState& st = V.st[slice];
+    const LMParamsDev& P = V.prm[slice];
+    double j1 = sum_partials(slot_ptr(V.part, slice, SLOT_J1), V.n_jvp_blocks, sh);
+    if (threadIdx.x == 0 && P.beta0 <= 0.0) {
+        const double n2 = (double)V.g.n * V.g.n;
+        st.beta = P.tau * j1 / (2.0 * n2);
+        st.beta_init = st.beta;
+        if (!(st.beta > 0.0) || !isfinite(st.beta)) {
+            st.status = -4;
+            st.stop_reason = 3;
+            st.done = 1;
+        }
+    }
+}
+
+__global__ void k_lm_init(LMState* st, const LMParamsDev* prm, int n_slices)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slices) return;
+    LMState z = {};
+    z.beta = prm[s].beta0 > 0.0 ? prm[s].beta0 : 0.0;
+    z.beta_init = z.beta;
+    z.nu = 2.0;
+    z.dirty = 1;
+    z.final_slot = SLOT_PHI_DATA_U;
+    st[s] = z;
+}
+
+// Gain ratio test and damping update (one block per slice).
+__global__ void __launch_bounds__(256) k_decide(VecArgs V, int hook_present)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.x;
+    LMState& st = V.st[slice];
+    if (st.done) return;
+    const LMParamsDev& P = V.prm[slice];
+    const double phid_u = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_U), V.n_march_blocks, sh);
+    const double regu = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_U), V.n_ew_blocks, sh);
+    const double phid_t = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_T), V.n_march_blocks, sh);
+    const double regt = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_T), V.n_ew_blocks, sh);
+    const double gs = sum_partials(slot_ptr(V.part, slice, SLOT_GS), V.n_ew_blocks, sh);
+    const double srs = sum_partials(slot_ptr(V.part, slice, SLOT_SRS), V.n_ew_blocks, sh);
+    const double js = sum_partials(slot_ptr(V.part, slice, SLOT_JS), V.n_jvp_blocks, sh);
+    const double ss = sum_partials(slot_ptr(V.part, slice, SLOT_SNORM), V.n_ew_blocks, sh);
+    const double uu = sum_partials(slot_ptr(V.part, slice, SLOT_UNORM), V.n_ew_blocks, sh);
+    if (threadIdx.x != 0) return;
+    (void)hook_present;
+    const int k = st.k;
+    const double phi_u = 0.5 * phid_u + 0.5 * regu;
+    const double phi_t = 0.5 * phid_t + 0.5 * regt;
+    const double pred = -(gs + 0.5 * (js + srs));
+    const double ared = phi_u - phi_t;
+    const double rho = pred > 0.0 ? ared / pred : -INFINITY;
+    const int acc = P.has_replay ? (P.replay[k] != 0) : (rho > P.eta);
+    if (V.rep) {
+        ReportDev& R = V.rep[slice];
+        R.phi[k] = phi_u;
+        R.rho[k] = rho;
+        R.beta[k] = st.beta;
+        R.pred[k] = pred;
+        R.ared[k] = ared;
+        R.accepted[k] = (int8_t)acc;
+        R.hook_accepted[k] = 0;
+    }
+    st.phi_u = phi_u;
+    st.pred = pred;
+    st.ared = ared;
+    st.rho = rho;
+    st.hook_keep = 0;
+    st.k = k + 1;
+    if (!isfinite(phi_u)) {
+        st.status = -4;
+        st.stop_reason = 3;
+        st.accepted = 0;
+        st.done_next = 1;
+        return;
+    }
+    if (acc) {
+        const double t = 2.0 * rho - 1.0;
+        const double fct = 1.0 - t * t * t;
+        st.beta *= (fct > 1.0 / 3.0 ? fct : 1.0 / 3.0);
+        st.nu = 2.0;
+        st.final_slot = SLOT_PHI_DATA_T;
+    } else {
+        st.beta *= st.nu;
+        st.nu *= 2.0;
+        st.final_slot = SLOT_PHI_DATA_U;
+    }
+    st.accepted = acc;
+    st.dirty = acc;
+    if (acc && P.tol > 0.0 && (ared <= P.tol * phi_u || sqrt(ss) <= P.tol * sqrt(uu))) {
+        st.stop_reason = 1;
+        st.done_next = 1;
+    }
+    if (!(st.beta <= 1e16 * st.beta_init)) {
+        st.stop_reason = 2;
+        st.done_next = 1;
+    }
+}
+
+// Safeguard of a hook proposal u~ (Prop. 3.2, Alg. 2): keep it iff
+// rho(s~) > eta and m(s~) <= m(s), i.e. pred(s~) >= pred(s).
+__global__ void __launch_bounds__(256) k_hook_decide(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.x;
+    LMState& st = V.st[slice];
+    if (st.done || !st.accepted) return;
+    const LMParamsDev& P = V.prm[slice];
+    const double phid_h = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_H), V.n_march_blocks, sh);
+    const double regt = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_T), V.n_ew_blocks, sh);
+    const double gs = sum_partials(slot_ptr(V.part, slice, SLOT_GS), V.n_ew_blocks, sh);
+    const double srs = sum_partials(slot_ptr(V.part, slice, SLOT_SRS), V.n_ew_blocks, sh);
+    const double js = sum_partials(slot_ptr(V.part, slice, SLOT_JS), V.n_jvp_blocks, sh);
+    if (threadIdx.x != 0) return;
+    const double phi_h = 0.5 * phid_h + 0.5 * regt;
+    const double pred_h = -(gs + 0.5 * (js + srs));
+    const double rho_h = pred_h > 0.0 ? (st.phi_u - phi_h) / pred_h : -INFINITY;
+    if (rho_h > P.eta && pred_h >= st.pred) {
+        st.hook_keep = 1;
+        st.final_slot = SLOT_PHI_DATA_H;
+        if (V.rep) V.rep[slice].hook_accepted[st.k - 1] = 1;
+    }
+}
+
+// Accept: u <- u' (or the kept hook proposal, held in q) when the decision of
+// this iteration accepted.
+__global__ void __launch_bounds__(EW_THREADS) k_accept(VecArgs V)
+{
+    const int slice = blockIdx.y;
+    const LMState& st = V.st[slice];
+    if (st.done || !st.accepted) return;
+    const int n2 = V.g.n * V.g.n;
+    const size_t vo = (size_t)slice * V.vstride;
+    const float* src = st.hook_keep ? V.q : V.ut;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n2) {
+        V.u[vo + m] = src[vo + m];
+        V.u[vo + n2 + m] = src[vo + n2 + m];
+    }
+}
+
+// End of an outer iteration: apply a stop decided in k_decide.
+__global__ void k_commit(LMState* st, int n_slices)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slices) return;
+    if (st[s].done_next) st[s].done = 1;
+}
+
+// Final report: Phi of the returned maps with the alphas of iteration
+// iters_run; one block per slice, plus the scalar fields.
+__global__ void __launch_bounds__(EW_THREADS) k_final_reg(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.y;
+    const LMState& st = V.st[slice];
+    const Geo& g = V.g;
+    const int n = g.n, n2 = n * n;
+    float af, am;
+    alphas_at(V.prm[slice], st.k, af, am);
+    const size_t vo = (size_t)slice * V.vstride;
+    double reg = 0.0;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n2) {
+        const int r = m / n, c = m - r * n;
+        reg = (double)af * grad2(V.u + vo, n, r, c) + (double)am * grad2(V.u + vo + n2, n, r, c);
+    }
+    double s = block_sum(reg, sh);
+    if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_PHI_REG_U)[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_finish(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.x;
+    const LMState& st = V.st[slice];
+    // Phi_data of the final iterate: the trial's if the last step was
+    // accepted, else the linearisation point's.
+    const int slot = st.final_slot;
+    const double phid = sum_partials(slot_ptr(V.part, slice, slot), V.n_march_blocks, sh);
+    const double reg = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_U), V.n_ew_blocks, sh);
+    if (threadIdx.x != 0 || !V.rep) return;
+    ReportDev& R = V.rep[slice];
+    R.phi[st.k] = st.k == 0 ? NAN : 0.5 * phid + 0.5 * reg;
+    R.scalars[0] = (double)st.status;
+    R.scalars[1] = (double)st.k;
+    R.scalars[2] = st.beta;
+    R.scalars[3] = (double)st.stop_reason;
+}
+
+// ------------------------------------------------------------- launchers
+// (host-callable wrappers used by the runtime; grid shapes are set there)
+#define INST_MARCH(L, M) template __global__ void k_march<L, M>(MarchArgs);
+INST_MARCH(true, MARCH_FWD)
+INST_MARCH(true, MARCH_LIN)
+INST_MARCH(true, MARCH_TRIAL)
+INST_MARCH(false, MARCH_FWD)
+INST_MARCH(false, MARCH_LIN)
+INST_MARCH(false, MARCH_TRIAL)
+#define INST_JVP(L, M) template __global__ void k_jvp_lin<L, M>(JvpArgs);
+INST_JVP(true, JVP_PLAIN)
+INST_JVP(true, JVP_NORMAL)
+INST_JVP(true, JVP_SQNORM)
+INST_JVP(false, JVP_PLAIN)
+INST_JVP(false, JVP_NORMAL)
+INST_JVP(false, JVP_SQNORM)
+
+}  // namespace pget

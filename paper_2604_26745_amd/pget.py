@@ -1,0 +1,398 @@
+"""Thin ctypes binding of libpget (include/pget.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of ``libpget.so``.  torch tensors provide device memory and the
+current HIP stream.  If the library is not built, every call raises
+``RuntimeError`` -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpget.so")
+
+PGET_OK = 0
+STATUS_NAMES = {
+    0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "workspace missing or too small",
+    -4: "non-finite value in the solver", -5: "unsupported geometry",
+}
+OP_FORWARD, OP_JVP, OP_VJP, OP_LM = 0, 1, 2, 3
+
+
+class PgetError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__("%s failed: %s (%d)" % (where, STATUS_NAMES.get(status, "?"), status))
+        self.status = status
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+        ("psf_radius", ctypes.c_int32), ("angle0", ctypes.c_double), ("arc", ctypes.c_double),
+        ("bin_size", ctypes.c_double), ("step", ctypes.c_double), ("psf_sigma", ctypes.c_double),
+        ("atten_scale", ctypes.c_double),
+    ]
+
+
+class LMParams(ctypes.Structure):
+    _fields_ = [
+        ("max_outer", ctypes.c_int32), ("n_cg", ctypes.c_int32),
+        ("alpha_f", ctypes.c_double), ("alpha_mu", ctypes.c_double),
+        ("alpha_decay", ctypes.c_double), ("alpha_decay_until", ctypes.c_int32),
+        ("beta0", ctypes.c_double), ("tau", ctypes.c_double), ("eta", ctypes.c_double),
+        ("d_f", ctypes.c_double), ("d_mu", ctypes.c_double),
+        ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double),
+        ("mu_lo", ctypes.c_double), ("mu_hi", ctypes.c_double),
+        ("tol", ctypes.c_double), ("replay", ctypes.POINTER(ctypes.c_int8)),
+    ]
+
+
+class LMReportC(ctypes.Structure):
+    _fields_ = [
+        ("scalars", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("rho", ctypes.c_void_p),
+        ("beta", ctypes.c_void_p), ("pred", ctypes.c_void_p), ("ared", ctypes.c_void_p),
+        ("gnorm", ctypes.c_void_p), ("accepted", ctypes.c_void_p),
+        ("hook_accepted", ctypes.c_void_p), ("cg_rr", ctypes.c_void_p),
+    ]
+
+
+REFINE_FN = ctypes.CFUNCTYPE(
+    ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+)
+
+_lib = None
+
+
+def load_library():
+    """Load libpget.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            "libpget.so is not built (%s); run __graft_entry__.build() first" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V = ctypes.POINTER, ctypes.c_void_p
+    lib.pget_plan_create.argtypes = [P(Geometry), ctypes.c_int, P(V)]
+    lib.pget_plan_create.restype = ctypes.c_int
+    lib.pget_plan_destroy.argtypes = [V]
+    lib.pget_plan_destroy.restype = None
+    lib.pget_plan_n_samples.argtypes = [V]
+    lib.pget_plan_n_samples.restype = ctypes.c_int32
+    lib.pget_plan_psf_half_width.argtypes = [V]
+    lib.pget_plan_psf_half_width.restype = ctypes.c_int32
+    lib.pget_workspace_bytes.argtypes = [V, ctypes.c_int32, ctypes.c_int32]
+    lib.pget_workspace_bytes.restype = ctypes.c_size_t
+    lib.pget_forward.argtypes = [V, V, V, V, V, V]
+    lib.pget_forward.restype = ctypes.c_int
+    lib.pget_jvp.argtypes = [V, V, V, V, V, V, V, V, V]
+    lib.pget_jvp.restype = ctypes.c_int
+    lib.pget_vjp.argtypes = [V, V, V, V, V, V, V, V]
+    lib.pget_vjp.restype = ctypes.c_int
+    lib.pget_lm_solve.argtypes = [V, V, V, V, P(LMParams), REFINE_FN, V, P(LMReportC), V, V]
+    lib.pget_lm_solve.restype = ctypes.c_int
+    lib.pget_lm_solve_batched.argtypes = [V, ctypes.c_int32, P(V), P(V), P(V), P(LMParams),
+                                          P(LMReportC), V, V]
+    lib.pget_lm_solve_batched.restype = ctypes.c_int
+    lib.pget_status_string.argtypes = [ctypes.c_int]
+    lib.pget_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check(rc: int, where: str):
+    if rc != PGET_OK:
+        raise PgetError(rc, where)
+
+
+@dataclass
+class SolverParams:
+    """Mirror of pget_lm_params (defaults: the readings of the paper used here)."""
+
+    max_outer: int = 15
+    n_cg: int = 30
+    alpha_f: float = 1e-2
+    alpha_mu: float = 1e-2
+    alpha_decay: float = 1.0
+    alpha_decay_until: int = 0
+    beta0: float = 0.0
+    tau: float = 1e-3
+    eta: float = 1e-3
+    d_f: float = 1.0
+    d_mu: float = 1.0
+    f_lo: float = 0.0
+    f_hi: float = math.inf
+    mu_lo: float = 0.0
+    mu_hi: float = math.inf
+    tol: float = 0.0
+    replay: Optional[Sequence[int]] = None
+
+    def to_c(self):
+        p = LMParams()
+        for k, _ in LMParams._fields_:
+            if k == "replay":
+                continue
+            setattr(p, k, getattr(self, k))
+        keep = None
+        if self.replay is not None:
+            keep = (ctypes.c_int8 * len(self.replay))(*[int(v) for v in self.replay])
+            p.replay = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int8))
+        return p, keep
+
+
+@dataclass
+class LMReport:
+    status: int = 0
+    iters_run: int = 0
+    beta_final: float = 0.0
+    stop_reason: int = 0
+    phi: List[float] = field(default_factory=list)
+    rho: List[float] = field(default_factory=list)
+    beta: List[float] = field(default_factory=list)
+    pred: List[float] = field(default_factory=list)
+    ared: List[float] = field(default_factory=list)
+    gnorm: List[float] = field(default_factory=list)
+    accepted: List[int] = field(default_factory=list)
+    hook_accepted: List[int] = field(default_factory=list)
+    cg_rr: List[List[float]] = field(default_factory=list)
+
+
+class _ReportBuffers:
+    """Device buffers one report is written into."""
+
+    def __init__(self, max_outer: int, n_cg: int, device):
+        torch = _torch()
+        f64 = dict(dtype=torch.float64, device=device)
+        self.max_outer, self.n_cg = max_outer, n_cg
+        self.scalars = torch.zeros(4, **f64)
+        self.phi = torch.full((max_outer + 1,), math.nan, **f64)
+        self.rho = torch.zeros(max_outer, **f64)
+        self.beta = torch.zeros(max_outer, **f64)
+        self.pred = torch.zeros(max_outer, **f64)
+        self.ared = torch.zeros(max_outer, **f64)
+        self.gnorm = torch.zeros(max_outer, **f64)
+        self.accepted = torch.zeros(max_outer, dtype=torch.int8, device=device)
+        self.hook_accepted = torch.zeros(max_outer, dtype=torch.int8, device=device)
+        self.cg_rr = torch.zeros(max_outer * n_cg, **f64)
+
+    def c(self):
+        r = LMReportC()
+        for k, _ in LMReportC._fields_:
+            setattr(r, k, getattr(self, k).data_ptr())
+        return r
+
+    def to_report(self) -> LMReport:
+        sc = self.scalars.cpu().tolist()
+        k = int(sc[1])
+        return LMReport(
+            status=int(sc[0]), iters_run=k, beta_final=sc[2], stop_reason=int(sc[3]),
+            phi=self.phi.cpu().tolist()[: k + 1], rho=self.rho.cpu().tolist()[:k],
+            beta=self.beta.cpu().tolist()[:k], pred=self.pred.cpu().tolist()[:k],
+            ared=self.ared.cpu().tolist()[:k], gnorm=self.gnorm.cpu().tolist()[:k],
+            accepted=self.accepted.cpu().tolist()[:k],
+            hook_accepted=self.hook_accepted.cpu().tolist()[:k],
+            cg_rr=self.cg_rr.view(self.max_outer, self.n_cg).cpu().tolist()[:k],
+        )
+
+
+class Plan:
+    """A slice shape: geometry tables on the device plus cached workspaces."""
+
+    def __init__(self, n: int, n_angles: int, n_bins: int, angle0: float = 0.0,
+                 arc: float = 2.0 * math.pi, bin_size: float = 1.0, step: float = 1.0,
+                 psf_sigma: float = 1.5, psf_radius: int = -1, atten_scale: float = 1.0):
+        self.lib = load_library()
+        self.geom = Geometry(n, n_angles, n_bins, psf_radius, angle0, arc, bin_size, step,
+                             psf_sigma, atten_scale)
+        h = ctypes.c_void_p()
+        _check(self.lib.pget_plan_create(ctypes.byref(self.geom), 0, ctypes.byref(h)),
+               "pget_plan_create")
+        self.handle = h
+        self.n, self.n_angles, self.n_bins = n, n_angles, n_bins
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.pget_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def n_samples(self) -> int:
+        return int(self.lib.pget_plan_n_samples(self.handle))
+
+    @property
+    def psf_half_width(self) -> int:
+        return int(self.lib.pget_plan_psf_half_width(self.handle))
+
+    def workspace_bytes(self, op: int, batch: int = 1) -> int:
+        return int(self.lib.pget_workspace_bytes(self.handle, op, batch))
+
+    def workspace(self, op: int, batch: int = 1):
+        torch = _torch()
+        key = (op, batch)
+        if key not in self._ws:
+            nbytes = self.workspace_bytes(op, batch)
+            if nbytes == 0:
+                raise PgetError(-1, "pget_workspace_bytes")
+            self._ws[key] = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        return self._ws[key]
+
+    # -- operators ----------------------------------------------------------
+    def _img(self, t):
+        torch = _torch()
+        if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != (self.n, self.n):
+            raise ValueError("expected a float32 CUDA tensor of shape (%d, %d)" % (self.n, self.n))
+        return t.contiguous()
+
+    def _sino(self, t):
+        torch = _torch()
+        if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != (self.n_angles, self.n_bins):
+            raise ValueError("expected a float32 CUDA tensor of shape (%d, %d)"
+                             % (self.n_angles, self.n_bins))
+        return t.contiguous()
+
+    def forward(self, f, mu):
+        torch = _torch()
+        f, mu = self._img(f), self._img(mu)
+        y = torch.empty((self.n_angles, self.n_bins), dtype=torch.float32, device=f.device)
+        ws = self.workspace(OP_FORWARD)
+        _check(self.lib.pget_forward(self.handle, _ptr(f), _ptr(mu), _ptr(y), _ptr(ws), _stream()),
+               "pget_forward")
+        return y
+
+    def jvp(self, f, mu, vf, vmu, want_y: bool = False):
+        torch = _torch()
+        f, mu, vf, vmu = (self._img(t) for t in (f, mu, vf, vmu))
+        jv = torch.empty((self.n_angles, self.n_bins), dtype=torch.float32, device=f.device)
+        y = torch.empty_like(jv) if want_y else None
+        ws = self.workspace(OP_JVP)
+        _check(self.lib.pget_jvp(self.handle, _ptr(f), _ptr(mu), _ptr(vf), _ptr(vmu), _ptr(jv),
+                                 _ptr(y), _ptr(ws), _stream()), "pget_jvp")
+        return (jv, y) if want_y else jv
+
+    def vjp(self, f, mu, w):
+        torch = _torch()
+        f, mu, w = self._img(f), self._img(mu), self._sino(w)
+        gf = torch.empty_like(f)
+        gm = torch.empty_like(f)
+        ws = self.workspace(OP_VJP)
+        _check(self.lib.pget_vjp(self.handle, _ptr(f), _ptr(mu), _ptr(w), _ptr(gf), _ptr(gm),
+                                 _ptr(ws), _stream()), "pget_vjp")
+        return gf, gm
+
+    # -- solver -------------------------------------------------------------
+    def lm_solve(self, y, f0, mu0, params: SolverParams, hook=None, sync: bool = True):
+        """Reconstruct one slice.  ``hook(f, mu, s_f, s_mu) -> (f~, mu~)`` takes
+        and returns torch tensors (the learned refinement of Alg. 2)."""
+        torch = _torch()
+        y = self._sino(y)
+        f = self._img(f0).clone()
+        mu = self._img(mu0).clone()
+        prm, keep = params.to_c()
+        rb = _ReportBuffers(params.max_outer, params.n_cg, f.device)
+        rc_struct = rb.c()
+        ws = self.workspace(OP_LM, 1)
+        n = self.n
+        cb = REFINE_FN(0)
+        if hook is not None:
+            def _cb(user, pf, pm, psf, psm, pft, pmt, stream):
+                try:
+                    tens = [_wrap_device(p, (n, n)) for p in (pf, pm, psf, psm, pft, pmt)]
+                    ft, mt = hook(tens[0], tens[1], tens[2], tens[3])
+                    tens[4].copy_(ft)
+                    tens[5].copy_(mt)
+                    return 0
+                except Exception:
+                    return 1
+            cb = REFINE_FN(_cb)
+        _check(self.lib.pget_lm_solve(self.handle, _ptr(y), _ptr(f), _ptr(mu), ctypes.byref(prm),
+                                      cb, None, ctypes.byref(rc_struct), _ptr(ws), _stream()),
+               "pget_lm_solve")
+        del keep
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        return f, mu, rb
+
+    def lm_solve_batched(self, ys, f0s, mu0s, params: Sequence[SolverParams], sync: bool = True):
+        torch = _torch()
+        B = len(ys)
+        ys = [self._sino(t) for t in ys]
+        fs = [self._img(t).clone() for t in f0s]
+        ms = [self._img(t).clone() for t in mu0s]
+        arr = ctypes.c_void_p * B
+        cp = (LMParams * B)()
+        keeps = []
+        for i, p in enumerate(params):
+            c, k = p.to_c()
+            cp[i] = c
+            keeps.append(k)
+        rbs = [_ReportBuffers(params[0].max_outer, params[0].n_cg, fs[0].device) for _ in range(B)]
+        reps = (LMReportC * B)(*[r.c() for r in rbs])
+        ws = self.workspace(OP_LM, B)
+        _check(self.lib.pget_lm_solve_batched(
+            self.handle, B, arr(*[t.data_ptr() for t in ys]), arr(*[t.data_ptr() for t in fs]),
+            arr(*[t.data_ptr() for t in ms]), cp, reps, _ptr(ws), _stream()),
+            "pget_lm_solve_batched")
+        del keeps
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        return fs, ms, rbs
+
+
+def _wrap_device(ptr, shape):
+    """A torch view of device memory owned by the library (hook arguments)."""
+    torch = _torch()
+    n = 1
+    for s in shape:
+        n *= s
+
+    class _Holder:
+        pass
+
+    h = _Holder()
+    h.__cuda_array_interface__ = {
+        "shape": tuple(shape), "typestr": "<f4", "data": (int(ptr), False), "version": 2,
+        "strides": None,
+    }
+    return torch.as_tensor(h, device="cuda")
+
+
+# C-ABI names, for callers who prefer them
+def pget_forward(plan: Plan, f, mu):
+    return plan.forward(f, mu)
+
+
+def pget_jvp(plan: Plan, f, mu, vf, vmu, want_y: bool = False):
+    return plan.jvp(f, mu, vf, vmu, want_y)
+
+
+def pget_vjp(plan: Plan, f, mu, w):
+    return plan.vjp(f, mu, w)
+
+
+def pget_lm_solve(plan: Plan, y, f0, mu0, params: SolverParams, hook=None):
+    return plan.lm_solve(y, f0, mu0, params, hook)
+
+
+def pget_lm_solve_batched(plan: Plan, ys, f0s, mu0s, params):
+    return plan.lm_solve_batched(ys, f0s, mu0s, params)

@@ -1,0 +1,194 @@
+"""GPU parity of the device-resident Levenberg-Marquardt solver.
+
+The oracle runs the same iteration in FP64.  Accept decisions near rho = eta
+are knife-edge between FP32 and FP64, so the comparison replays the oracle's
+decisions on the GPU (``replay``); every other quantity is the GPU's own.
+Tolerances: objective per iteration 1e-4 relative, predicted/actual
+decrease 1e-3 relative (differences of nearby FP32 sums), final maps 1e-3
+relative L2.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import lm as OLM
+from paper_2604_26745_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2604_26745_amd import pget  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def T(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+def H(t):
+    return t.detach().cpu().double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+SMALL = inputs.SliceConfig("lattice3_n24", 24, 36, 36, n_rods=3, rod_radius=2.0, pitch=6.0,
+                           can_half=10.0, n_empty=1, max_outer=6, n_cg=8)
+
+
+def problem(cfg, seed=0):
+    og = O.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    f_true, mu_true = inputs.rod_lattice(cfg, seed)
+    y = inputs.poisson_counts(O.forward(og, f_true, mu_true), cfg.peak_counts, seed)
+    f0, mu0 = OLM.initial_guess(og, y)
+    return og, y, f0, mu0, f_true, mu_true
+
+
+def compare(rep, orep, f, mu, of, om, tol_phi=1e-4, tol_map=1e-3):
+    assert rep.iters_run == orep.iters_run
+    assert rep.accepted == orep.accepted
+    for k in range(rep.iters_run):
+        e = abs(rep.phi[k] - orep.phi[k]) / orep.phi[k]
+        log("k=%d phi %.8g / %.8g (%.1e) rho %.5g / %.5g beta %.4g / %.4g acc %d" % (
+            k, rep.phi[k], orep.phi[k], e, rep.rho[k], orep.rho[k], rep.beta[k], orep.beta[k],
+            rep.accepted[k]))
+        assert e <= tol_phi
+        assert abs(rep.beta[k] - orep.beta[k]) <= 1e-3 * orep.beta[k]
+        if np.isfinite(orep.pred[k]) and orep.pred[k] > 0:
+            assert abs(rep.pred[k] - orep.pred[k]) <= 1e-3 * abs(orep.pred[k])
+    assert abs(rep.phi[-1] - orep.phi[-1]) <= tol_phi * orep.phi[-1]
+    assert rel(H(f), of) <= tol_map
+    assert rel(H(mu), om) <= tol_map
+
+
+def test_lm_small_trajectory_with_replay():
+    og, y, f0, mu0, _, _ = problem(SMALL)
+    p = OLM.LMParams(max_outer=SMALL.max_outer, n_cg=SMALL.n_cg)
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(
+        max_outer=SMALL.max_outer, n_cg=SMALL.n_cg, replay=orep.accepted))
+    rep = rb.to_report()
+    assert rep.status == 0
+    compare(rep, orep, f, mu, of, om)
+    # CG residual trace of the first iteration
+    for m in range(SMALL.n_cg):
+        assert abs(rep.cg_rr[0][m] - orep.cg_rr[0][m]) <= 1e-3 * orep.cg_rr[0][0]
+    assert abs(rep.gnorm[0] - orep.gnorm[0]) <= 1e-5 * orep.gnorm[0]
+
+
+def test_lm_decisions_match_without_replay():
+    og, y, f0, mu0, _, _ = problem(SMALL, seed=1)
+    p = OLM.LMParams(max_outer=SMALL.max_outer, n_cg=SMALL.n_cg)
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0),
+                              pget.SolverParams(max_outer=SMALL.max_outer, n_cg=SMALL.n_cg))
+    rep = rb.to_report()
+    # decisions agree wherever rho is not within 1e-3 of eta
+    for k in range(rep.iters_run):
+        if abs(orep.rho[k] - p.eta) > 1e-3:
+            assert rep.accepted[k] == orep.accepted[k]
+
+
+def test_lm_64_workload_with_replay():
+    cfg = inputs.SMALL_64
+    og, y, f0, mu0, _, _ = problem(cfg)
+    p = OLM.LMParams(max_outer=3, n_cg=cfg.n_cg)
+    log("oracle LM 64x64, 3 outer x %d CG" % cfg.n_cg)
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p)
+    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(
+        max_outer=3, n_cg=cfg.n_cg, replay=orep.accepted))
+    compare(rb.to_report(), orep, f, mu, of, om)
+
+
+def test_batched_equals_alone():
+    cfgs = [SMALL, inputs.scaled(SMALL, n_empty=2)]
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    prm = pget.SolverParams(max_outer=4, n_cg=6)
+    ys, f0s, m0s = [], [], []
+    for i, c in enumerate(cfgs):
+        og, y, f0, mu0, _, _ = problem(c, seed=i)
+        ys.append(T(y)); f0s.append(T(f0)); m0s.append(T(mu0))
+    fs, ms, rbs = plan.lm_solve_batched(ys, f0s, m0s, [prm, prm])
+    for i in range(2):
+        fa, ma, ra = plan.lm_solve(ys[i], f0s[i], m0s[i], prm)
+        assert torch.equal(fa, fs[i]) and torch.equal(ma, ms[i])
+        assert ra.to_report().phi == rbs[i].to_report().phi
+
+
+def test_hook_identity_and_garbage():
+    og, y, f0, mu0, f_true, mu_true = problem(SMALL)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    prm = pget.SolverParams(max_outer=5, n_cg=6)
+    f1, m1, r1 = plan.lm_solve(T(y), T(f0), T(mu0), prm)
+    ident = lambda f, mu, sf, sm: (f + sf, mu + sm)
+    f2, m2, r2 = plan.lm_solve(T(y), T(f0), T(mu0), prm, hook=ident)
+    rep1, rep2 = r1.to_report(), r2.to_report()
+    assert rep2.hook_accepted == rep2.accepted
+    assert rel(H(f2), H(f1)) <= 1e-6
+    nan = lambda f, mu, sf, sm: (torch.full_like(f, float("nan")), mu)
+    f3, m3, r3 = plan.lm_solve(T(y), T(f0), T(mu0), prm, hook=nan)
+    assert sum(r3.to_report().hook_accepted) == 0
+    assert torch.equal(f3, f1) and torch.equal(m3, m1)
+
+
+def test_hook_decisions_match_oracle():
+    og, y, f0, mu0, f_true, mu_true = problem(SMALL)
+    p = OLM.LMParams(max_outer=6, n_cg=6)
+
+    def blend_np(f, mu, sf, sm):
+        return (f + sf + 0.5 * (f_true - (f + sf)), mu + sm + 0.5 * (mu_true - (mu + sm)))
+
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p, hook=blend_np)
+    ft, mt = T(f_true), T(mu_true)
+
+    def blend(f, mu, sf, sm):
+        return (f + sf + 0.5 * (ft - (f + sf)), mu + sm + 0.5 * (mt - (mu + sm)))
+
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(
+        max_outer=6, n_cg=6, replay=orep.accepted), hook=blend)
+    rep = rb.to_report()
+    assert rep.hook_accepted == orep.hook_accepted
+    assert sum(rep.hook_accepted) >= 1
+    assert rel(H(f), of) <= 1e-3
+
+
+def test_nonfinite_input_reported():
+    og, y, f0, mu0, _, _ = problem(SMALL)
+    y = y.copy()
+    y[3, 4] = np.nan
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(max_outer=3, n_cg=4))
+    rep = rb.to_report()
+    assert rep.status == -4 and rep.stop_reason == 3
+    assert torch.isfinite(f).all()
+
+
+def test_early_exit_tolerance():
+    og, y, f0, mu0, _, _ = problem(SMALL)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0),
+                              pget.SolverParams(max_outer=40, n_cg=8, tol=0.1))
+    rep = rb.to_report()
+    p = OLM.LMParams(max_outer=40, n_cg=8, tol=0.1)
+    _, _, orep = OLM.lm_solve(og, y, f0, mu0, p)
+    log("early exit: gpu %d iterations (%s), oracle %d (%s)" % (
+        rep.iters_run, rep.stop_reason, orep.iters_run, orep.stop_reason))
+    assert orep.stop_reason == "tol"
+    assert rep.stop_reason == 1 and rep.iters_run < 40
+    assert rep.iters_run == orep.iters_run
+    # the report of a stopped solve ends at the last iteration run
+    assert len(rep.phi) == rep.iters_run + 1 and np.isfinite(rep.phi[-1])

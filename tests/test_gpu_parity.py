@@ -1,0 +1,146 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (FP32 arithmetic on the GPU):
+  forward, J v, J^T w   relative L2 error <= 1e-5 (the target of the build),
+                        elementwise max |err| / max |ref| <= 1e-4.
+  LM                    with the oracle's accept decisions replayed, the
+                        per-iteration objective within 1e-4 relative and the
+                        final maps within 1e-3 relative L2 (CG in FP32
+                        amplifies rounding by the condition number).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import lm as OLM
+from paper_2604_26745_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2604_26745_amd import pget  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def T(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+def H(t):
+    return t.detach().cpu().double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# (n, n_angles, n_bins, sigma): tiny, ragged, the 64 and 128 workloads, a map
+# too large for LDS, and a slice whose detector is narrower than the map
+SHAPES = [
+    (16, 24, 24, 1.5),
+    (33, 37, 50, 1.5),
+    (17, 9, 13, 0.0),
+    (64, 120, 96, 1.5),
+    (128, 360, 192, 1.5),
+    (150, 60, 220, 1.5),
+    (96, 30, 80, 2.0),
+]
+
+
+def phantom(n, seed, nb=None):
+    cfg = inputs.SliceConfig("t", n, 8, nb or n, n_rods=5, rod_radius=max(1.0, n / 24),
+                             pitch=n / 7, can_half=0.42 * n, n_empty=2, rod_mu=None)
+    f, mu = inputs.rod_lattice(cfg, seed)
+    rng = np.random.default_rng(seed)
+    return f + 0.05 * rng.uniform(0, 1, f.shape), mu + 0.002 * rng.uniform(0, 1, mu.shape)
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda s: "n%d_a%d_b%d_s%g" % s)
+def case(request):
+    n, na, nb, sig = request.param
+    log("case n=%d angles=%d bins=%d sigma=%g" % (n, na, nb, sig))
+    og = O.Geometry(n, na, nb, psf_sigma=sig)
+    plan = pget.Plan(n, na, nb, psf_sigma=sig)
+    f, mu = phantom(n, n + na)
+    return og, plan, f, mu
+
+
+def test_forward(case):
+    og, plan, f, mu = case
+    y_ref = O.forward(og, f, mu)
+    y = H(plan.forward(T(f), T(mu)))
+    log("forward rel %.3e max %.3e" % (rel(y, y_ref), maxrel(y, y_ref)))
+    assert rel(y, y_ref) <= 1e-5
+    assert maxrel(y, y_ref) <= 1e-4
+
+
+def test_jvp(case):
+    og, plan, f, mu = case
+    rng = np.random.default_rng(1)
+    vf = rng.standard_normal(f.shape)
+    vm = 0.05 * rng.standard_normal(f.shape)
+    ref = O.jvp(og, f, mu, vf, vm)
+    jv, y = plan.jvp(T(f), T(mu), T(vf), T(vm), want_y=True)
+    log("jvp rel %.3e max %.3e" % (rel(H(jv), ref), maxrel(H(jv), ref)))
+    assert rel(H(jv), ref) <= 1e-5
+    assert maxrel(H(jv), ref) <= 1e-4
+    assert rel(H(y), O.forward(og, f, mu)) <= 1e-5
+
+
+def test_vjp(case):
+    og, plan, f, mu = case
+    rng = np.random.default_rng(2)
+    w = rng.standard_normal(og.sino_shape)
+    gf_ref, gm_ref = O.vjp(og, f, mu, w)
+    gf, gm = plan.vjp(T(f), T(mu), T(w))
+    log("vjp rel f %.3e mu %.3e" % (rel(H(gf), gf_ref), rel(H(gm), gm_ref)))
+    assert rel(H(gf), gf_ref) <= 1e-5
+    assert rel(H(gm), gm_ref) <= 1e-5
+    assert maxrel(H(gf), gf_ref) <= 1e-4
+    assert maxrel(H(gm), gm_ref) <= 1e-4
+
+
+def test_adjoint_identity_on_gpu(case):
+    og, plan, f, mu = case
+    rng = np.random.default_rng(3)
+    vf = rng.standard_normal(f.shape)
+    vm = rng.standard_normal(f.shape)
+    w = rng.standard_normal(og.sino_shape)
+    jv = H(plan.jvp(T(f), T(mu), T(vf), T(vm)))
+    gf, gm = plan.vjp(T(f), T(mu), T(w))
+    lhs = float(np.sum(jv * w))
+    rhs = float(np.sum(vf * H(gf)) + np.sum(vm * H(gm)))
+    scale = float(np.linalg.norm(jv) * np.linalg.norm(w))
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_repeat_is_bitwise_deterministic(case):
+    og, plan, f, mu = case
+    w = np.random.default_rng(4).standard_normal(og.sino_shape)
+    a = plan.vjp(T(f), T(mu), T(w))
+    b = plan.vjp(T(f), T(mu), T(w))
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert torch.equal(plan.forward(T(f), T(mu)), plan.forward(T(f), T(mu)))
+
+
+def test_invalid_arguments_rejected():
+    with pytest.raises(pget.PgetError):
+        pget.Plan(1, 10, 10)
+    with pytest.raises(pget.PgetError):
+        pget.Plan(16, 10, 10, bin_size=0.5)
+    plan = pget.Plan(16, 10, 10)
+    assert plan.workspace_bytes(pget.OP_FORWARD, 2) == 0
