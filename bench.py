@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Throughput of Levenberg-Marquardt reconstructions on one MI355X.
+
+One step = one full reconstruction (15 outer LM iterations x 30 CG steps,
+FP32, no early exit) of every slice of a batch of independent 128 x 128
+slices, 360 angles over a full turn x 192 detector bins, Gaussian collimator
+sigma 1.5 bins, gradient penalty alpha = 1e-2.  Inputs are seeded synthetic
+9 x 9 rod-lattice phantoms with Poisson counting noise (peak 1e4), resident
+in HBM before the timed region starts.  Prints ONE JSON line.
+
+Measured alongside: each kernel class's device time from HIP events on the
+launch stream (the dominant class gives the roofline entry), and the FP64
+CPU oracle timed on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# FP32 work per in-support lattice sample of one operator pass (algorithmic
+# count, see the measurement section of the design notes): the adjoint
+# spreads two coefficients to the four bilinear neighbours (28 FLOP), the
+# linearised Jacobian product gathers two fields from four neighbours and
+# weights them (26 FLOP), the ray march adds the attenuation sums and one exp
+# (30 FLOP).
+FLOP_PER_SAMPLE = {"vjp": 28.0, "gradient": 28.0, "jvp": 26.0, "march": 30.0}
+PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 vector peak (FMA = 2 FLOP)
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=64, help="slices reconstructed per step")
+    ap.add_argument("--outer", type=int, default=15)
+    ap.add_argument("--cg", type=int, default=30)
+    ap.add_argument("--no-single", action="store_true", help="skip the single-slice latency run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="0: min(16, cpu count)")
+    return ap.parse_args()
+
+
+def make_inputs(plan, cfg, batch, torch, inputs, np):
+    """Phantoms (inputs module), clean data from the library's forward map,
+    Poisson noise, and the closed-form initial guess mu0 = 0, f0 = c0."""
+    ys, f0s, m0s = [], [], []
+    one = torch.ones((cfg.n, cfg.n), dtype=torch.float32, device="cuda")
+    zero = torch.zeros_like(one)
+    a1 = plan.forward(one, zero).double().cpu().numpy()
+    for s in range(batch):
+        f, mu = inputs.rod_lattice(cfg, s)
+        T = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+        y_clean = plan.forward(T(f), T(mu)).double().cpu().numpy()
+        y = inputs.poisson_counts(y_clean, cfg.peak_counts, s)
+        c0 = float((a1 * y).sum() / (a1 * a1).sum())
+        ys.append(T(y))
+        f0s.append(torch.full((cfg.n, cfg.n), c0, dtype=torch.float32, device="cuda"))
+        m0s.append(zero.clone())
+    return ys, f0s, m0s
+
+
+def cpu_baseline(cfg, workers: int):
+    """The FP64 oracle on host cores, on a bounded sample: each worker times
+    one forward, one Jacobian product and one adjoint at full size on its own
+    slice; a reconstruction is 15 x (2 forward + 1 JVP + 31 adjoint + 30 JVP)
+    + 1 JVP passes, so recon/s = workers / (that many seconds)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_sample, [(cfg, s) for s in range(workers)])
+        wall = time.perf_counter() - t0
+    t_fwd = sum(r[0] for r in res) / len(res)
+    t_jvp = sum(r[1] for r in res) / len(res)
+    t_vjp = sum(r[2] for r in res) / len(res)
+    K, M = cfg.max_outer, cfg.n_cg
+    per_recon = K * (2 * t_fwd + (M + 1) * t_jvp + (M + 1) * t_vjp) + t_jvp
+    return {
+        "value": workers / per_recon, "unit": "reconstructions/s", "cores": workers,
+        "kind": "oracle",
+        "sample": ("FP64 C oracle, one forward + one J v + one J^T w per worker at %dx%d, %d angles, "
+                   "%d bins (%.1f s wall on %d workers), scaled to %d x (%d CG) passes per "
+                   "reconstruction: %.1f s per reconstruction per core"
+                   % (cfg.n, cfg.n, cfg.n_angles, cfg.n_bins, wall, workers, K, M, per_recon)),
+    }
+
+
+def _oracle_sample(arg):
+    cfg, seed = arg
+    import numpy as np
+    import oracle
+    from paper_2604_26745_amd import inputs
+    g = oracle.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    f, mu = inputs.rod_lattice(cfg, seed)
+    rng = np.random.default_rng(seed)
+    t0 = time.perf_counter()
+    y = oracle.forward(g, f, mu)
+    t1 = time.perf_counter()
+    oracle.jvp(g, f, mu, f, mu)
+    t2 = time.perf_counter()
+    oracle.vjp(g, f, mu, y + rng.standard_normal(y.shape))
+    t3 = time.perf_counter()
+    return t1 - t0, t2 - t1, t3 - t2
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("pget_kernels.hip", "pget_internal.h"):
+        with open(os.path.join(ROOT, "paper_2604_26745_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str, workload: str):
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+        ent = data.get(workload, {}).get(kernel)
+        if not ent or ent.get("kernel_source") != kernel_source_hash():
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(independent slices would shard across GPUs with no communication)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2604_26745_amd import inputs, pget
+
+    if not os.path.exists(pget.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = inputs.scaled(inputs.MAIN_128, max_outer=args.outer, n_cg=args.cg)
+    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    B = args.batch
+    ys, f0s, m0s = make_inputs(plan, cfg, B, torch, inputs, np)
+    prm = [pget.SolverParams(max_outer=cfg.max_outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha,
+                             alpha_mu=cfg.alpha) for _ in range(B)]
+    print("bench: %d slices of %s, %d outer x %d CG, warmup %d, steps %d"
+          % (B, cfg.name, cfg.max_outer, cfg.n_cg, args.warmup, args.steps), file=sys.stderr,
+          flush=True)
+    for w in range(args.warmup):
+        plan.lm_solve_batched(ys, f0s, m0s, prm)
+        print("bench: warmup %d done" % (w + 1), file=sys.stderr, flush=True)
+
+    # timed region: K steps, events on every launch of the heavy classes
+    classes = (1 << pget.KC_VJP) | (1 << pget.KC_JVP) | (1 << pget.KC_MARCH) | \
+              (1 << pget.KC_VECTOR) | (1 << pget.KC_GRADIENT)
+    per_step = cfg.max_outer * (3 * cfg.n_cg + 12) + 8
+    pget.timing_enable(classes, per_step * args.steps + 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reports = None
+    for s in range(args.steps):
+        fs, ms, reports = plan.lm_solve_batched(ys, f0s, m0s, prm, sync=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+    kt = {pget.KERNEL_CLASS_NAMES[c]: pget.timing_read(c) for c in
+          (pget.KC_VJP, pget.KC_JVP, pget.KC_MARCH, pget.KC_VECTOR, pget.KC_GRADIENT)}
+    pget.timing_enable(0, 0)
+    reps = [r.to_report() for r in reports]
+    assert all(r.status == 0 for r in reps), "solver reported a failure"
+    print("bench: timed %.3f s; kernel ms (total, launches): %s" % (
+        elapsed, {k: (round(v[0], 2), v[1]) for k, v in kt.items()}), file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel class
+    dom = max(kt, key=lambda k: kt[k][0])
+    tot_ms, launches = kt[dom]
+    avg_s = tot_ms / 1e3 / max(launches, 1)
+    units = plan.support_samples * B
+    achieved = FLOP_PER_SAMPLE[dom] * units / avg_s / 1e12
+    workload = "%s_batch%d" % (cfg.name, B)
+    kernel_name = {"vjp": "k_vjp_lin", "gradient": "k_vjp_lin", "jvp": "k_jvp_lin",
+                   "march": "k_march"}.get(dom, dom)
+    roofline = {
+        "bound": "alu", "kernel": kernel_name, "achieved": round(achieved, 3),
+        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+        "traffic": traffic_from_profile(kernel_name, workload),
+        "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+        "flop_per_unit": FLOP_PER_SAMPLE[dom], "units_per_launch": units,
+    }
+    kernel_share = {k: round(v[0] / (1e3 * elapsed), 4) for k, v in kt.items()}
+
+    single = None
+    if not args.no_single:
+        ps = prm[:1]
+        plan.lm_solve(ys[0], f0s[0], m0s[0], ps[0])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        plan.lm_solve(ys[0], f0s[0], m0s[0], ps[0])
+        torch.cuda.synchronize()
+        single = {"latency_ms": round(1e3 * (time.perf_counter() - t2), 2)}
+        single["recon_per_s"] = round(1e3 / single["latency_ms"], 3)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        print("bench: CPU oracle sample on %d workers" % workers, file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg, workers)
+
+    out = {
+        "metric": "LM reconstructions/s at 128^2 x 360 angles (FP32)",
+        "value": round(value, 4),
+        "unit": "reconstructions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": workload,
+            "slices_per_step": B,
+            "grid": cfg.n, "angles": cfg.n_angles, "bins": cfg.n_bins, "psf_sigma": cfg.psf_sigma,
+            "outer": cfg.max_outer, "cg": cfg.n_cg, "alpha": cfg.alpha,
+            "phantom": "9x9 rod lattice, r=4 px, pitch 12 px, 5 empty rods, Poisson peak 1e4",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_time_share": kernel_share,
+        "single_slice": single,
+        "final_phi_mean": float(np.mean([r.phi[-1] for r in reps])),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

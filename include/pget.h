@@ -62,14 +62,14 @@ typedef enum { PGET_FP32 = 0 } pget_storage;
  * atten_scale is the constant correction c of eq. d_fwd_model.
  */
 typedef struct {
-    int32_t n;          /* N, 2 <= N <= 1024                                 */
-    int32_t n_angles;   /* >= 1                                              */
+    int32_t n;          /* N, 2 <= N <= 512                                  */
+    int32_t n_angles;   /* 1 .. 1024                                         */
     int32_t n_bins;     /* >= 1                                              */
     int32_t psf_radius; /* taps per side; < 0 -> ceil(3*psf_sigma); <= 32   */
     double angle0;      /* radians                                           */
     double arc;         /* radians, e.g. 2*pi for a full turn                */
-    double bin_size;    /* > 0, pixels                                       */
-    double step;        /* > 0, pixels                                       */
+    double bin_size;    /* >= 1, pixels (at most 3x3 gather candidates)     */
+    double step;        /* >= 1, pixels                                      */
     double psf_sigma;   /* >= 0, bins; 0 = no blur                           */
     double atten_scale; /* > 0                                               */
 } pget_geometry;
@@ -88,9 +88,12 @@ enum { PGET_OP_FORWARD = 0, PGET_OP_JVP = 1, PGET_OP_VJP = 2, PGET_OP_LM = 3 };
 pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pget_plan** out);
 void pget_plan_destroy(pget_plan* plan);
 
-/* Derived sizes: samples per ray n_t, and the collimator half width. */
+/* Derived sizes: samples per ray n_t, the collimator half width, and the
+ * number of lattice samples (angle, bin, sample) whose bilinear footprint
+ * meets the map -- the work unit of one operator pass. */
 int32_t pget_plan_n_samples(const pget_plan* plan);
 int32_t pget_plan_psf_half_width(const pget_plan* plan);
+int64_t pget_plan_support_samples(const pget_plan* plan);
 
 /*
  * Device workspace needed by `op` for `batch` slices of this plan's shape
@@ -221,6 +224,27 @@ pget_status pget_lm_solve_batched(const pget_plan* plan, int32_t n_slices, const
                                   float* const* f_inout, float* const* mu_inout,
                                   const pget_lm_params* params, const pget_lm_report* reports,
                                   void* ws, hipStream_t stream);
+
+/*
+ * Kernel timing for measurement tools.  pget_timing_enable(classes, capacity)
+ * brackets every later launch of the kernel classes in the bit mask `classes`
+ * (1 << PGET_KC_*) with HIP events on the launch's own stream, up to
+ * `capacity` launches in total (0 disables and frees the events).
+ * pget_timing_read waits for the recorded events of one class and returns the
+ * summed device time in milliseconds and the number of launches.  Not
+ * thread-safe; meant for benchmarks and profilers.
+ */
+enum {
+    PGET_KC_MARCH = 0,   /* ray march: forward / linearisation / trial point */
+    PGET_KC_JVP = 1,     /* Jacobian product from the stored weights          */
+    PGET_KC_VJP = 2,     /* adjoint gather (CG solve, pget_vjp)               */
+    PGET_KC_VECTOR = 3,  /* element-wise CG / step kernels                    */
+    PGET_KC_CONTROL = 4, /* per-slice decisions, packing, blur                */
+    PGET_KC_GRADIENT = 5 /* adjoint gather of the gradient (skipped when the
+                            iterate did not change)                           */
+};
+pget_status pget_timing_enable(int32_t classes, int32_t capacity);
+pget_status pget_timing_read(int32_t kernel_class, double* total_ms, int64_t* launches);
 
 /* Human-readable name of a status code (static string). */
 const char* pget_status_string(pget_status status);

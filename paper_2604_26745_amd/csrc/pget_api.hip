@@ -24,6 +24,7 @@ struct pget_plan {
     int op_threads;      // threads per block of k_march / k_jvp_lin
     int tiles_x;         // VJP tiles per edge
     int device;
+    int64_t support;     // lattice samples inside the support
 };
 
 namespace {
@@ -137,11 +138,43 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
 
 inline char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
+// ---- optional launch timing (pget_timing_enable)
+struct TimingRec {
+    int cls;
+    hipEvent_t start, stop;
+};
+struct Timing {
+    int classes = 0;
+    int capacity = 0;
+    std::vector<hipEvent_t> pool;   // 2 * capacity events
+    std::vector<TimingRec> recs;
+} g_timing;
+
+// RAII bracket around one kernel launch of class `cls` on stream `s`.
+struct Timed {
+    TimingRec* rec = nullptr;
+    hipStream_t s;
+    Timed(int cls, hipStream_t stream) : s(stream)
+    {
+        if (!(g_timing.classes & (1 << cls))) return;
+        if ((int)g_timing.recs.size() >= g_timing.capacity) return;
+        const size_t k = g_timing.recs.size();
+        g_timing.recs.push_back(TimingRec{cls, g_timing.pool[2 * k], g_timing.pool[2 * k + 1]});
+        rec = &g_timing.recs.back();
+        (void)hipEventRecord(rec->start, s);
+    }
+    ~Timed()
+    {
+        if (rec) (void)hipEventRecord(rec->stop, s);
+    }
+};
+
 Tables tables_of(const pget_plan* P) { return P->t; }
 
 template <bool LDS, int M>
 void launch_march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStream_t s)
 {
+    Timed t(PGET_KC_MARCH, s);
     hipLaunchKernelGGL((k_march<LDS, M>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes, s, A);
 }
 template <int M>
@@ -153,6 +186,7 @@ void march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStr
 template <bool LDS, int M>
 void launch_jvp(const pget_plan* P, const JvpArgs& A, int blocks, int batch, hipStream_t s)
 {
+    Timed t(PGET_KC_JVP, s);
     hipLaunchKernelGGL((k_jvp_lin<LDS, M>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes, s, A);
 }
 template <int M>
@@ -167,6 +201,7 @@ void pack(const pget_plan* P, const PairSrc& src, const double* part, float2* ou
 {
     const int total = P->g.pitch * P->g.pitch;
     const int blocks = std::min(1024, (total + 255) / 256);
+    Timed t(PGET_KC_CONTROL, s);
     hipLaunchKernelGGL(k_pack, dim3(blocks, batch), dim3(256), 0, s, P->g, src, part, out,
                        (long long)total, st);
 }
@@ -252,6 +287,7 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
             }
             if (hi < lo) { lo = 1; hi = 0; }
             clip[(size_t)a * nb + j] = make_int2(lo, hi);
+            if (hi >= lo) P->support += hi - lo + 1;
             if (hi >= lo) {
                 int2& gr = grange[(size_t)a * ng + j / RG];
                 if (gr.y < gr.x) gr = make_int2(lo, hi);
@@ -339,6 +375,7 @@ void pget_plan_destroy(pget_plan* plan)
 
 int32_t pget_plan_n_samples(const pget_plan* plan) { return plan ? plan->g.n_t : -1; }
 int32_t pget_plan_psf_half_width(const pget_plan* plan) { return plan ? plan->g.K : -1; }
+int64_t pget_plan_support_samples(const pget_plan* plan) { return plan ? plan->support : -1; }
 
 size_t pget_workspace_bytes(const pget_plan* plan, int32_t op, int32_t batch)
 {
@@ -428,8 +465,11 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     Layout L = layout_for(P, PGET_OP_VJP, 1, sh, 256, 256);
     linearise(P, f, mu, nullptr, ws, L, sh, stream);
     float* wt = reinterpret_cast<float*>(at(ws, L.sino_a));
-    hipLaunchKernelGGL(k_psf, dim3(P->g.n_angles), dim3(256), P->g.n_bins * sizeof(float), stream, P->g,
-                       P->t.taps, w, wt);
+    {
+        Timed t_(PGET_KC_CONTROL, stream);
+        hipLaunchKernelGGL(k_psf, dim3(P->g.n_angles), dim3(256), P->g.n_bins * sizeof(float), stream, P->g,
+                           P->t.taps, w, wt);
+    }
     VjpArgs V = {};
     V.g = P->g;
     V.t = P->t;
@@ -444,9 +484,15 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     V.gpart_slice_stride = 0;
     V.tiles_x = P->tiles_x;
     V.groups = sh.groups;
-    hipLaunchKernelGGL(k_vjp_lin, dim3(sh.n_vjp_blocks, 1), dim3(VJP_THREADS), 0, stream, V);
-    hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, (int)n2,
-                       sh.groups, V.gpart, (long long)V.gpart_group_stride, gf, gmu);
+    {
+        Timed t_(PGET_KC_VJP, stream);
+        hipLaunchKernelGGL(k_vjp_lin, dim3(sh.n_vjp_blocks, 1), dim3(VJP_THREADS), 0, stream, V);
+    }
+    {
+        Timed t_(PGET_KC_VECTOR, stream);
+        hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, (int)n2,
+                           sh.groups, V.gpart, (long long)V.gpart_group_stride, gf, gmu);
+    }
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
 }
 
@@ -658,37 +704,67 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
     enqueue_march(S, S.lin, MARCH_LIN);
     if (k == 0 && need_beta0) {
         enqueue_jvp(S, S.jones, JVP_SQNORM);
-        hipLaunchKernelGGL(k_beta0, dim3(S.B), dim3(256), 0, S.stream, S.V);
+        {
+            Timed t_(PGET_KC_CONTROL, S.stream);
+            hipLaunchKernelGGL(k_beta0, dim3(S.B), dim3(256), 0, S.stream, S.V);
+        }
     }
-    hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vgrad);
+    {
+        Timed t_(PGET_KC_GRADIENT, S.stream);
+        hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vgrad);
+    }
     VecArgs Vg = S.V;
     Vg.gpart = S.vgrad.gpart;
-    hipLaunchKernelGGL(k_grad_init, ew, dim3(EW_THREADS), 0, S.stream, Vg);
+    {
+        Timed t_(PGET_KC_VECTOR, S.stream);
+        hipLaunchKernelGGL(k_grad_init, ew, dim3(EW_THREADS), 0, S.stream, Vg);
+    }
     for (int m = 0; m < n_cg; ++m) {
         JvpArgs J = S.jcg;
         J.src.rr_slot_cur = rr_slot(m);
         J.src.rr_slot_prev = rr_slot(m + 2);
         J.src.first = (m == 0);
         enqueue_jvp(S, J, JVP_NORMAL);
-        hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vcg);
+        {
+            Timed t_(PGET_KC_VJP, S.stream);
+            hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vcg);
+        }
         VecArgs V = S.V;
         V.cg_step = m;
-        hipLaunchKernelGGL(k_cg_q, ew, dim3(EW_THREADS), 0, S.stream, V);
-        hipLaunchKernelGGL(k_cg_x, ew, dim3(EW_THREADS), 0, S.stream, V);
+        {
+            Timed t_(PGET_KC_VECTOR, S.stream);
+            hipLaunchKernelGGL(k_cg_q, ew, dim3(EW_THREADS), 0, S.stream, V);
+        }
+        {
+            Timed t_(PGET_KC_VECTOR, S.stream);
+            hipLaunchKernelGGL(k_cg_x, ew, dim3(EW_THREADS), 0, S.stream, V);
+        }
     }
     VecArgs Vt = S.V;
     Vt.cg_step = n_cg;
-    hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vt);
+    {
+        Timed t_(PGET_KC_VECTOR, S.stream);
+        hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vt);
+    }
     enqueue_jvp(S, S.jpred, JVP_SQNORM);
     enqueue_march(S, S.trial, MARCH_TRIAL);
-    hipLaunchKernelGGL(k_decide, dim3(S.B), dim3(256), 0, S.stream, S.V, hook_present ? 1 : 0);
+    {
+        Timed t_(PGET_KC_CONTROL, S.stream);
+        hipLaunchKernelGGL(k_decide, dim3(S.B), dim3(256), 0, S.stream, S.V, hook_present ? 1 : 0);
+    }
 }
 
 void enqueue_commit(Solve& S)
 {
     const dim3 ew(S.sh.n_ew_blocks, S.B);
-    hipLaunchKernelGGL(k_accept, ew, dim3(EW_THREADS), 0, S.stream, S.V);
-    hipLaunchKernelGGL(k_commit, dim3((S.B + 63) / 64), dim3(64), 0, S.stream, S.V.st, S.B);
+    {
+        Timed t_(PGET_KC_VECTOR, S.stream);
+        hipLaunchKernelGGL(k_accept, ew, dim3(EW_THREADS), 0, S.stream, S.V);
+    }
+    {
+        Timed t_(PGET_KC_CONTROL, S.stream);
+        hipLaunchKernelGGL(k_commit, dim3((S.B + 63) / 64), dim3(64), 0, S.stream, S.V.st, S.B);
+    }
 }
 
 // The hook path of Alg. 2 for slice 0 (batch 1): host round trip per
@@ -709,13 +785,19 @@ pget_status run_hook(Solve& S, pget_refine_fn hook, void* user)
     Vh.ut = prop;
     Vh.hook_mode = 1;
     const dim3 ew(S.sh.n_ew_blocks, S.B);
-    hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vh);
+    {
+        Timed t_(PGET_KC_VECTOR, S.stream);
+        hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vh);
+    }
     enqueue_jvp(S, S.jpred, JVP_SQNORM);
     MarchArgs T = S.trial;
     T.src = planar_src(prop, prop + n2, 2 * n2);
     T.slot = SLOT_PHI_DATA_H;
     enqueue_march(S, T, MARCH_TRIAL);
-    hipLaunchKernelGGL(k_hook_decide, dim3(S.B), dim3(256), 0, S.stream, Vh);
+    {
+        Timed t_(PGET_KC_CONTROL, S.stream);
+        hipLaunchKernelGGL(k_hook_decide, dim3(S.B), dim3(256), 0, S.stream, Vh);
+    }
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
 }
 
@@ -794,7 +876,10 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
     }
     // the host vectors above must outlive the uploads
     HIP_TRY(hipStreamSynchronize(stream));
-    hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
+    {
+        Timed t_(PGET_KC_CONTROL, stream);
+        hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
+    }
     for (int k = 0; k < max_outer; ++k) {
         enqueue_iteration(S, k, n_cg, need_beta0, hook != nullptr);
         if (hook) {
@@ -803,8 +888,14 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
         }
         enqueue_commit(S);
     }
-    hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, stream, S.V);
-    hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, stream, S.V);
+    {
+        Timed t_(PGET_KC_VECTOR, stream);
+        hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, stream, S.V);
+    }
+    {
+        Timed t_(PGET_KC_CONTROL, stream);
+        hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, stream, S.V);
+    }
     for (int b = 0; b < B; ++b) {
         HIP_TRY(hipMemcpyAsync(f[b], S.V.u + b * 2 * n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
         HIP_TRY(hipMemcpyAsync(mu[b], S.V.u + b * 2 * n2 + n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
@@ -816,6 +907,42 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
 }  // namespace
 
 extern "C" {
+
+pget_status pget_timing_enable(int32_t classes, int32_t capacity)
+{
+    if (capacity < 0) return PGET_ERR_INVALID_ARG;
+    for (hipEvent_t e : g_timing.pool) (void)hipEventDestroy(e);
+    g_timing.pool.clear();
+    g_timing.recs.clear();
+    g_timing.classes = 0;
+    g_timing.capacity = 0;
+    if (capacity == 0 || classes == 0) return PGET_OK;
+    g_timing.pool.resize(2 * (size_t)capacity);
+    for (auto& e : g_timing.pool)
+        if (hipEventCreate(&e) != hipSuccess) return PGET_ERR_HIP;
+    g_timing.recs.reserve(capacity);
+    g_timing.classes = classes;
+    g_timing.capacity = capacity;
+    return PGET_OK;
+}
+
+pget_status pget_timing_read(int32_t kernel_class, double* total_ms, int64_t* launches)
+{
+    if (!total_ms || !launches) return PGET_ERR_INVALID_ARG;
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (const TimingRec& r : g_timing.recs) {
+        if (r.cls != kernel_class) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) return PGET_ERR_HIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) return PGET_ERR_HIP;
+        sum += ms;
+        ++cnt;
+    }
+    *total_ms = sum;
+    *launches = cnt;
+    return PGET_OK;
+}
 
 pget_status pget_lm_solve(const pget_plan* plan, const float* y, float* f_inout, float* mu_inout,
                           const pget_lm_params* params, pget_refine_fn hook, void* hook_user,

@@ -22,6 +22,9 @@ STATUS_NAMES = {
     -4: "non-finite value in the solver", -5: "unsupported geometry",
 }
 OP_FORWARD, OP_JVP, OP_VJP, OP_LM = 0, 1, 2, 3
+KC_MARCH, KC_JVP, KC_VJP, KC_VECTOR, KC_CONTROL, KC_GRADIENT = 0, 1, 2, 3, 4, 5
+KERNEL_CLASS_NAMES = {KC_MARCH: "march", KC_JVP: "jvp", KC_VJP: "vjp", KC_VECTOR: "vector",
+                      KC_CONTROL: "control", KC_GRADIENT: "gradient"}
 
 
 class PgetError(RuntimeError):
@@ -87,6 +90,12 @@ def load_library():
     lib.pget_plan_n_samples.restype = ctypes.c_int32
     lib.pget_plan_psf_half_width.argtypes = [V]
     lib.pget_plan_psf_half_width.restype = ctypes.c_int32
+    lib.pget_plan_support_samples.argtypes = [V]
+    lib.pget_plan_support_samples.restype = ctypes.c_int64
+    lib.pget_timing_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.pget_timing_enable.restype = ctypes.c_int
+    lib.pget_timing_read.argtypes = [ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
+    lib.pget_timing_read.restype = ctypes.c_int
     lib.pget_workspace_bytes.argtypes = [V, ctypes.c_int32, ctypes.c_int32]
     lib.pget_workspace_bytes.restype = ctypes.c_size_t
     lib.pget_forward.argtypes = [V, V, V, V, V, V]
@@ -244,6 +253,10 @@ class Plan:
     def psf_half_width(self) -> int:
         return int(self.lib.pget_plan_psf_half_width(self.handle))
 
+    @property
+    def support_samples(self) -> int:
+        return int(self.lib.pget_plan_support_samples(self.handle))
+
     def workspace_bytes(self, op: int, batch: int = 1) -> int:
         return int(self.lib.pget_workspace_bytes(self.handle, op, batch))
 
@@ -375,6 +388,20 @@ def _wrap_device(ptr, shape):
         "strides": None,
     }
     return torch.as_tensor(h, device="cuda")
+
+
+def timing_enable(classes: int, capacity: int) -> None:
+    """Bracket later launches of the kernel classes in the bit mask with HIP events."""
+    _check(load_library().pget_timing_enable(classes, capacity), "pget_timing_enable")
+
+
+def timing_read(kernel_class: int):
+    """(summed device milliseconds, launches) of one kernel class."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load_library().pget_timing_read(kernel_class, ctypes.byref(ms), ctypes.byref(n)),
+           "pget_timing_read")
+    return ms.value, n.value
 
 
 # C-ABI names, for callers who prefer them
