@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-single", action="store_true", help="skip the single-slice latency run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0, help="0: min(16, cpu count)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 256 MiB device copy (scale for HBM counters)")
     return ap.parse_args()
 
 
@@ -155,6 +157,12 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = inputs.scaled(inputs.MAIN_128, max_outer=args.outer, n_cg=args.cg)
     plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
     B = args.batch

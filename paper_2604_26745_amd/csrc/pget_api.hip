@@ -20,8 +20,10 @@ struct pget_plan {
     Tables t;
     void* table_mem;     // one device allocation holding every table
     bool lds_img;        // the bordered map pair fits in LDS
-    size_t op_lds_bytes; // dynamic LDS of k_march / k_jvp_lin
-    int op_threads;      // threads per block of k_march / k_jvp_lin
+    size_t op_lds_bytes; // dynamic LDS of k_march
+    int op_threads;      // threads per block of k_march
+    size_t img_lds;      // LDS bytes of the staged map pair (0 if not staged)
+    int max_japb;        // most angle slots per k_jvp_lin block that fit in LDS
     int tiles_x;         // VJP tiles per edge
     int device;
     int64_t support;     // lattice samples inside the support
@@ -63,8 +65,12 @@ int half_width(const pget_geometry* g)
 
 // Launch shapes for a batch of `batch` slices.
 struct Shapes {
-    int apb;          // angles per block of k_march / k_jvp_lin
-    int n_op_blocks;  // blocks per slice
+    int apb;          // angles per block of k_march
+    int n_op_blocks;  // blocks per slice of k_march
+    int japb;         // angle slots per block of k_jvp_lin
+    int n_jvp_blocks; // blocks per slice of k_jvp_lin
+    int jvp_threads;
+    size_t jvp_lds;
     int groups;       // angle groups of the adjoint gather
     int n_vjp_blocks; // blocks per slice of k_vjp_lin
     int n_ew_blocks;  // blocks per slice of the element-wise kernels
@@ -77,11 +83,17 @@ Shapes shapes_for(const pget_plan* P, int batch)
     // enough blocks to cover the chip twice; more angles per block when the
     // batch already does (the staged map is then reused across angles)
     int want = std::max(1, (P->g.n_angles * batch) / (4 * cus));
-    s.apb = std::min(4, want);
+    s.apb = std::min(8, want);
     s.n_op_blocks = (P->g.n_angles + s.apb - 1) / s.apb;
+    const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
+    int jwant = std::max(1, (slots * batch) / (2 * cus));
+    s.japb = std::max(1, std::min(P->max_japb, jwant));
+    s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
+    s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
+    s.jvp_lds = P->img_lds + 2 * (size_t)s.japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
     const int tiles = P->tiles_x * P->tiles_x;
     int g = (2 * cus + tiles * batch - 1) / (tiles * batch);
-    g = std::max(1, std::min(g, P->g.n_angles));
+    g = std::max(1, std::min(g, slots));
     s.groups = g;
     s.n_vjp_blocks = tiles * g;
     s.n_ew_blocks = (P->g.n * P->g.n + EW_THREADS - 1) / EW_THREADS;
@@ -184,16 +196,17 @@ void march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStr
     else launch_march<false, M>(P, A, blocks, batch, s);
 }
 template <bool LDS, int M>
-void launch_jvp(const pget_plan* P, const JvpArgs& A, int blocks, int batch, hipStream_t s)
+void launch_jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
     Timed t(PGET_KC_JVP, s);
-    hipLaunchKernelGGL((k_jvp_lin<LDS, M>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes, s, A);
+    hipLaunchKernelGGL((k_jvp_lin<LDS, M>), dim3(sh.n_jvp_blocks, batch), dim3(sh.jvp_threads), sh.jvp_lds,
+                       s, A);
 }
 template <int M>
-void jvp(const pget_plan* P, const JvpArgs& A, int blocks, int batch, hipStream_t s)
+void jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
-    if (P->lds_img) launch_jvp<true, M>(P, A, blocks, batch, s);
-    else launch_jvp<false, M>(P, A, blocks, batch, s);
+    if (P->lds_img) launch_jvp<true, M>(P, A, sh, batch, s);
+    else launch_jvp<false, M>(P, A, sh, batch, s);
 }
 
 void pack(const pget_plan* P, const PairSrc& src, const double* part, float2* out, int batch,
@@ -204,6 +217,16 @@ void pack(const pget_plan* P, const PairSrc& src, const double* part, float2* ou
     Timed t(PGET_KC_CONTROL, s);
     hipLaunchKernelGGL(k_pack, dim3(blocks, batch), dim3(256), 0, s, P->g, src, part, out,
                        (long long)total, st);
+}
+
+void fill_zero(void* p, size_t bytes, hipStream_t s)
+{
+    const long long n4 = (long long)(bytes / 16);
+    const int blocks = (int)std::min<long long>(4096, (n4 + 255) / 256);
+    if (n4 > 0) {
+        Timed t_(PGET_KC_CONTROL, s);
+        hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, reinterpret_cast<float4*>(p), n4);
+    }
 }
 
 PairSrc planar_src(const float* f, const float* mu, long long stride)
@@ -258,6 +281,7 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     g.c_att = (float)geom->atten_scale;
     g.kq = (float)(-geom->atten_scale * geom->step * geom->step);
     g.ln2_scale = (float)(geom->atten_scale * geom->step * 1.4426950408889634);
+    g.paired = (geom->n_angles % 2 == 0) && fabs(geom->arc - 2.0 * M_PI) <= 1e-12 * 2.0 * M_PI;
 
     // ---- tables in double precision, stored rounded to float
     const int na = g.n_angles, nb = g.n_bins, nt = g.n_t, ng = g.n_groups, K = g.K;
@@ -344,16 +368,29 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         return PGET_ERR_UNSUPPORTED;
     }
     P->op_threads = std::min(ng, 16) * WAVE;
-    if (P->op_lds_bytes > 64 * 1024) {
-        const int bytes = (int)P->op_lds_bytes;
+    P->img_lds = P->lds_img ? img_bytes : 0;
+    {
+        const size_t per_slot = 2 * (size_t)(g.paired ? 2 : 1) * nb * sizeof(float);
+        P->max_japb = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / per_slot);
+        if (P->max_japb < 1) {
+            (void)hipFree(P->table_mem);
+            delete P;
+            return PGET_ERR_UNSUPPORTED;
+        }
+    }
+    {
+        const int bytes = (int)lds_budget;
         bool attr_ok = true;
-        if (P->lds_img) {
+        {
             attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
             attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_LIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
             attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_TRIAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
             attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
             attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_NORMAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
             attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_SQNORM>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_NORMAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_SQNORM>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
         }
         if (!attr_ok) {
             (void)hipFree(P->table_mem);
@@ -423,6 +460,9 @@ static void linearise(const pget_plan* P, const float* f, const float* mu, float
     A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
     A.yout = y_or_null;
     A.angles_per_block = sh.apb;
+    // samples outside the support are never written; the adjoint reads them
+    // (with zero interpolation weight), so they must hold finite values
+    fill_zero(A.wts, (size_t)A.wts_stride * sizeof(float2), stream);
     if (!P->lds_img) {
         A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
         pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
@@ -452,7 +492,8 @@ pget_status pget_jvp(const pget_plan* P, const float* f, const float* mu, const 
         A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
         pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
     }
-    jvp<JVP_PLAIN>(P, A, sh.n_op_blocks, 1, stream);
+    A.angles_per_block = sh.japb;
+    jvp<JVP_PLAIN>(P, A, sh, 1, stream);
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
 }
 
@@ -609,7 +650,7 @@ void setup(Solve& S)
     J.out = wt_cg;
     J.part = part;
     J.st = st;
-    J.angles_per_block = S.sh.apb;
+    J.angles_per_block = S.sh.japb;
     float* r = reinterpret_cast<float*>(at(ws, S.L.r));
     float* p = reinterpret_cast<float*>(at(ws, S.L.p));
     J.src = PairSrc{};
@@ -668,7 +709,7 @@ void setup(Solve& S)
     V.gpart_slice_stride = S.vcg.gpart_slice_stride;
     V.groups = S.sh.groups;
     V.part = part;
-    V.n_jvp_blocks = S.sh.n_op_blocks;
+    V.n_jvp_blocks = S.sh.n_jvp_blocks;
     V.n_ew_blocks = S.sh.n_ew_blocks;
     V.n_march_blocks = S.sh.n_op_blocks;
     V.st = st;
@@ -686,8 +727,8 @@ void enqueue_march(Solve& S, const MarchArgs& A, int mode)
 void enqueue_jvp(Solve& S, const JvpArgs& A, int mode)
 {
     if (!S.P->lds_img) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream);
-    if (mode == JVP_NORMAL) jvp<JVP_NORMAL>(S.P, A, S.sh.n_op_blocks, S.B, S.stream);
-    else jvp<JVP_SQNORM>(S.P, A, S.sh.n_op_blocks, S.B, S.stream);
+    if (mode == JVP_NORMAL) jvp<JVP_NORMAL>(S.P, A, S.sh, S.B, S.stream);
+    else jvp<JVP_SQNORM>(S.P, A, S.sh, S.B, S.stream);
 }
 
 // Model decrease and objective of the step held in ut (k_trial already run):
@@ -879,6 +920,7 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
     {
         Timed t_(PGET_KC_CONTROL, stream);
         hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
+    fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * sizeof(float2), stream);
     }
     for (int k = 0; k < max_outer; ++k) {
         enqueue_iteration(S, k, n_cg, need_beta0, hook != nullptr);

@@ -36,6 +36,8 @@ struct Geo {
     float c_att;    // attenuation scale c
     float kq;       // -c * step^2: weight of the attenuation derivative
     float ln2_scale;  // c * step * log2(e): exponent scale for exp2
+    int paired;     // n_angles even over a full turn: angle a + n_angles/2 samples the
+                    // same lattice points as angle a with bins and samples mirrored
 };
 
 // Device-resident tables of a plan.
@@ -163,7 +165,7 @@ struct JvpArgs {
     int slot;               // SQNORM: slot of ||K z||^2
     const LMState* st;
     int skip_if_clean;      // for the initial-damping probe: run only when dirty
-    int angles_per_block;
+    int angles_per_block;   // angle slots per block (a slot is an angle pair when paired)
 };
 
 struct VjpArgs {
@@ -212,6 +214,7 @@ __global__ void k_pack(Geo g, PairSrc s, const double* part, float2* out, long l
                        const LMState* st);
 __global__ void k_psf(Geo g, const float* taps_g, const float* in, float* out);
 __global__ void k_vjp_lin(VjpArgs A);
+__global__ void k_fill_zero(float4* p, long long n4);
 __global__ void k_sum_groups(int n2, int groups, const float* gpart, long long group_stride, float* gf,
                              float* gm);
 __global__ void k_grad_init(VecArgs V);

@@ -141,15 +141,27 @@ __device__ __forceinline__ float2 src_value(const PairSrc& s, int slice, int idx
     return v;
 }
 
-// Stage the zero-bordered pair image ((N+2)^2 float2) into `dst`.
+// Stage the zero-bordered pair image ((N+2)^2 float2) into `dst`.  Four
+// pixels per thread per trip so that their loads are in flight together.
 __device__ void stage_image(float2* dst, const PairSrc& s, int slice, int n, int pitch, float beta)
 {
     const int total = pitch * pitch;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        int rr = idx / pitch - 1, cc = idx - (idx / pitch) * pitch - 1;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (rr >= 0 && rr < n && cc >= 0 && cc < n) v = src_value(s, slice, rr * n + cc, beta);
-        dst[idx] = v;
+    constexpr int U = 4;
+    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+        float2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int rr = idx / pitch - 1, cc = idx - (idx / pitch) * pitch - 1;
+            v[u] = make_float2(0.0f, 0.0f);
+            if (idx < total && rr >= 0 && rr < n && cc >= 0 && cc < n)
+                v[u] = src_value(s, slice, rr * n + cc, beta);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) dst[idx] = v[u];
+        }
     }
 }
 
@@ -288,6 +300,12 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 // ----------------------------------------------------------- linear JVP
 
 
+// Work items of a block are (angle slot, ray group) pairs spread over all
+// waves; one barrier precedes the collimator epilogue of every angle of the
+// block.  When the geometry is paired, a slot holds angle a and its mirror
+// a' = a + n_angles/2: ray j of a and ray n_bins-1-j of a' visit the same
+// points (sample i of one is sample n_t-1-i of the other), so one bilinear
+// sample of the direction serves both rays.
 template <bool LDS_IMG, int MODE>
 __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
 {
@@ -297,10 +315,15 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const Geo& g = A.g;
     const int slice = blockIdx.y;
     if (A.st && A.st[slice].done) return;
+    const int per_slot = g.paired ? 2 : 1;
+    const int n_slots = g.paired ? g.n_angles / 2 : g.n_angles;
+    const int slot0 = blockIdx.x * A.angles_per_block;
+    const int nslot = min(A.angles_per_block, n_slots - slot0);
+    const int nrows = nslot * per_slot;   // sinogram rows produced by this block
     float2* simg = reinterpret_cast<float2*>(smem_raw);
     const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
-    float* rowz = reinterpret_cast<float*>(simg + img_elems);
-    float* rowy = rowz + g.n_bins;
+    float* rowz = reinterpret_cast<float*>(simg + img_elems);   // [nrows][n_bins]
+    float* rowy = rowz + A.angles_per_block * per_slot * g.n_bins;
     for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = A.t.taps[k];
     if (LDS_IMG) {
         const float beta = resolve_beta(A.src, A.part, slice, sh);
@@ -311,54 +334,89 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int q = lane & (SPL - 1), jj = lane >> 2;
-    double acc2 = 0.0;
-    for (int ab = 0; ab < A.angles_per_block; ++ab) {
-        const int a = blockIdx.x * A.angles_per_block + ab;
-        if (a >= g.n_angles) break;
+    const float2* wslice = A.wts + (size_t)slice * A.wts_stride;
+    const float* tslice = A.tsum + (size_t)slice * A.sino_stride;
+    const int n_items = nslot * g.n_groups;
+    for (int item = wave; item < n_items; item += nwaves) {
+        const int sl = item / g.n_groups, grp = item - sl * g.n_groups;
+        const int a = slot0 + sl;
+        const int am = a + g.n_angles / 2;   // mirror angle (paired only)
         const float4 tr = A.t.trig[a];
-        const float2* wrow = A.wts + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
-        for (int grp = wave; grp < g.n_groups; grp += nwaves) {
-            const int j = grp * RG + jj;
-            const bool ray_ok = j < g.n_bins;
-            int2 cl = make_int2(1, 0);
-            float2 rb = make_float2(0.0f, 0.0f);
-            float T = 0.0f;
-            if (ray_ok) {
-                cl = A.t.clip[(size_t)a * g.n_bins + j];
-                rb = A.t.rbase[(size_t)a * g.n_bins + j];
-                T = A.tsum[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + j];
+        const int j = grp * RG + jj;
+        const int jm = g.n_bins - 1 - j;
+        const bool ray_ok = j < g.n_bins;
+        int2 cl = make_int2(1, 0);
+        float2 rb = make_float2(0.0f, 0.0f);
+        float T = 0.0f, Tm = 0.0f;
+        if (ray_ok) {
+            cl = A.t.clip[(size_t)a * g.n_bins + j];
+            rb = A.t.rbase[(size_t)a * g.n_bins + j];
+            T = tslice[(size_t)a * g.n_bins + j];
+            if (g.paired) Tm = tslice[(size_t)am * g.n_bins + jm];
+        }
+        const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
+        const float2* wrow = wslice + (size_t)a * g.n_t * g.n_bins;
+        const float2* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
+        float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
+        // JU trips of the sample loop per pass: their weight loads are issued
+        // together before any of them is used; lanes outside their ray's
+        // support use (0, T), which makes both terms vanish
+        constexpr int JU = 8;
+        for (int i0 = gr.y; i0 >= gr.x; i0 -= JU * SPL) {
+            float2 w[JU], wm[JU];
+#pragma unroll
+            for (int u = 0; u < JU; ++u) {
+                const int i = i0 - u * SPL - q;
+                const bool ok = (i >= cl.x) && (i <= cl.y);
+                w[u] = ok ? wrow[(size_t)i * g.n_bins + j] : make_float2(0.0f, T);
+                if (g.paired)
+                    wm[u] = ok ? wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : make_float2(0.0f, Tm);
             }
-            const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
-            float accf = 0.0f, accq = 0.0f;
-            for (int i0 = gr.y; i0 >= gr.x; i0 -= SPL) {
-                const int i = i0 - q;
-                if (i >= cl.x && i <= cl.y) {
-                    const float ti = (float)i - g.t_off;
-                    const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
-                    const float2 v = bilerp(img, g.pitch, g.n, col, row);
-                    const float2 w = wrow[(size_t)i * g.n_bins + j];
-                    accf = fmaf(w.x, v.x, accf);
-                    accq = fmaf(T - w.y, v.y, accq);
+#pragma unroll
+            for (int u = 0; u < JU; ++u) {
+                const int i = i0 - u * SPL - q;
+                const float ti = (float)i - g.t_off;
+                const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
+                const float2 v = bilerp(img, g.pitch, g.n, col, row);
+                accf = fmaf(w[u].x, v.x, accf);
+                accq = fmaf(T - w[u].y, v.y, accq);
+                if (g.paired) {
+                    accfm = fmaf(wm[u].x, v.x, accfm);
+                    accqm = fmaf(Tm - wm[u].y, v.y, accqm);
                 }
             }
-            accf = quad_sum(accf);
-            accq = quad_sum(accq);
-            if (ray_ok && q == 0) rowz[j] = fmaf(g.kq, accq, accf);
         }
+        accf = quad_sum(accf);
+        accq = quad_sum(accq);
+        if (ray_ok && q == 0) rowz[sl * g.n_bins + j] = fmaf(g.kq, accq, accf);
+        if (g.paired) {
+            accfm = quad_sum(accfm);
+            accqm = quad_sum(accqm);
+            if (ray_ok && q == 0) rowz[(nslot + sl) * g.n_bins + jm] = fmaf(g.kq, accqm, accfm);
+        }
+    }
+    __syncthreads();
+    // collimator epilogue over every (row, bin) of the block; row r < nslot is
+    // angle slot0 + r, row nslot + r its mirror
+    const int nel = nrows * g.n_bins;
+    double acc2 = 0.0;
+    for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+        const int r = e / g.n_bins, jb = e - r * g.n_bins;
+        const float y = psf_at(rowz + r * g.n_bins, taps, g.K, g.n_bins, jb);
+        const int a = r < nslot ? slot0 + r : slot0 + (r - nslot) + g.n_angles / 2;
+        const size_t o = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins + jb;
+        if (MODE == JVP_PLAIN) A.out[o] = y;
+        if (MODE == JVP_NORMAL) rowy[e] = y;
+        if (MODE == JVP_SQNORM) acc2 += (double)y * (double)y;
+    }
+    if (MODE == JVP_NORMAL) {
         __syncthreads();
-        const size_t srow = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
-        for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) {
-            const float y = psf_at(rowz, taps, g.K, g.n_bins, j);
-            if (MODE == JVP_PLAIN) A.out[srow + j] = y;
-            if (MODE == JVP_NORMAL) rowy[j] = y;
-            if (MODE == JVP_SQNORM) acc2 += (double)y * (double)y;
+        for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+            const int r = e / g.n_bins, jb = e - r * g.n_bins;
+            const int a = r < nslot ? slot0 + r : slot0 + (r - nslot) + g.n_angles / 2;
+            A.out[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + jb] =
+                psf_at(rowy + r * g.n_bins, taps, g.K, g.n_bins, jb);
         }
-        if (MODE == JVP_NORMAL) {
-            __syncthreads();
-            for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x)
-                A.out[srow + j] = psf_at(rowy, taps, g.K, g.n_bins, j);
-        }
-        __syncthreads();
     }
     if (MODE == JVP_SQNORM) {
         double s = block_sum(acc2, sh);
@@ -381,11 +439,117 @@ __global__ void __launch_bounds__(256) k_psf(Geo g, const float* taps_g, const f
 
 // ------------------------------------------------------- adjoint (gather)
 
+// Lattice window of one pixel tile at one angle: first candidate rows/columns
+// minus a margin of one, and the window extent (<= VFP).
+struct Window {
+    int jlo, ilo, wj, wi;
+};
+
+__device__ __forceinline__ Window tile_window(const Geo& g, float4 tr, int tr0, int tc0)
+{
+    const float SQ2 = 1.41421356f;
+    const float cs = tr.z, sn = tr.w;
+    const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
+    const float xa = (float)tc0 - g.half, xb = (float)(tc0 + VT - 1) - g.half;
+    const float ya = (float)tr0 - g.half, yb = (float)(tr0 + VT - 1) - g.half;
+    float umin = 1e30f, umax = -1e30f, vmin = 1e30f, vmax = -1e30f;
+#pragma unroll
+    for (int cnr = 0; cnr < 4; ++cnr) {
+        const float x = (cnr & 1) ? xb : xa, y = (cnr & 2) ? yb : ya;
+        const float u = fmaf(-x * sn + y * cs, inv_ds, g.s_off);
+        const float v = fmaf(x * cs + y * sn, inv_dt, g.t_off);
+        umin = fminf(umin, u); umax = fmaxf(umax, u);
+        vmin = fminf(vmin, v); vmax = fmaxf(vmax, v);
+    }
+    Window w;
+    w.jlo = (int)floorf(umin - SQ2);          // first candidate - 1
+    w.ilo = (int)floorf(vmin - SQ2);
+    // last candidate is floor(max - sqrt2) + 3; one more column of margin
+    w.wj = min(VFP, (int)floorf(umax - SQ2) + 5 - w.jlo);
+    w.wi = min(VFP, (int)floorf(vmax - SQ2) + 5 - w.ilo);
+    return w;
+}
+
+// Window rows per wave: the block's 4 waves take rows w, w+4, ...; lane =
+// window column.  No integer division in the staging index math.
+constexpr int VROWS = (VFP + 3) / 4;
+
+// Loads of one angle's window into registers (weight pair per point, and the
+// blurred cotangent and ray total of the lane's column).  Points off the
+// lattice rectangle load nothing; the weights buffer holds zeros outside the
+// support, and such samples carry zero tent weight for every pixel of the map.
+struct Stage {
+    float2 w[VROWS];
+    float2 wm[VROWS];   // mirror angle, same points (paired geometry)
+    float wt, t, wtm, tm;
+};
+
+__device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const float2* wbase, int slice,
+                                           int a, const Window& W)
+{
+    const Geo& g = A.g;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform row index base
+    const int am = a + g.n_angles / 2;
+    const float2* wrow = wbase + (size_t)a * g.n_t * g.n_bins;
+    const float2* wrowm = wbase + (size_t)am * g.n_t * g.n_bins;
+    const size_t sbase = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
+    const size_t sbasem = (size_t)slice * A.sino_stride + (size_t)am * g.n_bins;
+    const int j = W.jlo + lane;
+    const int jm = g.n_bins - 1 - j;
+    const bool jok = lane < W.wj && j >= 0 && j < g.n_bins;
+    S.wt = jok ? A.wt[sbase + j] : 0.0f;
+    S.t = jok ? A.tsum[sbase + j] : 0.0f;
+    S.wtm = (jok && g.paired) ? A.wt[sbasem + jm] : 0.0f;
+    S.tm = (jok && g.paired) ? A.tsum[sbasem + jm] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < VROWS; ++k) {
+        S.w[k] = make_float2(0.0f, 0.0f);
+        S.wm[k] = make_float2(0.0f, 0.0f);
+    }
+    if (jok) {
+#pragma unroll
+        for (int k = 0; k < VROWS; ++k) {
+            const int ii = wave + 4 * k;
+            const int i = W.ilo + ii;
+            if (ii < W.wi && i >= 0 && i < g.n_t) {   // wave-uniform condition
+                S.w[k] = wrow[(size_t)i * g.n_bins + j];
+                if (g.paired) S.wm[k] = wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm];
+            }
+        }
+    }
+}
+
+// Staged value of a lattice point: the coefficients of f and mu it spreads
+// (step*E*wt and kq*(T - R')*wt), summed with those of the mirror angle's
+// sample at the same point when the geometry is paired.
+__device__ __forceinline__ void stage_store(float2* lat, const Stage& S, float kq)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (lane >= VFP) return;
+    const float kw = kq * S.wt, kwm = kq * S.wtm;
+#pragma unroll
+    for (int k = 0; k < VROWS; ++k) {
+        const int ii = wave + 4 * k;
+        if (ii < VFP) {
+            const float cf = fmaf(S.wm[k].x, S.wtm, S.w[k].x * S.wt);
+            const float cm = fmaf(kwm, S.tm - S.wm[k].y, kw * (S.t - S.w[k].y));
+            lat[ii * VFP + lane] = make_float2(cf, cm);
+        }
+    }
+}
+
+// tent(d) = max(0, 1 - |d|); med3 against [0, 1] lets the compiler fold it
+// into the clamp bit of the subtraction
+__device__ __forceinline__ float tent(float d)
+{
+    return __builtin_amdgcn_fmed3f(1.0f - fabsf(d), 0.0f, 1.0f);
+}
+
 __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
 {
     __shared__ float2 lat[VFP * VFP];
-    __shared__ int2 rclip[VFP];
-    __shared__ float2 rcoef[VFP];   // (step-free weight of a: wt_j, T_j)
     const Geo& g = A.g;
     const int slice = blockIdx.y;
     if (A.st) {
@@ -395,106 +559,92 @@ __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
     const int ntile = A.tiles_x * A.tiles_x;
     const int tile = blockIdx.x % ntile, grp = blockIdx.x / ntile;
     const int tr0 = (tile / A.tiles_x) * VT, tc0 = (tile % A.tiles_x) * VT;
-    const int apg = (g.n_angles + A.groups - 1) / A.groups;
-    const int a_begin = grp * apg, a_end = min(g.n_angles, a_begin + apg);
+    const int n_slots = g.paired ? g.n_angles / 2 : g.n_angles;
+    const int apg = (n_slots + A.groups - 1) / A.groups;
+    const int a_begin = grp * apg, a_end = min(n_slots, a_begin + apg);
 
-    // this thread's pixels: one row, 4 consecutive columns
-    const int prow = tr0 + (threadIdx.x >> 3);
-    const int pcol = tc0 + (threadIdx.x & 7) * 4;
-    const float px0 = (float)pcol - g.half, py = (float)prow - g.half;
+    // this thread's 4 pixels: the same position in the four 8x8 blocks of its
+    // wave's 16x16 quarter (a wave touches one compact 8x8 block per step)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int qr = tr0 + (wave >> 1) * 16, qc = tc0 + (wave & 1) * 16;
+    int prow[4], pcol[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        prow[b] = qr + (b >> 1) * 8 + (lane >> 3);
+        pcol[b] = qc + (b & 1) * 8 + (lane & 7);
+    }
     float accf[4] = {0.f, 0.f, 0.f, 0.f}, accm[4] = {0.f, 0.f, 0.f, 0.f};
     const float SQ2 = 1.41421356f;
     const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
     const float2* wbase = A.wts + (size_t)slice * A.wts_stride;
 
+    Stage S;
+    Window Wn = {0, 0, 0, 0};
+    if (a_begin < a_end) {
+        Wn = tile_window(g, A.t.trig[a_begin], tr0, tc0);
+        stage_load(S, A, wbase, slice, a_begin, Wn);
+    }
     for (int a = a_begin; a < a_end; ++a) {
+        const Window W = Wn;
+        __syncthreads();   // the previous angle's gather is done with lat
+        stage_store(lat, S, g.kq);
+        __syncthreads();
+        if (a + 1 < a_end) {   // next angle's loads fly during this gather
+            Wn = tile_window(g, A.t.trig[a + 1], tr0, tc0);
+            stage_load(S, A, wbase, slice, a + 1, Wn);
+        }
         const float4 tr = A.t.trig[a];
         const float cs = tr.z, sn = tr.w;
-        // lattice coordinates of the tile corners -> staged window
-        const float xa = (float)tc0 - g.half, xb = (float)(tc0 + VT - 1) - g.half;
-        const float ya = (float)tr0 - g.half, yb = (float)(tr0 + VT - 1) - g.half;
-        float umin = 1e30f, umax = -1e30f, vmin = 1e30f, vmax = -1e30f;
-#pragma unroll
-        for (int cnr = 0; cnr < 4; ++cnr) {
-            const float x = (cnr & 1) ? xb : xa, y = (cnr & 2) ? yb : ya;
-            const float u = fmaf(-x * sn + y * cs, inv_ds, g.s_off);
-            const float v = fmaf(x * cs + y * sn, inv_dt, g.t_off);
-            umin = fminf(umin, u); umax = fmaxf(umax, u);
-            vmin = fminf(vmin, v); vmax = fmaxf(vmax, v);
-        }
-        const int jlo = (int)floorf(umin - SQ2);     // = first candidate - 1 (margin)
-        const int ilo = (int)floorf(vmin - SQ2);
-        const size_t sbase = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
-        __syncthreads();   // previous angle's gather is done with lat / rclip
-        for (int k = threadIdx.x; k < VFP; k += blockDim.x) {
-            const int j = jlo + k;
-            int2 cl = make_int2(1, 0);
-            float2 rc = make_float2(0.0f, 0.0f);
-            if (j >= 0 && j < g.n_bins) {
-                cl = A.t.clip[(size_t)a * g.n_bins + j];
-                rc = make_float2(A.wt[sbase + j], A.tsum[sbase + j]);
-            }
-            rclip[k] = cl;
-            rcoef[k] = rc;
-        }
-        __syncthreads();
-        const float2* wrow = wbase + (size_t)a * g.n_t * g.n_bins;
-        for (int idx = threadIdx.x; idx < VFP * VFP; idx += blockDim.x) {
-            const int ii = idx / VFP, jj = idx - ii * VFP;
-            const int i = ilo + ii, j = jlo + jj;
-            const int2 cl = rclip[jj];
-            float2 val = make_float2(0.0f, 0.0f);
-            if (i >= cl.x && i <= cl.y) {
-                const float2 w = wrow[(size_t)i * g.n_bins + j];
-                const float2 rc = rcoef[jj];
-                val = make_float2(w.x * rc.x, g.kq * (rc.y - w.y) * rc.x);
-            }
-            lat[idx] = val;
-        }
-        __syncthreads();
-        // displacement (pixel -> lattice point) per unit lattice step
+        // displacement (pixel -> lattice point) per unit lattice step, and its
+        // value at the 3x3 candidate offsets (built from sums: no 0*x or 2*x)
         const float A1 = -g.bin_size * sn, A2 = g.step * cs;   // dx
         const float A3 = g.bin_size * cs, A4 = g.step * sn;    // dy
+        const float oxj[3] = {0.0f, A1, A1 + A1}, oxi[3] = {0.0f, A2, A2 + A2};
+        const float oyj[3] = {0.0f, A3, A3 + A3}, oyi[3] = {0.0f, A4, A4 + A4};
 #pragma unroll
-        for (int pxi = 0; pxi < 4; ++pxi) {
-            const float x = px0 + (float)pxi;
-            const float u = fmaf(-x * sn + py * cs, inv_ds, g.s_off);
-            const float v = fmaf(x * cs + py * sn, inv_dt, g.t_off);
+        for (int b = 0; b < 4; ++b) {
+            const float x = (float)pcol[b] - g.half, y = (float)prow[b] - g.half;
+            const float u = fmaf(-x * sn + y * cs, inv_ds, g.s_off);
+            const float v = fmaf(x * cs + y * sn, inv_dt, g.t_off);
             const float ju = floorf(u - SQ2) + 1.0f, iv = floorf(v - SQ2) + 1.0f;
             const float du0 = ju - u, dv0 = iv - v;
             const float dx0 = fmaf(du0, A1, dv0 * A2), dy0 = fmaf(du0, A3, dv0 * A4);
-            const int jb = min(max((int)ju - jlo, 0), VFP - 3);
-            const int ib = min(max((int)iv - ilo, 0), VFP - 3);
+            const int jb = min(max((int)ju - W.jlo, 0), VFP - 3);
+            const int ib = min(max((int)iv - W.ilo, 0), VFP - 3);
             const float2* L = lat + ib * VFP + jb;
             float sf = 0.0f, sm = 0.0f;
 #pragma unroll
             for (int di = 0; di < 3; ++di) {
+                const float rx = dx0 + oxi[di], ry = dy0 + oyi[di];
 #pragma unroll
                 for (int dj = 0; dj < 3; ++dj) {
-                    const float dx = dx0 + ((float)dj * A1 + (float)di * A2);
-                    const float dy = dy0 + ((float)dj * A3 + (float)di * A4);
-                    const float w = fmaxf(0.0f, 1.0f - fabsf(dx)) * fmaxf(0.0f, 1.0f - fabsf(dy));
+                    const float w = tent(rx + oxj[dj]) * tent(ry + oyj[dj]);
                     const float2 c = L[di * VFP + dj];
                     sf = fmaf(w, c.x, sf);
                     sm = fmaf(w, c.y, sm);
                 }
             }
-            accf[pxi] += sf;
-            accm[pxi] += sm;
+            accf[b] += sf;
+            accm[b] += sm;
         }
     }
-    if (prow < g.n) {
-        float* out = A.gpart + (size_t)grp * A.gpart_group_stride + (size_t)slice * A.gpart_slice_stride;
-        const int n2 = g.n * g.n;
+    float* out = A.gpart + (size_t)grp * A.gpart_group_stride + (size_t)slice * A.gpart_slice_stride;
+    const int n2 = g.n * g.n;
 #pragma unroll
-        for (int pxi = 0; pxi < 4; ++pxi) {
-            const int c = pcol + pxi;
-            if (c < g.n) {
-                out[prow * g.n + c] = accf[pxi];
-                out[n2 + prow * g.n + c] = accm[pxi];
-            }
+    for (int b = 0; b < 4; ++b) {
+        if (prow[b] < g.n && pcol[b] < g.n) {
+            out[prow[b] * g.n + pcol[b]] = accf[b];
+            out[n2 + prow[b] * g.n + pcol[b]] = accm[b];
         }
     }
+}
+
+// Zero fill (kernels, not memset, so that captured graphs stay clean).
+__global__ void __launch_bounds__(256) k_fill_zero(float4* p, long long n4)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n4;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // Sum of the angle-group partial images (fixed order) into gf / gmu.

@@ -48,16 +48,18 @@ def maxrel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-# (n, n_angles, n_bins, sigma): tiny, ragged, the 64 and 128 workloads, a map
-# too large for LDS, and a slice whose detector is narrower than the map
+# (n, n_angles, n_bins, sigma, arc): tiny, ragged (odd angle count: no
+# mirrored angle pairs), the 64 and 128 workloads, a map too large for LDS, a
+# detector narrower than the map, and a half turn (even count, no pairs)
 SHAPES = [
-    (16, 24, 24, 1.5),
-    (33, 37, 50, 1.5),
-    (17, 9, 13, 0.0),
-    (64, 120, 96, 1.5),
-    (128, 360, 192, 1.5),
-    (150, 60, 220, 1.5),
-    (96, 30, 80, 2.0),
+    (16, 24, 24, 1.5, 2 * math.pi),
+    (33, 37, 50, 1.5, 2 * math.pi),
+    (17, 9, 13, 0.0, 2 * math.pi),
+    (64, 120, 96, 1.5, 2 * math.pi),
+    (128, 360, 192, 1.5, 2 * math.pi),
+    (150, 60, 220, 1.5, 2 * math.pi),
+    (96, 30, 80, 2.0, 2 * math.pi),
+    (40, 20, 60, 1.5, math.pi),
 ]
 
 
@@ -69,12 +71,13 @@ def phantom(n, seed, nb=None):
     return f + 0.05 * rng.uniform(0, 1, f.shape), mu + 0.002 * rng.uniform(0, 1, mu.shape)
 
 
-@pytest.fixture(scope="module", params=SHAPES, ids=lambda s: "n%d_a%d_b%d_s%g" % s)
+@pytest.fixture(scope="module", params=SHAPES,
+                ids=lambda s: "n%d_a%d_b%d_s%g_arc%.2f" % s)
 def case(request):
-    n, na, nb, sig = request.param
-    log("case n=%d angles=%d bins=%d sigma=%g" % (n, na, nb, sig))
-    og = O.Geometry(n, na, nb, psf_sigma=sig)
-    plan = pget.Plan(n, na, nb, psf_sigma=sig)
+    n, na, nb, sig, arc = request.param
+    log("case n=%d angles=%d bins=%d sigma=%g arc=%.3f" % (n, na, nb, sig, arc))
+    og = O.Geometry(n, na, nb, psf_sigma=sig, arc=arc)
+    plan = pget.Plan(n, na, nb, psf_sigma=sig, arc=arc)
     f, mu = phantom(n, n + na)
     return og, plan, f, mu
 
