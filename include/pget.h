@@ -246,6 +246,17 @@ enum {
 pget_status pget_timing_enable(int32_t classes, int32_t capacity);
 pget_status pget_timing_read(int32_t kernel_class, double* total_ms, int64_t* launches);
 
+/*
+ * Replay of the solver's kernel sequence as a HIP graph (default on).  The
+ * sequence of a solve without hook is captured once per (plan, workspace,
+ * batch, max_outer, n_cg) and replayed on later calls with the same key;
+ * inputs and parameters are uploaded before each replay.  Graphs are not used
+ * while kernel timing is enabled or when a hook is given.  enable = 0 turns
+ * replay off (every call launches its kernels directly).  Results are the same
+ * either way, bit for bit.
+ */
+pget_status pget_set_graphs(int32_t enable);
+
 /* Human-readable name of a status code (static string). */
 const char* pget_status_string(pget_status status);
 

@@ -27,7 +27,16 @@ struct pget_plan {
     int tiles_x;         // VJP tiles per edge
     int device;
     int64_t support;     // lattice samples inside the support
+    struct GraphEntry {
+        void* ws;
+        int batch, max_outer, n_cg, need_beta0;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;   // instantiated solver sequences
+    hipStream_t capture_stream = nullptr;
 };
+
+static bool g_use_graphs = true;
 
 namespace {
 
@@ -406,6 +415,8 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
 void pget_plan_destroy(pget_plan* plan)
 {
     if (!plan) return;
+    for (auto& e : plan->graphs) (void)hipGraphExecDestroy(e.exec);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
     (void)hipFree(plan->table_mem);
     delete plan;
 }
@@ -917,26 +928,54 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
     }
     // the host vectors above must outlive the uploads
     HIP_TRY(hipStreamSynchronize(stream));
-    {
-        Timed t_(PGET_KC_CONTROL, stream);
-        hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
-    fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * sizeof(float2), stream);
-    }
-    for (int k = 0; k < max_outer; ++k) {
-        enqueue_iteration(S, k, n_cg, need_beta0, hook != nullptr);
-        if (hook) {
-            pget_status rc = run_hook(S, hook, hook_user);
-            if (rc != PGET_OK) return rc;
+    auto enqueue_all = [&](Solve& SS) {
+        hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, SS.stream, SS.V.st, SS.V.prm, B);
+        fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * sizeof(float2), SS.stream);
+        for (int k = 0; k < max_outer; ++k) {
+            enqueue_iteration(SS, k, n_cg, need_beta0, false);
+            enqueue_commit(SS);
         }
-        enqueue_commit(S);
-    }
-    {
-        Timed t_(PGET_KC_VECTOR, stream);
-        hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, stream, S.V);
-    }
-    {
-        Timed t_(PGET_KC_CONTROL, stream);
-        hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, stream, S.V);
+        hipLaunchKernelGGL(k_final_reg, dim3(SS.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, SS.stream, SS.V);
+        hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, SS.stream, SS.V);
+    };
+    const bool graph_ok = g_use_graphs && !hook && g_timing.classes == 0;
+    if (!graph_ok) {
+        if (!hook) {
+            enqueue_all(S);
+        } else {
+            hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
+            fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * sizeof(float2), stream);
+            for (int k = 0; k < max_outer; ++k) {
+                enqueue_iteration(S, k, n_cg, need_beta0, true);
+                pget_status rc = run_hook(S, hook, hook_user);
+                if (rc != PGET_OK) return rc;
+                enqueue_commit(S);
+            }
+            hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, stream, S.V);
+            hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, stream, S.V);
+        }
+    } else {
+        pget_plan* PM = const_cast<pget_plan*>(P);
+        hipGraphExec_t exec = nullptr;
+        for (auto& e : PM->graphs)
+            if (e.ws == ws && e.batch == B && e.max_outer == max_outer && e.n_cg == n_cg &&
+                e.need_beta0 == (int)need_beta0)
+                exec = e.exec;
+        if (!exec) {
+            if (!PM->capture_stream)
+                HIP_TRY(hipStreamCreateWithFlags(&PM->capture_stream, hipStreamNonBlocking));
+            Solve C = S;
+            C.stream = PM->capture_stream;
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(C.stream, hipStreamCaptureModeThreadLocal));
+            enqueue_all(C);
+            HIP_TRY(hipStreamEndCapture(C.stream, &graph));
+            hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return PGET_ERR_HIP;
+            PM->graphs.push_back(pget_plan::GraphEntry{ws, B, max_outer, n_cg, (int)need_beta0, exec});
+        }
+        HIP_TRY(hipGraphLaunch(exec, stream));
     }
     for (int b = 0; b < B; ++b) {
         HIP_TRY(hipMemcpyAsync(f[b], S.V.u + b * 2 * n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
@@ -949,6 +988,12 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
 }  // namespace
 
 extern "C" {
+
+pget_status pget_set_graphs(int32_t enable)
+{
+    g_use_graphs = enable != 0;
+    return PGET_OK;
+}
 
 pget_status pget_timing_enable(int32_t classes, int32_t capacity)
 {

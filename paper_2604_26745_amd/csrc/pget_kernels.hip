@@ -336,9 +336,16 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const int q = lane & (SPL - 1), jj = lane >> 2;
     const float2* wslice = A.wts + (size_t)slice * A.wts_stride;
     const float* tslice = A.tsum + (size_t)slice * A.sino_stride;
+    // Items are taken from a block-wide counter (dynamic balance), longest
+    // first: ray groups ordered from the middle of the detector outward.
+    __shared__ int next_item;
+    if (threadIdx.x == 0) next_item = nwaves;
+    __syncthreads();
     const int n_items = nslot * g.n_groups;
-    for (int item = wave; item < n_items; item += nwaves) {
-        const int sl = item / g.n_groups, grp = item - sl * g.n_groups;
+    const int gc = g.n_groups / 2;
+    for (int item = wave; item < n_items;) {
+        const int rank = item / nslot, sl = item - rank * nslot;
+        const int grp = (rank & 1) ? gc - (rank + 1) / 2 : gc + rank / 2;
         const int a = slot0 + sl;
         const int am = a + g.n_angles / 2;   // mirror angle (paired only)
         const float4 tr = A.t.trig[a];
@@ -358,12 +365,13 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         const float2* wrow = wslice + (size_t)a * g.n_t * g.n_bins;
         const float2* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
         float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
-        // JU trips of the sample loop per pass: their weight loads are issued
-        // together before any of them is used; lanes outside their ray's
-        // support use (0, T), which makes both terms vanish
-        constexpr int JU = 8;
-        for (int i0 = gr.y; i0 >= gr.x; i0 -= JU * SPL) {
-            float2 w[JU], wm[JU];
+        // The sample loop is software-pipelined: the weights of trip t+1 (JU
+        // samples per lane) are loaded while trip t is computed.  Lanes outside
+        // their ray's support use (0, T), which makes both terms vanish.
+        constexpr int JU = 4;
+        constexpr int STEP = JU * SPL;
+        float2 wa[JU], wma[JU], wb[JU], wmb[JU];
+        auto load = [&](int i0, float2* w, float2* wm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
                 const int i = i0 - u * SPL - q;
@@ -372,6 +380,8 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                 if (g.paired)
                     wm[u] = ok ? wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : make_float2(0.0f, Tm);
             }
+        };
+        auto compute = [&](int i0, const float2* w, const float2* wm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
                 const int i = i0 - u * SPL - q;
@@ -385,6 +395,18 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                     accqm = fmaf(Tm - wm[u].y, v.y, accqm);
                 }
             }
+        };
+        int i0 = gr.y;
+        if (i0 >= gr.x) load(i0, wa, wma);
+        while (i0 >= gr.x) {
+            const int i1 = i0 - STEP;
+            if (i1 >= gr.x) load(i1, wb, wmb);
+            compute(i0, wa, wma);
+            if (i1 < gr.x) break;
+            const int i2 = i1 - STEP;
+            if (i2 >= gr.x) load(i2, wa, wma);
+            compute(i1, wb, wmb);
+            i0 = i2;
         }
         accf = quad_sum(accf);
         accq = quad_sum(accq);
@@ -394,6 +416,9 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             accqm = quad_sum(accqm);
             if (ray_ok && q == 0) rowz[(nslot + sl) * g.n_bins + jm] = fmaf(g.kq, accqm, accfm);
         }
+        int nxt = 0;
+        if (lane == 0) nxt = atomicAdd(&next_item, 1);
+        item = __shfl(nxt, 0, 64);
     }
     __syncthreads();
     // collimator epilogue over every (row, bin) of the block; row r < nslot is

@@ -96,6 +96,8 @@ def load_library():
     lib.pget_timing_enable.restype = ctypes.c_int
     lib.pget_timing_read.argtypes = [ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.pget_timing_read.restype = ctypes.c_int
+    lib.pget_set_graphs.argtypes = [ctypes.c_int32]
+    lib.pget_set_graphs.restype = ctypes.c_int
     lib.pget_workspace_bytes.argtypes = [V, ctypes.c_int32, ctypes.c_int32]
     lib.pget_workspace_bytes.restype = ctypes.c_size_t
     lib.pget_forward.argtypes = [V, V, V, V, V, V]
@@ -388,6 +390,11 @@ def _wrap_device(ptr, shape):
         "strides": None,
     }
     return torch.as_tensor(h, device="cuda")
+
+
+def set_graphs(enable: bool) -> None:
+    """Replay the solver's kernel sequence as a HIP graph (default) or not."""
+    _check(load_library().pget_set_graphs(1 if enable else 0), "pget_set_graphs")
 
 
 def timing_enable(classes: int, capacity: int) -> None:

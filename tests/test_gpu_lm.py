@@ -192,3 +192,33 @@ def test_early_exit_tolerance():
     assert rep.iters_run == orep.iters_run
     # the report of a stopped solve ends at the last iteration run
     assert len(rep.phi) == rep.iters_run + 1 and np.isfinite(rep.phi[-1])
+
+
+def test_graph_replay_matches_eager_launches():
+    """The captured solver sequence replayed several times, with other GPU
+    work and synchronisations in between, gives the eager result bit for bit."""
+    og, y, f0, mu0, _, _ = problem(SMALL)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    prm = pget.SolverParams(max_outer=4, n_cg=6)
+    pget.set_graphs(False)
+    try:
+        fe, me, re_ = plan.lm_solve(T(y), T(f0), T(mu0), prm)
+    finally:
+        pget.set_graphs(True)
+    ref = re_.to_report()
+    for rep_i in range(3):
+        fg, mg, rg = plan.lm_solve(T(y), T(f0), T(mu0), prm)
+        assert torch.equal(fg, fe) and torch.equal(mg, me), rep_i
+        assert rg.to_report().phi == ref.phi
+        # unrelated eager work between replays
+        plan.forward(T(f0), T(mu0))
+        torch.cuda.synchronize()
+    # a different input through the same captured graph
+    y2 = y * 1.1
+    f2, m2, r2 = plan.lm_solve(T(y2), T(f0), T(mu0), prm)
+    pget.set_graphs(False)
+    try:
+        f3, m3, r3 = plan.lm_solve(T(y2), T(f0), T(mu0), prm)
+    finally:
+        pget.set_graphs(True)
+    assert torch.equal(f2, f3) and torch.equal(m2, m3)
