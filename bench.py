@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-single", action="store_true", help="skip the single-slice latency run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0, help="0: min(16, cpu count)")
+    ap.add_argument("--workload", default="main", choices=["main", "mixed"],
+                    help="main: batch of 128^2 slices (the headline metric); mixed: 64 slices of "
+                         "mixed sizes {64..256}^2 solved together vs one at a time")
+    ap.add_argument("--autotune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (scale for HBM counters)")
     return ap.parse_args()
@@ -141,6 +145,79 @@ def traffic_from_profile(kernel: str, workload: str):
         return None
 
 
+def run_mixed(args, torch, np, inputs, pget):
+    """64 slices with grid sizes drawn from {64, 96, 128, 192, 256}^2, 360
+    angles, 1.5x grid bins, 9x9 or 17x17 lattices, Poisson peak 10^U(3,5);
+    solved together (one plan per size, groups concurrent) and, as the
+    comparison, one slice at a time with the same kernels."""
+    n = args.batch
+    cfgs = [inputs.mixed_config(s)[0] for s in range(n)]
+    cfgs = [inputs.scaled(c, max_outer=args.outer, n_cg=args.cg) for c in cfgs]
+    plans = {}
+    for c in cfgs:
+        if c.n not in plans:
+            plans[c.n] = pget.Plan(c.n, c.n_angles, c.n_bins, psf_sigma=c.psf_sigma)
+    ys, f0s, m0s, pl = [], [], [], []
+    ones = {}
+    for s, c in enumerate(cfgs):
+        plan = plans[c.n]
+        if c.n not in ones:
+            o = torch.ones((c.n, c.n), dtype=torch.float32, device="cuda")
+            ones[c.n] = plan.forward(o, torch.zeros_like(o)).double().cpu().numpy()
+        a1 = ones[c.n]
+        f, mu = inputs.rod_lattice(c, s)
+        T = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+        y = inputs.poisson_counts(plan.forward(T(f), T(mu)).double().cpu().numpy(), c.peak_counts, s)
+        c0 = float((a1 * y).sum() / (a1 * a1).sum())
+        ys.append(T(y)); pl.append(plan)
+        f0s.append(torch.full((c.n, c.n), c0, dtype=torch.float32, device="cuda"))
+        m0s.append(torch.zeros((c.n, c.n), dtype=torch.float32, device="cuda"))
+    prm = [pget.SolverParams(max_outer=c.max_outer, n_cg=c.n_cg, alpha_f=c.alpha, alpha_mu=c.alpha)
+           for c in cfgs]
+    counts = {}
+    for c in cfgs:
+        counts[c.n] = counts.get(c.n, 0) + 1
+    if args.autotune:
+        for nn, plan in plans.items():
+            plan.autotune(counts[nn])
+            plan.autotune(1)
+    print("bench: mixed batch sizes %s" % sorted(counts.items()), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        pget.lm_solve_multi(pl, ys, f0s, m0s, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fs, ms, rbs = pget.lm_solve_multi(pl, ys, f0s, m0s, prm, sync=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = n * args.steps / el
+    # plain per-slice solver: same kernels, one slice at a time
+    for s in range(min(n, len(plans))):
+        pl[s].lm_solve(ys[s], f0s[s], m0s[s], prm[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(n):
+        pl[s].lm_solve(ys[s], f0s[s], m0s[s], prm[s], sync=False)
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t1
+    plain = n / el1
+    reps = [r.to_report() for r in rbs]
+    assert all(r.status == 0 for r in reps)
+    out = {
+        "metric": "LM reconstructions/s, mixed grid sizes {64..256}^2 x 360 angles (FP32)",
+        "value": round(value, 4), "unit": "reconstructions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mixed_sizes_%d_slices" % n, "sizes": sorted(counts.items()),
+                   "outer": args.outer, "cg": args.cg, "autotuned": bool(args.autotune),
+                   "tuned_shapes": {str(k): p.tuned_shape(counts[k]) for k, p in plans.items()}},
+        "plain_per_slice": {"value": round(plain, 4), "unit": "reconstructions/s",
+                            "speedup": round(value / plain, 3)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -157,6 +234,9 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "mixed":
+        run_mixed(args, torch, np, inputs, pget)
+        return
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

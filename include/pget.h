@@ -257,6 +257,38 @@ pget_status pget_timing_read(int32_t kernel_class, double* total_ms, int64_t* la
  */
 pget_status pget_set_graphs(int32_t enable);
 
+/*
+ * Slices of different shapes solved together (mixed grid sizes): slice s
+ * uses plans[s]; slices sharing a plan form one group solved as a batch, and
+ * the groups run concurrently on the device (one graph launch when graphs are
+ * on).  Arguments as for pget_lm_solve_batched, per slice; within a group all
+ * slices must share max_outer and n_cg.  ws must hold
+ * pget_workspace_bytes_multi(n_slices, plans) bytes; ws_bytes is its size.
+ * Each slice's result is the one pget_lm_solve gives for it alone.
+ */
+size_t pget_workspace_bytes_multi(int32_t n_slices, const pget_plan* const* plans);
+pget_status pget_lm_solve_multi(int32_t n_slices, const pget_plan* const* plans, const float* const* y,
+                                float* const* f_inout, float* const* mu_inout,
+                                const pget_lm_params* params, const pget_lm_report* reports, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Autotuner of launch shapes: times the candidate shapes of the Jacobian
+ * product (angle slots per block: 1, 2, 4, ...) and of the adjoint gather
+ * (angle groups split across blocks: 1, 2, 4, ...) for `batch` slices of this
+ * plan's shape on zero-filled data, and keeps the fastest pair in the plan
+ * for later solves of that batch size.  ws: at least
+ * pget_workspace_bytes(plan, PGET_OP_LM, batch) bytes (its contents are
+ * overwritten).  Synchronises `stream`.  The Jacobian product's shape does
+ * not change any result bit; the adjoint's angle grouping changes the order in
+ * which per-angle contributions are added (rounding-level differences between
+ * shapes); a given shape is bitwise reproducible.
+ * pget_tuned_shape reports the shape a solve of `batch` slices will use and
+ * returns 1 if it came from the autotuner, 0 if from the default heuristic.
+ */
+pget_status pget_autotune(pget_plan* plan, int32_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
+int32_t pget_tuned_shape(const pget_plan* plan, int32_t batch, int32_t* japb, int32_t* vjp_groups);
+
 /* Human-readable name of a status code (static string). */
 const char* pget_status_string(pget_status status);
 

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <new>
 #include <vector>
 
@@ -27,16 +28,22 @@ struct pget_plan {
     int tiles_x;         // VJP tiles per edge
     int device;
     int64_t support;     // lattice samples inside the support
-    struct GraphEntry {
-        void* ws;
-        int batch, max_outer, n_cg, need_beta0;
-        hipGraphExec_t exec;
-    };
-    std::vector<GraphEntry> graphs;   // instantiated solver sequences
-    hipStream_t capture_stream = nullptr;
+    std::vector<std::array<int, 3>> tuned;   // (batch, japb, vjp groups) picked by pget_autotune
 };
 
 static bool g_use_graphs = true;
+
+// Instantiated solver sequences, keyed by workspace and the groups solved.
+struct GraphKey {
+    void* ws;
+    std::vector<std::array<long long, 6>> groups;   // plan, batch, outer, cg, beta0, offset
+    bool operator==(const GraphKey& o) const { return ws == o.ws && groups == o.groups; }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+};
+static std::vector<GraphEntry> g_graphs;
 
 namespace {
 
@@ -103,6 +110,15 @@ Shapes shapes_for(const pget_plan* P, int batch)
     const int tiles = P->tiles_x * P->tiles_x;
     int g = (2 * cus + tiles * batch - 1) / (tiles * batch);
     g = std::max(1, std::min(g, slots));
+    s.groups = g;
+    for (const auto& t : P->tuned)
+        if (t[0] == batch) {
+            s.japb = std::max(1, std::min(P->max_japb, t[1]));
+            s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
+            s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
+            s.jvp_lds = P->img_lds + 2 * (size_t)s.japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+            g = std::max(1, std::min(t[2], slots));
+        }
     s.groups = g;
     s.n_vjp_blocks = tiles * g;
     s.n_ew_blocks = (P->g.n * P->g.n + EW_THREADS - 1) / EW_THREADS;
@@ -415,8 +431,16 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
 void pget_plan_destroy(pget_plan* plan)
 {
     if (!plan) return;
-    for (auto& e : plan->graphs) (void)hipGraphExecDestroy(e.exec);
-    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    for (size_t k = 0; k < g_graphs.size();) {
+        bool uses = false;
+        for (auto& gk : g_graphs[k].key.groups) uses |= gk[0] == (long long)(intptr_t)plan;
+        if (uses) {
+            (void)hipGraphExecDestroy(g_graphs[k].exec);
+            g_graphs.erase(g_graphs.begin() + k);
+        } else {
+            ++k;
+        }
+    }
     (void)hipFree(plan->table_mem);
     delete plan;
 }
@@ -871,22 +895,64 @@ void copy_report(const ReportDev& R, const pget_lm_report* out, int max_outer, i
     cp(out->cg_rr, R.cg_rr, (size_t)max_outer * n_cg * sizeof(double));
 }
 
-pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* const* f,
-                       float* const* mu, const pget_lm_params* params, const pget_lm_report* reports,
-                       pget_refine_fn hook, void* hook_user, void* ws, hipStream_t stream)
-{
-    if (!P || B < 1 || !y || !f || !mu || !params) return PGET_ERR_INVALID_ARG;
-    if (!ws) return PGET_ERR_WORKSPACE;
-    const int max_outer = params[0].max_outer, n_cg = params[0].n_cg;
-    bool need_beta0 = false;
-    for (int b = 0; b < B; ++b) {
-        if (!params_ok(&params[b])) return PGET_ERR_INVALID_ARG;
-        if (params[b].max_outer != max_outer || params[b].n_cg != n_cg) return PGET_ERR_INVALID_ARG;
-        if (!y[b] || !f[b] || !mu[b]) return PGET_ERR_INVALID_ARG;
-        if (params[b].beta0 <= 0.0) need_beta0 = true;
-    }
-    if (hook && B != 1) return PGET_ERR_INVALID_ARG;
+// One group of slices sharing a plan: its solve state and host-side copies
+// of parameters and report descriptors.
+struct Group {
     Solve S;
+    int max_outer = 0, n_cg = 0;
+    bool need_beta0 = false;
+    std::vector<LMParamsDev> prm;
+    std::vector<ReportDev> rep;
+    std::vector<const float*> y;
+    std::vector<float*> f, mu;
+    std::vector<const pget_lm_report*> reports;
+};
+
+// Internal streams (default priority) and events for fork/join.
+struct StreamPool {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    hipStream_t get(size_t k)
+    {
+        while (streams.size() <= k) {
+            hipStream_t s = nullptr;
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+            streams.push_back(s);
+        }
+        return streams[k];
+    }
+    hipEvent_t event(size_t k)
+    {
+        while (events.size() <= k) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+            events.push_back(e);
+        }
+        return events[k];
+    }
+} g_pool;
+
+
+size_t group_bytes(const pget_plan* P, int B)
+{
+    Shapes sh = shapes_for(P, B);
+    return align_up(layout_for(P, PGET_OP_LM, B, sh, 256, 256).total);
+}
+
+// Validate, lay out and upload one group (uploads on `stream`).
+pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStream_t stream)
+{
+    const pget_lm_params* params = nullptr;
+    (void)params;
+    G.max_outer = G.prm.empty() ? 0 : G.prm[0].max_outer;
+    G.n_cg = G.prm.empty() ? 0 : G.prm[0].n_cg;
+    G.need_beta0 = false;
+    for (int b = 0; b < B; ++b) {
+        if (G.prm[b].max_outer != G.max_outer || G.prm[b].n_cg != G.n_cg) return PGET_ERR_INVALID_ARG;
+        if (!G.y[b] || !G.f[b] || !G.mu[b]) return PGET_ERR_INVALID_ARG;
+        if (G.prm[b].beta0 <= 0.0) G.need_beta0 = true;
+    }
+    Solve& S = G.S;
     S.P = P;
     S.B = B;
     S.sh = shapes_for(P, B);
@@ -896,93 +962,199 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
     setup(S);
     const Geo& g = P->g;
     const size_t n2 = (size_t)g.n * g.n, sino = (size_t)g.n_angles * g.n_bins;
-
-    // parameters and report descriptors (small host -> device uploads)
-    std::vector<LMParamsDev> prm(B);
-    std::vector<ReportDev> rep(B);
+    const int max_outer = G.max_outer, n_cg = G.n_cg;
+    G.rep.assign(B, ReportDev{});
     const size_t per = align_up((size_t)(max_outer + 1) * 6 * sizeof(double) + 2 * (size_t)max_outer +
                                 (size_t)max_outer * n_cg * sizeof(double) + 4 * sizeof(double) + 64);
     for (int b = 0; b < B; ++b) {
-        prm[b] = to_dev(params[b]);
         char* base = at(ws, S.L.reparr + (size_t)b * per);
         size_t o = 0;
         auto take = [&](size_t bytes) { char* p = base + o; o += (bytes + 7) / 8 * 8; return p; };
-        rep[b].phi = reinterpret_cast<double*>(take((max_outer + 1) * sizeof(double)));
-        rep[b].rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        rep[b].beta = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        rep[b].pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        rep[b].ared = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        rep[b].gnorm = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        rep[b].cg_rr = reinterpret_cast<double*>(take((size_t)max_outer * n_cg * sizeof(double)));
-        rep[b].scalars = reinterpret_cast<double*>(take(4 * sizeof(double)));
-        rep[b].accepted = reinterpret_cast<int8_t*>(take(max_outer));
-        rep[b].hook_accepted = reinterpret_cast<int8_t*>(take(max_outer));
+        ReportDev& R = G.rep[b];
+        R.phi = reinterpret_cast<double*>(take((max_outer + 1) * sizeof(double)));
+        R.rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.beta = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.ared = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.gnorm = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.cg_rr = reinterpret_cast<double*>(take((size_t)max_outer * n_cg * sizeof(double)));
+        R.scalars = reinterpret_cast<double*>(take(4 * sizeof(double)));
+        R.accepted = reinterpret_cast<int8_t*>(take(max_outer));
+        R.hook_accepted = reinterpret_cast<int8_t*>(take(max_outer));
     }
-    HIP_TRY(hipMemcpyAsync(const_cast<LMParamsDev*>(S.V.prm), prm.data(), B * sizeof(LMParamsDev), hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(S.V.rep, rep.data(), B * sizeof(ReportDev), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(const_cast<LMParamsDev*>(S.V.prm), G.prm.data(), B * sizeof(LMParamsDev),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(S.V.rep, G.rep.data(), B * sizeof(ReportDev), hipMemcpyHostToDevice, stream));
     float* ymeas = reinterpret_cast<float*>(at(ws, S.L.ymeas));
     for (int b = 0; b < B; ++b) {
-        HIP_TRY(hipMemcpyAsync(ymeas + b * sino, y[b], sino * sizeof(float), hipMemcpyDeviceToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(S.V.u + b * 2 * n2, f[b], n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(S.V.u + b * 2 * n2 + n2, mu[b], n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(ymeas + b * sino, G.y[b], sino * sizeof(float), hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(S.V.u + b * 2 * n2, G.f[b], n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(S.V.u + b * 2 * n2 + n2, G.mu[b], n2 * sizeof(float), hipMemcpyDeviceToDevice,
+                               stream));
     }
-    // the host vectors above must outlive the uploads
+    return PGET_OK;
+}
+
+// The whole device-resident solve of one group (no hook).
+void enqueue_group(Group& G, hipStream_t s)
+{
+    Solve SS = G.S;
+    SS.stream = s;
+    const int B = SS.B;
+    hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, s, SS.V.st, SS.V.prm, B);
+    fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * sizeof(float2), s);
+    for (int k = 0; k < G.max_outer; ++k) {
+        enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false);
+        enqueue_commit(SS);
+    }
+    hipLaunchKernelGGL(k_final_reg, dim3(SS.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, s, SS.V);
+    hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, s, SS.V);
+}
+
+// All groups forked from `origin` onto their own streams and joined back.
+pget_status enqueue_forked(std::vector<Group>& groups, hipStream_t origin, size_t stream_base)
+{
+    if (groups.size() == 1) {
+        enqueue_group(groups[0], origin);
+        return PGET_OK;
+    }
+    hipEvent_t fork = g_pool.event(0);
+    if (!fork) return PGET_ERR_HIP;
+    HIP_TRY(hipEventRecord(fork, origin));
+    for (size_t k = 0; k < groups.size(); ++k) {
+        hipStream_t sk = g_pool.get(stream_base + k);
+        if (!sk) return PGET_ERR_HIP;
+        HIP_TRY(hipStreamWaitEvent(sk, fork, 0));
+        enqueue_group(groups[k], sk);
+        hipEvent_t done = g_pool.event(1 + k);
+        if (!done) return PGET_ERR_HIP;
+        HIP_TRY(hipEventRecord(done, sk));
+        HIP_TRY(hipStreamWaitEvent(origin, done, 0));
+    }
+    return PGET_OK;
+}
+
+pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* hook_user, void* ws,
+                         hipStream_t stream)
+{
+    // uploads went through host vectors owned by `groups`; wait for them
     HIP_TRY(hipStreamSynchronize(stream));
-    auto enqueue_all = [&](Solve& SS) {
-        hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, SS.stream, SS.V.st, SS.V.prm, B);
-        fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * sizeof(float2), SS.stream);
-        for (int k = 0; k < max_outer; ++k) {
-            enqueue_iteration(SS, k, n_cg, need_beta0, false);
-            enqueue_commit(SS);
-        }
-        hipLaunchKernelGGL(k_final_reg, dim3(SS.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, SS.stream, SS.V);
-        hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, SS.stream, SS.V);
-    };
     const bool graph_ok = g_use_graphs && !hook && g_timing.classes == 0;
-    if (!graph_ok) {
-        if (!hook) {
-            enqueue_all(S);
-        } else {
-            hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
-            fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * sizeof(float2), stream);
-            for (int k = 0; k < max_outer; ++k) {
-                enqueue_iteration(S, k, n_cg, need_beta0, true);
-                pget_status rc = run_hook(S, hook, hook_user);
-                if (rc != PGET_OK) return rc;
-                enqueue_commit(S);
-            }
-            hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, stream, S.V);
-            hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, stream, S.V);
+    if (hook) {
+        Group& G = groups[0];
+        Solve& S = G.S;
+        const int B = S.B;
+        hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
+        fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * sizeof(float2), stream);
+        for (int k = 0; k < G.max_outer; ++k) {
+            enqueue_iteration(S, k, G.n_cg, G.need_beta0, true);
+            pget_status rc = run_hook(S, hook, hook_user);
+            if (rc != PGET_OK) return rc;
+            enqueue_commit(S);
         }
+        hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, stream, S.V);
+        hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, stream, S.V);
+    } else if (!graph_ok) {
+        pget_status rc = enqueue_forked(groups, stream, 1);
+        if (rc != PGET_OK) return rc;
     } else {
-        pget_plan* PM = const_cast<pget_plan*>(P);
+        GraphKey key;
+        key.ws = ws;
+        for (auto& G : groups)
+            key.groups.push_back({(long long)(intptr_t)G.S.P, G.S.B, G.max_outer, G.n_cg, (long long)G.need_beta0,
+                                  (long long)((char*)G.S.ws - (char*)ws)});
         hipGraphExec_t exec = nullptr;
-        for (auto& e : PM->graphs)
-            if (e.ws == ws && e.batch == B && e.max_outer == max_outer && e.n_cg == n_cg &&
-                e.need_beta0 == (int)need_beta0)
-                exec = e.exec;
+        for (auto& e : g_graphs)
+            if (e.key == key) exec = e.exec;
         if (!exec) {
-            if (!PM->capture_stream)
-                HIP_TRY(hipStreamCreateWithFlags(&PM->capture_stream, hipStreamNonBlocking));
-            Solve C = S;
-            C.stream = PM->capture_stream;
+            hipStream_t cs = g_pool.get(0);
+            if (!cs) return PGET_ERR_HIP;
             hipGraph_t graph = nullptr;
-            HIP_TRY(hipStreamBeginCapture(C.stream, hipStreamCaptureModeThreadLocal));
-            enqueue_all(C);
-            HIP_TRY(hipStreamEndCapture(C.stream, &graph));
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            pget_status rc = enqueue_forked(groups, cs, 1);
+            hipError_t ee = hipStreamEndCapture(cs, &graph);
+            if (rc != PGET_OK) return rc;
+            if (ee != hipSuccess) return PGET_ERR_HIP;
             hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return PGET_ERR_HIP;
-            PM->graphs.push_back(pget_plan::GraphEntry{ws, B, max_outer, n_cg, (int)need_beta0, exec});
+            g_graphs.push_back(GraphEntry{key, exec});
         }
         HIP_TRY(hipGraphLaunch(exec, stream));
     }
-    for (int b = 0; b < B; ++b) {
-        HIP_TRY(hipMemcpyAsync(f[b], S.V.u + b * 2 * n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(mu[b], S.V.u + b * 2 * n2 + n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
-        if (reports) copy_report(rep[b], &reports[b], max_outer, n_cg, stream);
+    for (auto& G : groups) {
+        const Geo& g = G.S.P->g;
+        const size_t n2 = (size_t)g.n * g.n;
+        for (int b = 0; b < G.S.B; ++b) {
+            HIP_TRY(hipMemcpyAsync(G.f[b], G.S.V.u + b * 2 * n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+            HIP_TRY(hipMemcpyAsync(G.mu[b], G.S.V.u + b * 2 * n2 + n2, n2 * sizeof(float),
+                                   hipMemcpyDeviceToDevice, stream));
+            if (G.reports[b]) copy_report(G.rep[b], G.reports[b], G.max_outer, G.n_cg, stream);
+        }
     }
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* const* f,
+                       float* const* mu, const pget_lm_params* params, const pget_lm_report* reports,
+                       pget_refine_fn hook, void* hook_user, void* ws, hipStream_t stream)
+{
+    if (!P || B < 1 || !y || !f || !mu || !params) return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    if (hook && B != 1) return PGET_ERR_INVALID_ARG;
+    std::vector<Group> groups(1);
+    Group& G = groups[0];
+    for (int b = 0; b < B; ++b) {
+        if (!params_ok(&params[b])) return PGET_ERR_INVALID_ARG;
+        G.prm.push_back(to_dev(params[b]));
+        G.y.push_back(y[b]);
+        G.f.push_back(f[b]);
+        G.mu.push_back(mu[b]);
+        G.reports.push_back(reports ? &reports[b] : nullptr);
+    }
+    pget_status rc = group_prepare(G, P, B, ws, stream);
+    if (rc != PGET_OK) return rc;
+    return solve_groups(groups, hook, hook_user, ws, stream);
+}
+
+pget_status solve_multi(int n, const pget_plan* const* plans, const float* const* y, float* const* f,
+                        float* const* mu, const pget_lm_params* params, const pget_lm_report* reports,
+                        void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 1 || !plans || !y || !f || !mu || !params) return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    // groups by plan, in order of first appearance
+    std::vector<const pget_plan*> order;
+    std::vector<std::vector<int>> members;
+    for (int s = 0; s < n; ++s) {
+        if (!plans[s] || !params_ok(&params[s])) return PGET_ERR_INVALID_ARG;
+        size_t k = 0;
+        while (k < order.size() && order[k] != plans[s]) ++k;
+        if (k == order.size()) {
+            order.push_back(plans[s]);
+            members.emplace_back();
+        }
+        members[k].push_back(s);
+    }
+    std::vector<Group> groups(order.size());
+    size_t off = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        const int B = (int)members[k].size();
+        const size_t bytes = group_bytes(order[k], B);
+        if (off + bytes > ws_bytes) return PGET_ERR_WORKSPACE;
+        Group& G = groups[k];
+        for (int s : members[k]) {
+            G.prm.push_back(to_dev(params[s]));
+            G.y.push_back(y[s]);
+            G.f.push_back(f[s]);
+            G.mu.push_back(mu[s]);
+            G.reports.push_back(reports ? &reports[s] : nullptr);
+        }
+        pget_status rc = group_prepare(G, order[k], B, at(ws, off), stream);
+        if (rc != PGET_OK) return rc;
+        off += bytes;
+    }
+    return solve_groups(groups, nullptr, nullptr, ws, stream);
 }
 
 }  // namespace
@@ -1039,6 +1211,130 @@ pget_status pget_lm_solve(const pget_plan* plan, const float* y, float* f_inout,
     float* fs[1] = {f_inout};
     float* ms[1] = {mu_inout};
     return solve_impl(plan, 1, ys, fs, ms, params, report, hook, hook_user, ws, stream);
+}
+
+pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!P || batch < 1) return PGET_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < group_bytes(P, batch)) return PGET_ERR_WORKSPACE;
+    // captured solver sequences of this plan used the old shapes
+    for (size_t k = 0; k < g_graphs.size();) {
+        bool uses = false;
+        for (auto& gk : g_graphs[k].key.groups) uses |= gk[0] == (long long)(intptr_t)P;
+        if (uses) {
+            (void)hipGraphExecDestroy(g_graphs[k].exec);
+            g_graphs.erase(g_graphs.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+    // drop an earlier choice for this batch so that the candidates below rule
+    for (size_t k = 0; k < P->tuned.size(); ++k)
+        if (P->tuned[k][0] == batch) {
+            P->tuned.erase(P->tuned.begin() + k);
+            break;
+        }
+    fill_zero(ws, group_bytes(P, batch), stream);
+    const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_it = [&](auto&& launch) -> float {
+        launch();   // warm
+        float best = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            (void)hipEventRecord(e0, stream);
+            launch();
+            (void)hipEventRecord(e1, stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    int best_japb = 1, best_groups = 1;
+    float best_j = 1e30f, best_v = 1e30f;
+    // candidates share one workspace layout: the layout only depends on the
+    // largest group count, so size the search within what the workspace holds
+    Solve S;
+    S.P = P;
+    S.B = batch;
+    S.sh = shapes_for(P, batch);
+    S.L = layout_for(P, PGET_OP_LM, batch, S.sh, 256, 256);
+    S.ws = ws;
+    S.stream = stream;
+    setup(S);
+    for (int japb = 1; japb <= P->max_japb; japb *= 2) {
+        Shapes sh = S.sh;
+        sh.japb = japb;
+        sh.n_jvp_blocks = (slots + japb - 1) / japb;
+        sh.jvp_threads = std::min(16, japb * P->g.n_groups) * WAVE;
+        sh.jvp_lds = P->img_lds + 2 * (size_t)japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+        JvpArgs J = S.jcg;
+        J.src = planar_src(S.V.u, S.V.u + (size_t)P->g.n * P->g.n, 2LL * P->g.n * P->g.n);
+        J.st = nullptr;
+        J.angles_per_block = japb;
+        const float t = time_it([&] {
+            if (!P->lds_img) pack(P, J.src, nullptr, S.gimg, batch, nullptr, stream);
+            jvp<JVP_NORMAL>(P, J, sh, batch, stream);
+        });
+        if (t < best_j) { best_j = t; best_japb = japb; }
+    }
+    // the adjoint's partial images live in a buffer sized for S.sh.groups
+    for (int grp = 1; grp <= S.sh.groups; grp *= 2) {
+        VjpArgs V = S.vcg;
+        V.st = nullptr;
+        V.groups = grp;
+        const int blocks = P->tiles_x * P->tiles_x * grp;
+        const float t = time_it([&] {
+            hipLaunchKernelGGL(k_vjp_lin, dim3(blocks, batch), dim3(VJP_THREADS), 0, stream, V);
+        });
+        if (t < best_v) { best_v = t; best_groups = grp; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->tuned.push_back({batch, best_japb, best_groups});
+    return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+int32_t pget_tuned_shape(const pget_plan* P, int32_t batch, int32_t* japb, int32_t* vjp_groups)
+{
+    if (!P || batch < 1) return 0;
+    Shapes sh = shapes_for(P, batch);
+    if (japb) *japb = sh.japb;
+    if (vjp_groups) *vjp_groups = sh.groups;
+    for (const auto& t : P->tuned)
+        if (t[0] == batch) return 1;
+    return 0;
+}
+
+size_t pget_workspace_bytes_multi(int32_t n_slices, const pget_plan* const* plans)
+{
+    if (n_slices < 1 || !plans) return 0;
+    std::vector<const pget_plan*> order;
+    std::vector<int> counts;
+    for (int s = 0; s < n_slices; ++s) {
+        if (!plans[s]) return 0;
+        size_t k = 0;
+        while (k < order.size() && order[k] != plans[s]) ++k;
+        if (k == order.size()) {
+            order.push_back(plans[s]);
+            counts.push_back(0);
+        }
+        ++counts[k];
+    }
+    size_t total = 0;
+    for (size_t k = 0; k < order.size(); ++k) total += group_bytes(order[k], counts[k]);
+    return total;
+}
+
+pget_status pget_lm_solve_multi(int32_t n_slices, const pget_plan* const* plans, const float* const* y,
+                                float* const* f_inout, float* const* mu_inout,
+                                const pget_lm_params* params, const pget_lm_report* reports, void* ws,
+                                size_t ws_bytes, hipStream_t stream)
+{
+    return solve_multi(n_slices, plans, y, f_inout, mu_inout, params, reports, ws, ws_bytes, stream);
 }
 
 pget_status pget_lm_solve_batched(const pget_plan* plan, int32_t n_slices, const float* const* y,

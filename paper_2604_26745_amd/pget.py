@@ -96,6 +96,15 @@ def load_library():
     lib.pget_timing_enable.restype = ctypes.c_int
     lib.pget_timing_read.argtypes = [ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.pget_timing_read.restype = ctypes.c_int
+    lib.pget_autotune.argtypes = [V, ctypes.c_int32, V, ctypes.c_size_t, V]
+    lib.pget_autotune.restype = ctypes.c_int
+    lib.pget_tuned_shape.argtypes = [V, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.pget_tuned_shape.restype = ctypes.c_int32
+    lib.pget_workspace_bytes_multi.argtypes = [ctypes.c_int32, P(V)]
+    lib.pget_workspace_bytes_multi.restype = ctypes.c_size_t
+    lib.pget_lm_solve_multi.argtypes = [ctypes.c_int32, P(V), P(V), P(V), P(V), P(LMParams),
+                                        P(LMReportC), V, ctypes.c_size_t, V]
+    lib.pget_lm_solve_multi.restype = ctypes.c_int
     lib.pget_set_graphs.argtypes = [ctypes.c_int32]
     lib.pget_set_graphs.restype = ctypes.c_int
     lib.pget_workspace_bytes.argtypes = [V, ctypes.c_int32, ctypes.c_int32]
@@ -348,6 +357,18 @@ class Plan:
             torch.cuda.current_stream().synchronize()
         return f, mu, rb
 
+    def autotune(self, batch: int = 1):
+        """Pick the fastest launch shapes for solves of `batch` slices."""
+        ws = self.workspace(OP_LM, batch)
+        _check(self.lib.pget_autotune(self.handle, batch, _ptr(ws), ws.numel(), _stream()),
+               "pget_autotune")
+        return self.tuned_shape(batch)
+
+    def tuned_shape(self, batch: int = 1):
+        ja, vg = ctypes.c_int32(), ctypes.c_int32()
+        tuned = self.lib.pget_tuned_shape(self.handle, batch, ctypes.byref(ja), ctypes.byref(vg))
+        return {"jvp_angle_slots": ja.value, "vjp_angle_groups": vg.value, "tuned": bool(tuned)}
+
     def lm_solve_batched(self, ys, f0s, mu0s, params: Sequence[SolverParams], sync: bool = True):
         torch = _torch()
         B = len(ys)
@@ -372,6 +393,47 @@ class Plan:
         if sync:
             torch.cuda.current_stream().synchronize()
         return fs, ms, rbs
+
+
+_multi_ws = {}
+
+
+def lm_solve_multi(plans: Sequence["Plan"], ys, f0s, mu0s, params: Sequence[SolverParams],
+                   sync: bool = True):
+    """Slices of mixed shapes: slice s uses plans[s]; slices sharing a plan are
+    batched and the groups run concurrently (pget_lm_solve_multi)."""
+    torch = _torch()
+    lib = load_library()
+    n = len(plans)
+    arr = ctypes.c_void_p * n
+    handles = arr(*[p.handle.value for p in plans])
+    ys = [p._sino(t) for p, t in zip(plans, ys)]
+    fs = [p._img(t).clone() for p, t in zip(plans, f0s)]
+    ms = [p._img(t).clone() for p, t in zip(plans, mu0s)]
+    cp = (LMParams * n)()
+    keeps = []
+    for i, p in enumerate(params):
+        c, k = p.to_c()
+        cp[i] = c
+        keeps.append(k)
+    rbs = [_ReportBuffers(p.max_outer, p.n_cg, fs[0].device) for p in params]
+    reps = (LMReportC * n)(*[r.c() for r in rbs])
+    nbytes = lib.pget_workspace_bytes_multi(n, handles)
+    if nbytes == 0:
+        raise PgetError(-1, "pget_workspace_bytes_multi")
+    key = tuple(p.handle.value for p in plans)
+    ws = _multi_ws.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        _multi_ws[key] = ws
+    _check(lib.pget_lm_solve_multi(
+        n, handles, arr(*[t.data_ptr() for t in ys]), arr(*[t.data_ptr() for t in fs]),
+        arr(*[t.data_ptr() for t in ms]), cp, reps, _ptr(ws), ws.numel(), _stream()),
+        "pget_lm_solve_multi")
+    del keeps
+    if sync:
+        torch.cuda.current_stream().synchronize()
+    return fs, ms, rbs
 
 
 def _wrap_device(ptr, shape):

@@ -222,3 +222,41 @@ def test_graph_replay_matches_eager_launches():
     finally:
         pget.set_graphs(True)
     assert torch.equal(f2, f3) and torch.equal(m2, m3)
+
+
+def test_mixed_sizes_match_alone():
+    """Slices of three shapes solved together: each result equals the same
+    slice solved alone within the FP32 tolerance (the adjoint's angle grouping
+    may differ between the two launch shapes)."""
+    cfgs = [inputs.scaled(SMALL, n=24, n_angles=36, n_bins=36),
+            inputs.scaled(SMALL, n=32, n_angles=40, n_bins=48, pitch=8.0, can_half=13.0),
+            inputs.scaled(SMALL, n=20, n_angles=30, n_bins=30, pitch=5.0, can_half=8.0)]
+    order = [0, 1, 0, 2, 1]
+    plans = {i: pget.Plan(c.n, c.n_angles, c.n_bins) for i, c in enumerate(cfgs)}
+    prm = pget.SolverParams(max_outer=4, n_cg=6)
+    ys, f0s, m0s, pl = [], [], [], []
+    for s, ci in enumerate(order):
+        og, y, f0, mu0, _, _ = problem(cfgs[ci], seed=s)
+        ys.append(T(y)); f0s.append(T(f0)); m0s.append(T(mu0)); pl.append(plans[ci])
+    for graphs in (True, False):
+        pget.set_graphs(graphs)
+        try:
+            fs, ms, rbs = pget.lm_solve_multi(pl, ys, f0s, m0s, [prm] * len(order))
+        finally:
+            pget.set_graphs(True)
+        for s in range(len(order)):
+            fa, ma, ra = pl[s].lm_solve(ys[s], f0s[s], m0s[s], prm)
+            assert rel(H(fs[s]), H(fa)) <= 1e-5 and rel(H(ms[s]), H(ma)) <= 1e-5
+            pa, pm = ra.to_report().phi, rbs[s].to_report().phi
+            assert all(abs(a - b) <= 1e-6 * abs(a) for a, b in zip(pa, pm))
+
+
+def test_autotune_keeps_results():
+    og, y, f0, mu0, _, _ = problem(SMALL)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    prm = pget.SolverParams(max_outer=3, n_cg=5)
+    f1, m1, _ = plan.lm_solve(T(y), T(f0), T(mu0), prm)
+    shape = plan.autotune(1)
+    assert shape["tuned"] and shape["jvp_angle_slots"] >= 1 and shape["vjp_angle_groups"] >= 1
+    f2, m2, _ = plan.lm_solve(T(y), T(f0), T(mu0), prm)
+    assert rel(H(f2), H(f1)) <= 1e-5 and rel(H(m2), H(m1)) <= 1e-5
