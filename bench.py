@@ -48,9 +48,16 @@ def parse():
     ap.add_argument("--no-single", action="store_true", help="skip the single-slice latency run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0, help="0: min(16, cpu count)")
-    ap.add_argument("--workload", default="main", choices=["main", "mixed"],
+    ap.add_argument("--workload", default="main", choices=["main", "mixed", "serve"],
                     help="main: batch of 128^2 slices (the headline metric); mixed: 64 slices of "
-                         "mixed sizes {64..256}^2 solved together vs one at a time")
+                         "mixed sizes {64..256}^2 solved together vs one at a time; serve: "
+                         "open-loop Poisson requests of mixed sizes through the continuous-batching "
+                         "server vs the plain per-slice solver")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=5.0, help="serve: seconds of arrivals")
+    ap.add_argument("--pool", type=int, default=64, help="serve: distinct request payloads")
+    ap.add_argument("--streams", type=int, default=4, help="serve: concurrent solves")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: in-flight workspace cap")
     ap.add_argument("--autotune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (scale for HBM counters)")
@@ -218,6 +225,43 @@ def run_mixed(args, torch, np, inputs, pget):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args, torch, pget):
+    """Continuous batching of mixed-size requests (Poisson arrivals, early exit
+    at tolerance 1e-4) against the plain per-slice solver on the same trace."""
+    from paper_2604_26745_amd import serve
+    plans, pool = serve.make_pool(args.pool, args.outer, args.cg)
+    prm = pget.SolverParams(max_outer=args.outer, n_cg=args.cg, tol=1e-4)
+    ex = serve.GpuExecutor(plans, pool, prm, n_slots=args.streams)
+    srv = serve.Server(ex, hbm_budget=args.hbm_budget_gb * 1e9, n_slots=args.streams)
+    print("bench: serve warm-up (graph capture per size and batch)", file=sys.stderr, flush=True)
+    srv.warm()
+    reqs = serve.make_trace(args.rate, args.duration, pool, seed=0)
+    print("bench: serving %d requests at %.0f/s" % (len(reqs), args.rate), file=sys.stderr, flush=True)
+    st = serve.run_trace(srv, reqs)
+    print("bench: served %s" % st, file=sys.stderr, flush=True)
+    reqs2 = serve.make_trace(args.rate, args.duration, pool, seed=0)
+    pl = serve.run_plain(plans, pool, prm, reqs2)
+    print("bench: plain %s" % pl, file=sys.stderr, flush=True)
+    out = {
+        "metric": "serving: LM reconstructions/s with p50/p99 latency, mixed sizes {64..256}^2",
+        "value": round(st["recon_per_s"], 4), "unit": "reconstructions/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * st["makespan_s"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serve_poisson_%g_per_s_%gs" % (args.rate, args.duration),
+                   "requests": len(reqs), "pool": args.pool, "streams": args.streams,
+                   "hbm_budget_gb": args.hbm_budget_gb, "tol": 1e-4, "outer": args.outer,
+                   "cg": args.cg},
+        "latency_ms": {"p50": round(st["p50_ms"], 2), "p99": round(st["p99_ms"], 2),
+                       "mean": round(st["mean_ms"], 2)},
+        "mean_batch": round(st["mean_batch"], 3),
+        "peak_in_flight_gb": round(st["peak_in_flight_gb"], 3),
+        "plain_per_slice": {"recon_per_s": round(pl["recon_per_s"], 4),
+                            "p50_ms": round(pl["p50_ms"], 2), "p99_ms": round(pl["p99_ms"], 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -236,6 +280,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "mixed":
         run_mixed(args, torch, np, inputs, pget)
+        return
+    if args.workload == "serve":
+        run_serve(args, torch, pget)
         return
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

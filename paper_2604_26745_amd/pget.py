@@ -369,7 +369,12 @@ class Plan:
         tuned = self.lib.pget_tuned_shape(self.handle, batch, ctypes.byref(ja), ctypes.byref(vg))
         return {"jvp_angle_slots": ja.value, "vjp_angle_groups": vg.value, "tuned": bool(tuned)}
 
-    def lm_solve_batched(self, ys, f0s, mu0s, params: Sequence[SolverParams], sync: bool = True):
+    def lm_solve_batched(self, ys, f0s, mu0s, params: Sequence[SolverParams], sync: bool = True,
+                         ws=None):
+        """Solve a batch of slices of this shape.  ``ws`` is an optional
+        caller-owned workspace (uint8 CUDA tensor of at least
+        ``workspace_bytes(OP_LM, len(ys))`` bytes); concurrent solves on
+        different streams need distinct workspaces."""
         torch = _torch()
         B = len(ys)
         ys = [self._sino(t) for t in ys]
@@ -384,7 +389,10 @@ class Plan:
             keeps.append(k)
         rbs = [_ReportBuffers(params[0].max_outer, params[0].n_cg, fs[0].device) for _ in range(B)]
         reps = (LMReportC * B)(*[r.c() for r in rbs])
-        ws = self.workspace(OP_LM, B)
+        if ws is None:
+            ws = self.workspace(OP_LM, B)
+        elif ws.numel() < self.workspace_bytes(OP_LM, B):
+            raise PgetError(-3, "lm_solve_batched")
         _check(self.lib.pget_lm_solve_batched(
             self.handle, B, arr(*[t.data_ptr() for t in ys]), arr(*[t.data_ptr() for t in fs]),
             arr(*[t.data_ptr() for t in ms]), cp, reps, _ptr(ws), _stream()),

@@ -260,3 +260,39 @@ def test_autotune_keeps_results():
     assert shape["tuned"] and shape["jvp_angle_slots"] >= 1 and shape["vjp_angle_groups"] >= 1
     f2, m2, _ = plan.lm_solve(T(y), T(f0), T(mu0), prm)
     assert rel(H(f2), H(f1)) <= 1e-5 and rel(H(m2), H(m1)) <= 1e-5
+
+
+def test_serving_results_equal_alone():
+    """Requests served by the continuous-batching loop (batched with others of
+    their size, several solves in flight on different streams) give the result
+    of the same slice solved alone, within the FP32 tolerance."""
+    from paper_2604_26745_amd import serve
+    cfgs = {24: inputs.scaled(SMALL, n=24, n_angles=36, n_bins=36),
+            32: inputs.scaled(SMALL, n=32, n_angles=40, n_bins=48, pitch=8.0, can_half=13.0)}
+    plans = {n: pget.Plan(c.n, c.n_angles, c.n_bins) for n, c in cfgs.items()}
+    pool = []
+    for k in range(6):
+        c = cfgs[24 if k % 2 else 32]
+        og, y, f0, mu0, _, _ = problem(c, seed=k)
+        pool.append(serve.Slice(c, T(y), T(f0), T(mu0)))
+    prm = pget.SolverParams(max_outer=4, n_cg=6, tol=1e-4)
+    ex = serve.GpuExecutor(plans, pool, prm, n_slots=2)
+    srv = serve.Server(ex, hbm_budget=1e12, n_slots=2, max_batch=4)
+    reqs = [serve.Request(k, 0.0005 * k, pool[k % 6].cfg.n, k % 6) for k in range(12)]
+    outputs = {}
+    orig_launch = ex.launch
+
+    def launch(size, rs, slot):
+        h = orig_launch(size, rs, slot)
+        for i, r in enumerate(rs):
+            outputs[r.rid] = (h[1][0][i], h[1][1][i])
+        return h
+
+    ex.launch = launch
+    st = serve.run_trace(srv, reqs, timeout=120)
+    assert st["requests"] == 12 and max(srv.batches) > 1
+    for r in reqs:
+        sl = pool[r.slot]
+        fa, ma, _ = plans[r.size].lm_solve(sl.y, sl.f0, sl.mu0, prm)
+        f, m = outputs[r.rid]
+        assert rel(H(f), H(fa)) <= 1e-5 and rel(H(m), H(ma)) <= 1e-5

@@ -1,0 +1,114 @@
+"""The serving loop's admission, batching and budget logic, driven by a fake
+executor on the CPU (no GPU, deterministic simulated durations)."""
+import math
+
+import pytest
+
+from paper_2604_26745_amd import serve
+
+
+class FakeExecutor:
+    """Each launch finishes after `cost[size] * batch` simulated seconds."""
+
+    def __init__(self, cost, bytes_per_slice):
+        self.cost, self.bps = cost, bytes_per_slice
+        self.now = 0.0
+        self.launches = []
+
+    def workspace_bytes(self, size, b):
+        return self.bps[size] * b
+
+    def launch(self, size, reqs, slot):
+        end = self.now + self.cost[size] * len(reqs)
+        self.launches.append((self.now, size, [r.rid for r in reqs], slot))
+        return end
+
+    def done(self, handle):
+        return self.now >= handle
+
+    def warm(self, batch_sizes):
+        pass
+
+
+def drive(server, ex, reqs, dt=1e-3, horizon=100.0):
+    i, done, n = 0, 0, len(reqs)
+    t = 0.0
+    while done < n:
+        assert t < horizon
+        ex.now = t
+        while i < n and reqs[i].arrival <= t:
+            server.queue.append(reqs[i])
+            i += 1
+        done += server.poll(t)
+        server.admit(t)
+        t += dt
+    return t
+
+
+def R(k, t, size):
+    return serve.Request(k, t, size, 0)
+
+
+def test_same_size_requests_are_batched_in_arrival_order():
+    ex = FakeExecutor({64: 0.01, 128: 0.04}, {64: 1, 128: 4})
+    srv = serve.Server(ex, hbm_budget=1e9, n_slots=1, max_batch=8)
+    # a long request occupies the only slot while 6 more queue up
+    reqs = [R(0, 0.0, 128)] + [R(k, 0.001 * k, 64 if k % 2 else 128) for k in range(1, 7)]
+    drive(srv, ex, reqs)
+    batches = [(l[1], l[2]) for l in ex.launches]
+    # the oldest queued request decides the size of the next batch, which
+    # takes the largest power-of-two count of queued requests of that size in
+    # arrival order
+    assert batches == [(128, [0]), (64, [1, 3]), (128, [2, 4]), (64, [5]), (128, [6])]
+    assert all(not math.isnan(r.done) for r in reqs)
+
+
+def test_budget_limits_in_flight_bytes():
+    ex = FakeExecutor({64: 0.05}, {64: 10})
+    srv = serve.Server(ex, hbm_budget=25, n_slots=8, max_batch=1)
+    reqs = [R(k, 0.0, 64) for k in range(6)]
+    drive(srv, ex, reqs)
+    assert srv.max_in_flight_bytes <= 25
+    # two at a time fit the budget: three waves
+    starts = sorted(set(round(l[0], 3) for l in ex.launches))
+    assert len(starts) == 3
+
+
+def test_oversized_batch_admitted_when_idle():
+    ex = FakeExecutor({256: 0.01}, {256: 100})
+    srv = serve.Server(ex, hbm_budget=50, n_slots=2, max_batch=2)
+    reqs = [R(0, 0.0, 256)]
+    drive(srv, ex, reqs)
+    assert len(ex.launches) == 1 and srv.max_in_flight_bytes == 100
+
+
+def test_slots_refill_as_work_completes():
+    ex = FakeExecutor({64: 0.02}, {64: 1})
+    srv = serve.Server(ex, hbm_budget=1e9, n_slots=2, max_batch=1)
+    reqs = [R(k, 0.0, 64) for k in range(5)]
+    drive(srv, ex, reqs)
+    slots_in_use = {}
+    for t0, size, ids, slot in ex.launches:
+        slots_in_use.setdefault(round(t0, 3), []).append(slot)
+    # at most 2 concurrent, 3 waves for 5 requests
+    assert all(len(v) <= 2 for v in slots_in_use.values())
+    assert len(slots_in_use) == 3
+
+
+def test_summary_percentiles():
+    reqs = [serve.Request(k, 0.0, 64, 0, admit=0.0, done=0.001 * (k + 1)) for k in range(100)]
+    st = serve.summarize(reqs, 0.1, [1] * 100, 0)
+    assert abs(st["p50_ms"] - 50.5) < 1e-6
+    assert abs(st["p99_ms"] - 99.01) < 1e-6
+    assert abs(st["recon_per_s"] - 1000.0) < 1e-9
+
+
+def test_trace_is_seeded():
+    class P:  # minimal pool entries
+        def __init__(self, n):
+            self.cfg = type("C", (), {"n": n})()
+    pool = [P(64), P(128), P(256)]
+    a = serve.make_trace(50.0, 2.0, pool, seed=3)
+    b = serve.make_trace(50.0, 2.0, pool, seed=3)
+    assert [(r.arrival, r.size) for r in a] == [(r.arrival, r.size) for r in b]
+    assert 60 <= len(a) <= 140
