@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--streams", type=int, default=4, help="serve: concurrent solves")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: in-flight workspace cap")
     ap.add_argument("--autotune", action="store_true", help="autotune launch shapes first")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16"],
+                    help="storage of staged maps and per-sample weights")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (scale for HBM counters)")
     return ap.parse_args()
@@ -163,7 +165,7 @@ def run_mixed(args, torch, np, inputs, pget):
     plans = {}
     for c in cfgs:
         if c.n not in plans:
-            plans[c.n] = pget.Plan(c.n, c.n_angles, c.n_bins, psf_sigma=c.psf_sigma)
+            plans[c.n] = pget.Plan(c.n, c.n_angles, c.n_bins, psf_sigma=c.psf_sigma, storage=args.storage)
     ys, f0s, m0s, pl = [], [], [], []
     ones = {}
     for s, c in enumerate(cfgs):
@@ -291,8 +293,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     cfg = inputs.scaled(inputs.MAIN_128, max_outer=args.outer, n_cg=args.cg)
-    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, storage=args.storage)
     B = args.batch
+    if args.autotune:
+        print("bench: autotune %s" % plan.autotune(B), file=sys.stderr, flush=True)
     ys, f0s, m0s = make_inputs(plan, cfg, B, torch, inputs, np)
     prm = [pget.SolverParams(max_outer=cfg.max_outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha,
                              alpha_mu=cfg.alpha) for _ in range(B)]
@@ -374,7 +378,7 @@ def main():
         cpu = cpu_baseline(cfg, workers)
 
     out = {
-        "metric": "LM reconstructions/s at 128^2 x 360 angles (FP32)",
+        "metric": "LM reconstructions/s at 128^2 x 360 angles (%s)" % args.storage.upper(),
         "value": round(value, 4),
         "unit": "reconstructions/s",
         "n_gpus": 1,
@@ -384,10 +388,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.storage == "fp32" else "bf16-storage/f32-compute",
         "data": "synthetic",
         "config": {
             "workload": workload,
+            "storage": args.storage,
             "slices_per_step": B,
             "grid": cfg.n, "angles": cfg.n_angles, "bins": cfg.n_bins, "psf_sigma": cfg.psf_sigma,
             "outer": cfg.max_outer, "cg": cfg.n_cg, "alpha": cfg.alpha,

@@ -45,8 +45,19 @@ typedef enum {
     PGET_ERR_UNSUPPORTED = -5  /* geometry outside what the kernels handle   */
 } pget_status;
 
-/* Storage type of maps and sinograms handed to the library. */
-typedef enum { PGET_FP32 = 0 } pget_storage;
+/*
+ * Storage of the Jacobian's two large internal streams: the per-sample
+ * weights written by the linearisation and the map pair (search direction)
+ * staged for J v.  PGET_FP32 keeps them in binary32; PGET_BF16 rounds them
+ * to bfloat16 (round to nearest even), halving their memory traffic and the
+ * LDS footprint of J v.  The ray march that gives the forward map, the
+ * residual and the objective always reads the maps in FP32, so with
+ * PGET_BF16 the solver runs an inexact-Jacobian LM (gradient, CG operator and
+ * predicted decrease carry the rounding) whose gain ratio still uses the
+ * exact objective.  Every sum is accumulated in FP32 and every reduction of
+ * the solver in FP64 either way; maps and sinograms at the API are FP32.
+ */
+typedef enum { PGET_FP32 = 0, PGET_BF16 = 1 } pget_storage;
 
 /*
  * Parallel-beam geometry of one slice (Sec. 2.1, eq. fwd_model and its

@@ -209,12 +209,15 @@ def lm_solve(
     p: LMParams,
     hook: Optional[HookFn] = None,
     replay: Optional[List[int]] = None,
+    on_iterate: Optional[Callable] = None,
 ):
     """Run the LM iteration; returns (f, mu, LMReport).
 
     ``replay`` forces the accept decision of each outer iteration (1 accept,
     0 reject) instead of the test rho > eta; everything else is unchanged.
     ``hook(f, mu, s_f, s_mu) -> (f~, mu~)`` is the learned refinement.
+    ``on_iterate(k, f, mu)`` (reporting only) sees the iterate after outer
+    iteration k.
     """
     f = np.array(f0, dtype=np.float64)
     mu = np.array(mu0, dtype=np.float64)
@@ -257,10 +260,14 @@ def lm_solve(
             rep.hook_accepted.append(hook_ok)
             if p.tol > 0.0 and (it.ared <= p.tol * it.phi or snorm <= p.tol * unorm):
                 rep.stop_reason = "tol"
+                if on_iterate is not None:
+                    on_iterate(k, f, mu)
                 break
         else:
             beta, nu = nielsen_update(beta, nu, False, it.rho)
             rep.hook_accepted.append(0)
+        if on_iterate is not None:
+            on_iterate(k, f, mu)
         if beta > 1e16 * beta_init:
             rep.stop_reason = "beta_overflow"
             break

@@ -20,7 +20,11 @@ struct pget_plan {
     Geo g;
     Tables t;
     void* table_mem;     // one device allocation holding every table
-    bool lds_img;        // the bordered map pair fits in LDS
+    bool bf16;           // BF16 storage of staged maps and per-sample weights
+    size_t px_bytes;     // bytes of one staged map pair (8 FP32, 4 BF16)
+    size_t w_bytes;      // bytes of one per-sample weight pair
+    bool lds_img;        // the FP32 map pair of the ray march fits in LDS
+    bool jvp_lds;        // the map pair of the Jacobian product (storage type) fits in LDS
     size_t op_lds_bytes; // dynamic LDS of k_march
     int op_threads;      // threads per block of k_march
     size_t img_lds;      // LDS bytes of the staged map pair (0 if not staged)
@@ -143,12 +147,12 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
     const size_t sino = (size_t)g.n_angles * g.n_bins;
     const size_t lat = (size_t)g.n_angles * g.n_t * g.n_bins;
     if (op != PGET_OP_FORWARD) {
-        L.wts = take(B * lat * sizeof(float2));
+        L.wts = take(B * lat * P->w_bytes);
         L.tsum = take(B * sino * sizeof(float));
     }
     L.sino_a = take(B * sino * sizeof(float));
     L.sino_b = take(B * sino * sizeof(float));
-    L.gimg = P->lds_img ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
+    L.gimg = (P->lds_img && P->jvp_lds) ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
     L.part = take(B * (size_t)N_SLOTS * SLOT_WIDTH * sizeof(double));
     if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.groups * B * 2 * n2 * sizeof(float));
     if (op == PGET_OP_LM) {
@@ -212,7 +216,12 @@ template <bool LDS, int M>
 void launch_march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStream_t s)
 {
     Timed t(PGET_KC_MARCH, s);
-    hipLaunchKernelGGL((k_march<LDS, M>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes, s, A);
+    if (P->bf16)
+        hipLaunchKernelGGL((k_march<LDS, M, BF16S>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes,
+                           s, A);
+    else
+        hipLaunchKernelGGL((k_march<LDS, M, F32S>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes,
+                           s, A);
 }
 template <int M>
 void march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStream_t s)
@@ -224,24 +233,40 @@ template <bool LDS, int M>
 void launch_jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
     Timed t(PGET_KC_JVP, s);
-    hipLaunchKernelGGL((k_jvp_lin<LDS, M>), dim3(sh.n_jvp_blocks, batch), dim3(sh.jvp_threads), sh.jvp_lds,
-                       s, A);
+    if (P->bf16)
+        hipLaunchKernelGGL((k_jvp_lin<LDS, M, BF16S>), dim3(sh.n_jvp_blocks, batch), dim3(sh.jvp_threads),
+                           sh.jvp_lds, s, A);
+    else
+        hipLaunchKernelGGL((k_jvp_lin<LDS, M, F32S>), dim3(sh.n_jvp_blocks, batch), dim3(sh.jvp_threads),
+                           sh.jvp_lds, s, A);
 }
 template <int M>
 void jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
-    if (P->lds_img) launch_jvp<true, M>(P, A, sh, batch, s);
+    if (P->jvp_lds) launch_jvp<true, M>(P, A, sh, batch, s);
     else launch_jvp<false, M>(P, A, sh, batch, s);
 }
 
-void pack(const pget_plan* P, const PairSrc& src, const double* part, float2* out, int batch,
-          const LMState* st, hipStream_t s)
+void launch_vjp(const pget_plan* P, const VjpArgs& V, int blocks, int batch, hipStream_t s)
+{
+    if (P->bf16) hipLaunchKernelGGL(k_vjp_lin<BF16S>, dim3(blocks, batch), dim3(VJP_THREADS), 0, s, V);
+    else hipLaunchKernelGGL(k_vjp_lin<F32S>, dim3(blocks, batch), dim3(VJP_THREADS), 0, s, V);
+}
+
+// Global bordered copy of a map pair: FP32 for the ray march (jvp_store =
+// false), the plan's storage for the Jacobian product (jvp_store = true).
+void pack(const pget_plan* P, const PairSrc& src, const double* part, void* out, int batch,
+          const LMState* st, hipStream_t s, bool jvp_store = false)
 {
     const int total = P->g.pitch * P->g.pitch;
     const int blocks = std::min(1024, (total + 255) / 256);
     Timed t(PGET_KC_CONTROL, s);
-    hipLaunchKernelGGL(k_pack, dim3(blocks, batch), dim3(256), 0, s, P->g, src, part, out,
-                       (long long)total, st);
+    if (P->bf16 && jvp_store)
+        hipLaunchKernelGGL(k_pack<BF16S>, dim3(blocks, batch), dim3(256), 0, s, P->g, src, part, out,
+                           (long long)total, st);
+    else
+        hipLaunchKernelGGL(k_pack<F32S>, dim3(blocks, batch), dim3(256), 0, s, P->g, src, part, out,
+                           (long long)total, st);
 }
 
 void fill_zero(void* p, size_t bytes, hipStream_t s)
@@ -286,10 +311,13 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     if (!out) return PGET_ERR_INVALID_ARG;
     *out = nullptr;
     if (!geometry_ok(geom)) return PGET_ERR_INVALID_ARG;
-    if (storage != PGET_FP32) return PGET_ERR_UNSUPPORTED;
+    if (storage != PGET_FP32 && storage != PGET_BF16) return PGET_ERR_UNSUPPORTED;
     pget_plan* P = new (std::nothrow) pget_plan();
     if (!P) return PGET_ERR_HIP;
     P->geom = *geom;
+    P->bf16 = storage == PGET_BF16;
+    P->px_bytes = P->bf16 ? 4 : 8;
+    P->w_bytes = P->bf16 ? 4 : 8;
     Geo& g = P->g;
     g.n = geom->n;
     g.n_angles = geom->n_angles;
@@ -382,7 +410,10 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     P->t.taps = reinterpret_cast<const float*>(base + o_taps);
 
     // ---- launch shapes
+    // the ray march stages the FP32 map pair; the Jacobian product stages the
+    // pair in the storage type
     const size_t img_bytes = (size_t)g.pitch * g.pitch * sizeof(float2);
+    const size_t jimg_bytes = (size_t)g.pitch * g.pitch * P->px_bytes;
     const size_t row_bytes = 2 * (size_t)nb * sizeof(float);
     const size_t lds_budget = 160 * 1024 - 2048;   // static shared arrays take the rest
     P->lds_img = img_bytes + row_bytes <= lds_budget;
@@ -393,9 +424,10 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         return PGET_ERR_UNSUPPORTED;
     }
     P->op_threads = std::min(ng, 16) * WAVE;
-    P->img_lds = P->lds_img ? img_bytes : 0;
     {
         const size_t per_slot = 2 * (size_t)(g.paired ? 2 : 1) * nb * sizeof(float);
+        P->jvp_lds = jimg_bytes + per_slot <= lds_budget;
+        P->img_lds = P->jvp_lds ? jimg_bytes : 0;
         P->max_japb = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / per_slot);
         if (P->max_japb < 1) {
             (void)hipFree(P->table_mem);
@@ -407,15 +439,30 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         const int bytes = (int)lds_budget;
         bool attr_ok = true;
         {
-            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_LIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_TRIAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_NORMAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_SQNORM>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_NORMAL>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
-            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_SQNORM>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_FWD, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_LIN, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_TRIAL, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_PLAIN, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_NORMAL, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_SQNORM, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_FWD, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_LIN, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_TRIAL, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_PLAIN, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_NORMAL, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_SQNORM, F32S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_FWD, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_LIN, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_TRIAL, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_PLAIN, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_NORMAL, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_SQNORM, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_FWD, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_LIN, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_TRIAL, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_PLAIN, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_NORMAL, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_SQNORM, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
         }
         if (!attr_ok) {
             (void)hipFree(P->table_mem);
@@ -474,8 +521,8 @@ pget_status pget_forward(const pget_plan* P, const float* f, const float* mu, fl
     A.yout = y;
     A.angles_per_block = sh.apb;
     if (!P->lds_img) {
-        A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
-        pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
+        A.gimg = at(ws, L.gimg);
+        pack(P, A.src, nullptr, at(ws, L.gimg), 1, nullptr, stream);
     }
     march<MARCH_FWD>(P, A, sh.n_op_blocks, 1, stream);
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
@@ -489,7 +536,7 @@ static void linearise(const pget_plan* P, const float* f, const float* mu, float
     A.g = P->g;
     A.t = P->t;
     A.src = planar_src(f, mu, 0);
-    A.wts = reinterpret_cast<float2*>(at(ws, L.wts));
+    A.wts = at(ws, L.wts);
     A.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
     A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
     A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
@@ -497,10 +544,10 @@ static void linearise(const pget_plan* P, const float* f, const float* mu, float
     A.angles_per_block = sh.apb;
     // samples outside the support are never written; the adjoint reads them
     // (with zero interpolation weight), so they must hold finite values
-    fill_zero(A.wts, (size_t)A.wts_stride * sizeof(float2), stream);
+    fill_zero(at(ws, L.wts), (size_t)A.wts_stride * P->w_bytes, stream);
     if (!P->lds_img) {
-        A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
-        pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
+        A.gimg = at(ws, L.gimg);
+        pack(P, A.src, nullptr, at(ws, L.gimg), 1, nullptr, stream);
     }
     march<MARCH_LIN>(P, A, sh.n_op_blocks, 1, stream);
 }
@@ -517,15 +564,15 @@ pget_status pget_jvp(const pget_plan* P, const float* f, const float* mu, const 
     A.g = P->g;
     A.t = P->t;
     A.src = planar_src(vf, vmu, 0);
-    A.wts = reinterpret_cast<float2*>(at(ws, L.wts));
+    A.wts = at(ws, L.wts);
     A.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
     A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
     A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
     A.out = jv;
     A.angles_per_block = sh.apb;
-    if (!P->lds_img) {
-        A.gimg = reinterpret_cast<float2*>(at(ws, L.gimg));
-        pack(P, A.src, nullptr, const_cast<float2*>(A.gimg), 1, nullptr, stream);
+    if (!P->jvp_lds) {
+        A.gimg = at(ws, L.gimg);
+        pack(P, A.src, nullptr, at(ws, L.gimg), 1, nullptr, stream, true);
     }
     A.angles_per_block = sh.japb;
     jvp<JVP_PLAIN>(P, A, sh, 1, stream);
@@ -549,7 +596,7 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     VjpArgs V = {};
     V.g = P->g;
     V.t = P->t;
-    V.wts = reinterpret_cast<float2*>(at(ws, L.wts));
+    V.wts = at(ws, L.wts);
     V.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
     V.wt = wt;
     V.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
@@ -562,7 +609,7 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     V.groups = sh.groups;
     {
         Timed t_(PGET_KC_VJP, stream);
-        hipLaunchKernelGGL(k_vjp_lin, dim3(sh.n_vjp_blocks, 1), dim3(VJP_THREADS), 0, stream, V);
+        launch_vjp(P, V, sh.n_vjp_blocks, 1, stream);
     }
     {
         Timed t_(PGET_KC_VECTOR, stream);
@@ -624,7 +671,7 @@ struct Solve {
     JvpArgs jcg, jpred, jones;
     VjpArgs vgrad, vcg;
     VecArgs V;
-    float2* gimg;
+    void* gimg;
 };
 
 void setup(Solve& S)
@@ -639,12 +686,12 @@ void setup(Solve& S)
     float* u = reinterpret_cast<float*>(at(ws, S.L.u));
     float* ut = reinterpret_cast<float*>(at(ws, S.L.ut));
     LMState* st = reinterpret_cast<LMState*>(at(ws, S.L.state));
-    float2* wts = reinterpret_cast<float2*>(at(ws, S.L.wts));
+    void* wts = at(ws, S.L.wts);
     float* tsum = reinterpret_cast<float*>(at(ws, S.L.tsum));
     float* wt_res = reinterpret_cast<float*>(at(ws, S.L.sino_a));   // K (A(u) - y)
     float* wt_cg = reinterpret_cast<float*>(at(ws, S.L.sino_b));    // K K J p
     const float* ymeas = reinterpret_cast<float*>(at(ws, S.L.ymeas));
-    S.gimg = P->lds_img ? nullptr : reinterpret_cast<float2*>(at(ws, S.L.gimg));
+    S.gimg = (P->lds_img && P->jvp_lds) ? nullptr : at(ws, S.L.gimg);
 
     MarchArgs& M = S.lin;
     M = MarchArgs{};
@@ -761,7 +808,7 @@ void enqueue_march(Solve& S, const MarchArgs& A, int mode)
 
 void enqueue_jvp(Solve& S, const JvpArgs& A, int mode)
 {
-    if (!S.P->lds_img) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream);
+    if (!S.P->jvp_lds) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream, true);
     if (mode == JVP_NORMAL) jvp<JVP_NORMAL>(S.P, A, S.sh, S.B, S.stream);
     else jvp<JVP_SQNORM>(S.P, A, S.sh, S.B, S.stream);
 }
@@ -787,7 +834,7 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
     }
     {
         Timed t_(PGET_KC_GRADIENT, S.stream);
-        hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vgrad);
+        launch_vjp(S.P, S.vgrad, S.sh.n_vjp_blocks, S.B, S.stream);
     }
     VecArgs Vg = S.V;
     Vg.gpart = S.vgrad.gpart;
@@ -803,7 +850,7 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
         enqueue_jvp(S, J, JVP_NORMAL);
         {
             Timed t_(PGET_KC_VJP, S.stream);
-            hipLaunchKernelGGL(k_vjp_lin, dim3(S.sh.n_vjp_blocks, S.B), dim3(VJP_THREADS), 0, S.stream, S.vcg);
+            launch_vjp(S.P, S.vcg, S.sh.n_vjp_blocks, S.B, S.stream);
         }
         VecArgs V = S.V;
         V.cg_step = m;
@@ -1002,7 +1049,7 @@ void enqueue_group(Group& G, hipStream_t s)
     SS.stream = s;
     const int B = SS.B;
     hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, s, SS.V.st, SS.V.prm, B);
-    fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * sizeof(float2), s);
+    fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * SS.P->w_bytes, s);
     for (int k = 0; k < G.max_outer; ++k) {
         enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false);
         enqueue_commit(SS);
@@ -1045,7 +1092,7 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
         Solve& S = G.S;
         const int B = S.B;
         hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
-        fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * sizeof(float2), stream);
+        fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * S.P->w_bytes, stream);
         for (int k = 0; k < G.max_outer; ++k) {
             enqueue_iteration(S, k, G.n_cg, G.need_beta0, true);
             pget_status rc = run_hook(S, hook, hook_user);
@@ -1276,7 +1323,7 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
         J.st = nullptr;
         J.angles_per_block = japb;
         const float t = time_it([&] {
-            if (!P->lds_img) pack(P, J.src, nullptr, S.gimg, batch, nullptr, stream);
+            if (!P->jvp_lds) pack(P, J.src, nullptr, S.gimg, batch, nullptr, stream, true);
             jvp<JVP_NORMAL>(P, J, sh, batch, stream);
         });
         if (t < best_j) { best_j = t; best_japb = japb; }
@@ -1288,7 +1335,7 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
         V.groups = grp;
         const int blocks = P->tiles_x * P->tiles_x * grp;
         const float t = time_it([&] {
-            hipLaunchKernelGGL(k_vjp_lin, dim3(blocks, batch), dim3(VJP_THREADS), 0, stream, V);
+            launch_vjp(P, V, blocks, batch, stream);
         });
         if (t < best_v) { best_v = t; best_groups = grp; }
     }

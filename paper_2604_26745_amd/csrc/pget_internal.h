@@ -137,9 +137,9 @@ struct MarchArgs {
     Geo g;
     Tables t;
     PairSrc src;            // (f, mu)
-    const float2* gimg;     // global bordered image when not staged in LDS
+    const void* gimg;       // global bordered image when not staged in LDS
     long long gimg_stride;
-    float2* wts;            // MARCH_LIN: [n_angles][n_t][n_bins] (step*E, R')
+    void* wts;              // MARCH_LIN: [n_angles][n_t][n_bins] (step*E, R') pairs
     float* tsum;            // MARCH_LIN: [n_angles][n_bins] sum of lambda*E
     long long wts_stride, sino_stride;
     const float* ymeas;     // measured sinogram (residual modes) or null
@@ -155,9 +155,9 @@ struct JvpArgs {
     Geo g;
     Tables t;
     PairSrc src;            // the direction v (or the CG direction p)
-    const float2* gimg;
+    const void* gimg;
     long long gimg_stride;
-    const float2* wts;
+    const void* wts;
     const float* tsum;
     long long wts_stride, sino_stride;
     float* out;             // PLAIN: K z;  NORMAL: K K z
@@ -171,7 +171,7 @@ struct JvpArgs {
 struct VjpArgs {
     Geo g;
     Tables t;
-    const float2* wts;
+    const void* wts;
     const float* tsum;
     const float* wt;        // blurred cotangent per ray [n_angles][n_bins]
     long long wts_stride, sino_stride;
@@ -208,12 +208,18 @@ struct VecArgs {
     int hook_mode;          // k_trial: 1 -> ut holds the hook's proposal (no clamp)
 };
 
-template <bool LDS_IMG, int MODE> __global__ void k_march(MarchArgs A);
-template <bool LDS_IMG, int MODE> __global__ void k_jvp_lin(JvpArgs A);
-__global__ void k_pack(Geo g, PairSrc s, const double* part, float2* out, long long out_stride,
+// Storage of the two large streams (staged map pairs, per-sample weight
+// pairs): FP32 pairs, or BF16 pairs packed in 32 bits.  Arithmetic is FP32
+// either way.
+struct F32S;
+struct BF16S;
+template <bool LDS_IMG, int MODE, typename S> __global__ void k_march(MarchArgs A);
+template <bool LDS_IMG, int MODE, typename S> __global__ void k_jvp_lin(JvpArgs A);
+template <typename S>
+__global__ void k_pack(Geo g, PairSrc s, const double* part, void* out, long long out_stride,
                        const LMState* st);
 __global__ void k_psf(Geo g, const float* taps_g, const float* in, float* out);
-__global__ void k_vjp_lin(VjpArgs A);
+template <typename S> __global__ void k_vjp_lin(VjpArgs A);
 __global__ void k_fill_zero(float4* p, long long n4);
 __global__ void k_sum_groups(int n2, int groups, const float* gpart, long long group_stride, float* gf,
                              float* gm);

@@ -100,18 +100,48 @@ __device__ __forceinline__ const double* slot_ptr(const double* part, int slice,
     return part + ((size_t)slice * N_SLOTS + slot) * SLOT_WIDTH;
 }
 
+// ------------------------------------------------------------ storage
+__device__ __forceinline__ uint32_t bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even on the dropped half
+    return u >> 16;
+}
+
+struct F32S {
+    using px_t = float2;
+    using w_t = float2;
+    static __device__ __forceinline__ float2 px(px_t v) { return v; }
+    static __device__ __forceinline__ px_t to_px(float2 v) { return v; }
+    static __device__ __forceinline__ float2 w(w_t v) { return v; }
+    static __device__ __forceinline__ w_t to_w(float a, float b) { return make_float2(a, b); }
+};
+
+struct BF16S {
+    using px_t = uint32_t;   // low half: first value, high half: second value
+    using w_t = uint32_t;
+    static __device__ __forceinline__ float2 px(px_t v)
+    {
+        return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
+    }
+    static __device__ __forceinline__ px_t to_px(float2 v) { return bf16_rne(v.x) | (bf16_rne(v.y) << 16); }
+    static __device__ __forceinline__ float2 w(w_t v) { return px(v); }
+    static __device__ __forceinline__ w_t to_w(float a, float b) { return bf16_rne(a) | (bf16_rne(b) << 16); }
+};
+
 // Bilinear sample of the zero-bordered interleaved map pair at (col, row)
 // in pixel-index coordinates.  Index clamping keeps FP32 rounding at the
 // support edge inside the bordered array.
-__device__ __forceinline__ float2 bilerp(const float2* __restrict__ img, int pitch, int n, float col,
-                                         float row)
+template <typename S>
+__device__ __forceinline__ float2 bilerp(const typename S::px_t* __restrict__ img, int pitch, int n,
+                                         float col, float row)
 {
     float cf = floorf(col), rf = floorf(row);
     int c0 = min(max((int)cf, -1), n - 1);
     int r0 = min(max((int)rf, -1), n - 1);
     float fc = col - (float)c0, fr = row - (float)r0;
-    const float2* p = img + (r0 + 1) * pitch + (c0 + 1);
-    float2 v00 = p[0], v01 = p[1], v10 = p[pitch], v11 = p[pitch + 1];
+    const typename S::px_t* p = img + (r0 + 1) * pitch + (c0 + 1);
+    const float2 v00 = S::px(p[0]), v01 = S::px(p[1]), v10 = S::px(p[pitch]), v11 = S::px(p[pitch + 1]);
     float tx = fmaf(fc, v01.x - v00.x, v00.x);
     float ty = fmaf(fc, v01.y - v00.y, v00.y);
     float bx = fmaf(fc, v11.x - v10.x, v10.x);
@@ -143,7 +173,9 @@ __device__ __forceinline__ float2 src_value(const PairSrc& s, int slice, int idx
 
 // Stage the zero-bordered pair image ((N+2)^2 float2) into `dst`.  Four
 // pixels per thread per trip so that their loads are in flight together.
-__device__ void stage_image(float2* dst, const PairSrc& s, int slice, int n, int pitch, float beta)
+template <typename S>
+__device__ void stage_image(typename S::px_t* dst, const PairSrc& s, int slice, int n, int pitch,
+                            float beta)
 {
     const int total = pitch * pitch;
     constexpr int U = 4;
@@ -160,13 +192,14 @@ __device__ void stage_image(float2* dst, const PairSrc& s, int slice, int n, int
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int idx = base + u * blockDim.x;
-            if (idx < total) dst[idx] = v[u];
+            if (idx < total) dst[idx] = S::to_px(v[u]);
         }
     }
 }
 
 // Global bordered copy for maps too large for LDS.
-__global__ void __launch_bounds__(256) k_pack(Geo g, PairSrc s, const double* part, float2* out,
+template <typename SP>
+__global__ void __launch_bounds__(256) k_pack(Geo g, PairSrc s, const double* part, void* out_v,
                                               long long out_stride, const LMState* st)
 {
     __shared__ double sh[16];
@@ -174,12 +207,12 @@ __global__ void __launch_bounds__(256) k_pack(Geo g, PairSrc s, const double* pa
     if (st && st[slice].done) return;
     float beta = resolve_beta(s, part, slice, sh);
     const int pitch = g.pitch, total = pitch * pitch;
-    float2* dst = out + (size_t)slice * out_stride;
+    typename SP::px_t* dst = static_cast<typename SP::px_t*>(out_v) + (size_t)slice * out_stride;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
         int rr = idx / pitch - 1, cc = idx - (idx / pitch) * pitch - 1;
         float2 v = make_float2(0.0f, 0.0f);
         if (rr >= 0 && rr < g.n && cc >= 0 && cc < g.n) v = src_value(s, slice, rr * g.n + cc, beta);
-        dst[idx] = v;
+        dst[idx] = SP::to_px(v);
     }
 }
 
@@ -198,7 +231,7 @@ __device__ __forceinline__ float psf_at(const float* x, const float* taps, int K
 // ------------------------------------------------------------------ march
 
 
-template <bool LDS_IMG, int MODE>
+template <bool LDS_IMG, int MODE, typename S>
 __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 {
     extern __shared__ float4 smem_raw[];
@@ -210,13 +243,17 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
         if (A.st[slice].done) return;
         if (MODE == MARCH_LIN && !A.st[slice].dirty) return;
     }
-    float2* simg = reinterpret_cast<float2*>(smem_raw);
+    // the objective and the linearisation always see the maps in FP32; S only
+    // selects the storage of the weights written for the Jacobian products
+    using px_t = typename F32S::px_t;
+    using w_t = typename S::w_t;
+    px_t* simg = reinterpret_cast<px_t*>(smem_raw);
     const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
     float* rowp = reinterpret_cast<float*>(simg + img_elems);   // raw ray sums  [n_bins]
     float* rowr = rowp + g.n_bins;                              // residual      [n_bins]
     for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = A.t.taps[k];
-    if (LDS_IMG) stage_image(simg, A.src, slice, g.n, g.pitch, 0.0f);
-    const float2* img = LDS_IMG ? simg : A.gimg + (size_t)slice * A.gimg_stride;
+    if (LDS_IMG) stage_image<F32S>(simg, A.src, slice, g.n, g.pitch, 0.0f);
+    const px_t* img = LDS_IMG ? simg : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -238,8 +275,9 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
             }
             const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
             float carry_mu = 0.0f, carry_le = 0.0f;
-            float2* wrow = nullptr;
-            if (MODE == MARCH_LIN) wrow = A.wts + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
+            w_t* wrow = nullptr;
+            if (MODE == MARCH_LIN)
+                wrow = static_cast<w_t*>(A.wts) + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
             for (int i0 = gr.y; i0 >= gr.x; i0 -= SPL) {
                 const int i = i0 - q;
                 const bool act = (i >= cl.x) && (i <= cl.y);
@@ -247,7 +285,7 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                 if (act) {
                     const float ti = (float)i - g.t_off;
                     const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
-                    const float2 v = bilerp(img, g.pitch, g.n, col, row);
+                    const float2 v = bilerp<F32S>(img, g.pitch, g.n, col, row);
                     lam = v.x;
                     mu = v.y;
                 }
@@ -262,7 +300,7 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                 quad_scan(le, q, lincl, ltot);
                 if (MODE == MARCH_LIN && act) {
                     const float rprime = carry_le + (lincl - hs * le);
-                    wrow[(size_t)i * g.n_bins + j] = make_float2(g.step * E, rprime);
+                    wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, rprime);
                 }
                 carry_le += ltot;
             }
@@ -306,7 +344,7 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 // a' = a + n_angles/2: ray j of a and ray n_bins-1-j of a' visit the same
 // points (sample i of one is sample n_t-1-i of the other), so one bilinear
 // sample of the direction serves both rays.
-template <bool LDS_IMG, int MODE>
+template <bool LDS_IMG, int MODE, typename S>
 __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
 {
     extern __shared__ float4 smem_raw[];
@@ -320,21 +358,23 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const int slot0 = blockIdx.x * A.angles_per_block;
     const int nslot = min(A.angles_per_block, n_slots - slot0);
     const int nrows = nslot * per_slot;   // sinogram rows produced by this block
-    float2* simg = reinterpret_cast<float2*>(smem_raw);
+    using px_t = typename S::px_t;
+    using w_t = typename S::w_t;
+    px_t* simg = reinterpret_cast<px_t*>(smem_raw);
     const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
     float* rowz = reinterpret_cast<float*>(simg + img_elems);   // [nrows][n_bins]
     float* rowy = rowz + A.angles_per_block * per_slot * g.n_bins;
     for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = A.t.taps[k];
     if (LDS_IMG) {
         const float beta = resolve_beta(A.src, A.part, slice, sh);
-        stage_image(simg, A.src, slice, g.n, g.pitch, beta);
+        stage_image<S>(simg, A.src, slice, g.n, g.pitch, beta);
     }
-    const float2* img = LDS_IMG ? simg : A.gimg + (size_t)slice * A.gimg_stride;
+    const px_t* img = LDS_IMG ? simg : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int q = lane & (SPL - 1), jj = lane >> 2;
-    const float2* wslice = A.wts + (size_t)slice * A.wts_stride;
+    const w_t* wslice = static_cast<const w_t*>(A.wts) + (size_t)slice * A.wts_stride;
     const float* tslice = A.tsum + (size_t)slice * A.sino_stride;
     // Items are taken from a block-wide counter (dynamic balance), longest
     // first: ray groups ordered from the middle of the detector outward.
@@ -362,8 +402,8 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             if (g.paired) Tm = tslice[(size_t)am * g.n_bins + jm];
         }
         const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
-        const float2* wrow = wslice + (size_t)a * g.n_t * g.n_bins;
-        const float2* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
+        const w_t* wrow = wslice + (size_t)a * g.n_t * g.n_bins;
+        const w_t* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
         float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
         // The sample loop is software-pipelined: the weights of trip t+1 (JU
         // samples per lane) are loaded while trip t is computed.  Lanes outside
@@ -376,9 +416,9 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             for (int u = 0; u < JU; ++u) {
                 const int i = i0 - u * SPL - q;
                 const bool ok = (i >= cl.x) && (i <= cl.y);
-                w[u] = ok ? wrow[(size_t)i * g.n_bins + j] : make_float2(0.0f, T);
+                w[u] = ok ? S::w(wrow[(size_t)i * g.n_bins + j]) : make_float2(0.0f, T);
                 if (g.paired)
-                    wm[u] = ok ? wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : make_float2(0.0f, Tm);
+                    wm[u] = ok ? S::w(wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm]) : make_float2(0.0f, Tm);
             }
         };
         auto compute = [&](int i0, const float2* w, const float2* wm) {
@@ -387,7 +427,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                 const int i = i0 - u * SPL - q;
                 const float ti = (float)i - g.t_off;
                 const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
-                const float2 v = bilerp(img, g.pitch, g.n, col, row);
+                const float2 v = bilerp<S>(img, g.pitch, g.n, col, row);
                 accf = fmaf(w[u].x, v.x, accf);
                 accq = fmaf(T - w[u].y, v.y, accq);
                 if (g.paired) {
@@ -509,15 +549,16 @@ struct Stage {
     float wt, t, wtm, tm;
 };
 
-__device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const float2* wbase, int slice,
-                                           int a, const Window& W)
+template <typename SP>
+__device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const typename SP::w_t* wbase,
+                                           int slice, int a, const Window& W)
 {
     const Geo& g = A.g;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform row index base
     const int am = a + g.n_angles / 2;
-    const float2* wrow = wbase + (size_t)a * g.n_t * g.n_bins;
-    const float2* wrowm = wbase + (size_t)am * g.n_t * g.n_bins;
+    const typename SP::w_t* wrow = wbase + (size_t)a * g.n_t * g.n_bins;
+    const typename SP::w_t* wrowm = wbase + (size_t)am * g.n_t * g.n_bins;
     const size_t sbase = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
     const size_t sbasem = (size_t)slice * A.sino_stride + (size_t)am * g.n_bins;
     const int j = W.jlo + lane;
@@ -538,8 +579,8 @@ __device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const flo
             const int ii = wave + 4 * k;
             const int i = W.ilo + ii;
             if (ii < W.wi && i >= 0 && i < g.n_t) {   // wave-uniform condition
-                S.w[k] = wrow[(size_t)i * g.n_bins + j];
-                if (g.paired) S.wm[k] = wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm];
+                S.w[k] = SP::w(wrow[(size_t)i * g.n_bins + j]);
+                if (g.paired) S.wm[k] = SP::w(wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm]);
             }
         }
     }
@@ -572,6 +613,7 @@ __device__ __forceinline__ float tent(float d)
     return __builtin_amdgcn_fmed3f(1.0f - fabsf(d), 0.0f, 1.0f);
 }
 
+template <typename SP>
 __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
 {
     __shared__ float2 lat[VFP * VFP];
@@ -601,13 +643,13 @@ __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
     float accf[4] = {0.f, 0.f, 0.f, 0.f}, accm[4] = {0.f, 0.f, 0.f, 0.f};
     const float SQ2 = 1.41421356f;
     const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
-    const float2* wbase = A.wts + (size_t)slice * A.wts_stride;
+    const typename SP::w_t* wbase = static_cast<const typename SP::w_t*>(A.wts) + (size_t)slice * A.wts_stride;
 
     Stage S;
     Window Wn = {0, 0, 0, 0};
     if (a_begin < a_end) {
         Wn = tile_window(g, A.t.trig[a_begin], tr0, tc0);
-        stage_load(S, A, wbase, slice, a_begin, Wn);
+        stage_load<SP>(S, A, wbase, slice, a_begin, Wn);
     }
     for (int a = a_begin; a < a_end; ++a) {
         const Window W = Wn;
@@ -616,7 +658,7 @@ __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
         __syncthreads();
         if (a + 1 < a_end) {   // next angle's loads fly during this gather
             Wn = tile_window(g, A.t.trig[a + 1], tr0, tc0);
-            stage_load(S, A, wbase, slice, a + 1, Wn);
+            stage_load<SP>(S, A, wbase, slice, a + 1, Wn);
         }
         const float4 tr = A.t.trig[a];
         const float cs = tr.z, sn = tr.w;
@@ -1128,19 +1170,17 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
 
 // ------------------------------------------------------------- launchers
 // (host-callable wrappers used by the runtime; grid shapes are set there)
-#define INST_MARCH(L, M) template __global__ void k_march<L, M>(MarchArgs);
-INST_MARCH(true, MARCH_FWD)
-INST_MARCH(true, MARCH_LIN)
-INST_MARCH(true, MARCH_TRIAL)
-INST_MARCH(false, MARCH_FWD)
-INST_MARCH(false, MARCH_LIN)
-INST_MARCH(false, MARCH_TRIAL)
-#define INST_JVP(L, M) template __global__ void k_jvp_lin<L, M>(JvpArgs);
-INST_JVP(true, JVP_PLAIN)
-INST_JVP(true, JVP_NORMAL)
-INST_JVP(true, JVP_SQNORM)
-INST_JVP(false, JVP_PLAIN)
-INST_JVP(false, JVP_NORMAL)
-INST_JVP(false, JVP_SQNORM)
+#define INST_MARCH(L, M, S) template __global__ void k_march<L, M, S>(MarchArgs);
+#define INST_JVP(L, M, S) template __global__ void k_jvp_lin<L, M, S>(JvpArgs);
+#define INST_ALL(S)                                                                           \
+    INST_MARCH(true, MARCH_FWD, S) INST_MARCH(true, MARCH_LIN, S) INST_MARCH(true, MARCH_TRIAL, S) \
+    INST_MARCH(false, MARCH_FWD, S) INST_MARCH(false, MARCH_LIN, S)                           \
+    INST_MARCH(false, MARCH_TRIAL, S)                                                         \
+    INST_JVP(true, JVP_PLAIN, S) INST_JVP(true, JVP_NORMAL, S) INST_JVP(true, JVP_SQNORM, S)  \
+    INST_JVP(false, JVP_PLAIN, S) INST_JVP(false, JVP_NORMAL, S) INST_JVP(false, JVP_SQNORM, S) \
+    template __global__ void k_vjp_lin<S>(VjpArgs);                                           \
+    template __global__ void k_pack<S>(Geo, PairSrc, const double*, void*, long long, const LMState*);
+INST_ALL(F32S)
+INST_ALL(BF16S)
 
 }  // namespace pget

@@ -239,13 +239,17 @@ class Plan:
 
     def __init__(self, n: int, n_angles: int, n_bins: int, angle0: float = 0.0,
                  arc: float = 2.0 * math.pi, bin_size: float = 1.0, step: float = 1.0,
-                 psf_sigma: float = 1.5, psf_radius: int = -1, atten_scale: float = 1.0):
+                 psf_sigma: float = 1.5, psf_radius: int = -1, atten_scale: float = 1.0,
+                 storage: str = "fp32"):
         self.lib = load_library()
         self.geom = Geometry(n, n_angles, n_bins, psf_radius, angle0, arc, bin_size, step,
                              psf_sigma, atten_scale)
+        if storage not in ("fp32", "bf16"):
+            raise ValueError("storage must be 'fp32' or 'bf16'")
+        self.storage = storage
         h = ctypes.c_void_p()
-        _check(self.lib.pget_plan_create(ctypes.byref(self.geom), 0, ctypes.byref(h)),
-               "pget_plan_create")
+        _check(self.lib.pget_plan_create(ctypes.byref(self.geom), 0 if storage == "fp32" else 1,
+                                          ctypes.byref(h)), "pget_plan_create")
         self.handle = h
         self.n, self.n_angles, self.n_bins = n, n_angles, n_bins
         self._ws = {}
