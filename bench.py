@@ -328,7 +328,9 @@ def main():
     # launches: events are not recorded inside a replayed graph)
     classes = (1 << pget.KC_VJP) | (1 << pget.KC_JVP) | (1 << pget.KC_MARCH) | \
               (1 << pget.KC_VECTOR) | (1 << pget.KC_GRADIENT)
-    per_step = cfg.max_outer * (3 * cfg.n_cg + 12) + 8
+    # timed launches per outer iteration: n_cg J^T, n_cg + 2 J, 2 n_cg + 6
+    # vector kernels, 2 marches and the gradient; room to spare
+    per_step = cfg.max_outer * (5 * cfg.n_cg + 24) + 16
     pget.timing_enable(classes, per_step + 64)
     torch.cuda.synchronize()
     t2 = time.perf_counter()

@@ -31,6 +31,8 @@ struct pget_plan {
     int max_japb;        // most angle slots per k_jvp_lin block that fit in LDS
     int tiles_x;         // VJP tiles per edge
     int device;
+    int n_cu;            // compute units of the device
+    int vjp_resident;    // k_vjp_lin blocks resident per compute unit
     int64_t support;     // lattice samples inside the support
     std::vector<std::array<int, 3>> tuned;   // (batch, japb, vjp groups) picked by pget_autotune
 };
@@ -92,14 +94,23 @@ struct Shapes {
     int jvp_threads;
     size_t jvp_lds;
     int groups;       // angle groups of the adjoint gather
+    int gcap;         // angle groups the partial-image buffers hold
     int n_vjp_blocks; // blocks per slice of k_vjp_lin
     int n_ew_blocks;  // blocks per slice of the element-wise kernels
 };
 
+// Angle slots of the adjoint gather: one slot takes an angle with its mirror
+// (paired) and the quarter-turn pair (quad).
+int vjp_slots(const pget_plan* P)
+{
+    const Geo& g = P->g;
+    return g.quad ? g.n_angles / 4 : g.paired ? g.n_angles / 2 : g.n_angles;
+}
+
 Shapes shapes_for(const pget_plan* P, int batch)
 {
     Shapes s;
-    const int cus = 256;
+    const int cus = P->n_cu;
     // enough blocks to cover the chip twice; more angles per block when the
     // batch already does (the staged map is then reused across angles)
     int want = std::max(1, (P->g.n_angles * batch) / (4 * cus));
@@ -111,9 +122,19 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
     s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
     s.jvp_lds = P->img_lds + 2 * (size_t)s.japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+    // angle groups of the gather: the fewest launch rounds per unit of work
+    // (blocks of a group are equal), counted against the resident blocks
     const int tiles = P->tiles_x * P->tiles_x;
-    int g = (2 * cus + tiles * batch - 1) / (tiles * batch);
-    g = std::max(1, std::min(g, slots));
+    const int vslots = vjp_slots(P);
+    s.gcap = std::min(vslots, 8);
+    const long long resident = (long long)cus * std::max(1, P->vjp_resident);
+    int g = 1;
+    double best = 1e30;
+    for (int c = 1; c <= s.gcap; ++c) {
+        const long long blocks = (long long)tiles * batch * c;
+        const double cost = (double)((blocks + resident - 1) / resident) / c;
+        if (cost < best * (1.0 - 1e-9)) { best = cost; g = c; }
+    }
     s.groups = g;
     for (const auto& t : P->tuned)
         if (t[0] == batch) {
@@ -121,7 +142,7 @@ Shapes shapes_for(const pget_plan* P, int batch)
             s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
             s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
             s.jvp_lds = P->img_lds + 2 * (size_t)s.japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
-            g = std::max(1, std::min(t[2], slots));
+            g = std::max(1, std::min(t[2], s.gcap));
         }
     s.groups = g;
     s.n_vjp_blocks = tiles * g;
@@ -154,9 +175,9 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
     L.sino_b = take(B * sino * sizeof(float));
     L.gimg = (P->lds_img && P->jvp_lds) ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
     L.part = take(B * (size_t)N_SLOTS * SLOT_WIDTH * sizeof(double));
-    if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.groups * B * 2 * n2 * sizeof(float));
+    if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.gcap * B * 2 * n2 * sizeof(float));
     if (op == PGET_OP_LM) {
-        L.gpart_grad = take((size_t)sh.groups * B * 2 * n2 * sizeof(float));
+        L.gpart_grad = take((size_t)sh.gcap * B * 2 * n2 * sizeof(float));
         L.ymeas = take(B * sino * sizeof(float));
         L.u = take(B * 2 * n2 * sizeof(float));
         L.ut = take(B * 2 * n2 * sizeof(float));
@@ -247,10 +268,18 @@ void jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipS
     else launch_jvp<false, M>(P, A, sh, batch, s);
 }
 
-void launch_vjp(const pget_plan* P, const VjpArgs& V, int blocks, int batch, hipStream_t s)
+// The grid is (tiles * V.groups, batch): the kernel decodes (slice, group,
+// tile) from the linear block id with exactly these extents.
+void launch_vjp(const pget_plan* P, const VjpArgs& V, int batch, hipStream_t s)
 {
-    if (P->bf16) hipLaunchKernelGGL(k_vjp_lin<BF16S>, dim3(blocks, batch), dim3(VJP_THREADS), 0, s, V);
-    else hipLaunchKernelGGL(k_vjp_lin<F32S>, dim3(blocks, batch), dim3(VJP_THREADS), 0, s, V);
+    const dim3 grid(P->tiles_x * P->tiles_x * V.groups, batch), block(VJP_THREADS);
+    if (P->bf16) {
+        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<BF16S, true>), grid, block, 0, s, V);
+        else hipLaunchKernelGGL((k_vjp_lin<BF16S, false>), grid, block, 0, s, V);
+    } else {
+        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<F32S, true>), grid, block, 0, s, V);
+        else hipLaunchKernelGGL((k_vjp_lin<F32S, false>), grid, block, 0, s, V);
+    }
 }
 
 // Global bordered copy of a map pair: FP32 for the ray march (jvp_store =
@@ -335,6 +364,10 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     g.kq = (float)(-geom->atten_scale * geom->step * geom->step);
     g.ln2_scale = (float)(geom->atten_scale * geom->step * 1.4426950408889634);
     g.paired = (geom->n_angles % 2 == 0) && fabs(geom->arc - 2.0 * M_PI) <= 1e-12 * 2.0 * M_PI;
+    g.quad = g.paired && geom->n_angles % 4 == 0 && geom->step == geom->bin_size &&
+             (g.n_bins - g.n_t) % 2 == 0;
+    g.rot_c = (g.n_t + g.n_bins) / 2 - 1;
+    g.rot_d = (g.n_bins - g.n_t) / 2;
 
     // ---- tables in double precision, stored rounded to float
     const int na = g.n_angles, nb = g.n_bins, nt = g.n_t, ng = g.n_groups, K = g.K;
@@ -471,6 +504,19 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         }
     }
     P->tiles_x = (g.n + VT - 1) / VT;
+    {
+        int occ = 0;
+        const void* vk = g.quad ? (P->bf16 ? (const void*)k_vjp_lin<BF16S, true> : (const void*)k_vjp_lin<F32S, true>)
+                                : (P->bf16 ? (const void*)k_vjp_lin<BF16S, false> : (const void*)k_vjp_lin<F32S, false>);
+        if (hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vk, VJP_THREADS, 0) != hipSuccess) {
+            (void)hipFree(P->table_mem);
+            delete P;
+            return PGET_ERR_HIP;
+        }
+        P->n_cu = std::max(1, P->n_cu);
+        P->vjp_resident = std::max(1, occ);
+    }
     *out = P;
     return PGET_OK;
 }
@@ -609,7 +655,7 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     V.groups = sh.groups;
     {
         Timed t_(PGET_KC_VJP, stream);
-        launch_vjp(P, V, sh.n_vjp_blocks, 1, stream);
+        launch_vjp(P, V, 1, stream);
     }
     {
         Timed t_(PGET_KC_VECTOR, stream);
@@ -834,7 +880,7 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
     }
     {
         Timed t_(PGET_KC_GRADIENT, S.stream);
-        launch_vjp(S.P, S.vgrad, S.sh.n_vjp_blocks, S.B, S.stream);
+        launch_vjp(S.P, S.vgrad, S.B, S.stream);
     }
     VecArgs Vg = S.V;
     Vg.gpart = S.vgrad.gpart;
@@ -850,7 +896,7 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
         enqueue_jvp(S, J, JVP_NORMAL);
         {
             Timed t_(PGET_KC_VJP, S.stream);
-            launch_vjp(S.P, S.vcg, S.sh.n_vjp_blocks, S.B, S.stream);
+            launch_vjp(S.P, S.vcg, S.B, S.stream);
         }
         VecArgs V = S.V;
         V.cg_step = m;
@@ -1328,14 +1374,13 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
         });
         if (t < best_j) { best_j = t; best_japb = japb; }
     }
-    // the adjoint's partial images live in a buffer sized for S.sh.groups
-    for (int grp = 1; grp <= S.sh.groups; grp *= 2) {
+    // the adjoint's partial images live in a buffer sized for S.sh.gcap
+    for (int grp = 1; grp <= S.sh.gcap; ++grp) {
         VjpArgs V = S.vcg;
         V.st = nullptr;
         V.groups = grp;
-        const int blocks = P->tiles_x * P->tiles_x * grp;
         const float t = time_it([&] {
-            launch_vjp(P, V, blocks, batch, stream);
+            launch_vjp(P, V, batch, stream);
         });
         if (t < best_v) { best_v = t; best_groups = grp; }
     }

@@ -38,6 +38,11 @@ struct Geo {
     float ln2_scale;  // c * step * log2(e): exponent scale for exp2
     int paired;     // n_angles even over a full turn: angle a + n_angles/2 samples the
                     // same lattice points as angle a with bins and samples mirrored
+    int quad;       // paired, n_angles % 4 == 0, step == bin_size and n_bins - n_t even:
+                    // sample (i', j') of angle a + n_angles/4 is the point (i, j) =
+                    // (rot_c - j', i' + rot_d) of angle a's lattice
+    int rot_c;      // (n_t + n_bins)/2 - 1
+    int rot_d;      // (n_bins - n_t)/2
 };
 
 // Device-resident tables of a plan.
@@ -219,7 +224,7 @@ template <typename S>
 __global__ void k_pack(Geo g, PairSrc s, const double* part, void* out, long long out_stride,
                        const LMState* st);
 __global__ void k_psf(Geo g, const float* taps_g, const float* in, float* out);
-template <typename S> __global__ void k_vjp_lin(VjpArgs A);
+template <typename S, bool QUAD> __global__ void k_vjp_lin(VjpArgs A);
 __global__ void k_fill_zero(float4* p, long long n4);
 __global__ void k_sum_groups(int n2, int groups, const float* gpart, long long group_stride, float* gf,
                              float* gm);

@@ -535,27 +535,47 @@ __device__ __forceinline__ Window tile_window(const Geo& g, float4 tr, int tr0, 
     return w;
 }
 
+// Window of angle a + n_angles/4 holding the same points as window W of
+// angle a (quarter-turn geometry): point (i, j) of a is (j - rot_d, rot_c - i)
+// of the rotated angle, so the rotated window's columns run over W's rows
+// (reversed) and its rows over W's columns.
+__device__ __forceinline__ Window rot_window(const Geo& g, const Window& W)
+{
+    Window r;
+    r.jlo = g.rot_c - (W.ilo + W.wi - 1);
+    r.ilo = W.jlo - g.rot_d;
+    r.wj = W.wi;
+    r.wi = W.wj;
+    return r;
+}
+
 // Window rows per wave: the block's 4 waves take rows w, w+4, ...; lane =
 // window column.  No integer division in the staging index math.
 constexpr int VROWS = (VFP + 3) / 4;
+// LDS row pitch of the staged window (odd in float2 pairs' halves: the
+// transposed adds of the rotated angles spread over the banks)
+constexpr int LP = VFP + 1;
 
-// Loads of one angle's window into registers (weight pair per point, and the
-// blurred cotangent and ray total of the lane's column).  Points off the
-// lattice rectangle load nothing; the weights buffer holds zeros outside the
-// support, and such samples carry zero tent weight for every pixel of the map.
+// One angle's window in registers: weight pair per point (rows wave + 4k,
+// column lane) and the blurred cotangent and ray total of the lane's column,
+// with the same for the mirror angle when the geometry is paired.
 struct Stage {
     float2 w[VROWS];
     float2 wm[VROWS];   // mirror angle, same points (paired geometry)
     float wt, t, wtm, tm;
 };
 
+// Loads of one angle's window into registers (weight pair per point, and the
+// blurred cotangent and ray total of the lane's column).  Rows past the
+// window or off the lattice are skipped (wave-uniform tests) and read as zero;
+// lanes whose column is off the window or the detector read zero.
 template <typename SP>
 __device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const typename SP::w_t* wbase,
                                            int slice, int a, const Window& W)
 {
     const Geo& g = A.g;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform row index base
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int am = a + g.n_angles / 2;
     const typename SP::w_t* wrow = wbase + (size_t)a * g.n_t * g.n_bins;
     const typename SP::w_t* wrowm = wbase + (size_t)am * g.n_t * g.n_bins;
@@ -578,7 +598,7 @@ __device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const typ
         for (int k = 0; k < VROWS; ++k) {
             const int ii = wave + 4 * k;
             const int i = W.ilo + ii;
-            if (ii < W.wi && i >= 0 && i < g.n_t) {   // wave-uniform condition
+            if (ii < W.wi && i >= 0 && i < g.n_t) {
                 S.w[k] = SP::w(wrow[(size_t)i * g.n_bins + j]);
                 if (g.paired) S.wm[k] = SP::w(wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm]);
             }
@@ -601,9 +621,46 @@ __device__ __forceinline__ void stage_store(float2* lat, const Stage& S, float k
         if (ii < VFP) {
             const float cf = fmaf(S.wm[k].x, S.wtm, S.w[k].x * S.wt);
             const float cm = fmaf(kwm, S.tm - S.wm[k].y, kw * (S.t - S.w[k].y));
-            lat[ii * VFP + lane] = make_float2(cf, cm);
+            lat[ii * LP + lane] = make_float2(cf, cm);
         }
     }
+}
+
+// Adds the staged coefficients of the rotated pair (a + n_angles/4 and its
+// mirror, loaded over rot_window(W)) to the points of W they coincide with:
+// rotated column lane is W's row W.wi - 1 - lane, rotated row ii is W's column
+// ii.  Every point has one owner thread.
+__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage& S, float kq, const Window& W)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (lane >= W.wi) return;
+    const float kw = kq * S.wt, kwm = kq * S.wtm;
+    float2* row = lat + (W.wi - 1 - lane) * LP;
+#pragma unroll
+    for (int k = 0; k < VROWS; ++k) {
+        const int ii = wave + 4 * k;
+        if (ii < W.wj) {
+            const float cf = fmaf(S.wm[k].x, S.wtm, S.w[k].x * S.wt);
+            const float cm = fmaf(kwm, S.tm - S.wm[k].y, kw * (S.t - S.w[k].y));
+            float2 v = row[ii];
+            v.x += cf;
+            v.y += cm;
+            row[ii] = v;
+        }
+    }
+}
+
+// Logical work item of workgroup `lin` (linear id) among `total`: the
+// hardware places workgroup lin on XCD lin % N_XCD, so XCD x runs items
+// [x * per, (x + 1) * per) in order.  The tail beyond a multiple of N_XCD
+// keeps its own ids.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_item(int lin, int total)
+{
+    const int per = total / N_XCD;
+    if (lin >= per * N_XCD) return lin;
+    return (lin % N_XCD) * per + lin / N_XCD;
 }
 
 // tent(d) = max(0, 1 - |d|); med3 against [0, 1] lets the compiler fold it
@@ -613,22 +670,29 @@ __device__ __forceinline__ float tent(float d)
     return __builtin_amdgcn_fmed3f(1.0f - fabsf(d), 0.0f, 1.0f);
 }
 
-template <typename SP>
-__global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
+template <typename SP, bool QUAD>
+__global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_eu(3))) k_vjp_lin(VjpArgs A)
 {
-    __shared__ float2 lat[VFP * VFP];
+    __shared__ float2 lat[VFP * LP];
     const Geo& g = A.g;
-    const int slice = blockIdx.y;
+    // Workgroups go to the XCDs round-robin by linear id; give each XCD a
+    // contiguous run of (slice, group, tile) items so that neighbouring tiles
+    // (whose lattice windows overlap) share that XCD's L2.
+    const int ntile = A.tiles_x * A.tiles_x;
+    int item = xcd_item(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int tile = item % ntile;
+    item /= ntile;
+    const int grp = item % A.groups, slice = item / A.groups;
     if (A.st) {
         if (A.st[slice].done) return;
         if (A.skip_if_clean && !A.st[slice].dirty) return;
     }
-    const int ntile = A.tiles_x * A.tiles_x;
-    const int tile = blockIdx.x % ntile, grp = blockIdx.x / ntile;
     const int tr0 = (tile / A.tiles_x) * VT, tc0 = (tile % A.tiles_x) * VT;
-    const int n_slots = g.paired ? g.n_angles / 2 : g.n_angles;
+    // a slot gathers angle a, its mirror (paired) and the quarter-turn pair (QUAD)
+    const int n_slots = QUAD ? g.n_angles / 4 : g.paired ? g.n_angles / 2 : g.n_angles;
     const int apg = (n_slots + A.groups - 1) / A.groups;
     const int a_begin = grp * apg, a_end = min(n_slots, a_begin + apg);
+    const int qa = g.n_angles / 4;
 
     // this thread's 4 pixels: the same position in the four 8x8 blocks of its
     // wave's 16x16 quarter (a wave touches one compact 8x8 block per step)
@@ -645,20 +709,26 @@ __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
     const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
     const typename SP::w_t* wbase = static_cast<const typename SP::w_t*>(A.wts) + (size_t)slice * A.wts_stride;
 
-    Stage S;
+    Stage S, R;
     Window Wn = {0, 0, 0, 0};
     if (a_begin < a_end) {
         Wn = tile_window(g, A.t.trig[a_begin], tr0, tc0);
         stage_load<SP>(S, A, wbase, slice, a_begin, Wn);
+        if (QUAD) stage_load<SP>(R, A, wbase, slice, a_begin + qa, rot_window(g, Wn));
     }
     for (int a = a_begin; a < a_end; ++a) {
         const Window W = Wn;
         __syncthreads();   // the previous angle's gather is done with lat
         stage_store(lat, S, g.kq);
+        if (QUAD) {
+            __syncthreads();
+            stage_add_rot(lat, R, g.kq, W);
+        }
         __syncthreads();
         if (a + 1 < a_end) {   // next angle's loads fly during this gather
             Wn = tile_window(g, A.t.trig[a + 1], tr0, tc0);
             stage_load<SP>(S, A, wbase, slice, a + 1, Wn);
+            if (QUAD) stage_load<SP>(R, A, wbase, slice, a + 1 + qa, rot_window(g, Wn));
         }
         const float4 tr = A.t.trig[a];
         const float cs = tr.z, sn = tr.w;
@@ -678,7 +748,7 @@ __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
             const float dx0 = fmaf(du0, A1, dv0 * A2), dy0 = fmaf(du0, A3, dv0 * A4);
             const int jb = min(max((int)ju - W.jlo, 0), VFP - 3);
             const int ib = min(max((int)iv - W.ilo, 0), VFP - 3);
-            const float2* L = lat + ib * VFP + jb;
+            const float2* L = lat + ib * LP + jb;
             float sf = 0.0f, sm = 0.0f;
 #pragma unroll
             for (int di = 0; di < 3; ++di) {
@@ -686,7 +756,7 @@ __global__ void __launch_bounds__(VJP_THREADS) k_vjp_lin(VjpArgs A)
 #pragma unroll
                 for (int dj = 0; dj < 3; ++dj) {
                     const float w = tent(rx + oxj[dj]) * tent(ry + oyj[dj]);
-                    const float2 c = L[di * VFP + dj];
+                    const float2 c = L[di * LP + dj];
                     sf = fmaf(w, c.x, sf);
                     sm = fmaf(w, c.y, sm);
                 }
@@ -1178,7 +1248,8 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
     INST_MARCH(false, MARCH_TRIAL, S)                                                         \
     INST_JVP(true, JVP_PLAIN, S) INST_JVP(true, JVP_NORMAL, S) INST_JVP(true, JVP_SQNORM, S)  \
     INST_JVP(false, JVP_PLAIN, S) INST_JVP(false, JVP_NORMAL, S) INST_JVP(false, JVP_SQNORM, S) \
-    template __global__ void k_vjp_lin<S>(VjpArgs);                                           \
+    template __global__ void k_vjp_lin<S, false>(VjpArgs);                                    \
+    template __global__ void k_vjp_lin<S, true>(VjpArgs);                                     \
     template __global__ void k_pack<S>(Geo, PairSrc, const double*, void*, long long, const LMState*);
 INST_ALL(F32S)
 INST_ALL(BF16S)

@@ -140,6 +140,42 @@ def test_repeat_is_bitwise_deterministic(case):
     assert torch.equal(plan.forward(T(f), T(mu)), plan.forward(T(f), T(mu)))
 
 
+def n_samples(n, step):
+    return 2 * math.ceil((n / math.sqrt(2) + 1) / step)
+
+
+# Adjoint gather variants: (n, n_angles, n_bins, bin_size, step).  Four-angle
+# folding (quarter turn onto the same lattice points) needs a full turn,
+# n_angles % 4 == 0, step == bin_size and n_bins - n_t even; the cases cover
+# folding with a detector narrower and wider than the sample count, folding at
+# spacing 2, and geometries one condition short of it.
+GATHER_CASES = [
+    (96, 40, 60, 1.0, 1.0),     # folds, n_bins < n_t
+    (70, 36, 112, 1.0, 1.0),    # folds, n_bins > n_t
+    (64, 48, 48, 2.0, 2.0),     # folds at spacing 2
+    (64, 120, 95, 1.0, 1.0),    # n_bins - n_t odd: mirror pairs only
+    (48, 44, 70, 1.0, 1.5),     # step != bin_size: mirror pairs only
+    (48, 42, 70, 1.0, 1.0),     # n_angles % 4 == 2: mirror pairs only
+]
+
+
+@pytest.mark.parametrize("n,na,nb,bs,st", GATHER_CASES,
+                         ids=lambda v: str(v))
+def test_vjp_gather_variants(n, na, nb, bs, st):
+    nt = n_samples(n, st)
+    folds = na % 4 == 0 and bs == st and (nb - nt) % 2 == 0
+    log("gather case n=%d angles=%d bins=%d bin=%g step=%g n_t=%d folds=%s" % (n, na, nb, bs, st, nt, folds))
+    og = O.Geometry(n, na, nb, bin_size=bs, step=st)
+    plan = pget.Plan(n, na, nb, bin_size=bs, step=st)
+    f, mu = phantom(n, 7 + n)
+    w = np.random.default_rng(8).standard_normal(og.sino_shape)
+    gf_ref, gm_ref = O.vjp(og, f, mu, w)
+    gf, gm = plan.vjp(T(f), T(mu), T(w))
+    log("vjp rel f %.3e mu %.3e" % (rel(H(gf), gf_ref), rel(H(gm), gm_ref)))
+    assert rel(H(gf), gf_ref) <= 1e-5 and rel(H(gm), gm_ref) <= 1e-5
+    assert maxrel(H(gf), gf_ref) <= 1e-4 and maxrel(H(gm), gm_ref) <= 1e-4
+
+
 def test_invalid_arguments_rejected():
     with pytest.raises(pget.PgetError):
         pget.Plan(1, 10, 10)
