@@ -360,6 +360,10 @@ def main():
         "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
         "flop_per_unit": FLOP_PER_SAMPLE[dom], "units_per_launch": units,
     }
+    if roofline["traffic"]:
+        # counter-measured HBM rate of the same launches (the weight stream)
+        roofline["hbm_gbs"] = round(roofline["traffic"] / avg_s / 1e9, 1)
+        roofline["hbm_frac"] = round(roofline["traffic"] / avg_s / 1e9 / PEAK_HBM_GBS, 4)
     kernel_share = {k: round(v[0] / (1e3 * instrumented_s), 4) for k, v in kt.items()}
 
     single = None
