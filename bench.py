@@ -364,7 +364,17 @@ def main():
         # counter-measured HBM rate of the same launches (the weight stream)
         roofline["hbm_gbs"] = round(roofline["traffic"] / avg_s / 1e9, 1)
         roofline["hbm_frac"] = round(roofline["traffic"] / avg_s / 1e9 / PEAK_HBM_GBS, 4)
+    # HBM GB/s of the projector (A, the ray march) and both Jacobian products:
+    # committed counter bytes per launch over this run's average launch time
+    kernel_gbs = {}
+    for cls, kname in (("march", "k_march"), ("jvp", "k_jvp_lin"), ("vjp", "k_vjp_lin")):
+        b = traffic_from_profile(kname, workload)
+        ms, n = kt[cls]
+        if b and n:
+            kernel_gbs[kname] = round(b / (ms / 1e3 / n) / 1e9, 1)
     kernel_share = {k: round(v[0] / (1e3 * instrumented_s), 4) for k, v in kt.items()}
+    if kernel_gbs:
+        roofline["kernel_hbm_gbs"] = kernel_gbs
 
     single = None
     if not args.no_single:
