@@ -224,7 +224,8 @@ pget_status pget_lm_solve(const pget_plan* plan, const float* y, float* f_inout,
                           const pget_lm_report* report, void* ws, hipStream_t stream);
 
 /*
- * n_slices independent reconstructions of the same plan shape solved
+ * n_slices >= 1 (else PGET_ERR_INVALID_ARG) independent reconstructions of
+ * the same plan shape solved
  * together (every kernel launch covers all slices).  y, f_inout, mu_inout
  * are arrays of n_slices device pointers (host arrays of pointers);
  * params and reports are arrays of n_slices entries (reports may be NULL).

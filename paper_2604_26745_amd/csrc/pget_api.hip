@@ -122,17 +122,20 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
     s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
     s.jvp_lds = P->img_lds + 2 * (size_t)s.japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
-    // angle groups of the gather: the fewest launch rounds per unit of work
-    // (blocks of a group are equal), counted against the resident blocks
+    // angle groups of the gather: the fewest launch rounds times the work of
+    // one block (its angle slots plus about one slot of fixed cost), counted
+    // against the resident blocks.  Small batches may split the angles finely
+    // to fill the chip; the partial-image buffers hold gcap groups.
     const int tiles = P->tiles_x * P->tiles_x;
     const int vslots = vjp_slots(P);
-    s.gcap = std::min(vslots, 8);
+    s.gcap = std::min(vslots, batch >= 16 ? 8 : 32);
     const long long resident = (long long)cus * std::max(1, P->vjp_resident);
     int g = 1;
     double best = 1e30;
     for (int c = 1; c <= s.gcap; ++c) {
         const long long blocks = (long long)tiles * batch * c;
-        const double cost = (double)((blocks + resident - 1) / resident) / c;
+        const double rounds = (double)((blocks + resident - 1) / resident);
+        const double cost = rounds * ((double)((vslots + c - 1) / c) + 1.0);
         if (cost < best * (1.0 - 1e-9)) { best = cost; g = c; }
     }
     s.groups = g;

@@ -381,6 +381,10 @@ class Plan:
         different streams need distinct workspaces."""
         torch = _torch()
         B = len(ys)
+        if not (len(f0s) == len(mu0s) == len(params) == B):
+            raise ValueError("lm_solve_batched: ys, f0s, mu0s and params differ in length")
+        if B == 0:   # nothing to solve (the C call requires n_slices >= 1)
+            return [], [], []
         ys = [self._sino(t) for t in ys]
         fs = [self._img(t).clone() for t in f0s]
         ms = [self._img(t).clone() for t in mu0s]

@@ -1,0 +1,128 @@
+"""Edge cases of the HIP path through the C ABI, against the FP64 oracle where
+there is a value to compare: the largest grid (512 x 512, the map read from a
+bordered copy in HBM) and the largest angle count (1024) the geometry check
+admits, one past each limit, zero emission (the forward map and the
+attenuation part of J v are exactly zero), zero attenuation, and empty or
+mismatched batches.  Operator tolerances as in test_gpu_parity (relative L2
+<= 1e-5, max-abs / max-ref <= 1e-4) up to 256 x 256 maps.  For larger maps
+the relative L2 bound of the Jacobian products is 2e-5: sample positions are
+FP32 coordinates in pixel units, one rounding near 512 is 1.5e-5 px, and the
+white-noise directions of the test turn a position error into a relative
+error of about the same size (measured 1.0e-5 at 512 x 512; the forward map
+of the smooth phantom stays at 3e-7).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_26745_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2604_26745_amd import pget  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def T(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+def H(t):
+    return t.detach().cpu().double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def phantom(n, seed):
+    cfg = inputs.SliceConfig("t", n, 8, n, n_rods=5, rod_radius=max(1.0, n / 24), pitch=n / 7,
+                             can_half=0.42 * n, n_empty=2, rod_mu=None)
+    f, mu = inputs.rod_lattice(cfg, seed)
+    return f, mu
+
+
+@pytest.mark.parametrize("n,na,nb", [(512, 12, 730), (24, 1024, 36)], ids=["n512", "a1024"])
+def test_operators_at_size_limits(n, na, nb):
+    log("limit case n=%d angles=%d bins=%d" % (n, na, nb))
+    og = O.Geometry(n, na, nb)
+    plan = pget.Plan(n, na, nb)
+    f, mu = phantom(n, 3)
+    rng = np.random.default_rng(9)
+    vf, vm = rng.standard_normal(f.shape), 0.05 * rng.standard_normal(f.shape)
+    w = rng.standard_normal(og.sino_shape)
+    y = H(plan.forward(T(f), T(mu)))
+    y_ref = O.forward(og, f, mu)
+    jv = H(plan.jvp(T(f), T(mu), T(vf), T(vm)))
+    jv_ref = O.jvp(og, f, mu, vf, vm)
+    gf, gm = plan.vjp(T(f), T(mu), T(w))
+    gf_ref, gm_ref = O.vjp(og, f, mu, w)
+    errs = [rel(y, y_ref), rel(jv, jv_ref), rel(H(gf), gf_ref), rel(H(gm), gm_ref)]
+    log("forward %.2e jvp %.2e vjp f %.2e mu %.2e" % tuple(errs))
+    assert errs[0] <= 1e-5
+    assert max(errs[1:]) <= (1e-5 if n <= 256 else 2e-5)
+    assert maxrel(y, y_ref) <= 1e-4 and maxrel(jv, jv_ref) <= 1e-4
+    assert maxrel(H(gf), gf_ref) <= 1e-4 and maxrel(H(gm), gm_ref) <= 1e-4
+
+
+def test_one_past_each_limit_is_rejected():
+    with pytest.raises(pget.PgetError):
+        pget.Plan(513, 12, 730)
+    with pytest.raises(pget.PgetError):
+        pget.Plan(24, 1025, 36)
+    with pytest.raises(pget.PgetError):
+        pget.Plan(24, 0, 36)
+
+
+def test_zero_emission_is_exactly_zero():
+    n, na, nb = 48, 60, 70
+    plan = pget.Plan(n, na, nb)
+    _, mu = phantom(n, 4)
+    f = np.zeros((n, n))
+    rng = np.random.default_rng(10)
+    vm = rng.standard_normal(f.shape)
+    assert torch.count_nonzero(plan.forward(T(f), T(mu))).item() == 0
+    # with no emission the attenuation direction has no effect on the data
+    jv = plan.jvp(T(f), T(mu), T(np.zeros_like(f)), T(vm))
+    assert torch.count_nonzero(jv).item() == 0
+    w = rng.standard_normal((na, nb))
+    gf, gm = plan.vjp(T(f), T(mu), T(w))
+    assert torch.count_nonzero(gm).item() == 0
+    og = O.Geometry(n, na, nb)
+    assert rel(H(gf), O.vjp(og, f, mu, w)[0]) <= 1e-5
+    log("zero emission: forward, attenuation part of J v and J^T w exactly zero")
+
+
+def test_zero_attenuation_matches_oracle():
+    n, na, nb = 40, 36, 60
+    og = O.Geometry(n, na, nb)
+    plan = pget.Plan(n, na, nb)
+    f, _ = phantom(n, 5)
+    mu = np.zeros_like(f)
+    y = H(plan.forward(T(f), T(mu)))
+    assert rel(y, O.forward(og, f, mu)) <= 1e-5
+
+
+def test_empty_and_mismatched_batches():
+    plan = pget.Plan(16, 12, 24)
+    assert plan.lm_solve_batched([], [], [], []) == ([], [], [])
+    with pytest.raises(ValueError):
+        plan.lm_solve_batched([torch.zeros((12, 24), device="cuda")], [], [], [])
+    lib = pget.load_library()
+    # the C entry point itself rejects n_slices < 1 before touching any pointer
+    rc = lib.pget_lm_solve_batched(plan.handle, 0, None, None, None, None, None, None, None)
+    assert rc == -1

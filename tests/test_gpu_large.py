@@ -1,6 +1,9 @@
-"""The 256x256 slice (17x17 rod lattice, 360 angles x 256 bins, 15 outer x 30
-CG) against the FP64 oracle's stored reconstruction (tests/golden/, written by
-make_lattice17_n256_reference.py from the oracle alone).
+"""Full-size slices against the FP64 oracle's stored reconstructions
+(tests/golden/, written by make_lattice*_reference.py from the oracle alone):
+the 256x256 slice (17x17 rod lattice, 360 angles x 256 bins, 15 outer x 30
+CG) solved alone in FP32 and BF16, and one 128x128 slice (9x9 lattice, 360 x
+192) solved as slice 0 of a batch of 64 -- the launch configuration of the
+benchmark -- with the other 63 slices solving freely beside it.
 
 With the oracle's accept decisions replayed, per-iterate objective and the
 maps after iterations 5, 10 and 15 are compared.  Stated tolerances:
@@ -28,6 +31,7 @@ if not torch.cuda.is_available():
 from paper_2604_26745_amd import pget  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lattice17_n256_oracle.npz")
+GOLDEN128 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lattice9_n128_oracle.npz")
 
 
 def rel(a, b):
@@ -69,3 +73,46 @@ def test_lattice17_n256_replayed(case, storage, tphi, tmap):
     assert max(errs) <= tphi
     for k in (5, 10, 15):
         assert maps[k][0] <= tmap and maps[k][1] <= tmap
+
+
+def test_lattice9_n128_as_slice_of_batch64():
+    """FP32: objective per iterate <= 1e-5 relative and maps after 5, 10 and 15
+    iterations <= 1e-5 relative L2 for the replayed slice."""
+    if not os.path.exists(GOLDEN128):
+        pytest.skip("stored oracle reconstruction not present")
+    ref = np.load(GOLDEN128)
+    cfg = inputs.MAIN_128
+    g = O.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    f_true, mu_true = inputs.rod_lattice(cfg, 0)
+    y = inputs.poisson_counts(O.forward(g, f_true, mu_true), cfg.peak_counts, 0)
+    f0, mu0 = OLM.initial_guess(g, y)
+    assert rel(ref["f0"], f0) < 1e-6
+    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+    ones = torch.ones((cfg.n, cfg.n), device="cuda")
+    a1 = plan.forward(ones, torch.zeros_like(ones)).double()
+    ys, f0s, m0s = [T(y)], [T(f0)], [T(mu0)]
+    for s_ in range(1, 64):   # the rest of the batch: other seeds of the same workload
+        f, mu = inputs.rod_lattice(cfg, s_)
+        yc = plan.forward(T(f), T(mu)).double().cpu().numpy()
+        ys_ = T(inputs.poisson_counts(yc, cfg.peak_counts, s_))
+        c0 = float((a1 * ys_.double()).sum() / (a1 * a1).sum())
+        ys.append(ys_)
+        f0s.append(torch.full_like(ones, c0))
+        m0s.append(torch.zeros_like(ones))
+    replay = [int(v) for v in ref["accepted"]]
+    errs, maps = [], {}
+    for k_end in (5, 10, 15):
+        base = dict(max_outer=k_end, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha)
+        prm = [pget.SolverParams(replay=replay[:k_end], **base)] + [pget.SolverParams(**base)] * 63
+        fs, ms, rbs = plan.lm_solve_batched(ys, f0s, m0s, prm)
+        rep = rbs[0].to_report()
+        if k_end == 15:
+            errs = [abs(rep.phi[k] - ref["phi"][k]) / ref["phi"][k] for k in range(len(ref["phi"]))]
+        maps[k_end] = (rel(fs[0].cpu().numpy(), ref["f%d" % k_end]), rel(ms[0].cpu().numpy(), ref["mu%d" % k_end]))
+    print("batch64 slice 0 phi rel err per iterate: %s" % " ".join("%.1e" % e for e in errs), flush=True)
+    print("batch64 slice 0 map rel L2 (f, mu) after 5/10/15: %s" % " ".join("(%.1e, %.1e)" % maps[k] for k in (5, 10, 15)),
+          flush=True)
+    assert max(errs) <= 1e-5
+    for k in (5, 10, 15):
+        assert maps[k][0] <= 1e-5 and maps[k][1] <= 1e-5
