@@ -17,7 +17,9 @@ rod edges are area-weighted.  Random draws, in this order, from
 replacement), the emission of each rod (row-major), the attenuation of each
 rod (row-major, when it is drawn).  Noise draws from ``default_rng([seed, 1])``;
 mixed-size configurations draw their size/lattice from ``default_rng([seed, 2])``
-and request arrivals from ``default_rng([seed, 3])``.
+and request arrivals from ``default_rng([seed, 3])``; the scanner-geometry
+phantoms (``scanner_phantom``) draw from ``default_rng([seed, 6])`` and their
+Gaussian noise from ``default_rng([seed, 5])``.
 """
 from __future__ import annotations
 
@@ -129,6 +131,132 @@ def rod_lattice(cfg: SliceConfig, seed: int = 0):
     f = f_hi.reshape(n, sub, n, sub).mean(axis=(1, 3))
     mu = mu_hi.reshape(n, sub, n, sub).mean(axis=(1, 3))
     return f, mu
+
+
+# ---- scanner geometry (physical units: millimetres)
+
+@dataclass(frozen=True)
+class ScannerConfig:
+    """A slice in the geometry of the measurement device: two banks of 91
+    detector elements whose readings interleave over a full turn to 182 bins
+    at 2 mm, a 165 x 165 reconstruction grid, data generated on a grid
+    ``oversample`` times finer.  Readings where the paper gives no number:
+    1 mm pixels (165 mm field), 360 angles, collimator response a Gaussian of
+    1 bin (2 mm) standard deviation, a 9 x 9 lattice at 14.4 mm pitch with
+    5.5 mm rod radius, rod centres perturbed by U(-0.5, 0.5) mm per axis,
+    water filling the field-of-view disk."""
+
+    name: str = "scanner9x9_n165_a360_b182"
+    n: int = 165
+    pixel_mm: float = 1.0
+    n_angles: int = 360
+    n_bins: int = 182
+    bin_mm: float = 2.0
+    psf_sigma_bins: float = 1.0
+    oversample: int = 2
+    n_rods: int = 9
+    pitch_mm: float = 14.4
+    rod_radius_mm: float = 5.5
+    jitter_mm: float = 0.5
+    rod_f_range: Tuple[float, float] = (6.5e5 / 7e5, 1.0)      # emission, in units of 7e5
+    rod_mu_range: Tuple[float, float] = (0.12, 0.14)            # 1/mm
+    water_mu: float = 0.0085                                    # 1/mm
+    noise: float = 0.02
+    max_outer: int = 15
+    n_cg: int = 30
+    alpha: float = 1e-2
+
+
+SCANNER_165 = ScannerConfig()
+
+
+def scanner_geometry(cfg: ScannerConfig, oversample: int = 1) -> dict:
+    """Plan arguments of the device geometry on a grid `oversample` times
+    finer than cfg.n: pixel size p = pixel_mm / oversample, bins and samples
+    in pixel units, attenuation per mm (atten_scale = p), and the factor p
+    that turns the plan's ray sums (step of one pixel) into millimetres."""
+    p = cfg.pixel_mm / oversample
+    return dict(n=cfg.n * oversample, n_angles=cfg.n_angles, n_bins=cfg.n_bins,
+                bin_size=cfg.bin_mm / p, step=1.0, psf_sigma=cfg.psf_sigma_bins,
+                atten_scale=p, y_scale=p)
+
+
+def scanner_phantom(cfg: ScannerConfig, seed: int = 0, kind: str = "missing", oversample: int = 1):
+    """Emission f (units of 7e5) and attenuation mu (1/mm) of a 9 x 9
+    assembly on the (oversample * n)^2 grid, 4 x 4 supersampled per pixel.
+
+    kind: "full" (all rods), "missing" (1..6 rods replaced by water),
+    "replaced" (5..6 rods without emission, attenuation kept), "medium"
+    (1..20 rods missing or replaced, present rods' emission down to 70 % of
+    the range's top).  Draws from ``default_rng([seed, 6])`` in this order:
+    rod jitter (x then y, row-major), emission, attenuation, the number of
+    changed rods, their indices, and (medium) which are replaced and the
+    emission scale of the others."""
+    rng = np.random.default_rng([seed, 6])
+    nr = cfg.n_rods
+    nt = nr * nr
+    jx = rng.uniform(-cfg.jitter_mm, cfg.jitter_mm, size=nt)
+    jy = rng.uniform(-cfg.jitter_mm, cfg.jitter_mm, size=nt)
+    rod_f = rng.uniform(cfg.rod_f_range[0], cfg.rod_f_range[1], size=nt)
+    rod_mu = rng.uniform(cfg.rod_mu_range[0], cfg.rod_mu_range[1], size=nt)
+    missing, replaced = set(), set()
+    if kind == "missing":
+        missing = set(int(i) for i in rng.choice(nt, size=int(rng.integers(1, 7)), replace=False))
+    elif kind == "replaced":
+        replaced = set(int(i) for i in rng.choice(nt, size=int(rng.integers(5, 7)), replace=False))
+    elif kind == "medium":
+        changed = rng.choice(nt, size=int(rng.integers(1, 21)), replace=False)
+        rep = rng.integers(0, 2, size=changed.size)
+        missing = set(int(i) for i, r in zip(changed, rep) if not r)
+        replaced = set(int(i) for i, r in zip(changed, rep) if r)
+        rod_f = rod_f * rng.uniform(0.7, 1.0, size=nt)
+    elif kind != "full":
+        raise ValueError("kind must be full, missing, replaced or medium")
+    n = cfg.n * oversample
+    px = cfg.pixel_mm / oversample
+    sub = 4
+    off = ((np.arange(sub) + 0.5) / sub - 0.5) * px
+    cc = (np.arange(n) - 0.5 * (n - 1)) * px
+    xs = (cc[:, None] + off[None, :]).reshape(-1)
+    X, Y = np.meshgrid(xs, xs)
+    fov = X ** 2 + Y ** 2 <= (0.5 * cfg.n * cfg.pixel_mm) ** 2
+    f_hi = np.zeros_like(X)
+    mu_hi = np.where(fov, cfg.water_mu, 0.0)
+    r = cfg.rod_radius_mm
+    for idx in range(nt):
+        if idx in missing:
+            continue
+        l, k = divmod(idx, nr)
+        cx = (k - 0.5 * (nr - 1)) * cfg.pitch_mm + jx[idx]
+        cy = (l - 0.5 * (nr - 1)) * cfg.pitch_mm + jy[idx]
+        lo_c = max(0, int(np.searchsorted(xs, cx - r - px)))
+        hi_c = min(xs.size, int(np.searchsorted(xs, cx + r + px)))
+        lo_r = max(0, int(np.searchsorted(xs, cy - r - px)))
+        hi_r = min(xs.size, int(np.searchsorted(xs, cy + r + px)))
+        Xw = X[lo_r:hi_r, lo_c:hi_c]
+        Yw = Y[lo_r:hi_r, lo_c:hi_c]
+        inside = (Xw - cx) ** 2 + (Yw - cy) ** 2 <= r * r
+        f_hi[lo_r:hi_r, lo_c:hi_c][inside] = 0.0 if idx in replaced else rod_f[idx]
+        mu_hi[lo_r:hi_r, lo_c:hi_c][inside] = rod_mu[idx]
+    f = f_hi.reshape(n, sub, n, sub).mean(axis=(1, 3))
+    mu = mu_hi.reshape(n, sub, n, sub).mean(axis=(1, 3))
+    return f, mu
+
+
+def fov_mask(cfg: ScannerConfig) -> np.ndarray:
+    """Pixels of the reconstruction grid whose centre lies in the field-of-view disk."""
+    cc = np.arange(cfg.n) - 0.5 * (cfg.n - 1)
+    X, Y = np.meshgrid(cc, cc)
+    return X ** 2 + Y ** 2 <= (0.5 * cfg.n) ** 2
+
+
+def gaussian_noise(y_clean: np.ndarray, level: float, seed: int = 0) -> np.ndarray:
+    """y = y_clean + e, e white Gaussian with ||e|| about level * ||y_clean||
+    (standard deviation level * rms(y_clean)); draws from default_rng([seed, 5])."""
+    rng = np.random.default_rng([seed, 5])
+    y_clean = np.asarray(y_clean, dtype=np.float64)
+    sd = level * float(np.sqrt(np.mean(y_clean * y_clean)))
+    return y_clean + sd * rng.standard_normal(y_clean.shape)
 
 
 def poisson_counts(y_clean: np.ndarray, peak: float, seed: int = 0) -> np.ndarray:
