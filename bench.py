@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-single", action="store_true", help="skip the single-slice latency run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0, help="0: min(16, cpu count)")
-    ap.add_argument("--workload", default="main", choices=["main", "mixed", "serve", "scanner"],
+    ap.add_argument("--workload", default="main", choices=["main", "mixed", "serve", "scanner", "deepgn"],
                     help="main: batch of 128^2 slices (the headline metric); mixed: 64 slices of "
                          "mixed sizes {64..256}^2 solved together vs one at a time; serve: "
                          "open-loop Poisson requests of mixed sizes through the continuous-batching "
@@ -61,6 +61,12 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16"],
                     help="storage of staged maps and per-sample weights")
+    ap.add_argument("--dg-set", default="lattice", choices=["lattice", "scanner"], help="deepgn: slice family")
+    ap.add_argument("--dg-k", type=int, default=3, help="deepgn: number of learned refinements")
+    ap.add_argument("--dg-train", type=int, default=192, help="deepgn: training slices")
+    ap.add_argument("--dg-test", type=int, default=16, help="deepgn: held-out slices")
+    ap.add_argument("--dg-outer", type=int, default=5, help="deepgn: outer iterations")
+    ap.add_argument("--dg-epochs", type=int, default=40, help="deepgn: epochs per network")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (scale for HBM counters)")
     return ap.parse_args()
@@ -291,6 +297,122 @@ def run_scanner(args, torch, np, inputs, pget):
     print(json.dumps(out), flush=True)
 
 
+def run_deepgn(args, torch, np, inputs, pget):
+    """Safeguarded Deep Gauss-Newton: K learned refinements trained per
+    Alg. 1 on synthetic slices (seeds 1000+), then Alg. 2 on held-out slices
+    (seeds 0..n_test-1) against plain LM at the same and at 15 outer
+    iterations.  --dg-set lattice: the 128^2 9x9 lattice of the main workload
+    (Poisson counts, f0 = c0, mu0 = 0, the solver defaults); scanner: the
+    165^2 scanner geometry (data from the 330^2 grid, 2 % Gaussian noise),
+    with the attenuation damped in units of its upper bound (d_mu = 50) and a
+    water-level start, for LM and Deep-GN alike.  Convolutions run without
+    MIOpen (PyTorch's GEMM path), so no kernel search runs on a fresh box."""
+    from paper_2604_26745_amd import refine
+    torch.backends.cudnn.enabled = False
+    T = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+    K, n_train, n_test, outer = args.dg_k, args.dg_train, args.dg_test, args.dg_outer
+    if args.dg_set == "scanner":
+        cfg = inputs.SCANNER_165
+        geo = {}
+        for o in (1, cfg.oversample):
+            d = inputs.scanner_geometry(cfg, o)
+            ys_ = d.pop("y_scale")
+            n = d.pop("n")
+            geo[o] = (pget.Plan(n, d.pop("n_angles"), d.pop("n_bins"), **d), ys_)
+        plan, _ = geo[1]
+        fine, fscale = geo[cfg.oversample]
+        kinds = ("full", "missing", "replaced", "medium")
+        mask = inputs.fov_mask(cfg)
+        water = np.where(mask, cfg.water_mu, 0.0)
+        f_max, mu_max = 1.0, 0.14
+        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha,
+                                d_mu=50.0)
+        wl = "deepgn_scanner9x9_n165_K%d" % K
+        extra = {"d_mu": 50.0, "mu0": "water in the field of view"}
+        data = "synthetic: scanner-geometry 9x9 assemblies, 2% Gaussian noise"
+    else:
+        cfg = inputs.MAIN_128
+        plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+        cc = np.arange(cfg.n) - 0.5 * (cfg.n - 1)
+        X, Y = np.meshgrid(cc, cc)
+        mask = X ** 2 + Y ** 2 <= (0.5 * cfg.n) ** 2
+        f_max, mu_max = 3.0, 0.05
+        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha)
+        wl = "deepgn_%s_K%d" % (cfg.name, K)
+        extra = {"mu0": "zero", "peak_counts": cfg.peak_counts}
+        data = "synthetic: 9x9 rod lattices, Poisson counts"
+    one = torch.ones((cfg.n, cfg.n), dtype=torch.float32, device="cuda")
+    a1 = plan.forward(one, torch.zeros_like(one)).double().cpu().numpy()
+
+    def sample(s_):
+        if args.dg_set == "scanner":
+            ff, mf = inputs.scanner_phantom(cfg, s_, kinds[s_ % 4], cfg.oversample)
+            y = inputs.gaussian_noise(fscale * fine.forward(T(ff), T(mf)).double().cpu().numpy(), cfg.noise, s_)
+            tf, tm = inputs.scanner_phantom(cfg, s_, kinds[s_ % 4], 1)
+            m0 = T(water)
+        else:
+            tf, tm = inputs.rod_lattice(cfg, s_)
+            y = inputs.poisson_counts(plan.forward(T(tf), T(tm)).double().cpu().numpy(), cfg.peak_counts, s_)
+            m0 = torch.zeros_like(one)
+        c0 = float((a1 * y).sum() / (a1 * a1).sum())
+        return T(y), (torch.full_like(one, c0), m0), (T(tf), T(tm))
+
+    train = [sample(1000 + i) for i in range(n_train)]
+    log("deepgn: %d training slices drawn" % n_train)
+    t0 = time.perf_counter()
+    models, rep = refine.train_networks(plan, [t[0] for t in train], [t[1] for t in train],
+                                        [t[2] for t in train], prm, K=K, epochs=args.dg_epochs, mask=mask,
+                                        log=log, f_max=f_max, mu_max=mu_max)
+    t_train = time.perf_counter() - t0
+    test = [sample(i) for i in range(n_test)]
+
+    def err(f, mu, tr):
+        tf, tm = tr[0].cpu().numpy(), tr[1].cpu().numpy()
+        return (float(np.linalg.norm((f.cpu().numpy() - tf)[mask]) / np.linalg.norm(tf[mask])),
+                float(np.linalg.norm((mu.cpu().numpy() - tm)[mask]) / np.linalg.norm(tm[mask])))
+
+    res = {"lm_%d" % outer: [], "lm_15": [], "deepgn_%d" % outer: []}
+    kept, calls, t_lm, t_dg, sg = 0, 0, 0.0, 0.0, []
+    for y, (f0, m0), tr in test:
+        torch.cuda.synchronize(); ta = time.perf_counter()
+        f, mu, _ = plan.lm_solve(y, f0, m0, prm)
+        torch.cuda.synchronize(); t_lm += time.perf_counter() - ta
+        res["lm_%d" % outer].append(err(f, mu, tr))
+        f, mu, _ = plan.lm_solve(y, f0, m0, pget.SolverParams(**{**prm.__dict__, "max_outer": 15}))
+        res["lm_15"].append(err(f, mu, tr))
+        st = {}
+        torch.cuda.synchronize(); ta = time.perf_counter()
+        f, mu, rb = refine.deep_gn_solve(plan, y, f0, m0, prm, models, st)
+        torch.cuda.synchronize(); t_dg += time.perf_counter() - ta
+        res["deepgn_%d" % outer].append(err(f, mu, tr))
+        r = rb.to_report()
+        kept += sum(r.hook_accepted)
+        calls += st["hook_calls"]
+        for k in range(r.iters_run):
+            if not math.isnan(r.hook_pred[k]):
+                sg.append((r.hook_rho[k], r.hook_pred[k] / r.pred[k]))
+    summ = {k: {"f_rel_err_fov": round(float(np.mean([e[0] for e in v])), 4),
+                "mu_rel_err_fov": round(float(np.mean([e[1] for e in v])), 4)} for k, v in res.items()}
+    out = {
+        "metric": "safeguarded Deep Gauss-Newton: reconstruction error after %d iterations vs plain LM" % outer,
+        "value": summ["deepgn_%d" % outer]["f_rel_err_fov"], "unit": "relative L2 error of f in the FOV",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * t_dg / n_test, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "%s, %d training / %d test slices" % (data, n_train, n_test),
+        "config": dict({"workload": wl, "outer": outer, "cg": cfg.n_cg, "cnn_params": rep.n_params,
+                        "epochs": args.dg_epochs, "train_s": round(t_train, 1)}, **extra),
+        "errors": summ, "hook_proposals_kept": kept, "hook_calls": calls,
+        "safeguard": {"evaluated": len(sg), "rho_gt_eta": sum(1 for a, _ in sg if a > prm.eta),
+                      "model_not_worse": sum(1 for _, b in sg if b >= 1.0),
+                      "median_rho": round(max(float(np.median([a for a, _ in sg])), -1e30), 4) if sg else None,
+                      "median_pred_ratio": round(float(np.median([b for _, b in sg])), 4) if sg else None},
+        "train_mse": {"lm_point": [round(v, 6) for v in rep.loss_before], "network": [round(v, 6) for v in rep.loss_after]},
+        "ms_per_solve": {"lm_%d" % outer: round(1e3 * t_lm / n_test, 2), "deepgn_%d" % outer: round(1e3 * t_dg / n_test, 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(args, torch, pget):
     """Continuous batching of mixed-size requests (Poisson arrivals, early exit
     at tolerance 1e-4) against the plain per-slice solver on the same trace."""
@@ -346,6 +468,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "mixed":
         run_mixed(args, torch, np, inputs, pget)
+        return
+    if args.workload == "deepgn":
+        run_deepgn(args, torch, np, inputs, pget)
         return
     if args.workload == "scanner":
         run_scanner(args, torch, np, inputs, pget)

@@ -182,6 +182,10 @@ typedef struct {
  *   rho, beta, pred, ared, gnorm [k]               [max_outer]
  *   accepted[k], hook_accepted[k]                  [max_outer]
  *   cg_rr[k * n_cg + m]  r^T r after CG step m     [max_outer * n_cg]
+ *   hook_rho[k], hook_pred[k]  rho(s~) and m(0) - m(s~) of the hook's
+ *                 proposal after iteration k (the two sides of the
+ *                 safeguard, with pred[k] = m(0) - m(s_k)); NaN where no
+ *                 proposal was evaluated.                [max_outer]
  *   beta_final    damping after the last iteration.
  * The scalar fields are written through `scalars` (device or host memory,
  * 4 doubles: status, iters_run, beta_final, stop_reason) when not NULL;
@@ -198,6 +202,8 @@ typedef struct {
     int8_t* accepted;
     int8_t* hook_accepted;
     double* cg_rr;
+    double* hook_rho;
+    double* hook_pred;
 } pget_lm_report;
 
 /*

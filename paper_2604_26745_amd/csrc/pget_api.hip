@@ -193,7 +193,7 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
         L.state = take(B * sizeof(LMState));
         L.params = take(B * sizeof(LMParamsDev));
         L.repdev = take(B * sizeof(ReportDev));
-        const size_t per = (size_t)(max_outer + 1) * 6 * sizeof(double) + 2 * (size_t)max_outer +
+        const size_t per = (size_t)(max_outer + 1) * 8 * sizeof(double) + 2 * (size_t)max_outer +
                            (size_t)max_outer * n_cg * sizeof(double) + 4 * sizeof(double) + 64;
         L.reparr = take(B * align_up(per));
     }
@@ -989,6 +989,8 @@ void copy_report(const ReportDev& R, const pget_lm_report* out, int max_outer, i
     cp(out->accepted, R.accepted, (size_t)max_outer);
     cp(out->hook_accepted, R.hook_accepted, (size_t)max_outer);
     cp(out->cg_rr, R.cg_rr, (size_t)max_outer * n_cg * sizeof(double));
+    cp(out->hook_rho, R.hook_rho, (size_t)max_outer * sizeof(double));
+    cp(out->hook_pred, R.hook_pred, (size_t)max_outer * sizeof(double));
 }
 
 // One group of slices sharing a plan: its solve state and host-side copies
@@ -1060,7 +1062,7 @@ pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStre
     const size_t n2 = (size_t)g.n * g.n, sino = (size_t)g.n_angles * g.n_bins;
     const int max_outer = G.max_outer, n_cg = G.n_cg;
     G.rep.assign(B, ReportDev{});
-    const size_t per = align_up((size_t)(max_outer + 1) * 6 * sizeof(double) + 2 * (size_t)max_outer +
+    const size_t per = align_up((size_t)(max_outer + 1) * 8 * sizeof(double) + 2 * (size_t)max_outer +
                                 (size_t)max_outer * n_cg * sizeof(double) + 4 * sizeof(double) + 64);
     for (int b = 0; b < B; ++b) {
         char* base = at(ws, S.L.reparr + (size_t)b * per);
@@ -1074,6 +1076,8 @@ pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStre
         R.ared = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
         R.gnorm = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
         R.cg_rr = reinterpret_cast<double*>(take((size_t)max_outer * n_cg * sizeof(double)));
+        R.hook_rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.hook_pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
         R.scalars = reinterpret_cast<double*>(take(4 * sizeof(double)));
         R.accepted = reinterpret_cast<int8_t*>(take(max_outer));
         R.hook_accepted = reinterpret_cast<int8_t*>(take(max_outer));

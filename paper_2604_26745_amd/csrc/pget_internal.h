@@ -117,6 +117,8 @@ struct ReportDev {
     int8_t* hook_accepted;
     double* cg_rr;   // [max_outer * n_cg]
     double* scalars; // [4]
+    double* hook_rho;   // [max_outer]
+    double* hook_pred;  // [max_outer]
 };
 
 

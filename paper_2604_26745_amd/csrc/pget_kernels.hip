@@ -1110,6 +1110,8 @@ __global__ void __launch_bounds__(256) k_decide(VecArgs V, int hook_present)
         R.ared[k] = ared;
         R.accepted[k] = (int8_t)acc;
         R.hook_accepted[k] = 0;
+        R.hook_rho[k] = NAN;
+        R.hook_pred[k] = NAN;
     }
     st.phi_u = phi_u;
     st.pred = pred;
@@ -1165,6 +1167,10 @@ __global__ void __launch_bounds__(256) k_hook_decide(VecArgs V)
     const double phi_h = 0.5 * phid_h + 0.5 * regt;
     const double pred_h = -(gs + 0.5 * (js + srs));
     const double rho_h = pred_h > 0.0 ? (st.phi_u - phi_h) / pred_h : -INFINITY;
+    if (V.rep) {
+        V.rep[slice].hook_rho[st.k - 1] = rho_h;
+        V.rep[slice].hook_pred[st.k - 1] = pred_h;
+    }
     if (rho_h > P.eta && pred_h >= st.pred) {
         st.hook_keep = 1;
         st.final_slot = SLOT_PHI_DATA_H;

@@ -61,6 +61,7 @@ class LMReportC(ctypes.Structure):
         ("beta", ctypes.c_void_p), ("pred", ctypes.c_void_p), ("ared", ctypes.c_void_p),
         ("gnorm", ctypes.c_void_p), ("accepted", ctypes.c_void_p),
         ("hook_accepted", ctypes.c_void_p), ("cg_rr", ctypes.c_void_p),
+        ("hook_rho", ctypes.c_void_p), ("hook_pred", ctypes.c_void_p),
     ]
 
 
@@ -194,6 +195,8 @@ class LMReport:
     accepted: List[int] = field(default_factory=list)
     hook_accepted: List[int] = field(default_factory=list)
     cg_rr: List[List[float]] = field(default_factory=list)
+    hook_rho: List[float] = field(default_factory=list)
+    hook_pred: List[float] = field(default_factory=list)
 
 
 class _ReportBuffers:
@@ -213,6 +216,8 @@ class _ReportBuffers:
         self.accepted = torch.zeros(max_outer, dtype=torch.int8, device=device)
         self.hook_accepted = torch.zeros(max_outer, dtype=torch.int8, device=device)
         self.cg_rr = torch.zeros(max_outer * n_cg, **f64)
+        self.hook_rho = torch.full((max_outer,), math.nan, **f64)
+        self.hook_pred = torch.full((max_outer,), math.nan, **f64)
 
     def c(self):
         r = LMReportC()
@@ -231,6 +236,7 @@ class _ReportBuffers:
             accepted=self.accepted.cpu().tolist()[:k],
             hook_accepted=self.hook_accepted.cpu().tolist()[:k],
             cg_rr=self.cg_rr.view(self.max_outer, self.n_cg).cpu().tolist()[:k],
+            hook_rho=self.hook_rho.cpu().tolist()[:k], hook_pred=self.hook_pred.cpu().tolist()[:k],
         )
 
 

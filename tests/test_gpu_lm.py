@@ -138,6 +138,13 @@ def test_hook_identity_and_garbage():
     rep1, rep2 = r1.to_report(), r2.to_report()
     assert rep2.hook_accepted == rep2.accepted
     assert rel(H(f2), H(f1)) <= 1e-6
+    # the identity proposal is the LM step itself: the same model decrease,
+    # NaN where no proposal was evaluated (rejected LM steps)
+    for a, hp, pr in zip(rep2.accepted, rep2.hook_pred, rep2.pred):
+        if a:
+            assert abs(hp - pr) <= 1e-4 * abs(pr)
+        else:
+            assert np.isnan(hp)
     nan = lambda f, mu, sf, sm: (torch.full_like(f, float("nan")), mu)
     f3, m3, r3 = plan.lm_solve(T(y), T(f0), T(mu0), prm, hook=nan)
     assert sum(r3.to_report().hook_accepted) == 0
@@ -164,6 +171,15 @@ def test_hook_decisions_match_oracle():
     assert rep.hook_accepted == orep.hook_accepted
     assert sum(rep.hook_accepted) >= 1
     assert rel(H(f), of) <= 1e-3
+    # both sides of the safeguard as reported, against the oracle's values
+    # (same tolerance as the maps: the proposals follow the FP32 iterates)
+    assert np.array_equal(np.isnan(rep.hook_pred), np.isnan(orep.hook_pred))
+    for a, b in zip(rep.hook_pred, orep.hook_pred):
+        if not np.isnan(b):
+            assert abs(a - b) <= 1e-3 * abs(b)
+    for a, b in zip(rep.hook_rho, orep.hook_rho):
+        if not np.isnan(b) and np.isfinite(b):
+            assert abs(a - b) <= 1e-3 * max(1.0, abs(b))
 
 
 def test_nonfinite_input_reported():
