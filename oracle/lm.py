@@ -10,7 +10,15 @@ readings where the paper is silent:
   L = grad^T grad.
 * step       CG with x0 = 0 and a fixed number of steps on
              (J^T J + beta D + R) x = -g, D = diag(d_f I, d_mu I)
-             (eq. LMA-step solved through its normal equations).
+             (eq. LMA-step solved through its normal equations),
+             preconditioned by W = diag(w_f I, w_mu I): the metric of the
+             variables scaled by their typical magnitudes (the paper solves
+             the constrained step by a scaled gradient projection, Sec. 2.2);
+             W = I is plain CG.
+* active set (option) a variable sitting on a bound whose gradient points
+             out of the box is held at zero step: CG runs on the free
+             variables, F (J^T J + beta D + R) F x = -F g, F the 0/1 mask of
+             free variables.  Off: every variable is free.
 * trial      u' = clamp(u + x) to the box constraints, s = u' - u.
 * model      pred = m(0) - m(s) = -(g.s + 0.5*(||J s||^2 + s.R s))  (eq. m-function)
 * gain ratio rho = (Phi(u) - Phi(u')) / pred  (eq. rho_agreement), -inf if pred <= 0;
@@ -50,6 +58,9 @@ class LMParams:
     mu_lo: float = 0.0
     mu_hi: float = np.inf
     tol: float = 0.0
+    w_f: float = 1.0
+    w_mu: float = 1.0
+    active_set: bool = False
 
 
 @dataclass
@@ -62,6 +73,8 @@ class LMReport:
     gnorm: List[float] = field(default_factory=list)
     accepted: List[int] = field(default_factory=list)
     hook_accepted: List[int] = field(default_factory=list)
+    hook_rho: List[float] = field(default_factory=list)    # rho(s~) of the proposal, NaN if none
+    hook_pred: List[float] = field(default_factory=list)   # m(0) - m(s~), NaN if none
     cg_rr: List[List[float]] = field(default_factory=list)
     iters_run: int = 0
     beta_final: float = 0.0
@@ -94,18 +107,19 @@ def normal_matvec(g: Geometry, f, mu, pf, pm, beta, p: LMParams, af, am):
     return qf, qm
 
 
-def cg(matvec: Callable, bf, bm, n_steps: int):
-    """Conjugate gradients from x0 = 0 for a fixed number of steps.
+def cg(matvec: Callable, bf, bm, n_steps: int, wf: float = 1.0, wm: float = 1.0):
+    """Conjugate gradients from x0 = 0 for a fixed number of steps,
+    preconditioned by W = diag(wf I, wm I) (z = W r; W = I is plain CG).
 
-    Returns (xf, xm, rr) where rr[m] is r^T r after step m (the recurrence
-    residual).  Stops early if p^T M p <= 0 or r^T r == 0; the remaining rr
-    entries then repeat the last value.
+    Returns (xf, xm, rr) where rr[m] is r^T W r after step m (the recurrence
+    residual).  Stops early if p^T M p <= 0 or r^T W r == 0; the remaining
+    rr entries then repeat the last value.
     """
     xf = np.zeros_like(bf)
     xm = np.zeros_like(bm)
     rf, rm = bf.copy(), bm.copy()
-    pf, pm = rf.copy(), rm.copy()
-    rr = float(np.sum(rf * rf) + np.sum(rm * rm))
+    pf, pm = wf * rf, wm * rm
+    rr = float(np.sum(rf * pf) + np.sum(rm * pm))
     trace = []
     for _ in range(n_steps):
         if rr == 0.0:
@@ -121,12 +135,22 @@ def cg(matvec: Callable, bf, bm, n_steps: int):
         xm += a * pm
         rf -= a * qf
         rm -= a * qm
-        rr_new = float(np.sum(rf * rf) + np.sum(rm * rm))
-        pf = rf + (rr_new / rr) * pf
-        pm = rm + (rr_new / rr) * pm
+        zf, zm = wf * rf, wm * rm
+        rr_new = float(np.sum(rf * zf) + np.sum(rm * zm))
+        pf = zf + (rr_new / rr) * pf
+        pm = zm + (rr_new / rr) * pm
         rr = rr_new
         trace.append(rr)
     return xf, xm, trace
+
+
+def free_set(f, mu, gf, gm, p: LMParams):
+    """0/1 masks of the free variables: a variable is held when it lies on
+    its lower bound with a positive gradient, or on its upper bound with a
+    negative one (the descent direction -g would leave the box there)."""
+    hold_f = ((f <= p.f_lo) & (gf > 0.0)) | ((f >= p.f_hi) & (gf < 0.0))
+    hold_m = ((mu <= p.mu_lo) & (gm > 0.0)) | ((mu >= p.mu_hi) & (gm < 0.0))
+    return (~hold_f).astype(np.float64), (~hold_m).astype(np.float64)
 
 
 def model_decrease(g: Geometry, f, mu, gf, gm, sf, sm, af, am) -> float:
@@ -185,9 +209,17 @@ def lm_iteration(g: Geometry, y, f, mu, beta, p: LMParams, k: int) -> Iterate:
     af, am = alphas_at(p, k)
     phi, r = objective(g, y, f, mu, af, am)
     gf, gm = gradient(g, f, mu, r, af, am)
-    xf, xm, rr = cg(
-        lambda a, b: normal_matvec(g, f, mu, a, b, beta, p, af, am), -gf, -gm, p.n_cg
-    )
+    if p.active_set:
+        ff, fm = free_set(f, mu, gf, gm, p)
+
+        def mv(a, b):
+            qf, qm = normal_matvec(g, f, mu, ff * a, fm * b, beta, p, af, am)
+            return ff * qf, fm * qm
+        xf, xm, rr = cg(mv, -ff * gf, -fm * gm, p.n_cg, p.w_f, p.w_mu)
+    else:
+        xf, xm, rr = cg(
+            lambda a, b: normal_matvec(g, f, mu, a, b, beta, p, af, am), -gf, -gm, p.n_cg, p.w_f, p.w_mu
+        )
     ft = np.clip(f + xf, p.f_lo, p.f_hi)
     mt = np.clip(mu + xm, p.mu_lo, p.mu_hi)
     sf, sm = ft - f, mt - mu
@@ -239,6 +271,7 @@ def lm_solve(
         acc = (it.rho > p.eta) if replay is None else bool(replay[k])
         rep.accepted.append(int(acc))
         hook_ok = 0
+        hook_vals = (np.nan, np.nan)
         rep.iters_run = k + 1
         if acc:
             unorm = float(np.sqrt(np.sum(f ** 2) + np.sum(mu ** 2)))
@@ -254,10 +287,13 @@ def lm_solve(
                 pred_t = model_decrease(g, f_old, mu_old, it.gf, it.gm, stf, stm, af, am)
                 phi_t, _ = objective(g, y, ft, mt, af, am)
                 rho_t = (it.phi - phi_t) / pred_t if pred_t > 0.0 else -np.inf
+                hook_vals = (rho_t, pred_t)
                 if rho_t > p.eta and pred_t >= it.pred:
                     f, mu = ft, mt
                     hook_ok = 1
             rep.hook_accepted.append(hook_ok)
+            rep.hook_rho.append(hook_vals[0])
+            rep.hook_pred.append(hook_vals[1])
             if p.tol > 0.0 and (it.ared <= p.tol * it.phi or snorm <= p.tol * unorm):
                 rep.stop_reason = "tol"
                 if on_iterate is not None:
@@ -266,6 +302,8 @@ def lm_solve(
         else:
             beta, nu = nielsen_update(beta, nu, False, it.rho)
             rep.hook_accepted.append(0)
+            rep.hook_rho.append(np.nan)
+            rep.hook_pred.append(np.nan)
         if on_iterate is not None:
             on_iterate(k, f, mu)
         if beta > 1e16 * beta_init:

@@ -202,6 +202,12 @@ def test_hook_identity_equals_plain_lm():
     # u + s equals the LM trial point, so m(s~) = m(s) and rho(s~) = rho(s) > eta
     assert np.allclose(f1, f2, rtol=0, atol=1e-12 * np.abs(f1).max())
     assert r2.hook_accepted == r2.accepted
+    for k in range(r2.iters_run):
+        if r2.accepted[k]:
+            assert abs(r2.hook_pred[k] - r2.pred[k]) <= 1e-9 * abs(r2.pred[k])
+            assert abs(r2.hook_rho[k] - r2.rho[k]) <= 1e-9 * max(1.0, abs(r2.rho[k]))
+        else:
+            assert np.isnan(r2.hook_pred[k]) and np.isnan(r2.hook_rho[k])
 
 
 def test_hook_garbage_is_rejected():
@@ -245,6 +251,8 @@ def test_hook_decision_follows_safeguard():
         rho_t = (phi - L.objective(g, y, ft, mt, af, am)[0]) / pred_t if pred_t > 0 else -np.inf
         expect = int(rho_t > p.eta and pred_t >= pred_s)
         assert rep.hook_accepted[k] == expect
+        assert abs(rep.hook_pred[k] - pred_t) <= 1e-12 * abs(pred_t)
+        assert abs(rep.pred[k] - pred_s) <= 1e-12 * abs(pred_s)
         kept.append(expect)
     assert sum(kept) >= 1
     if kept[-1] and acc_iters[-1] == rep.iters_run - 1:
@@ -257,3 +265,103 @@ def test_early_exit_on_tolerance():
     p = params(max_outer=30, tol=1e-2)
     _, _, rep = L.lm_solve(g, y, f0, mu0, p)
     assert rep.stop_reason == "tol" and rep.iters_run < 30
+
+
+def _spd_problem(n=4, seed=3):
+    """A dense SPD operator on pairs of n x n blocks, badly scaled between
+    the blocks like emission vs attenuation."""
+    rng = np.random.default_rng(seed)
+    k = 2 * n * n
+    A = rng.standard_normal((k, k))
+    S = np.diag(np.concatenate([np.ones(n * n), 30.0 * np.ones(n * n)]))
+    M = S @ (A @ A.T + 0.5 * np.eye(k)) @ S
+    b = rng.standard_normal(k)
+
+    def mv(a, c):
+        q = M @ np.concatenate([a.ravel(), c.ravel()])
+        return q[: n * n].reshape(n, n), q[n * n:].reshape(n, n)
+    return M, b, mv
+
+
+def test_preconditioned_cg_steps_equal_cg_on_scaled_system():
+    """PCG with W = diag(wf, wm) is CG on W^1/2 M W^1/2 in y = W^-1/2 x,
+    step by step: after each of 1..4 steps (far from convergence) the two
+    iterates agree, and so do the residual traces (r^T W r = r_y^T r_y)."""
+    n, wf, wm = 4, 1.0, 1.0 / 900.0
+    M, b, mv = _spd_problem(n)
+    bf, bm = b[: n * n].reshape(n, n), b[n * n:].reshape(n, n)
+    sw = np.concatenate([np.full(n * n, math.sqrt(wf)), np.full(n * n, math.sqrt(wm))])
+    Ms = sw[:, None] * M * sw[None, :]
+
+    def mvs(a, c):
+        q = Ms @ np.concatenate([a.ravel(), c.ravel()])
+        return q[: n * n].reshape(n, n), q[n * n:].reshape(n, n)
+    bs = sw * b
+    for steps in (1, 2, 3, 4):
+        xf, xm, rr = L.cg(mv, bf, bm, steps, wf, wm)
+        yf, ym, rr_s = L.cg(mvs, bs[: n * n].reshape(n, n), bs[n * n:].reshape(n, n), steps)
+        x = np.concatenate([xf.ravel(), xm.ravel()])
+        y = sw * np.concatenate([yf.ravel(), ym.ravel()])
+        assert np.linalg.norm(x - y) <= 1e-10 * np.linalg.norm(y), steps
+        assert np.allclose(rr, rr_s, rtol=1e-9, atol=0)
+
+
+def test_preconditioned_cg_converges_and_helps():
+    """Run to convergence PCG solves M x = b; on the badly scaled operator
+    the block scaling reaches a given residual in fewer steps than plain CG."""
+    n = 4
+    M, b, mv = _spd_problem(n)
+    bf, bm = b[: n * n].reshape(n, n), b[n * n:].reshape(n, n)
+    x_ref = np.linalg.solve(M, b)
+    xf, xm, _ = L.cg(mv, bf, bm, 200, 1.0, 1.0 / 900.0)
+    x = np.concatenate([xf.ravel(), xm.ravel()])
+    assert np.linalg.norm(x - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+    def err_after(steps, wm):
+        xf, xm, _ = L.cg(mv, bf, bm, steps, 1.0, wm)
+        return np.linalg.norm(np.concatenate([xf.ravel(), xm.ravel()]) - x_ref) / np.linalg.norm(x_ref)
+    assert err_after(12, 1.0 / 900.0) < 0.5 * err_after(12, 1.0)
+
+
+def test_free_set_rule():
+    p = params(f_lo=0.0, f_hi=2.0, mu_lo=0.0, mu_hi=0.5)
+    f = np.array([[0.0, 0.0, 1.0, 2.0, 2.0]])
+    gf = np.array([[1.0, -1.0, 5.0, -1.0, 1.0]])
+    mu = np.array([[0.0, 0.5, 0.2, 0.0, 0.5]])
+    gm = np.array([[0.0, -3.0, -3.0, -2.0, 2.0]])
+    ff, fm = L.free_set(f, mu, gf, gm, p)
+    # lower bound + positive gradient and upper bound + negative gradient are held
+    assert ff.tolist() == [[0.0, 1.0, 1.0, 0.0, 1.0]]
+    # mu on 0 with zero gradient stays free (no descent leaves the box there)
+    assert fm.tolist() == [[1.0, 0.0, 1.0, 1.0, 1.0]]
+
+
+def test_active_set_step_solves_reduced_system():
+    """With the active set on, the CG step is zero on held variables and on
+    the free ones equals the direct solve of the reduced normal system
+    M_FF x_F = -g_F (M built column by column, CG run to convergence)."""
+    n = 5
+    g = O.Geometry(n, 8, 10, psf_sigma=1.0)
+    rng = np.random.default_rng(4)
+    f = rng.uniform(0.5, 1.0, (n, n))
+    mu = rng.uniform(0.0, 0.2, (n, n))
+    f[0, :3] = 0.0
+    mu[2:, 1] = 0.0
+    p = params(active_set=True, w_f=1.0, w_mu=0.04, n_cg=400)
+    y = O.forward(g, rng.uniform(0.0, 1.5, (n, n)), rng.uniform(0.0, 0.3, (n, n)))
+    beta = 0.05
+    it = L.lm_iteration(g, y, f, mu, beta, p, 0)
+    ff, fm = L.free_set(f, mu, it.gf, it.gm, p)
+    assert ff.sum() + fm.sum() < 2 * n * n        # some variables are held
+    held = np.concatenate([ff.ravel(), fm.ravel()]) == 0.0
+    x = np.concatenate([it.xf.ravel(), it.xm.ravel()])
+    assert np.all(x[held] == 0.0)
+    M = dense_normal_matrix(g, f, mu, beta, p)
+    free = ~held
+    gvec = np.concatenate([it.gf.ravel(), it.gm.ravel()])
+    x_ref = np.linalg.solve(M[np.ix_(free, free)], -gvec[free])
+    assert np.linalg.norm(x[free] - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+    # without the active set the held variables would move
+    p_off = params(active_set=False, n_cg=400)
+    it_off = L.lm_iteration(g, y, f, mu, beta, p_off, 0)
+    assert np.abs(np.concatenate([it_off.xf.ravel(), it_off.xm.ravel()])[held]).max() > 0.0
