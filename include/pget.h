@@ -155,6 +155,14 @@ pget_status pget_vjp(const pget_plan* plan, const float* f, const float* mu, con
  * tol > 0 stops after an accepted step with ared <= tol*Phi or
  * ||s|| <= tol*||u||.  replay (test use): per outer iteration 1 = accept,
  * 0 = reject, instead of the rho test; NULL for the normal rule.
+ * w_f, w_mu (> 0; 0 means 1) precondition CG by W = diag(w_f I, w_mu I),
+ * the metric of variables scaled by their typical magnitudes, e.g. the
+ * squares of the upper bounds (the paper solves the constrained step by a
+ * scaled gradient projection, Sec. 2.2); 1, 1 is plain CG.  active_set = 1
+ * holds every variable that lies on a bound with its gradient pointing out
+ * of the box at zero step and runs CG on the free ones; 0 leaves every
+ * variable free (the clamp alone keeps the trial point in the box).
+ * cg_rr then reports r^T W r.
  */
 typedef struct {
     int32_t max_outer;        /* >= 1                                        */
@@ -168,6 +176,8 @@ typedef struct {
     double f_lo, f_hi, mu_lo, mu_hi;
     double tol;
     const int8_t* replay;     /* host pointer, max_outer entries, or NULL    */
+    double w_f, w_mu;         /* CG preconditioner, > 0 (0 -> 1)             */
+    int32_t active_set;       /* 0 or 1                                      */
 } pget_lm_params;
 
 /*

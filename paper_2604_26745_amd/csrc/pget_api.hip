@@ -156,7 +156,7 @@ Shapes shapes_for(const pget_plan* P, int batch)
 // Workspace layout.  Every buffer is 256-byte aligned.
 struct Layout {
     size_t wts, tsum, sino_a, sino_b, ymeas, gpart_grad, gpart_cg, gimg, part;
-    size_t u, ut, s, x, r, p, q, grad, state, params, repdev, reparr;
+    size_t u, ut, s, x, r, p, q, grad, fmask, state, params, repdev, reparr;
     size_t total;
 };
 
@@ -190,6 +190,7 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
         L.p = take(B * 2 * n2 * sizeof(float));
         L.q = take(B * 2 * n2 * sizeof(float));
         L.grad = take(B * 2 * n2 * sizeof(float));
+        L.fmask = take(B * 2 * n2);
         L.state = take(B * sizeof(LMState));
         L.params = take(B * sizeof(LMParamsDev));
         L.repdev = take(B * sizeof(ReportDev));
@@ -681,6 +682,8 @@ bool params_ok(const pget_lm_params* p)
     if (!(p->d_f > 0) || !(p->d_mu > 0) || !(p->eta >= 0) || !(p->tau > 0)) return false;
     if (!(p->f_lo <= p->f_hi) || !(p->mu_lo <= p->mu_hi)) return false;
     if (!(p->tol >= 0)) return false;
+    if (!(p->w_f >= 0) || !(p->w_mu >= 0) || !isfinite(p->w_f) || !isfinite(p->w_mu)) return false;
+    if (p->active_set != 0 && p->active_set != 1) return false;
     return true;
 }
 
@@ -703,6 +706,9 @@ LMParamsDev to_dev(const pget_lm_params& p)
     d.mu_lo = p.mu_lo;
     d.mu_hi = p.mu_hi;
     d.tol = p.tol;
+    d.w_f = p.w_f > 0 ? p.w_f : 1.0;
+    d.w_mu = p.w_mu > 0 ? p.w_mu : 1.0;
+    d.active_set = p.active_set;
     d.has_replay = p.replay != nullptr;
     if (p.replay)
         for (int k = 0; k < p.max_outer; ++k) d.replay[k] = p.replay[k];
@@ -792,6 +798,7 @@ void setup(Solve& S)
     J.src.stride = 2 * n2;
     J.src.kind = 1;
     J.src.n_rr = S.sh.n_ew_blocks;
+    J.src.prm = reinterpret_cast<const LMParamsDev*>(at(ws, S.L.params));
 
     float* s = reinterpret_cast<float*>(at(ws, S.L.s));
     S.jpred = J;
@@ -835,6 +842,7 @@ void setup(Solve& S)
     V.p = p;
     V.q = reinterpret_cast<float*>(at(ws, S.L.q));
     V.grad = reinterpret_cast<float*>(at(ws, S.L.grad));
+    V.fmask = reinterpret_cast<uint8_t*>(at(ws, S.L.fmask));
     V.gpart = S.vcg.gpart;
     V.gpart_group_stride = S.vcg.gpart_group_stride;
     V.gpart_slice_stride = S.vcg.gpart_slice_stride;

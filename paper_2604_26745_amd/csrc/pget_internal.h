@@ -61,6 +61,8 @@ struct LMParamsDev {
     int max_outer, n_cg;
     double beta0, tau, eta, d_f, d_mu;
     double f_lo, f_hi, mu_lo, mu_hi, tol;
+    double w_f, w_mu;       // CG preconditioner W = diag(w_f I, w_mu I)
+    int active_set;         // 1: CG on the free variables only
     int has_replay;
     int8_t replay[256];
 };
@@ -135,6 +137,7 @@ struct PairSrc {
     int rr_slot_prev;
     int n_rr;             // partials per rr slot
     int first;            // kind 1: 1 on the first CG step (beta = 0)
+    const LMParamsDev* prm;  // kind 1: per-slice scales w_f, w_mu of a (nullptr: 1)
 };
 
 enum MarchMode { MARCH_FWD = 0, MARCH_LIN = 1, MARCH_TRIAL = 2 };
@@ -201,6 +204,7 @@ struct VecArgs {
     float* p;               // CG direction (previous step's on entry to k_cg_x)
     float* q;               // (J^T J + beta D + R) p
     float* grad;            // gradient g
+    uint8_t* fmask;         // 1 where a variable is free (active set on)
     const float* gpart;     // angle-group partials of the adjoint
     long long gpart_group_stride, gpart_slice_stride;
     int groups;

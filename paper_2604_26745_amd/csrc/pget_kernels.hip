@@ -159,14 +159,21 @@ __device__ float resolve_beta(const PairSrc& s, const double* part, int slice, d
     return prev > 0.0 ? (float)(cur / prev) : 0.0f;
 }
 
-__device__ __forceinline__ float2 src_value(const PairSrc& s, int slice, int idx, float beta)
+// Scales of a in a source of kind 1 (the CG preconditioner W of the slice).
+__device__ __forceinline__ float2 src_scale(const PairSrc& s, int slice)
+{
+    if (s.kind != 1 || !s.prm) return make_float2(1.0f, 1.0f);
+    return make_float2((float)s.prm[slice].w_f, (float)s.prm[slice].w_mu);
+}
+
+__device__ __forceinline__ float2 src_value(const PairSrc& s, int slice, int idx, float beta, float2 w)
 {
     if (s.kind == 2) return make_float2(1.0f, 1.0f);
     size_t o = (size_t)slice * s.stride + idx;
     float2 v = make_float2(s.af[o], s.am[o]);
     if (s.kind == 1) {
-        v.x = fmaf(beta, s.bf[o], v.x);
-        v.y = fmaf(beta, s.bm[o], v.y);
+        v.x = fmaf(beta, s.bf[o], w.x * v.x);
+        v.y = fmaf(beta, s.bm[o], w.y * v.y);
     }
     return v;
 }
@@ -178,6 +185,7 @@ __device__ void stage_image(typename S::px_t* dst, const PairSrc& s, int slice, 
                             float beta)
 {
     const int total = pitch * pitch;
+    const float2 w = src_scale(s, slice);
     constexpr int U = 4;
     for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
         float2 v[U];
@@ -187,7 +195,7 @@ __device__ void stage_image(typename S::px_t* dst, const PairSrc& s, int slice, 
             const int rr = idx / pitch - 1, cc = idx - (idx / pitch) * pitch - 1;
             v[u] = make_float2(0.0f, 0.0f);
             if (idx < total && rr >= 0 && rr < n && cc >= 0 && cc < n)
-                v[u] = src_value(s, slice, rr * n + cc, beta);
+                v[u] = src_value(s, slice, rr * n + cc, beta, w);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -206,12 +214,13 @@ __global__ void __launch_bounds__(256) k_pack(Geo g, PairSrc s, const double* pa
     const int slice = blockIdx.y;
     if (st && st[slice].done) return;
     float beta = resolve_beta(s, part, slice, sh);
+    const float2 w = src_scale(s, slice);
     const int pitch = g.pitch, total = pitch * pitch;
     typename SP::px_t* dst = static_cast<typename SP::px_t*>(out_v) + (size_t)slice * out_stride;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
         int rr = idx / pitch - 1, cc = idx - (idx / pitch) * pitch - 1;
         float2 v = make_float2(0.0f, 0.0f);
-        if (rr >= 0 && rr < g.n && cc >= 0 && cc < g.n) v = src_value(s, slice, rr * g.n + cc, beta);
+        if (rr >= 0 && rr < g.n && cc >= 0 && cc < g.n) v = src_value(s, slice, rr * g.n + cc, beta, w);
         dst[idx] = SP::to_px(v);
     }
 }
@@ -834,7 +843,8 @@ __device__ __forceinline__ float grad2(const float* x, int n, int r, int c)
 }
 
 // Start of an outer iteration: g = J^T (A(u) - y) + R u;  CG state x = 0,
-// r = -g, p = 0;  partials of ||g||^2 (= r.r) and alpha ||grad u||^2.
+// r = -F g (F: the free-variable mask when the active set is on, else 1),
+// p = 0;  partials of r.W r, ||g||^2 and alpha ||grad u||^2.
 __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
 {
     __shared__ double sh[16];
@@ -847,7 +857,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
     alphas_at(V.prm[slice], st.k, af, am);
     const size_t vo = (size_t)slice * V.vstride;
     const float* gp = V.gpart + (size_t)slice * V.gpart_slice_stride;
-    double rr = 0.0, reg = 0.0;
+    const LMParamsDev& P = V.prm[slice];
+    double rr = 0.0, gg = 0.0, reg = 0.0;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m < n2) {
         const int r = m / n, c = m - r * n;
@@ -862,25 +873,39 @@ __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
         gm = fmaf(am, lap(um, n, r, c), gm);
         V.grad[vo + m] = gf;
         V.grad[vo + n2 + m] = gm;
-        V.r[vo + m] = -gf;
-        V.r[vo + n2 + m] = -gm;
+        float rf = -gf, rm = -gm;
+        if (P.active_set) {
+            // held: on the lower bound with g > 0, or on the upper bound with g < 0
+            const float f0 = uf[m], m0 = um[m];
+            const bool hold_f = (f0 <= (float)P.f_lo && gf > 0.0f) || (f0 >= (float)P.f_hi && gf < 0.0f);
+            const bool hold_m = (m0 <= (float)P.mu_lo && gm > 0.0f) || (m0 >= (float)P.mu_hi && gm < 0.0f);
+            V.fmask[vo + m] = hold_f ? 0 : 1;
+            V.fmask[vo + n2 + m] = hold_m ? 0 : 1;
+            if (hold_f) rf = 0.0f;
+            if (hold_m) rm = 0.0f;
+        }
+        V.r[vo + m] = rf;
+        V.r[vo + n2 + m] = rm;
         V.x[vo + m] = 0.0f;
         V.x[vo + n2 + m] = 0.0f;
         V.p[vo + m] = 0.0f;
         V.p[vo + n2 + m] = 0.0f;
-        rr = (double)gf * gf + (double)gm * gm;
+        rr = (double)(float)P.w_f * ((double)rf * rf) + (double)(float)P.w_mu * ((double)rm * rm);
+        gg = (double)gf * gf + (double)gm * gm;
         reg = (double)af * grad2(uf, n, r, c) + (double)am * grad2(um, n, r, c);
     }
     double s1 = block_sum(rr, sh);
+    double s3 = block_sum(gg, sh);
     double s2 = block_sum(reg, sh);
     if (threadIdx.x == 0) {
         slot_ptr(V.part, slice, SLOT_RR0)[blockIdx.x] = s1;
+        slot_ptr(V.part, slice, SLOT_GNORM)[blockIdx.x] = s3;
         slot_ptr(V.part, slice, SLOT_PHI_REG_U)[blockIdx.x] = s2;
     }
 }
 
-// CG step, first half: p = r + beta_cg p_old (beta_cg = rr_m / rr_{m-1}),
-// q = J^T J p + beta D p + R p, partials of gamma = p.q.
+// CG step, first half: p = W r + beta_cg p_old (beta_cg = rr_m / rr_{m-1},
+// rr = r.W r), q = F (J^T J p + beta D p + R p), partials of gamma = p.q.
 __global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
 {
     __shared__ double sh[16];
@@ -897,12 +922,15 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
         bcg = rr_prev > 0.0 ? (float)(rr_cur / rr_prev) : 0.0f;
         if (blockIdx.x == 0 && threadIdx.x == 0 && V.rep)
             V.rep[slice].cg_rr[(size_t)st.k * V.prm[slice].n_cg + (m_step - 1)] = rr_cur;
-    } else if (blockIdx.x == 0 && threadIdx.x == 0 && V.rep) {
-        V.rep[slice].gnorm[st.k] = sqrt(rr_cur);   // r = -g at the first step
+    } else if (blockIdx.x == 0 && V.rep) {
+        const double gg = sum_partials(slot_ptr(V.part, slice, SLOT_GNORM), V.n_ew_blocks, sh);
+        if (threadIdx.x == 0) V.rep[slice].gnorm[st.k] = sqrt(gg);
     }
     float af, am;
     alphas_at(V.prm[slice], st.k, af, am);
     const float bdf = (float)(st.beta * V.prm[slice].d_f), bdm = (float)(st.beta * V.prm[slice].d_mu);
+    const float wf = (float)V.prm[slice].w_f, wm = (float)V.prm[slice].w_mu;
+    const int act = V.prm[slice].active_set;
     const size_t vo = (size_t)slice * V.vstride;
     const float* gp = V.gpart + (size_t)slice * V.gpart_slice_stride;
     double gam = 0.0;
@@ -914,20 +942,25 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
         const float* pf = V.p + vo;
         const float* pm = pf + n2;
         // p at the pixel and its 4 neighbours
-        auto P = [&](const float* rr_, const float* pp_, int mm) { return fmaf(bcg, pp_[mm], rr_[mm]); };
-        const float pfc = P(rf, pf, m), pmc = P(rm, pm, m);
+        auto PF = [&](int mm) { return fmaf(bcg, pf[mm], wf * rf[mm]); };
+        auto PM = [&](int mm) { return fmaf(bcg, pm[mm], wm * rm[mm]); };
+        const float pfc = PF(m), pmc = PM(m);
         float lf = 0.0f, lm = 0.0f;
-        if (c > 0) { lf += pfc - P(rf, pf, m - 1); lm += pmc - P(rm, pm, m - 1); }
-        if (c + 1 < n) { lf += pfc - P(rf, pf, m + 1); lm += pmc - P(rm, pm, m + 1); }
-        if (r > 0) { lf += pfc - P(rf, pf, m - n); lm += pmc - P(rm, pm, m - n); }
-        if (r + 1 < n) { lf += pfc - P(rf, pf, m + n); lm += pmc - P(rm, pm, m + n); }
+        if (c > 0) { lf += pfc - PF(m - 1); lm += pmc - PM(m - 1); }
+        if (c + 1 < n) { lf += pfc - PF(m + 1); lm += pmc - PM(m + 1); }
+        if (r > 0) { lf += pfc - PF(m - n); lm += pmc - PM(m - n); }
+        if (r + 1 < n) { lf += pfc - PF(m + n); lm += pmc - PM(m + n); }
         float gf = 0.0f, gm = 0.0f;
         for (int k = 0; k < V.groups; ++k) {
             gf += gp[(size_t)k * V.gpart_group_stride + m];
             gm += gp[(size_t)k * V.gpart_group_stride + n2 + m];
         }
-        const float qf = fmaf(af, lf, fmaf(bdf, pfc, gf));
-        const float qm = fmaf(am, lm, fmaf(bdm, pmc, gm));
+        float qf = fmaf(af, lf, fmaf(bdf, pfc, gf));
+        float qm = fmaf(am, lm, fmaf(bdm, pmc, gm));
+        if (act) {
+            if (!V.fmask[vo + m]) qf = 0.0f;
+            if (!V.fmask[vo + n2 + m]) qm = 0.0f;
+        }
         V.q[vo + m] = qf;
         V.q[vo + n2 + m] = qm;
         gam = (double)pfc * qf + (double)pmc * qm;
@@ -937,7 +970,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
 }
 
 // CG step, second half: alpha = rr_m / gamma; x += alpha p; r -= alpha q;
-// p_old <- p; partials of rr_{m+1}.
+// p_old <- p; partials of rr_{m+1} = r.W r.
 __global__ void __launch_bounds__(EW_THREADS) k_cg_x(VecArgs V)
 {
     __shared__ double sh[16];
@@ -956,18 +989,19 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_x(VecArgs V)
     double gam = sum_partials(slot_ptr(V.part, slice, SLOT_GAMMA), V.n_ew_blocks, sh);
     const float alpha = (gam > 0.0 && rr_cur > 0.0) ? (float)(rr_cur / gam) : 0.0f;
     const size_t vo = (size_t)slice * V.vstride;
+    const float w2[2] = {(float)V.prm[slice].w_f, (float)V.prm[slice].w_mu};
     double rr = 0.0;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m < n2) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const size_t o = vo + (size_t)b * n2 + m;
-            const float p = fmaf(bcg, V.p[o], V.r[o]);
+            const float p = fmaf(bcg, V.p[o], w2[b] * V.r[o]);
             V.x[o] = fmaf(alpha, p, V.x[o]);
             const float rn = fmaf(-alpha, V.q[o], V.r[o]);
             V.r[o] = rn;
             V.p[o] = p;
-            rr += (double)rn * rn;
+            rr += (double)w2[b] * ((double)rn * rn);
         }
     }
     double s = block_sum(rr, sh);

@@ -52,6 +52,7 @@ class LMParams(ctypes.Structure):
         ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double),
         ("mu_lo", ctypes.c_double), ("mu_hi", ctypes.c_double),
         ("tol", ctypes.c_double), ("replay", ctypes.POINTER(ctypes.c_int8)),
+        ("w_f", ctypes.c_double), ("w_mu", ctypes.c_double), ("active_set", ctypes.c_int32),
     ]
 
 
@@ -166,6 +167,9 @@ class SolverParams:
     mu_hi: float = math.inf
     tol: float = 0.0
     replay: Optional[Sequence[int]] = None
+    w_f: float = 1.0          # CG preconditioner W = diag(w_f I, w_mu I)
+    w_mu: float = 1.0
+    active_set: int = 0       # 1: CG on the variables not held at a bound
 
     def to_c(self):
         p = LMParams()
