@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=64, help="slices reconstructed per step")
     ap.add_argument("--outer", type=int, default=15)
+    ap.add_argument("--solver", default="scaled", choices=["scaled", "plain"],
+                    help="scaled: damping and CG in variables divided by their typical magnitudes "
+                         "(1 for emission, 0.05 for attenuation) with the active set; plain: "
+                         "D = W = I, clamp only")
     ap.add_argument("--cg", type=int, default=30)
     ap.add_argument("--no-single", action="store_true", help="skip the single-slice latency run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -70,6 +74,30 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (scale for HBM counters)")
     return ap.parse_args()
+
+
+# Damped-step options of the main workload.  "scaled": the LM step taken in
+# variables divided by their typical magnitudes (emission 1, attenuation
+# 0.05 per pixel), i.e. identity damping and plain CG there (D = diag(1,
+# 1/0.05^2), W = D^-1), with the variables held at a bound left out of CG.
+SOLVER_OPTIONS = {
+    "scaled": {"w_mu": 0.05 ** 2, "d_mu": 1.0 / 0.05 ** 2, "active_set": 1},
+    "plain": {},
+}
+
+
+def quality(fs, ms, cfg, inputs, np):
+    """Mean relative L2 error of the reconstructions against the phantoms
+    inside the disk of the field of view."""
+    cc = np.arange(cfg.n) - 0.5 * (cfg.n - 1)
+    X, Y = np.meshgrid(cc, cc)
+    disk = X ** 2 + Y ** 2 <= (0.5 * cfg.n) ** 2
+    ef, em = [], []
+    for s in range(len(fs)):
+        tf, tm = inputs.rod_lattice(cfg, s)
+        ef.append(np.linalg.norm((fs[s].cpu().numpy() - tf)[disk]) / np.linalg.norm(tf[disk]))
+        em.append(np.linalg.norm((ms[s].cpu().numpy() - tm)[disk]) / np.linalg.norm(tm[disk]))
+    return {"f_rel_err_fov": round(float(np.mean(ef)), 4), "mu_rel_err_fov": round(float(np.mean(em)), 4)}
 
 
 def make_inputs(plan, cfg, batch, torch, inputs, np):
@@ -303,9 +331,9 @@ def run_deepgn(args, torch, np, inputs, pget):
     (seeds 0..n_test-1) against plain LM at the same and at 15 outer
     iterations.  --dg-set lattice: the 128^2 9x9 lattice of the main workload
     (Poisson counts, f0 = c0, mu0 = 0, the solver defaults); scanner: the
-    165^2 scanner geometry (data from the 330^2 grid, 2 % Gaussian noise),
-    with the attenuation damped in units of its upper bound (d_mu = 50) and a
-    water-level start, for LM and Deep-GN alike.  Convolutions run without
+    165^2 scanner geometry (data from the 330^2 grid, 2 % Gaussian noise)
+    with a water-level start.  Both use the scaled damped step with the
+    active set, for LM and Deep-GN alike.  Convolutions run without
     MIOpen (PyTorch's GEMM path), so no kernel search runs on a fresh box."""
     from paper_2604_26745_amd import refine
     torch.backends.cudnn.enabled = False
@@ -326,10 +354,11 @@ def run_deepgn(args, torch, np, inputs, pget):
         mask = inputs.fov_mask(cfg)
         water = np.where(mask, cfg.water_mu, 0.0)
         f_max, mu_max = 1.0, 0.14
-        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha,
-                                d_mu=50.0)
+        # the scaled step with attenuation in units of its upper bound 0.14 /mm
+        opts = {"w_mu": 0.14 ** 2, "d_mu": 1.0 / 0.14 ** 2, "active_set": 1}
+        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts)
         wl = "deepgn_scanner9x9_n165_K%d" % K
-        extra = {"d_mu": 50.0, "mu0": "water in the field of view"}
+        extra = {"solver": opts, "mu0": "water in the field of view"}
         data = "synthetic: scanner-geometry 9x9 assemblies, 2% Gaussian noise"
     else:
         cfg = inputs.MAIN_128
@@ -338,9 +367,10 @@ def run_deepgn(args, torch, np, inputs, pget):
         X, Y = np.meshgrid(cc, cc)
         mask = X ** 2 + Y ** 2 <= (0.5 * cfg.n) ** 2
         f_max, mu_max = 3.0, 0.05
-        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha)
+        opts = SOLVER_OPTIONS["scaled"]
+        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts)
         wl = "deepgn_%s_K%d" % (cfg.name, K)
-        extra = {"mu0": "zero", "peak_counts": cfg.peak_counts}
+        extra = {"solver": opts, "mu0": "zero", "peak_counts": cfg.peak_counts}
         data = "synthetic: 9x9 rod lattices, Poisson counts"
     one = torch.ones((cfg.n, cfg.n), dtype=torch.float32, device="cuda")
     a1 = plan.forward(one, torch.zeros_like(one)).double().cpu().numpy()
@@ -491,7 +521,7 @@ def main():
         print("bench: autotune %s" % plan.autotune(B), file=sys.stderr, flush=True)
     ys, f0s, m0s = make_inputs(plan, cfg, B, torch, inputs, np)
     prm = [pget.SolverParams(max_outer=cfg.max_outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha,
-                             alpha_mu=cfg.alpha) for _ in range(B)]
+                             alpha_mu=cfg.alpha, **SOLVER_OPTIONS[args.solver]) for _ in range(B)]
     print("bench: %d slices of %s, %d outer x %d CG, warmup %d, steps %d"
           % (B, cfg.name, cfg.max_outer, cfg.n_cg, args.warmup, args.steps), file=sys.stderr,
           flush=True)
@@ -561,9 +591,9 @@ def main():
     kernel_gbs = {}
     for cls, kname in (("march", "k_march"), ("jvp", "k_jvp_lin"), ("vjp", "k_vjp_lin")):
         b = traffic_from_profile(kname, workload)
-        ms, n = kt[cls]
+        cls_ms, n = kt[cls]
         if b and n:
-            kernel_gbs[kname] = round(b / (ms / 1e3 / n) / 1e9, 1)
+            kernel_gbs[kname] = round(b / (cls_ms / 1e3 / n) / 1e9, 1)
     kernel_share = {k: round(v[0] / (1e3 * instrumented_s), 4) for k, v in kt.items()}
     if kernel_gbs:
         roofline["kernel_hbm_gbs"] = kernel_gbs
@@ -604,8 +634,11 @@ def main():
             "slices_per_step": B,
             "grid": cfg.n, "angles": cfg.n_angles, "bins": cfg.n_bins, "psf_sigma": cfg.psf_sigma,
             "outer": cfg.max_outer, "cg": cfg.n_cg, "alpha": cfg.alpha,
+            "solver": dict({"name": args.solver}, **SOLVER_OPTIONS[args.solver]),
             "phantom": "9x9 rod lattice, r=4 px, pitch 12 px, 5 empty rods, Poisson peak 1e4",
         },
+        "quality": dict(quality(fs, ms, cfg, inputs, np),
+                        start=quality(f0s, m0s, cfg, inputs, np)),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_time_share": kernel_share,

@@ -116,3 +116,60 @@ def test_lattice9_n128_as_slice_of_batch64():
     assert max(errs) <= 1e-5
     for k in (5, 10, 15):
         assert maps[k][0] <= 1e-5 and maps[k][1] <= 1e-5
+
+
+GOLDEN128S = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lattice9_n128_scaled_oracle.npz")
+
+
+def test_lattice9_n128_scaled_as_slice_of_batch64():
+    """The benchmark's solver options (scaled damping and CG, active set) on
+    slice 0 of a batch of 64, against the stored oracle run of its first 3
+    iterations: the first linearisation tightly (objective 1e-6, gradient
+    norm 1e-5, the first three CG residuals 1e-3 of the start); then the
+    objective per iterate and the maps within five times the spread the
+    oracle itself shows under 1e-6 relative perturbations of its operator
+    products (stored with it), and at least as close as 1e-5."""
+    if not os.path.exists(GOLDEN128S):
+        pytest.skip("stored oracle reconstruction not present")
+    ref = np.load(GOLDEN128S)
+    cfg = inputs.MAIN_128
+    g = O.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    f_true, mu_true = inputs.rod_lattice(cfg, 0)
+    y = inputs.poisson_counts(O.forward(g, f_true, mu_true), cfg.peak_counts, 0)
+    f0, mu0 = OLM.initial_guess(g, y)
+    assert rel(ref["f0"], f0) < 1e-6
+    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+    ones = torch.ones((cfg.n, cfg.n), device="cuda")
+    a1 = plan.forward(ones, torch.zeros_like(ones)).double()
+    ys, f0s, m0s = [T(y)], [T(f0)], [T(mu0)]
+    for s_ in range(1, 64):
+        f, mu = inputs.rod_lattice(cfg, s_)
+        yc = plan.forward(T(f), T(mu)).double().cpu().numpy()
+        ys_ = T(inputs.poisson_counts(yc, cfg.peak_counts, s_))
+        c0 = float((a1 * ys_.double()).sum() / (a1 * a1).sum())
+        ys.append(ys_)
+        f0s.append(torch.full_like(ones, c0))
+        m0s.append(torch.zeros_like(ones))
+    outer = int(ref["outer"])
+    base = dict(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha,
+                w_mu=float(ref["w_mu"]), d_mu=float(ref["d_mu"]), active_set=1)
+    prm = [pget.SolverParams(replay=[int(v) for v in ref["accepted"]], **base)] + [pget.SolverParams(**base)] * 63
+    fs, ms, rbs = plan.lm_solve_batched(ys, f0s, m0s, prm)
+    rep = rbs[0].to_report()
+    assert rep.accepted == [int(v) for v in ref["accepted"]]
+    assert abs(rep.phi[0] - ref["phi"][0]) <= 1e-6 * ref["phi"][0]
+    assert abs(rep.gnorm[0] - ref["gnorm"][0]) <= 1e-5 * ref["gnorm"][0]
+    for m in range(3):
+        assert abs(rep.cg_rr[0][m] - ref["cg_rr0"][m]) <= 1e-3 * ref["cg_rr0"][0]
+    errs = [abs(rep.phi[k] - ref["phi"][k]) / ref["phi"][k] for k in range(len(ref["phi"]))]
+    bounds = [max(1e-5, 5 * v) for v in ref["spread_phi"]]
+    ef, em = rel(fs[0].cpu().numpy(), ref["f3"]), rel(ms[0].cpu().numpy(), ref["mu3"])
+    bf, bm = max(1e-5, 5 * float(ref["spread_f"])), max(1e-5, 5 * float(ref["spread_m"]))
+    print("scaled batch64 slice 0 phi rel err per iterate: %s (bounds %s)" % (
+        " ".join("%.1e" % e for e in errs), " ".join("%.1e" % b for b in bounds)), flush=True)
+    print("scaled batch64 slice 0 maps after %d: f %.1e (bound %.1e) mu %.1e (bound %.1e)" % (outer, ef, bf, em, bm),
+          flush=True)
+    for e, b in zip(errs, bounds):
+        assert e <= b
+    assert ef <= bf and em <= bm

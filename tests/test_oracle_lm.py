@@ -365,3 +365,36 @@ def test_active_set_step_solves_reduced_system():
     p_off = params(active_set=False, n_cg=400)
     it_off = L.lm_iteration(g, y, f, mu, beta, p_off, 0)
     assert np.abs(np.concatenate([it_off.xf.ravel(), it_off.xm.ravel()])[held]).max() > 0.0
+
+
+def test_safeguard_rejects_a_jump_to_the_phantom():
+    """A property of the safeguard (Prop. 3.2, Alg. 2) with the
+    Gauss-Newton model m_k of eq. m-function: m is linear in the
+    attenuation's exponential, so a proposal that jumps far from u_k is
+    judged by a model that no longer holds there.  On a 64 x 64 lattice
+    (scaled step with the active set), the phantom itself as the proposal
+    after the first LM step has m(0) - m(s~) < 0 although Phi(phantom) is
+    far below Phi(u_0 + s_0), so it is rejected; the point halfway from
+    u_0 + s_0 to the phantom is kept by rho but not by m(s~) <= m(s)."""
+    cfg = inputs.SMALL_64
+    g = O.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    ft, mt = inputs.rod_lattice(cfg, 0)
+    y = inputs.poisson_counts(O.forward(g, ft, mt), cfg.peak_counts, 0)
+    f0, mu0 = L.initial_guess(g, y)
+    p = L.LMParams(max_outer=1, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha,
+                   w_mu=0.05 ** 2, d_mu=1 / 0.05 ** 2, active_set=True)
+    beta = L.initial_damping(g, f0, mu0, p)
+    it = L.lm_iteration(g, y, f0, mu0, beta, p, 0)
+    assert it.rho > p.eta and it.pred > 0
+    af, am = p.alpha_f, p.alpha_mu
+    kept = []
+    for lam in (1.0, 0.5):
+        tf = it.f_trial + lam * (ft - it.f_trial)
+        tm = it.mu_trial + lam * (mt - it.mu_trial)
+        pred_t = L.model_decrease(g, f0, mu0, it.gf, it.gm, tf - f0, tm - mu0, af, am)
+        phi_t = L.objective(g, y, tf, tm, af, am)[0]
+        assert phi_t < it.phi_trial                      # both are better points than the LM trial
+        rho_t = (it.phi - phi_t) / pred_t if pred_t > 0 else -np.inf
+        kept.append((rho_t > p.eta, pred_t >= it.pred, pred_t))
+    assert kept[0][2] < 0 and not kept[0][0]            # the phantom: the model predicts an increase
+    assert kept[1][0] and not kept[1][1]                 # halfway: rho passes, m(s~) > m(s)
