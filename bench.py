@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=64, help="slices reconstructed per step")
     ap.add_argument("--outer", type=int, default=15)
+    ap.add_argument("--prior", type=float, default=0.0,
+                    help="geometry prior weight gamma (main and scanner workloads): gamma on "
+                         "emission and gamma / mu_scale^2 on attenuation wherever no rod can lie; 0 = off")
     ap.add_argument("--solver", default="scaled", choices=["scaled", "plain"],
                     help="scaled: damping and CG in variables divided by their typical magnitudes "
                          "(1 for emission, 0.05 for attenuation) with the active set; plain: "
@@ -84,6 +87,22 @@ SOLVER_OPTIONS = {
     "scaled": {"w_mu": 0.05 ** 2, "d_mu": 1.0 / 0.05 ** 2, "active_set": 1},
     "plain": {},
 }
+# The same for the scanner geometry: attenuation bounded by 0.14 /mm.
+SCANNER_SOLVER_OPTIONS = {
+    "scaled": {"w_mu": 0.14 ** 2, "d_mu": 1.0 / 0.14 ** 2, "active_set": 1},
+    "plain": {},
+}
+
+
+def prior_tensors(gamma, mu_scale, region, ref_f, ref_mu, torch, np):
+    """Device weights and references of the geometry prior (None when gamma
+    is 0): gamma on emission and gamma / mu_scale^2 on attenuation inside
+    the region where no rod can lie."""
+    if gamma <= 0.0:
+        return {}
+    w = np.stack([gamma * region, gamma / mu_scale ** 2 * region])
+    T = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    return {"prior_w": T(w), "prior_ref": T(np.stack([ref_f, ref_mu]))}
 
 
 def quality(fs, ms, cfg, inputs, np):
@@ -265,8 +284,11 @@ def run_scanner(args, torch, np, inputs, pget):
     """Scanner geometry: 9x9 assemblies (full / missing / replaced / medium
     rods in turn) drawn on a 330^2 grid of 0.5 mm pixels, projected there by
     the library, 2 % Gaussian noise, reconstructed batched on the 165^2 grid
-    of 1 mm pixels (182 bins of 2 mm, 360 angles).  Reports throughput and
-    the mean relative error of the maps inside the field of view."""
+    of 1 mm pixels (182 bins of 2 mm, 360 angles).  --solver scaled: the step
+    in variables divided by their upper bounds (emission 1, attenuation
+    0.14 /mm) with the active set, started from water inside the field of
+    view; plain: D = W = I from mu0 = 0.  Reports throughput and the mean
+    relative error of the maps inside the field of view."""
     import dataclasses
     cfg = dataclasses.replace(inputs.SCANNER_165, max_outer=args.outer, n_cg=args.cg)
     geo = {}
@@ -290,9 +312,14 @@ def run_scanner(args, torch, np, inputs, pget):
         c0 = float((a1 * y).sum() / (a1 * a1).sum())
         ys.append(T(y))
         f0s.append(torch.full((cfg.n, cfg.n), c0, dtype=torch.float32, device="cuda"))
-        m0s.append(torch.zeros((cfg.n, cfg.n), dtype=torch.float32, device="cuda"))
-    prm = [pget.SolverParams(max_outer=cfg.max_outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha)
-           for _ in range(B)]
+        if args.solver == "scaled":
+            m0s.append(T(np.where(inputs.fov_mask(cfg), cfg.water_mu, 0.0)))
+        else:
+            m0s.append(torch.zeros((cfg.n, cfg.n), dtype=torch.float32, device="cuda"))
+    opts = SCANNER_SOLVER_OPTIONS[args.solver]
+    prior = prior_tensors(args.prior, cfg.rod_mu_range[1], *inputs.scanner_rod_prior(cfg), torch, np)
+    prm = [pget.SolverParams(max_outer=cfg.max_outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts,
+                             **prior) for _ in range(B)]
     print("bench: scanner geometry, %d slices, data on the %d^2 grid" % (B, cfg.n * cfg.oversample),
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -316,7 +343,9 @@ def run_scanner(args, torch, np, inputs, pget):
         "dtype": "f32" if args.storage == "fp32" else "bf16-storage/f32-compute",
         "data": "synthetic: 9x9 assemblies on a 0.5 mm grid, 2% Gaussian noise",
         "config": {"workload": "%s_batch%d" % (cfg.name, B), "outer": cfg.max_outer, "cg": cfg.n_cg,
-                   "pixel_mm": cfg.pixel_mm, "bin_mm": cfg.bin_mm, "oversample": cfg.oversample},
+                   "pixel_mm": cfg.pixel_mm, "bin_mm": cfg.bin_mm, "oversample": cfg.oversample,
+                   "solver": dict({"name": args.solver, "prior_gamma": args.prior}, **opts),
+                   "mu0": "water in the field of view" if args.solver == "scaled" else "zero"},
         "quality": {"f_rel_err_fov": round(float(np.mean(ef)), 4), "mu_rel_err_fov": round(float(np.mean(em)), 4),
                     "initial_f_rel_err_fov": round(float(np.mean(
                         [np.linalg.norm((f0.cpu().numpy() - t[0])[mask]) / np.linalg.norm(t[0][mask])
@@ -354,8 +383,7 @@ def run_deepgn(args, torch, np, inputs, pget):
         mask = inputs.fov_mask(cfg)
         water = np.where(mask, cfg.water_mu, 0.0)
         f_max, mu_max = 1.0, 0.14
-        # the scaled step with attenuation in units of its upper bound 0.14 /mm
-        opts = {"w_mu": 0.14 ** 2, "d_mu": 1.0 / 0.14 ** 2, "active_set": 1}
+        opts = SCANNER_SOLVER_OPTIONS["scaled"]
         prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts)
         wl = "deepgn_scanner9x9_n165_K%d" % K
         extra = {"solver": opts, "mu0": "water in the field of view"}
@@ -520,8 +548,9 @@ def main():
     if args.autotune:
         print("bench: autotune %s" % plan.autotune(B), file=sys.stderr, flush=True)
     ys, f0s, m0s = make_inputs(plan, cfg, B, torch, inputs, np)
+    prior = prior_tensors(args.prior, 0.05, *inputs.lattice_rod_prior(cfg), torch, np)
     prm = [pget.SolverParams(max_outer=cfg.max_outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha,
-                             alpha_mu=cfg.alpha, **SOLVER_OPTIONS[args.solver]) for _ in range(B)]
+                             alpha_mu=cfg.alpha, **SOLVER_OPTIONS[args.solver], **prior) for _ in range(B)]
     print("bench: %d slices of %s, %d outer x %d CG, warmup %d, steps %d"
           % (B, cfg.name, cfg.max_outer, cfg.n_cg, args.warmup, args.steps), file=sys.stderr,
           flush=True)
@@ -634,7 +663,7 @@ def main():
             "slices_per_step": B,
             "grid": cfg.n, "angles": cfg.n_angles, "bins": cfg.n_bins, "psf_sigma": cfg.psf_sigma,
             "outer": cfg.max_outer, "cg": cfg.n_cg, "alpha": cfg.alpha,
-            "solver": dict({"name": args.solver}, **SOLVER_OPTIONS[args.solver]),
+            "solver": dict({"name": args.solver, "prior_gamma": args.prior}, **SOLVER_OPTIONS[args.solver]),
             "phantom": "9x9 rod lattice, r=4 px, pitch 12 px, 5 empty rods, Poisson peak 1e4",
         },
         "quality": dict(quality(fs, ms, cfg, inputs, np),

@@ -163,6 +163,14 @@ pget_status pget_vjp(const pget_plan* plan, const float* f, const float* mu, con
  * of the box at zero step and runs CG on the free ones; 0 leaves every
  * variable free (the clamp alone keeps the trial point in the box).
  * cg_rr then reports r^T W r.
+ * prior_w, prior_ref: the geometry prior (the paper's P1, P2, Sec. 2.2,
+ * penalising emission and attenuation outside the possible rod locations),
+ * Phi += 0.5 sum_m prior_w[m] (u[m] - prior_ref[m])^2 over the 2 N^2
+ * elements of u = (f, mu) (f block first, row-major, like the maps).  Device
+ * pointers owned by the caller, read on the stream until the solve ends;
+ * prior_w = NULL: no prior; prior_ref = NULL: zero reference.  Weights must
+ * be >= 0 (not checked: the solver reads them on the device); they are
+ * divided by the same continuation factor as the alphas.
  */
 typedef struct {
     int32_t max_outer;        /* >= 1                                        */
@@ -178,6 +186,8 @@ typedef struct {
     const int8_t* replay;     /* host pointer, max_outer entries, or NULL    */
     double w_f, w_mu;         /* CG preconditioner, > 0 (0 -> 1)             */
     int32_t active_set;       /* 0 or 1                                      */
+    const float* prior_w;     /* device, 2 N^2, or NULL                      */
+    const float* prior_ref;   /* device, 2 N^2, or NULL                      */
 } pget_lm_params;
 
 /*

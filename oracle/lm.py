@@ -29,6 +29,12 @@ readings where the paper is silent:
 * hook       after an accepted step, u~ = G(u, s) replaces u' iff
              rho(u~ - u) > eta and m(u~ - u) <= m(s)  (Prop. 3.2, Alg. 2).
 * continuation  alpha_k = alpha / decay**min(k, decay_until)  (Sec. 3.1).
+* geometry prior (option; the paper's P1, P2 of Sec. 2.2, which penalise
+             emission and attenuation outside the possible rod locations):
+             + 0.5 * sum_m w_f[m] (f[m] - r_f[m])^2 + the same for mu, with
+             per-pixel weights w >= 0 and references r given by the caller
+             (e.g. w = gamma outside the rod disks, r_mu = water there);
+             its Hessian diag(w) joins R, and it decays with the alphas.
 """
 from __future__ import annotations
 
@@ -61,6 +67,10 @@ class LMParams:
     w_f: float = 1.0
     w_mu: float = 1.0
     active_set: bool = False
+    prior_w_f: Optional[np.ndarray] = None
+    prior_w_mu: Optional[np.ndarray] = None
+    prior_ref_f: Optional[np.ndarray] = None
+    prior_ref_mu: Optional[np.ndarray] = None
 
 
 @dataclass
@@ -86,24 +96,48 @@ def alphas_at(p: LMParams, k: int):
     return p.alpha_f / decay, p.alpha_mu / decay
 
 
-def objective(g: Geometry, y, f, mu, af, am):
+def prior_at(p: LMParams, k: int):
+    """(w_f, w_mu, r_f, r_mu) of the geometry prior at outer iteration k
+    (weights divided by the same continuation factor as the alphas), or
+    None when the solve has no prior."""
+    if p.prior_w_f is None and p.prior_w_mu is None:
+        return None
+    decay = p.alpha_decay ** min(k, p.alpha_decay_until)
+
+    def arr(a, fill):
+        return np.full(np.shape(p.prior_w_f if p.prior_w_f is not None else p.prior_w_mu), fill) if a is None \
+            else np.asarray(a, dtype=np.float64)
+    return (arr(p.prior_w_f, 0.0) / decay, arr(p.prior_w_mu, 0.0) / decay,
+            arr(p.prior_ref_f, 0.0), arr(p.prior_ref_mu, 0.0))
+
+
+def objective(g: Geometry, y, f, mu, af, am, prior=None):
     """Phi(u) and the data residual A(u) - y."""
     r = forward(g, f, mu) - y
     phi = 0.5 * float(np.dot(r.ravel(), r.ravel())) + reg_energy(af, f) + reg_energy(am, mu)
+    if prior is not None:
+        wf, wm, rf, rm = prior
+        phi += 0.5 * float(np.sum(wf * (f - rf) ** 2) + np.sum(wm * (mu - rm) ** 2))
     return phi, r
 
 
-def gradient(g: Geometry, f, mu, r, af, am):
+def gradient(g: Geometry, f, mu, r, af, am, prior=None):
     gf, gm = vjp(g, f, mu, r)
-    return gf + reg_gradient(af, f), gm + reg_gradient(am, mu)
+    gf, gm = gf + reg_gradient(af, f), gm + reg_gradient(am, mu)
+    if prior is not None:
+        wf, wm, rf, rm = prior
+        gf, gm = gf + wf * (f - rf), gm + wm * (mu - rm)
+    return gf, gm
 
 
-def normal_matvec(g: Geometry, f, mu, pf, pm, beta, p: LMParams, af, am):
-    """(J^T J + beta D + R) [pf, pm]."""
+def normal_matvec(g: Geometry, f, mu, pf, pm, beta, p: LMParams, af, am, prior=None):
+    """(J^T J + beta D + R) [pf, pm]  (R includes the prior's diag(w))."""
     jp = jvp(g, f, mu, pf, pm)
     qf, qm = vjp(g, f, mu, jp)
     qf = qf + beta * p.d_f * pf + reg_gradient(af, pf)
     qm = qm + beta * p.d_mu * pm + reg_gradient(am, pm)
+    if prior is not None:
+        qf, qm = qf + prior[0] * pf, qm + prior[1] * pm
     return qf, qm
 
 
@@ -153,10 +187,12 @@ def free_set(f, mu, gf, gm, p: LMParams):
     return (~hold_f).astype(np.float64), (~hold_m).astype(np.float64)
 
 
-def model_decrease(g: Geometry, f, mu, gf, gm, sf, sm, af, am) -> float:
+def model_decrease(g: Geometry, f, mu, gf, gm, sf, sm, af, am, prior=None) -> float:
     """pred = m(0) - m(s) = -(g.s + 0.5*(||J s||^2 + s.R s))  (eq. m-function)."""
     js = jvp(g, f, mu, sf, sm)
     sRs = 2.0 * (reg_energy(af, sf) + reg_energy(am, sm))
+    if prior is not None:
+        sRs += float(np.sum(prior[0] * sf * sf) + np.sum(prior[1] * sm * sm))
     gs = float(np.sum(gf * sf) + np.sum(gm * sm))
     return -(gs + 0.5 * (float(np.sum(js * js)) + sRs))
 
@@ -207,24 +243,25 @@ class Iterate:
 def lm_iteration(g: Geometry, y, f, mu, beta, p: LMParams, k: int) -> Iterate:
     """One outer iteration up to (not including) the accept decision."""
     af, am = alphas_at(p, k)
-    phi, r = objective(g, y, f, mu, af, am)
-    gf, gm = gradient(g, f, mu, r, af, am)
+    pr = prior_at(p, k)
+    phi, r = objective(g, y, f, mu, af, am, pr)
+    gf, gm = gradient(g, f, mu, r, af, am, pr)
     if p.active_set:
         ff, fm = free_set(f, mu, gf, gm, p)
 
         def mv(a, b):
-            qf, qm = normal_matvec(g, f, mu, ff * a, fm * b, beta, p, af, am)
+            qf, qm = normal_matvec(g, f, mu, ff * a, fm * b, beta, p, af, am, pr)
             return ff * qf, fm * qm
         xf, xm, rr = cg(mv, -ff * gf, -fm * gm, p.n_cg, p.w_f, p.w_mu)
     else:
         xf, xm, rr = cg(
-            lambda a, b: normal_matvec(g, f, mu, a, b, beta, p, af, am), -gf, -gm, p.n_cg, p.w_f, p.w_mu
+            lambda a, b: normal_matvec(g, f, mu, a, b, beta, p, af, am, pr), -gf, -gm, p.n_cg, p.w_f, p.w_mu
         )
     ft = np.clip(f + xf, p.f_lo, p.f_hi)
     mt = np.clip(mu + xm, p.mu_lo, p.mu_hi)
     sf, sm = ft - f, mt - mu
-    pred = model_decrease(g, f, mu, gf, gm, sf, sm, af, am)
-    phi_t, _ = objective(g, y, ft, mt, af, am)
+    pred = model_decrease(g, f, mu, gf, gm, sf, sm, af, am, pr)
+    phi_t, _ = objective(g, y, ft, mt, af, am, pr)
     ared = phi - phi_t
     rho = ared / pred if pred > 0.0 else -np.inf
     return Iterate(phi, gf, gm, xf, xm, rr, sf, sm, pred, ared, rho, phi_t, ft, mt)
@@ -284,8 +321,9 @@ def lm_solve(
                 ft = np.asarray(ft, dtype=np.float64)
                 mt = np.asarray(mt, dtype=np.float64)
                 stf, stm = ft - f_old, mt - mu_old
-                pred_t = model_decrease(g, f_old, mu_old, it.gf, it.gm, stf, stm, af, am)
-                phi_t, _ = objective(g, y, ft, mt, af, am)
+                pr = prior_at(p, k)
+                pred_t = model_decrease(g, f_old, mu_old, it.gf, it.gm, stf, stm, af, am, pr)
+                phi_t, _ = objective(g, y, ft, mt, af, am, pr)
                 rho_t = (it.phi - phi_t) / pred_t if pred_t > 0.0 else -np.inf
                 hook_vals = (rho_t, pred_t)
                 if rho_t > p.eta and pred_t >= it.pred:
@@ -310,6 +348,6 @@ def lm_solve(
             rep.stop_reason = "beta_overflow"
             break
     af, am = alphas_at(p, rep.iters_run)
-    rep.phi.append(objective(g, y, f, mu, af, am)[0])
+    rep.phi.append(objective(g, y, f, mu, af, am, prior_at(p, rep.iters_run))[0])
     rep.beta_final = beta
     return f, mu, rep

@@ -709,6 +709,8 @@ LMParamsDev to_dev(const pget_lm_params& p)
     d.w_f = p.w_f > 0 ? p.w_f : 1.0;
     d.w_mu = p.w_mu > 0 ? p.w_mu : 1.0;
     d.active_set = p.active_set;
+    d.prior_w = p.prior_w;
+    d.prior_ref = p.prior_w ? p.prior_ref : nullptr;
     d.has_replay = p.replay != nullptr;
     if (p.replay)
         for (int k = 0; k < p.max_outer; ++k) d.replay[k] = p.replay[k];

@@ -63,6 +63,8 @@ struct LMParamsDev {
     double f_lo, f_hi, mu_lo, mu_hi, tol;
     double w_f, w_mu;       // CG preconditioner W = diag(w_f I, w_mu I)
     int active_set;         // 1: CG on the free variables only
+    const float* prior_w;   // geometry prior weights (2 N^2, f then mu) or nullptr
+    const float* prior_ref; // its reference maps (2 N^2) or nullptr (zero)
     int has_replay;
     int8_t replay[256];
 };

@@ -819,6 +819,22 @@ __device__ __forceinline__ void alphas_at(const LMParamsDev& p, int k, float& af
     am = (float)(p.alpha_mu / d);
 }
 
+// Continuation factor of the geometry prior's weights at outer iteration k
+// (the same division as the alphas').
+__device__ __forceinline__ float prior_scale(const LMParamsDev& p, int k)
+{
+    int e = min(k, p.alpha_decay_until);
+    return (float)(1.0 / pow(p.alpha_decay, (double)e));
+}
+
+// Weight and reference of the geometry prior for element mm of a slice's
+// (f, mu) pair (0 <= mm < 2 N^2), scaled by ps; zero weight without a prior.
+__device__ __forceinline__ void prior_at(const LMParamsDev& p, float ps, int mm, float& w, float& ref)
+{
+    w = p.prior_w ? ps * p.prior_w[mm] : 0.0f;
+    ref = p.prior_ref ? p.prior_ref[mm] : 0.0f;
+}
+
 // L x at pixel (r, c): sum over in-grid 4-neighbours of (x[m] - x[m'])
 __device__ __forceinline__ float lap(const float* x, int n, int r, int c)
 {
@@ -871,6 +887,17 @@ __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
         }
         gf = fmaf(af, lap(uf, n, r, c), gf);
         gm = fmaf(am, lap(um, n, r, c), gm);
+        double prior_e = 0.0;
+        if (P.prior_w) {
+            const float ps = prior_scale(P, st.k);
+            float wf, rf0, wm, rm0;
+            prior_at(P, ps, m, wf, rf0);
+            prior_at(P, ps, n2 + m, wm, rm0);
+            const float df = uf[m] - rf0, dm = um[m] - rm0;
+            gf = fmaf(wf, df, gf);
+            gm = fmaf(wm, dm, gm);
+            prior_e = (double)wf * ((double)df * df) + (double)wm * ((double)dm * dm);
+        }
         V.grad[vo + m] = gf;
         V.grad[vo + n2 + m] = gm;
         float rf = -gf, rm = -gm;
@@ -892,7 +919,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
         V.p[vo + n2 + m] = 0.0f;
         rr = (double)(float)P.w_f * ((double)rf * rf) + (double)(float)P.w_mu * ((double)rm * rm);
         gg = (double)gf * gf + (double)gm * gm;
-        reg = (double)af * grad2(uf, n, r, c) + (double)am * grad2(um, n, r, c);
+        reg = (double)af * grad2(uf, n, r, c) + (double)am * grad2(um, n, r, c) + prior_e;
     }
     double s1 = block_sum(rr, sh);
     double s3 = block_sum(gg, sh);
@@ -957,6 +984,14 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
         }
         float qf = fmaf(af, lf, fmaf(bdf, pfc, gf));
         float qm = fmaf(am, lm, fmaf(bdm, pmc, gm));
+        if (V.prm[slice].prior_w) {
+            const float ps = prior_scale(V.prm[slice], st.k);
+            float wf, wm, rf0, rm0;
+            prior_at(V.prm[slice], ps, m, wf, rf0);
+            prior_at(V.prm[slice], ps, n2 + m, wm, rm0);
+            qf = fmaf(wf, pfc, qf);
+            qm = fmaf(wm, pmc, qm);
+        }
         if (act) {
             if (!V.fmask[vo + m]) qf = 0.0f;
             if (!V.fmask[vo + n2 + m]) qm = 0.0f;
@@ -1067,6 +1102,15 @@ __global__ void __launch_bounds__(EW_THREADS) k_trial(VecArgs V)
         ss = (double)sf * sf + (double)sm * sm;
         uu = (double)uf[m] * uf[m] + (double)um[m] * um[m];
         regt = (double)af * gtf + (double)am * gtm;
+        if (P.prior_w) {
+            const float ps = prior_scale(P, st.k);
+            float wf, wm, rf0, rm0;
+            prior_at(P, ps, m, wf, rf0);
+            prior_at(P, ps, n2 + m, wm, rm0);
+            const float ef = tf - rf0, em = tm - rm0;
+            srs += (double)wf * ((double)sf * sf) + (double)wm * ((double)sm * sm);
+            regt += (double)wf * ((double)ef * ef) + (double)wm * ((double)em * em);
+        }
     }
     double v;
     v = block_sum(gs, sh);   if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_GS)[blockIdx.x] = v;
@@ -1254,6 +1298,15 @@ __global__ void __launch_bounds__(EW_THREADS) k_final_reg(VecArgs V)
     if (m < n2) {
         const int r = m / n, c = m - r * n;
         reg = (double)af * grad2(V.u + vo, n, r, c) + (double)am * grad2(V.u + vo + n2, n, r, c);
+        const LMParamsDev& P = V.prm[slice];
+        if (P.prior_w) {
+            const float ps = prior_scale(P, st.k);
+            float wf, wm, rf0, rm0;
+            prior_at(P, ps, m, wf, rf0);
+            prior_at(P, ps, n2 + m, wm, rm0);
+            const float df = V.u[vo + m] - rf0, dm = V.u[vo + n2 + m] - rm0;
+            reg += (double)wf * ((double)df * df) + (double)wm * ((double)dm * dm);
+        }
     }
     double s = block_sum(reg, sh);
     if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_PHI_REG_U)[blockIdx.x] = s;

@@ -243,6 +243,46 @@ def scanner_phantom(cfg: ScannerConfig, seed: int = 0, kind: str = "missing", ov
     return f, mu
 
 
+def _outside_rods(n: int, px: float, centres, reach: float) -> np.ndarray:
+    """1 where a pixel centre lies farther than `reach` from every centre."""
+    cc = (np.arange(n) - 0.5 * (n - 1)) * px
+    X, Y = np.meshgrid(cc, cc)
+    out = np.ones((n, n))
+    for cx, cy in centres:
+        out[(X - cx) ** 2 + (Y - cy) ** 2 <= reach * reach] = 0.0
+    return out
+
+
+def scanner_rod_prior(cfg: ScannerConfig, margin_mm: float = 1.0):
+    """Where the geometry prior applies (the paper's P1, P2: emission and
+    attenuation away from every possible rod location of the known 9 x 9
+    layout are penalised; no rod is assumed present).  Returns
+    (outside, ref_f, ref_mu) on the reconstruction grid: `outside` is 1 for
+    pixels farther than rod radius + jitter + margin from every nominal rod
+    centre, the references are no emission there and water attenuation
+    inside the field of view (0 outside it)."""
+    nr = cfg.n_rods
+    centres = [((k - 0.5 * (nr - 1)) * cfg.pitch_mm, (l - 0.5 * (nr - 1)) * cfg.pitch_mm)
+               for l in range(nr) for k in range(nr)]
+    out = _outside_rods(cfg.n, cfg.pixel_mm, centres, cfg.rod_radius_mm + cfg.jitter_mm + margin_mm)
+    ref_mu = np.where(fov_mask(cfg), cfg.water_mu, 0.0)
+    return out, np.zeros_like(out), ref_mu
+
+
+def lattice_rod_prior(cfg: SliceConfig, margin: float = 1.0):
+    """The same for the rod-lattice phantoms (pixel units): 1 farther than
+    rod radius + margin from every nominal centre; references no emission
+    and the background attenuation inside the can (0 outside it)."""
+    nr = cfg.n_rods
+    centres = [((k - 0.5 * (nr - 1)) * cfg.pitch, (l - 0.5 * (nr - 1)) * cfg.pitch)
+               for l in range(nr) for k in range(nr)]
+    out = _outside_rods(cfg.n, 1.0, centres, cfg.rod_radius + margin)
+    cc = np.arange(cfg.n) - 0.5 * (cfg.n - 1)
+    X, Y = np.meshgrid(cc, cc)
+    can = (np.abs(X) <= cfg.can_half) & (np.abs(Y) <= cfg.can_half)
+    return out, np.zeros_like(out), np.where(can, cfg.bg_mu, 0.0)
+
+
 def fov_mask(cfg: ScannerConfig) -> np.ndarray:
     """Pixels of the reconstruction grid whose centre lies in the field-of-view disk."""
     cc = np.arange(cfg.n) - 0.5 * (cfg.n - 1)

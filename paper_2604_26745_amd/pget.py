@@ -53,6 +53,7 @@ class LMParams(ctypes.Structure):
         ("mu_lo", ctypes.c_double), ("mu_hi", ctypes.c_double),
         ("tol", ctypes.c_double), ("replay", ctypes.POINTER(ctypes.c_int8)),
         ("w_f", ctypes.c_double), ("w_mu", ctypes.c_double), ("active_set", ctypes.c_int32),
+        ("prior_w", ctypes.c_void_p), ("prior_ref", ctypes.c_void_p),
     ]
 
 
@@ -170,17 +171,30 @@ class SolverParams:
     w_f: float = 1.0          # CG preconditioner W = diag(w_f I, w_mu I)
     w_mu: float = 1.0
     active_set: int = 0       # 1: CG on the variables not held at a bound
+    prior_w: object = None    # geometry prior: CUDA float32 (2, N, N) weights, or None
+    prior_ref: object = None  # its reference maps (2, N, N), or None (zero)
 
-    def to_c(self):
+    def to_c(self, n: Optional[int] = None):
         p = LMParams()
         for k, _ in LMParams._fields_:
-            if k == "replay":
+            if k in ("replay", "prior_w", "prior_ref"):
                 continue
             setattr(p, k, getattr(self, k))
-        keep = None
+        keep = []
         if self.replay is not None:
-            keep = (ctypes.c_int8 * len(self.replay))(*[int(v) for v in self.replay])
-            p.replay = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int8))
+            arr = (ctypes.c_int8 * len(self.replay))(*[int(v) for v in self.replay])
+            keep.append(arr)
+            p.replay = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int8))
+        for name in ("prior_w", "prior_ref"):
+            t = getattr(self, name)
+            if t is None:
+                continue
+            if not (t.is_cuda and t.dtype == _torch().float32 and t.is_contiguous()):
+                raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
+            if n is not None and t.numel() != 2 * n * n:
+                raise ValueError("%s must hold 2 x %d x %d values" % (name, n, n))
+            keep.append(t)
+            setattr(p, name, t.data_ptr())
         return p, keep
 
 
@@ -346,7 +360,7 @@ class Plan:
         y = self._sino(y)
         f = self._img(f0).clone()
         mu = self._img(mu0).clone()
-        prm, keep = params.to_c()
+        prm, keep = params.to_c(self.n)
         rb = _ReportBuffers(params.max_outer, params.n_cg, f.device)
         rc_struct = rb.c()
         ws = self.workspace(OP_LM, 1)
@@ -402,7 +416,7 @@ class Plan:
         cp = (LMParams * B)()
         keeps = []
         for i, p in enumerate(params):
-            c, k = p.to_c()
+            c, k = p.to_c(self.n)
             cp[i] = c
             keeps.append(k)
         rbs = [_ReportBuffers(params[0].max_outer, params[0].n_cg, fs[0].device) for _ in range(B)]
@@ -439,7 +453,7 @@ def lm_solve_multi(plans: Sequence["Plan"], ys, f0s, mu0s, params: Sequence[Solv
     cp = (LMParams * n)()
     keeps = []
     for i, p in enumerate(params):
-        c, k = p.to_c()
+        c, k = p.to_c(plans[i].n)
         cp[i] = c
         keeps.append(k)
     rbs = [_ReportBuffers(p.max_outer, p.n_cg, fs[0].device) for p in params]

@@ -1,5 +1,6 @@
 """GPU parity of the block-scaled CG and the active set of the damped step
-(solver options w_f, w_mu, active_set) against the FP64 oracle, with the
+(solver options w_f, w_mu, active_set) and of the geometry prior (prior_w,
+prior_ref, with and without continuation) against the FP64 oracle, with the
 oracle's accept decisions replayed (as in test_gpu_lm).
 
 With the scaled metric the LM steps are large and the trajectory becomes
@@ -189,3 +190,61 @@ def test_unit_scaling_is_plain_cg():
     f1, m1, _ = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(max_outer=3, n_cg=6))
     f2, m2, _ = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(max_outer=3, n_cg=6, w_f=0.0, w_mu=0.0))
     assert torch.equal(f1, f2) and torch.equal(m1, m2)
+
+
+def _prior(n, seed):
+    rng = np.random.default_rng(seed)
+    wf = rng.uniform(0.0, 5.0, (n, n)) * (rng.uniform(size=(n, n)) < 0.5)
+    wm = rng.uniform(0.0, 500.0, (n, n)) * (rng.uniform(size=(n, n)) < 0.5)
+    return wf, wm, rng.uniform(0.0, 0.5, (n, n)), rng.uniform(0.0, 0.02, (n, n))
+
+
+def _prior_dev(pr):
+    wf, wm, rf, rm = pr
+    return T(np.stack([wf, wm])), T(np.stack([rf, rm]))
+
+
+@pytest.mark.parametrize("decay", [1.0, 5.0], ids=["fixed", "continuation"])
+def test_prior_trajectory_with_replay(decay):
+    """The geometry prior (per-pixel weights and references) with the scaled
+    active-set step, 4 CG steps, and the alphas and prior weights divided by
+    5 per iteration for 3 iterations in the continuation case."""
+    og, y, f0, mu0 = problem(SMALL)
+    pr = _prior(SMALL.n, 21)
+    p = OLM.LMParams(max_outer=SMALL.max_outer, n_cg=SMALL.n_cg, w_mu=W_MU, active_set=True,
+                     alpha_decay=decay, alpha_decay_until=3,
+                     prior_w_f=pr[0], prior_w_mu=pr[1], prior_ref_f=pr[2], prior_ref_mu=pr[3])
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p)
+    pw, pref = _prior_dev(pr)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(
+        max_outer=SMALL.max_outer, n_cg=SMALL.n_cg, w_mu=W_MU, active_set=1, alpha_decay=decay,
+        alpha_decay_until=3, prior_w=pw, prior_ref=pref, replay=orep.accepted))
+    rep = rb.to_report()
+    assert rep.status == 0
+    compare(rep, orep, f, mu, of, om)
+    # the prior moved the solution: without it the oracle ends elsewhere
+    of2, om2, _ = OLM.lm_solve(og, y, f0, mu0, OLM.LMParams(
+        max_outer=SMALL.max_outer, n_cg=SMALL.n_cg, w_mu=W_MU, active_set=True, alpha_decay=decay,
+        alpha_decay_until=3))
+    assert rel(of2, of) > 1e-2
+
+
+def test_prior_in_batch_equal_alone_and_checked():
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    pa, pb = _prior_dev(_prior(SMALL.n, 22)), _prior_dev(_prior(SMALL.n, 23))
+    base = dict(max_outer=4, n_cg=4, w_mu=W_MU, active_set=1)
+    prms = [pget.SolverParams(**base), pget.SolverParams(prior_w=pa[0], prior_ref=pa[1], **base),
+            pget.SolverParams(prior_w=pb[0], **base)]
+    ys, f0s, m0s = [], [], []
+    for i in range(3):
+        og, y, f0, mu0 = problem(SMALL, seed=i)
+        ys.append(T(y)); f0s.append(T(f0)); m0s.append(T(mu0))
+    fs, ms, rbs = plan.lm_solve_batched(ys, f0s, m0s, prms)
+    for i in range(3):
+        fa, ma, ra = plan.lm_solve(ys[i], f0s[i], m0s[i], prms[i])
+        assert torch.equal(fa, fs[i]) and torch.equal(ma, ms[i])
+    with pytest.raises(ValueError):
+        plan.lm_solve(ys[0], f0s[0], m0s[0], pget.SolverParams(prior_w=pa[0][:1], **base))
+    with pytest.raises(ValueError):
+        plan.lm_solve(ys[0], f0s[0], m0s[0], pget.SolverParams(prior_w=pa[0].double(), **base))

@@ -398,3 +398,83 @@ def test_safeguard_rejects_a_jump_to_the_phantom():
         kept.append((rho_t > p.eta, pred_t >= it.pred, pred_t))
     assert kept[0][2] < 0 and not kept[0][0]            # the phantom: the model predicts an increase
     assert kept[1][0] and not kept[1][1]                 # halfway: rho passes, m(s~) > m(s)
+
+
+def _random_prior(shape, seed):
+    rng = np.random.default_rng(seed)
+    wf = rng.uniform(0.0, 5.0, shape) * (rng.uniform(size=shape) < 0.5)
+    wm = rng.uniform(0.0, 500.0, shape) * (rng.uniform(size=shape) < 0.5)
+    return wf, wm, rng.uniform(0.0, 0.5, shape), rng.uniform(0.0, 0.02, shape)
+
+
+def test_prior_keeps_rho_one_for_emission_steps():
+    """With the geometry prior (a quadratic in u) the model is still exact
+    for steps that leave mu unchanged: rho = 1, which pins the prior's
+    factors in Phi, g and pred together."""
+    g, y, _, _ = small_problem()
+    rng = np.random.default_rng(12)
+    f = rng.uniform(0.2, 1.0, g.image_shape)
+    mu = rng.uniform(0.0, 0.05, g.image_shape)
+    af, am = 1e-2, 3e-2
+    pr = _random_prior(g.image_shape, 13)
+    phi, r = L.objective(g, y, f, mu, af, am, pr)
+    gf, gm = L.gradient(g, f, mu, r, af, am, pr)
+    for scale in (1e-4, 1e-2):
+        sf = scale * rng.standard_normal(g.image_shape)
+        sm = np.zeros(g.image_shape)
+        pred = L.model_decrease(g, f, mu, gf, gm, sf, sm, af, am, pr)
+        phi_t, _ = L.objective(g, y, f + sf, mu, af, am, pr)
+        assert abs((phi - phi_t) - pred) <= 1e-9 * abs(pred) + 1e-13 * phi
+    # and the prior changes both sides (a dropped term would go unnoticed otherwise)
+    assert abs(L.objective(g, y, f, mu, af, am)[0] - phi) > 1e-3 * phi
+
+
+def test_prior_gradient_and_normal_matrix():
+    """g is the derivative of Phi with the prior (central differences); the
+    normal operator with beta = 0 equals the derivative of g along emission
+    directions (F is linear in f, so that derivative is exact)."""
+    g, y, _, _ = small_problem()
+    rng = np.random.default_rng(14)
+    f = rng.uniform(0.2, 1.0, g.image_shape)
+    mu = rng.uniform(0.0, 0.05, g.image_shape)
+    af, am = 1e-2, 1e-2
+    pr = _random_prior(g.image_shape, 15)
+    phi, r = L.objective(g, y, f, mu, af, am, pr)
+    gf, gm = L.gradient(g, f, mu, r, af, am, pr)
+    vf, vm = rng.standard_normal((2,) + g.image_shape)
+    h = 1e-6
+    fd = (L.objective(g, y, f + h * vf, mu + h * vm, af, am, pr)[0]
+          - L.objective(g, y, f - h * vf, mu - h * vm, af, am, pr)[0]) / (2 * h)
+    assert abs(fd - (np.sum(gf * vf) + np.sum(gm * vm))) <= 1e-6 * abs(fd)
+    p = params()
+    h = 1e-3
+    g1 = L.gradient(g, f + h * vf, mu, L.objective(g, y, f + h * vf, mu, af, am, pr)[1], af, am, pr)
+    g0 = L.gradient(g, f - h * vf, mu, L.objective(g, y, f - h * vf, mu, af, am, pr)[1], af, am, pr)
+    qf, _ = L.normal_matvec(g, f, mu, vf, np.zeros(g.image_shape), 0.0, p, af, am, pr)
+    assert np.linalg.norm((g1[0] - g0[0]) / (2 * h) - qf) <= 1e-8 * np.linalg.norm(qf)
+
+
+def test_strong_prior_pins_the_reference():
+    """Weights of 1e8 on a set of pixels hold the LM solution at the
+    prior's reference there (to the weight's ratio with the data term),
+    for emission and attenuation alike; elsewhere the solve is free."""
+    g, y, f_true, mu_true = small_problem()
+    f0, mu0 = L.initial_guess(g, y)
+    mask = np.zeros(g.image_shape)
+    mask[:4, :] = 1.0
+    rf = np.full(g.image_shape, 0.3)
+    rm = np.full(g.image_shape, 0.01)
+    p = params(max_outer=6, prior_w_f=1e8 * mask, prior_w_mu=1e8 * mask, prior_ref_f=rf, prior_ref_mu=rm)
+    f, mu, rep = L.lm_solve(g, y, f0, mu0, p)
+    assert sum(rep.accepted) >= 2
+    on = mask > 0
+    assert np.abs(f[on] - 0.3).max() <= 1e-4 and np.abs(mu[on] - 0.01).max() <= 1e-4
+    assert np.abs(f[~on] - 0.3).max() > 0.05
+
+
+def test_prior_decays_with_the_alphas():
+    p = params(alpha_decay=5.0, alpha_decay_until=2, prior_w_f=np.full((3, 3), 10.0))
+    for k, d in ((0, 1.0), (1, 5.0), (2, 25.0), (3, 25.0)):
+        wf, wm, rf, rm = L.prior_at(p, k)
+        assert np.allclose(wf, 10.0 / d) and np.all(wm == 0.0) and np.all(rf == 0.0) and np.all(rm == 0.0)
+    assert L.prior_at(params(), 0) is None

@@ -94,3 +94,34 @@ def test_noise_level():
     y = np.linspace(1.0, 2.0, 5000)
     yn = inputs.gaussian_noise(y, 0.02, 0)
     assert abs(np.linalg.norm(yn - y) / np.linalg.norm(y) - 0.02) < 2e-3
+
+
+def test_rod_prior_holds_for_every_phantom_kind():
+    """The geometry prior's region and references agree with the phantoms it
+    is meant for: no emission there, attenuation equal to the reference
+    (water in the field of view) except on pixels the field-of-view circle
+    cuts, for every kind and several seeds (rod jitter included)."""
+    out, ref_f, ref_mu = inputs.scanner_rod_prior(CFG)
+    assert 0.4 < out.mean() < 0.7 and np.all(ref_f == 0.0)
+    cc = np.arange(CFG.n) - 0.5 * (CFG.n - 1)
+    X, Y = np.meshgrid(cc, cc)
+    edge = np.abs(np.sqrt(X ** 2 + Y ** 2) - 0.5 * CFG.n) < 1.0
+    on = (out > 0) & ~edge
+    for seed in range(3):
+        for kind in ("full", "missing", "replaced", "medium"):
+            f, mu = inputs.scanner_phantom(CFG, seed, kind, 1)
+            assert f[out > 0].max() == 0.0
+            assert np.abs(mu - ref_mu)[on].max() <= 1e-12
+    # a rod that the prior region covered would show up as emission there
+    wider = inputs.scanner_rod_prior(CFG, margin_mm=-CFG.rod_radius_mm)[0]
+    f, _ = inputs.scanner_phantom(CFG, 0, "full", 1)
+    assert f[wider > 0].max() > 0.5
+
+
+def test_lattice_rod_prior_holds():
+    cfg = inputs.MAIN_128
+    out, ref_f, ref_mu = inputs.lattice_rod_prior(cfg)
+    for seed in range(4):
+        f, mu = inputs.rod_lattice(cfg, seed)
+        assert f[out > 0].max() == 0.0
+        assert np.abs(mu - ref_mu)[out > 0].max() <= 1e-12
