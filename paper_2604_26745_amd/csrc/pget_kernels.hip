@@ -111,6 +111,7 @@ __device__ __forceinline__ uint32_t bf16_rne(float x)
 struct F32S {
     using px_t = float2;
     using w_t = float2;
+    static constexpr int VJP_WAVES = 3;   // gather waves per SIMD (register budget 168)
     static __device__ __forceinline__ float2 px(px_t v) { return v; }
     static __device__ __forceinline__ px_t to_px(float2 v) { return v; }
     static __device__ __forceinline__ float2 w(w_t v) { return v; }
@@ -120,6 +121,7 @@ struct F32S {
 struct BF16S {
     using px_t = uint32_t;   // low half: first value, high half: second value
     using w_t = uint32_t;
+    static constexpr int VJP_WAVES = 4;   // half the staged weight registers (budget 128)
     static __device__ __forceinline__ float2 px(px_t v)
     {
         return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
@@ -415,33 +417,36 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         const w_t* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
         float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
         // The sample loop is software-pipelined: the weights of trip t+1 (JU
-        // samples per lane) are loaded while trip t is computed.  Lanes outside
-        // their ray's support use (0, T), which makes both terms vanish.
+        // samples per lane) are loaded while trip t is computed; they stay in
+        // their storage format until used.  Lanes outside their ray's support
+        // load nothing and use (0, T), which makes both terms vanish.
         constexpr int JU = 4;
         constexpr int STEP = JU * SPL;
-        float2 wa[JU], wma[JU], wb[JU], wmb[JU];
-        auto load = [&](int i0, float2* w, float2* wm) {
+        w_t wa[JU], wma[JU], wb[JU], wmb[JU];
+        auto load = [&](int i0, w_t* w, w_t* wm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
                 const int i = i0 - u * SPL - q;
                 const bool ok = (i >= cl.x) && (i <= cl.y);
-                w[u] = ok ? S::w(wrow[(size_t)i * g.n_bins + j]) : make_float2(0.0f, T);
-                if (g.paired)
-                    wm[u] = ok ? S::w(wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm]) : make_float2(0.0f, Tm);
+                w[u] = ok ? wrow[(size_t)i * g.n_bins + j] : w_t{};
+                if (g.paired) wm[u] = ok ? wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : w_t{};
             }
         };
-        auto compute = [&](int i0, const float2* w, const float2* wm) {
+        auto compute = [&](int i0, const w_t* w, const w_t* wm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
                 const int i = i0 - u * SPL - q;
+                const bool ok = (i >= cl.x) && (i <= cl.y);
                 const float ti = (float)i - g.t_off;
                 const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
                 const float2 v = bilerp<S>(img, g.pitch, g.n, col, row);
-                accf = fmaf(w[u].x, v.x, accf);
-                accq = fmaf(T - w[u].y, v.y, accq);
+                const float2 wv = S::w(w[u]);
+                accf = fmaf(wv.x, v.x, accf);
+                accq = fmaf(T - (ok ? wv.y : T), v.y, accq);
                 if (g.paired) {
-                    accfm = fmaf(wm[u].x, v.x, accfm);
-                    accqm = fmaf(Tm - wm[u].y, v.y, accqm);
+                    const float2 wmv = S::w(wm[u]);
+                    accfm = fmaf(wmv.x, v.x, accfm);
+                    accqm = fmaf(Tm - (ok ? wmv.y : Tm), v.y, accqm);
                 }
             }
         };
@@ -567,10 +572,13 @@ constexpr int LP = VFP + 1;
 
 // One angle's window in registers: weight pair per point (rows wave + 4k,
 // column lane) and the blurred cotangent and ray total of the lane's column,
-// with the same for the mirror angle when the geometry is paired.
+// with the same for the mirror angle when the geometry is paired.  The
+// weights stay in their storage format until they are staged in LDS, so
+// that no conversion waits on a load while the previous angle is gathered.
+template <typename SP>
 struct Stage {
-    float2 w[VROWS];
-    float2 wm[VROWS];   // mirror angle, same points (paired geometry)
+    typename SP::w_t w[VROWS];
+    typename SP::w_t wm[VROWS];   // mirror angle, same points (paired geometry)
     float wt, t, wtm, tm;
 };
 
@@ -579,7 +587,7 @@ struct Stage {
 // window or off the lattice are skipped (wave-uniform tests) and read as zero;
 // lanes whose column is off the window or the detector read zero.
 template <typename SP>
-__device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const typename SP::w_t* wbase,
+__device__ __forceinline__ void stage_load(Stage<SP>& S, const VjpArgs& A, const typename SP::w_t* wbase,
                                            int slice, int a, const Window& W)
 {
     const Geo& g = A.g;
@@ -599,8 +607,8 @@ __device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const typ
     S.tm = (jok && g.paired) ? A.tsum[sbasem + jm] : 0.0f;
 #pragma unroll
     for (int k = 0; k < VROWS; ++k) {
-        S.w[k] = make_float2(0.0f, 0.0f);
-        S.wm[k] = make_float2(0.0f, 0.0f);
+        S.w[k] = typename SP::w_t{};     // zero in either format
+        S.wm[k] = typename SP::w_t{};
     }
     if (jok) {
 #pragma unroll
@@ -608,8 +616,8 @@ __device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const typ
             const int ii = wave + 4 * k;
             const int i = W.ilo + ii;
             if (ii < W.wi && i >= 0 && i < g.n_t) {
-                S.w[k] = SP::w(wrow[(size_t)i * g.n_bins + j]);
-                if (g.paired) S.wm[k] = SP::w(wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm]);
+                S.w[k] = wrow[(size_t)i * g.n_bins + j];
+                if (g.paired) S.wm[k] = wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm];
             }
         }
     }
@@ -618,7 +626,8 @@ __device__ __forceinline__ void stage_load(Stage& S, const VjpArgs& A, const typ
 // Staged value of a lattice point: the coefficients of f and mu it spreads
 // (step*E*wt and kq*(T - R')*wt), summed with those of the mirror angle's
 // sample at the same point when the geometry is paired.
-__device__ __forceinline__ void stage_store(float2* lat, const Stage& S, float kq)
+template <typename SP>
+__device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, float kq)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -628,8 +637,9 @@ __device__ __forceinline__ void stage_store(float2* lat, const Stage& S, float k
     for (int k = 0; k < VROWS; ++k) {
         const int ii = wave + 4 * k;
         if (ii < VFP) {
-            const float cf = fmaf(S.wm[k].x, S.wtm, S.w[k].x * S.wt);
-            const float cm = fmaf(kwm, S.tm - S.wm[k].y, kw * (S.t - S.w[k].y));
+            const float2 w = SP::w(S.w[k]), wm = SP::w(S.wm[k]);
+            const float cf = fmaf(wm.x, S.wtm, w.x * S.wt);
+            const float cm = fmaf(kwm, S.tm - wm.y, kw * (S.t - w.y));
             lat[ii * LP + lane] = make_float2(cf, cm);
         }
     }
@@ -639,7 +649,8 @@ __device__ __forceinline__ void stage_store(float2* lat, const Stage& S, float k
 // mirror, loaded over rot_window(W)) to the points of W they coincide with:
 // rotated column lane is W's row W.wi - 1 - lane, rotated row ii is W's column
 // ii.  Every point has one owner thread.
-__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage& S, float kq, const Window& W)
+template <typename SP>
+__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, float kq, const Window& W)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -650,8 +661,9 @@ __device__ __forceinline__ void stage_add_rot(float2* lat, const Stage& S, float
     for (int k = 0; k < VROWS; ++k) {
         const int ii = wave + 4 * k;
         if (ii < W.wj) {
-            const float cf = fmaf(S.wm[k].x, S.wtm, S.w[k].x * S.wt);
-            const float cm = fmaf(kwm, S.tm - S.wm[k].y, kw * (S.t - S.w[k].y));
+            const float2 w = SP::w(S.w[k]), wm = SP::w(S.wm[k]);
+            const float cf = fmaf(wm.x, S.wtm, w.x * S.wt);
+            const float cm = fmaf(kwm, S.tm - wm.y, kw * (S.t - w.y));
             float2 v = row[ii];
             v.x += cf;
             v.y += cm;
@@ -680,7 +692,7 @@ __device__ __forceinline__ float tent(float d)
 }
 
 template <typename SP, bool QUAD>
-__global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_eu(3))) k_vjp_lin(VjpArgs A)
+__global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_eu(SP::VJP_WAVES))) k_vjp_lin(VjpArgs A)
 {
     __shared__ float2 lat[VFP * LP];
     const Geo& g = A.g;
@@ -718,7 +730,7 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
     const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
     const typename SP::w_t* wbase = static_cast<const typename SP::w_t*>(A.wts) + (size_t)slice * A.wts_stride;
 
-    Stage S, R;
+    Stage<SP> S, R;
     Window Wn = {0, 0, 0, 0};
     if (a_begin < a_end) {
         Wn = tile_window(g, A.t.trig[a_begin], tr0, tc0);
