@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--dg-test", type=int, default=16, help="deepgn: held-out slices")
     ap.add_argument("--dg-outer", type=int, default=5, help="deepgn: outer iterations")
     ap.add_argument("--dg-epochs", type=int, default=40, help="deepgn: epochs per network")
+    ap.add_argument("--no-bf16-variant", action="store_true",
+                    help="main workload: skip timing the BF16-storage variant beside FP32")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 256 MiB device copy (scale for HBM counters)")
     return ap.parse_args()
@@ -601,7 +603,7 @@ def main():
     avg_s = tot_ms / 1e3 / max(launches, 1)
     units = plan.support_samples * B
     achieved = FLOP_PER_SAMPLE[dom] * units / avg_s / 1e12
-    workload = "%s_batch%d" % (cfg.name, B)
+    workload = "%s_batch%d" % (cfg.name, B) + ("_bf16" if args.storage == "bf16" else "")
     kernel_name = {"vjp": "k_vjp_lin", "gradient": "k_vjp_lin", "jvp": "k_jvp_lin",
                    "march": "k_march"}.get(dom, dom)
     roofline = {
@@ -638,6 +640,26 @@ def main():
         single = {"latency_ms": round(1e3 * (time.perf_counter() - t2), 2)}
         single["recon_per_s"] = round(1e3 / single["latency_ms"], 3)
 
+    # the BF16-storage variant on the same inputs and options (weights and
+    # staged search direction in bfloat16, arithmetic in FP32)
+    bf16 = None
+    if args.storage == "fp32" and not args.no_bf16_variant:
+        plan_b = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, storage="bf16")
+        for _ in range(max(1, args.warmup)):
+            plan_b.lm_solve_batched(ys, f0s, m0s, prm)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(args.steps):
+            fb, mb, rb_ = plan_b.lm_solve_batched(ys, f0s, m0s, prm, sync=False)
+        torch.cuda.synchronize()
+        el_b = time.perf_counter() - tb
+        assert all(r.to_report().status == 0 for r in rb_), "BF16 solver reported a failure"
+        bf16 = {"value": round(B * args.steps / el_b, 4), "unit": "reconstructions/s",
+                "ms_per_step": round(1e3 * el_b / args.steps, 3), "speedup_vs_fp32": round((B * args.steps / el_b) / value, 3),
+                "dtype": "bf16-storage/f32-compute", "quality": quality(fb, mb, cfg, inputs, np)}
+        print("bench: BF16 storage %.2f recon/s" % bf16["value"], file=sys.stderr, flush=True)
+        del plan_b
+
     cpu = None
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
@@ -670,6 +692,7 @@ def main():
                         start=quality(f0s, m0s, cfg, inputs, np)),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "bf16_storage": bf16,
         "kernel_time_share": kernel_share,
         "instrumented_step_ms": round(1e3 * instrumented_s, 3),
         "single_slice": single,

@@ -61,6 +61,15 @@ __device__ __forceinline__ float quad_sum(float x)
     return x;
 }
 
+// Sum over the lanes of one ray (4: the quad; 2: lane pairs within it).
+template <int LANES>
+__device__ __forceinline__ float ray_sum(float x)
+{
+    x += qperm<QP_SWAP1>(x);
+    if (LANES == 4) x += qperm<QP_SWAP2>(x);
+    return x;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -112,6 +121,7 @@ struct F32S {
     using px_t = float2;
     using w_t = float2;
     static constexpr int VJP_WAVES = 3;   // gather waves per SIMD (register budget 168)
+    static constexpr int JVP_SPL = 4;     // Jacobian product: lanes per ray (16 rays x 8 B = a 128 B row)
     static __device__ __forceinline__ float2 px(px_t v) { return v; }
     static __device__ __forceinline__ px_t to_px(float2 v) { return v; }
     static __device__ __forceinline__ float2 w(w_t v) { return v; }
@@ -122,6 +132,7 @@ struct BF16S {
     using px_t = uint32_t;   // low half: first value, high half: second value
     using w_t = uint32_t;
     static constexpr int VJP_WAVES = 4;   // half the staged weight registers (budget 128)
+    static constexpr int JVP_SPL = 2;     // 32 rays x 4 B: a full 128 B row per load
     static __device__ __forceinline__ float2 px(px_t v)
     {
         return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
@@ -383,8 +394,14 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const px_t* img = LDS_IMG ? simg : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
     __syncthreads();
 
+    // A wave covers JR consecutive rays with JSPL lanes per ray, so that one
+    // load instruction reads whole 128-byte rows of the weight array (16 rays
+    // of FP32 pairs or 32 rays of BF16 pairs).
+    constexpr int JSPL = S::JVP_SPL;
+    constexpr int JR = 64 / JSPL;
+    constexpr int GPI = JR / RG;            // ray groups of the plan tables per item
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const int q = lane & (SPL - 1), jj = lane >> 2;
+    const int q = lane & (JSPL - 1), jj = lane / JSPL;
     const w_t* wslice = static_cast<const w_t*>(A.wts) + (size_t)slice * A.wts_stride;
     const float* tslice = A.tsum + (size_t)slice * A.sino_stride;
     // Items are taken from a block-wide counter (dynamic balance), longest
@@ -392,15 +409,16 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     __shared__ int next_item;
     if (threadIdx.x == 0) next_item = nwaves;
     __syncthreads();
-    const int n_items = nslot * g.n_groups;
-    const int gc = g.n_groups / 2;
+    const int n_ig = (g.n_groups + GPI - 1) / GPI;
+    const int n_items = nslot * n_ig;
+    const int gc = n_ig / 2;
     for (int item = wave; item < n_items;) {
         const int rank = item / nslot, sl = item - rank * nslot;
         const int grp = (rank & 1) ? gc - (rank + 1) / 2 : gc + rank / 2;
         const int a = slot0 + sl;
         const int am = a + g.n_angles / 2;   // mirror angle (paired only)
         const float4 tr = A.t.trig[a];
-        const int j = grp * RG + jj;
+        const int j = grp * JR + jj;
         const int jm = g.n_bins - 1 - j;
         const bool ray_ok = j < g.n_bins;
         int2 cl = make_int2(1, 0);
@@ -412,7 +430,14 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             T = tslice[(size_t)a * g.n_bins + j];
             if (g.paired) Tm = tslice[(size_t)am * g.n_bins + jm];
         }
-        const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
+        int2 gr = A.t.grange[(size_t)a * g.n_groups + grp * GPI];
+#pragma unroll
+        for (int h = 1; h < GPI; ++h) {     // union with the item's other plan groups
+            if (grp * GPI + h < g.n_groups) {
+                const int2 gh = A.t.grange[(size_t)a * g.n_groups + grp * GPI + h];
+                gr = make_int2(min(gr.x, gh.x), max(gr.y, gh.y));
+            }
+        }
         const w_t* wrow = wslice + (size_t)a * g.n_t * g.n_bins;
         const w_t* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
         float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
@@ -421,12 +446,12 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         // their storage format until used.  Lanes outside their ray's support
         // load nothing and use (0, T), which makes both terms vanish.
         constexpr int JU = 4;
-        constexpr int STEP = JU * SPL;
+        constexpr int STEP = JU * JSPL;
         w_t wa[JU], wma[JU], wb[JU], wmb[JU];
         auto load = [&](int i0, w_t* w, w_t* wm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
-                const int i = i0 - u * SPL - q;
+                const int i = i0 - u * JSPL - q;
                 const bool ok = (i >= cl.x) && (i <= cl.y);
                 w[u] = ok ? wrow[(size_t)i * g.n_bins + j] : w_t{};
                 if (g.paired) wm[u] = ok ? wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : w_t{};
@@ -435,7 +460,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         auto compute = [&](int i0, const w_t* w, const w_t* wm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
-                const int i = i0 - u * SPL - q;
+                const int i = i0 - u * JSPL - q;
                 const bool ok = (i >= cl.x) && (i <= cl.y);
                 const float ti = (float)i - g.t_off;
                 const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
@@ -462,12 +487,12 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             compute(i1, wb, wmb);
             i0 = i2;
         }
-        accf = quad_sum(accf);
-        accq = quad_sum(accq);
+        accf = ray_sum<JSPL>(accf);
+        accq = ray_sum<JSPL>(accq);
         if (ray_ok && q == 0) rowz[sl * g.n_bins + j] = fmaf(g.kq, accq, accf);
         if (g.paired) {
-            accfm = quad_sum(accfm);
-            accqm = quad_sum(accqm);
+            accfm = ray_sum<JSPL>(accfm);
+            accqm = ray_sum<JSPL>(accqm);
             if (ray_ok && q == 0) rowz[(nslot + sl) * g.n_bins + jm] = fmaf(g.kq, accqm, accfm);
         }
         int nxt = 0;
