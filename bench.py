@@ -236,7 +236,8 @@ def run_mixed(args, torch, np, inputs, pget):
         ys.append(T(y)); pl.append(plan)
         f0s.append(torch.full((c.n, c.n), c0, dtype=torch.float32, device="cuda"))
         m0s.append(torch.zeros((c.n, c.n), dtype=torch.float32, device="cuda"))
-    prm = [pget.SolverParams(max_outer=c.max_outer, n_cg=c.n_cg, alpha_f=c.alpha, alpha_mu=c.alpha)
+    prm = [pget.SolverParams(max_outer=c.max_outer, n_cg=c.n_cg, alpha_f=c.alpha, alpha_mu=c.alpha,
+                             **SOLVER_OPTIONS[args.solver])
            for c in cfgs]
     counts = {}
     for c in cfgs:
@@ -274,6 +275,7 @@ def run_mixed(args, torch, np, inputs, pget):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "mixed_sizes_%d_slices" % n, "sizes": sorted(counts.items()),
+                   "solver": dict({"name": args.solver}, **SOLVER_OPTIONS[args.solver]),
                    "outer": args.outer, "cg": args.cg, "autotuned": bool(args.autotune),
                    "tuned_shapes": {str(k): p.tuned_shape(counts[k]) for k, p in plans.items()}},
         "plain_per_slice": {"value": round(plain, 4), "unit": "reconstructions/s",
@@ -478,7 +480,7 @@ def run_serve(args, torch, pget):
     at tolerance 1e-4) against the plain per-slice solver on the same trace."""
     from paper_2604_26745_amd import serve
     plans, pool = serve.make_pool(args.pool, args.outer, args.cg)
-    prm = pget.SolverParams(max_outer=args.outer, n_cg=args.cg, tol=1e-4)
+    prm = pget.SolverParams(max_outer=args.outer, n_cg=args.cg, tol=1e-4, **SOLVER_OPTIONS[args.solver])
     ex = serve.GpuExecutor(plans, pool, prm, n_slots=args.streams)
     srv = serve.Server(ex, hbm_budget=args.hbm_budget_gb * 1e9, n_slots=args.streams)
     print("bench: serve warm-up (graph capture per size and batch)", file=sys.stderr, flush=True)
@@ -497,6 +499,7 @@ def run_serve(args, torch, pget):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "serve_poisson_%g_per_s_%gs" % (args.rate, args.duration),
+                   "solver": dict({"name": args.solver}, **SOLVER_OPTIONS[args.solver]),
                    "requests": len(reqs), "pool": args.pool, "streams": args.streams,
                    "hbm_budget_gb": args.hbm_budget_gb, "tol": 1e-4, "outer": args.outer,
                    "cg": args.cg},
