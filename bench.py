@@ -32,8 +32,13 @@ if ROOT not in sys.path:
 # linearised Jacobian product gathers two fields from four neighbours and
 # weights them (26 FLOP), the ray march adds the attenuation sums and one exp
 # (30 FLOP).
-FLOP_PER_SAMPLE = {"vjp": 28.0, "gradient": 28.0, "jvp": 26.0, "march": 30.0}
-PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 vector peak (FMA = 2 FLOP)
+# Algorithmic VALU work of one operator pass per in-support sample of the
+# rotated lattice (the method's arithmetic: bilinear taps, the attenuation
+# exponential, the per-ray sums and the tent gather), in lane-operations.
+LANE_OPS_PER_SAMPLE = {"vjp": 70.0, "gradient": 70.0, "jvp": 50.0, "march": 30.0}
+# FP32 VALU peak without packed math (the build disables packed FP32):
+# 256 CUs x 64 lanes x 2.4 GHz, one lane-operation (an FMA counts once) per lane and clock.
+PEAK_VALU_TLANEOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 
 
@@ -605,16 +610,16 @@ def main():
     tot_ms, launches = kt[dom]
     avg_s = tot_ms / 1e3 / max(launches, 1)
     units = plan.support_samples * B
-    achieved = FLOP_PER_SAMPLE[dom] * units / avg_s / 1e12
+    achieved = LANE_OPS_PER_SAMPLE[dom] * units / avg_s / 1e12
     workload = "%s_batch%d" % (cfg.name, B) + ("_bf16" if args.storage == "bf16" else "")
     kernel_name = {"vjp": "k_vjp_lin", "gradient": "k_vjp_lin", "jvp": "k_jvp_lin",
                    "march": "k_march"}.get(dom, dom)
     roofline = {
         "bound": "alu", "kernel": kernel_name, "achieved": round(achieved, 3),
-        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+        "peak": round(PEAK_VALU_TLANEOPS, 3), "unit": "Tlane-op/s", "frac": round(achieved / PEAK_VALU_TLANEOPS, 4),
         "traffic": traffic_from_profile(kernel_name, workload),
         "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-        "flop_per_unit": FLOP_PER_SAMPLE[dom], "units_per_launch": units,
+        "lane_ops_per_unit": LANE_OPS_PER_SAMPLE[dom], "units_per_launch": units,
     }
     if roofline["traffic"]:
         # counter-measured HBM rate of the same launches (the weight stream)
