@@ -99,16 +99,17 @@ def alphas_at(p: LMParams, k: int):
 def prior_at(p: LMParams, k: int):
     """(w_f, w_mu, r_f, r_mu) of the geometry prior at outer iteration k
     (weights divided by the same continuation factor as the alphas), or
-    None when the solve has no prior."""
+    None when the solve has no prior.  A missing weight or reference map
+    is zero."""
     if p.prior_w_f is None and p.prior_w_mu is None:
         return None
+    shape = np.shape(p.prior_w_f if p.prior_w_f is not None else p.prior_w_mu)
     decay = p.alpha_decay ** min(k, p.alpha_decay_until)
 
-    def arr(a, fill):
-        return np.full(np.shape(p.prior_w_f if p.prior_w_f is not None else p.prior_w_mu), fill) if a is None \
-            else np.asarray(a, dtype=np.float64)
-    return (arr(p.prior_w_f, 0.0) / decay, arr(p.prior_w_mu, 0.0) / decay,
-            arr(p.prior_ref_f, 0.0), arr(p.prior_ref_mu, 0.0))
+    def as_map(a):
+        return np.zeros(shape) if a is None else np.asarray(a, dtype=np.float64)
+    return (as_map(p.prior_w_f) / decay, as_map(p.prior_w_mu) / decay,
+            as_map(p.prior_ref_f), as_map(p.prior_ref_mu))
 
 
 def objective(g: Geometry, y, f, mu, af, am, prior=None):
