@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--dg-test", type=int, default=16, help="deepgn: held-out slices")
     ap.add_argument("--dg-outer", type=int, default=5, help="deepgn: outer iterations")
     ap.add_argument("--dg-epochs", type=int, default=40, help="deepgn: epochs per network")
+    ap.add_argument("--dg-decay", type=float, default=1.0,
+                    help="deepgn: divide the alphas by this factor per iteration (the paper uses 5)")
+    ap.add_argument("--dg-decay-until", type=int, default=3, help="deepgn: iterations the decay runs for")
     ap.add_argument("--no-bf16-variant", action="store_true",
                     help="main workload: skip timing the BF16-storage variant beside FP32")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -393,7 +396,8 @@ def run_deepgn(args, torch, np, inputs, pget):
         water = np.where(mask, cfg.water_mu, 0.0)
         f_max, mu_max = 1.0, 0.14
         opts = SCANNER_SOLVER_OPTIONS["scaled"]
-        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts)
+        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts,
+                                alpha_decay=args.dg_decay, alpha_decay_until=args.dg_decay_until)
         wl = "deepgn_scanner9x9_n165_K%d" % K
         extra = {"solver": opts, "mu0": "water in the field of view"}
         data = "synthetic: scanner-geometry 9x9 assemblies, 2% Gaussian noise"
@@ -405,7 +409,8 @@ def run_deepgn(args, torch, np, inputs, pget):
         mask = X ** 2 + Y ** 2 <= (0.5 * cfg.n) ** 2
         f_max, mu_max = 3.0, 0.05
         opts = SOLVER_OPTIONS["scaled"]
-        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts)
+        prm = pget.SolverParams(max_outer=outer, n_cg=cfg.n_cg, alpha_f=cfg.alpha, alpha_mu=cfg.alpha, **opts,
+                                alpha_decay=args.dg_decay, alpha_decay_until=args.dg_decay_until)
         wl = "deepgn_%s_K%d" % (cfg.name, K)
         extra = {"solver": opts, "mu0": "zero", "peak_counts": cfg.peak_counts}
         data = "synthetic: 9x9 rod lattices, Poisson counts"
@@ -468,7 +473,8 @@ def run_deepgn(args, torch, np, inputs, pget):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "%s, %d training / %d test slices" % (data, n_train, n_test),
         "config": dict({"workload": wl, "outer": outer, "cg": cfg.n_cg, "cnn_params": rep.n_params,
-                        "epochs": args.dg_epochs, "train_s": round(t_train, 1)}, **extra),
+                        "epochs": args.dg_epochs, "train_s": round(t_train, 1),
+                        "alpha_decay": [args.dg_decay, args.dg_decay_until]}, **extra),
         "errors": summ, "hook_proposals_kept": kept, "hook_calls": calls,
         "safeguard": {"evaluated": len(sg), "rho_gt_eta": sum(1 for a, _ in sg if a > prm.eta),
                       "model_not_worse": sum(1 for _, b in sg if b >= 1.0),
