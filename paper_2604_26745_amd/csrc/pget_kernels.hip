@@ -831,18 +831,41 @@ __global__ void __launch_bounds__(256) k_fill_zero(float4* p, long long n4)
 }
 
 // Sum of the angle-group partial images (fixed order) into gf / gmu.
+// Sum over the angle groups of the gather's partial images at element m of
+// a slice (f block at m, mu block at n2 + m), in group order; the loads of
+// eight groups are issued before their adds so that they overlap.
+__device__ __forceinline__ float2 sum_groups(const float* gp, long long group_stride, int groups, int m, int n2)
+{
+    float sf = 0.0f, sm = 0.0f;
+    int k = 0;
+    for (; k + 8 <= groups; k += 8) {
+        float vf[8], vm[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            vf[u] = gp[(size_t)(k + u) * group_stride + m];
+            vm[u] = gp[(size_t)(k + u) * group_stride + n2 + m];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sf += vf[u];
+            sm += vm[u];
+        }
+    }
+    for (; k < groups; ++k) {
+        sf += gp[(size_t)k * group_stride + m];
+        sm += gp[(size_t)k * group_stride + n2 + m];
+    }
+    return make_float2(sf, sm);
+}
+
 __global__ void __launch_bounds__(256) k_sum_groups(int n2, int groups, const float* gpart,
                                                     long long group_stride, float* gf, float* gm)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n2) return;
-    float sf = 0.0f, sm = 0.0f;
-    for (int k = 0; k < groups; ++k) {
-        sf += gpart[(size_t)k * group_stride + idx];
-        sm += gpart[(size_t)k * group_stride + n2 + idx];
-    }
-    gf[idx] = sf;
-    gm[idx] = sm;
+    const float2 s = sum_groups(gpart, group_stride, groups, idx, n2);
+    gf[idx] = s.x;
+    gm[idx] = s.y;
 }
 
 // ----------------------------------------------------------- LM kernels
@@ -917,11 +940,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
         const int r = m / n, c = m - r * n;
         const float* uf = V.u + vo;
         const float* um = uf + n2;
-        float gf = 0.0f, gm = 0.0f;
-        for (int k = 0; k < V.groups; ++k) {
-            gf += gp[(size_t)k * V.gpart_group_stride + m];
-            gm += gp[(size_t)k * V.gpart_group_stride + n2 + m];
-        }
+        const float2 gs = sum_groups(gp, V.gpart_group_stride, V.groups, m, n2);
+        float gf = gs.x, gm = gs.y;
         gf = fmaf(af, lap(uf, n, r, c), gf);
         gm = fmaf(am, lap(um, n, r, c), gm);
         double prior_e = 0.0;
@@ -1014,11 +1034,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
         if (c + 1 < n) { lf += pfc - PF(m + 1); lm += pmc - PM(m + 1); }
         if (r > 0) { lf += pfc - PF(m - n); lm += pmc - PM(m - n); }
         if (r + 1 < n) { lf += pfc - PF(m + n); lm += pmc - PM(m + n); }
-        float gf = 0.0f, gm = 0.0f;
-        for (int k = 0; k < V.groups; ++k) {
-            gf += gp[(size_t)k * V.gpart_group_stride + m];
-            gm += gp[(size_t)k * V.gpart_group_stride + n2 + m];
-        }
+        const float2 gs = sum_groups(gp, V.gpart_group_stride, V.groups, m, n2);
+        const float gf = gs.x, gm = gs.y;
         float qf = fmaf(af, lf, fmaf(bdf, pfc, gf));
         float qm = fmaf(am, lm, fmaf(bdm, pmc, gm));
         if (V.prm[slice].prior_w) {
