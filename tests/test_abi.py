@@ -54,3 +54,35 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pget, "_lib", None)
     with pytest.raises(RuntimeError):
         pget.load_library()
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Every field of the binding's ctypes mirrors of pget_geometry,
+    pget_lm_params and pget_lm_report sits at the offset the C compiler
+    gives it, and the sizes agree (a program built from include/pget.h
+    prints them)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    rocm_inc = "/opt/rocm/include"
+    if gcc is None or not os.path.exists(os.path.join(rocm_inc, "hip", "hip_runtime_api.h")):
+        pytest.skip("needs gcc and the HIP headers")
+    from paper_2604_26745_amd import pget
+    structs = {"pget_geometry": pget.Geometry, "pget_lm_params": pget.LMParams, "pget_lm_report": pget.LMReportC}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pget.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append('    printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for field, _ in cls._fields_:
+            lines.append('    printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, field, cname, field))
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-D__HIP_PLATFORM_AMD__", "-I" + rocm_inc, "-I" + os.path.dirname(HEADER),
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
