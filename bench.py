@@ -8,9 +8,22 @@ sigma 1.5 bins, gradient penalty alpha = 1e-2.  Inputs are seeded synthetic
 9 x 9 rod-lattice phantoms with Poisson counting noise (peak 1e4), resident
 in HBM before the timed region starts.  Prints ONE JSON line.
 
-Measured alongside: each kernel class's device time from HIP events on the
-launch stream (the dominant class gives the roofline entry), and the FP64
-CPU oracle timed on the host cores on a bounded sample of the same workload.
+The damped step is taken in variables divided by their typical magnitudes
+with the active set (--solver plain: D = W = I, clamp only).
+
+Measured alongside:
+* each kernel class's device time from HIP events on the launch stream (the
+  dominant class gives the roofline entry, with the counter-measured HBM
+  traffic of the committed profiles);
+* the same batch with BF16 storage of the Jacobian weights;
+* the reconstruction error against the phantoms;
+* a single slice's latency;
+* the FP64 CPU oracle, timed on the host cores on a bounded sample of the
+  same workload.
+
+Other workloads (--workload): mixed grid sizes, serving with p50/p99
+latency, the scanner geometry, and the safeguarded Deep Gauss-Newton
+comparison.
 """
 from __future__ import annotations
 
@@ -294,9 +307,10 @@ def run_mixed(args, torch, np, inputs, pget):
 
 def run_scanner(args, torch, np, inputs, pget):
     """Scanner geometry: 9x9 assemblies (full / missing / replaced / medium
-    rods in turn) drawn on a 330^2 grid of 0.5 mm pixels, projected there by
+    rods in turn) drawn on a 330^2 grid of 1 mm pixels, projected there by
     the library, 2 % Gaussian noise, reconstructed batched on the 165^2 grid
-    of 1 mm pixels (182 bins of 2 mm, 360 angles).  --solver scaled: the step
+    of 2 mm pixels (182 bins of 2 mm, 360 angles); the data are expressed in
+    the reconstruction grid's units (ray sums per 2 mm step).  --solver scaled: the step
     in variables divided by their upper bounds (emission 1, attenuation
     0.14 /mm) with the active set, started from water inside the field of
     view; plain: D = W = I from mu0 = 0.  Reports throughput and the mean
@@ -309,7 +323,7 @@ def run_scanner(args, torch, np, inputs, pget):
         ys_ = d.pop("y_scale")
         n = d.pop("n")
         geo[o] = (pget.Plan(n, d.pop("n_angles"), d.pop("n_bins"), storage=args.storage, **d), ys_)
-    plan, _ = geo[1]
+    plan, cscale = geo[1]
     fine, fscale = geo[cfg.oversample]
     T = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
     kinds = ("full", "missing", "replaced", "medium")
@@ -319,7 +333,7 @@ def run_scanner(args, torch, np, inputs, pget):
     ys, f0s, m0s, truth = [], [], [], []
     for s_ in range(B):
         ff, mf = inputs.scanner_phantom(cfg, s_, kinds[s_ % 4], cfg.oversample)
-        y = inputs.gaussian_noise(fscale * fine.forward(T(ff), T(mf)).double().cpu().numpy(), cfg.noise, s_)
+        y = inputs.gaussian_noise((fscale / cscale) * fine.forward(T(ff), T(mf)).double().cpu().numpy(), cfg.noise, s_)
         truth.append(inputs.scanner_phantom(cfg, s_, kinds[s_ % 4], 1))
         c0 = float((a1 * y).sum() / (a1 * a1).sum())
         ys.append(T(y))
@@ -353,7 +367,7 @@ def run_scanner(args, torch, np, inputs, pget):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.storage == "fp32" else "bf16-storage/f32-compute",
-        "data": "synthetic: 9x9 assemblies on a 0.5 mm grid, 2% Gaussian noise",
+        "data": "synthetic: 9x9 assemblies on a 1 mm grid, 2% Gaussian noise",
         "config": {"workload": "%s_batch%d" % (cfg.name, B), "outer": cfg.max_outer, "cg": cfg.n_cg,
                    "pixel_mm": cfg.pixel_mm, "bin_mm": cfg.bin_mm, "oversample": cfg.oversample,
                    "solver": dict({"name": args.solver, "prior_gamma": args.prior}, **opts),
@@ -389,7 +403,7 @@ def run_deepgn(args, torch, np, inputs, pget):
             ys_ = d.pop("y_scale")
             n = d.pop("n")
             geo[o] = (pget.Plan(n, d.pop("n_angles"), d.pop("n_bins"), **d), ys_)
-        plan, _ = geo[1]
+        plan, cscale = geo[1]
         fine, fscale = geo[cfg.oversample]
         kinds = ("full", "missing", "replaced", "medium")
         mask = inputs.fov_mask(cfg)
@@ -420,7 +434,7 @@ def run_deepgn(args, torch, np, inputs, pget):
     def sample(s_):
         if args.dg_set == "scanner":
             ff, mf = inputs.scanner_phantom(cfg, s_, kinds[s_ % 4], cfg.oversample)
-            y = inputs.gaussian_noise(fscale * fine.forward(T(ff), T(mf)).double().cpu().numpy(), cfg.noise, s_)
+            y = inputs.gaussian_noise((fscale / cscale) * fine.forward(T(ff), T(mf)).double().cpu().numpy(), cfg.noise, s_)
             tf, tm = inputs.scanner_phantom(cfg, s_, kinds[s_ % 4], 1)
             m0 = T(water)
         else:

@@ -141,14 +141,16 @@ class ScannerConfig:
     detector elements whose readings interleave over a full turn to 182 bins
     at 2 mm, a 165 x 165 reconstruction grid, data generated on a grid
     ``oversample`` times finer.  Readings where the paper gives no number:
-    1 mm pixels (165 mm field), 360 angles, collimator response a Gaussian of
-    1 bin (2 mm) standard deviation, a 9 x 9 lattice at 14.4 mm pitch with
-    5.5 mm rod radius, rod centres perturbed by U(-0.5, 0.5) mm per axis,
-    water filling the field-of-view disk."""
+    pixels of the detector spacing, 2 mm (a 330 mm field inside the 364 mm
+    detector span, the assembly a central section of the image), 360
+    angles, collimator response a Gaussian of 1 bin (2 mm) standard
+    deviation, a 9 x 9 lattice at 14.4 mm pitch with 5.5 mm rod radius, rod
+    centres perturbed by U(-0.5, 0.5) mm per axis, water filling the
+    field-of-view disk."""
 
     name: str = "scanner9x9_n165_a360_b182"
     n: int = 165
-    pixel_mm: float = 1.0
+    pixel_mm: float = 2.0
     n_angles: int = 360
     n_bins: int = 182
     bin_mm: float = 2.0
@@ -253,14 +255,18 @@ def _outside_rods(n: int, px: float, centres, reach: float) -> np.ndarray:
     return out
 
 
-def scanner_rod_prior(cfg: ScannerConfig, margin_mm: float = 1.0):
+def scanner_rod_prior(cfg: ScannerConfig, margin_mm: Optional[float] = None):
     """Where the geometry prior applies (the paper's P1, P2: emission and
     attenuation away from every possible rod location of the known 9 x 9
     layout are penalised; no rod is assumed present).  Returns
     (outside, ref_f, ref_mu) on the reconstruction grid: `outside` is 1 for
-    pixels farther than rod radius + jitter + margin from every nominal rod
-    centre, the references are no emission there and water attenuation
-    inside the field of view (0 outside it)."""
+    pixels whose centre is farther than rod radius + jitter + margin from
+    every nominal rod centre (margin: one pixel by default, more than the
+    pixel's half-diagonal, so that no such pixel overlaps a rod), the
+    references are no emission there and water attenuation inside the field
+    of view (0 outside it)."""
+    if margin_mm is None:
+        margin_mm = cfg.pixel_mm
     nr = cfg.n_rods
     centres = [((k - 0.5 * (nr - 1)) * cfg.pitch_mm, (l - 0.5 * (nr - 1)) * cfg.pitch_mm)
                for l in range(nr) for k in range(nr)]

@@ -1,22 +1,24 @@
 """Scanner geometry on the GPU against the FP64 oracle: the operators on the
-165 x 165 reconstruction grid (1 mm pixels, 182 bins of 2 pixels, 360
-angles) and on the 330 x 330 data grid (0.5 mm pixels, bins of 4 pixels,
-attenuation per mm through atten_scale 0.5), and the LM reconstruction of
-the stored slice (data from the fine grid with 2 % noise, tests/golden/)
-with the oracle's decisions replayed.  Tolerances: forward relative L2
-<= 1e-5 and max-abs / max-ref <= 1e-4 on both grids.  Jacobian products on
-the reconstruction grid: <= 1e-5 for band-limited directions (white noise
-smoothed by a Gaussian of one pixel, like the directions the solver
-produces), <= 2e-5 for white noise; on the data grid (used only for its
-forward map) <= 3e-5.  Sample positions are FP32 pixel coordinates reaching
-~180 px (~360 on the data grid), one rounding is up to 7.6e-6 px (1.5e-5),
-and the relative error of a product grows with that position error and with
-the bin spacing in pixels (2 and 4 here), since a pixel then draws on fewer
-lattice points.  LM: objective per iterate <= 1e-5 relative (measured
-6.2e-6), maps after 5 / 10 / 15 iterations <= 5e-5 relative L2 (measured
-f 2.1e-6, mu 1.4e-5 after 15: CG in FP32 amplifies the products' rounding
-by the conditioning of the damped normal matrix, which the strong
-attenuation of this geometry makes worse than in the lattice workloads).
+165 x 165 reconstruction grid (2 mm pixels, 182 bins of 1 pixel, 360
+angles) and on the 330 x 330 data grid (1 mm pixels, bins of 2 pixels,
+attenuation per mm through atten_scale 1), and the LM reconstruction of the
+stored slice (data from the fine grid with 2 % noise, in the reconstruction
+grid's units, tests/golden/) with the oracle's decisions replayed.
+Tolerances: forward relative L2 <= 1e-5 and max-abs / max-ref <= 1e-4 on
+both grids.  Jacobian products on the reconstruction grid (bins of one
+pixel, as in the lattice workloads): <= 1e-5 for band-limited directions
+(white noise smoothed by a Gaussian of one pixel, like the directions the
+solver produces) and white noise.  On the data grid (330 pixels, bins of 2
+pixels): <= 2e-5, as for every map above 256 pixels: sample positions are
+FP32 pixel coordinates reaching ~233 px, where one rounding is up to
+1.5e-5 px, and with bins of 2 pixels a pixel draws on fewer lattice points,
+so that rounding weighs more (measured 1.2e-5 for the adjoint).  LM:
+objective per iterate and maps after 5 / 10 / 15 iterations within five
+times the spread the oracle itself shows when every operator product is
+perturbed by 1e-6 relative noise (stored with its run), and at least as
+close as 1e-5 / 5e-5: in this geometry the first CG solve amplifies such a
+perturbation to about 5 % in the next objective (26 % in the predicted
+decrease), so FP32 and FP64 trajectories part there.
 """
 import os
 import sys
@@ -91,7 +93,9 @@ def test_scanner_operators(oversample, n_angles, smooth):
     log("scanner x%d %s: forward %.2e jvp %.2e vjp f %.2e mu %.2e"
         % ((oversample, "band-limited" if smooth else "white noise") + errs))
     assert errs[0] <= 1e-5 and maxrel(y, y_ref) <= 1e-4
-    bound = (1e-5 if smooth else 2e-5) if oversample == 1 else 3e-5
+    bins_px = CFG.bin_mm / (CFG.pixel_mm / oversample)
+    n = CFG.n * oversample
+    bound = 1e-5 if (n <= 256 and (bins_px == 1 or smooth)) else 2e-5
     assert max(errs[1:]) <= bound
     assert maxrel(jv, jv_ref) <= 1e-4
     assert maxrel(H(gf), gf_ref) <= 1e-4 and maxrel(H(gm), gm_ref) <= 1e-4
@@ -115,8 +119,70 @@ def test_scanner_lm_replayed():
         if k_end == 15:
             errs = [abs(rep.phi[k] - ref["phi"][k]) / ref["phi"][k] for k in range(len(ref["phi"]))]
         maps[k_end] = (rel(f.cpu().numpy(), ref["f%d" % k_end]), rel(mu.cpu().numpy(), ref["mu%d" % k_end]))
+    # five times the oracle's own spread under FP32-level perturbations of
+    # its operator products (stored with it), and at least as close as
+    # 1e-5 / 5e-5: the first CG solve of this geometry amplifies a 1e-6
+    # perturbation to about 5 % in the next objective
+    bounds = [max(1e-5, 5 * v) for v in ref["spread_phi"]]
+    mb = {k: [max(5e-5, 5 * v) for v in ref["spread_maps"][i]] for i, k in enumerate((5, 10, 15))}
     log("scanner phi rel err per iterate: %s" % " ".join("%.1e" % e for e in errs))
-    log("scanner map rel L2 (f, mu) after 5/10/15: %s" % " ".join("(%.1e, %.1e)" % maps[k] for k in (5, 10, 15)))
-    assert max(errs) <= 1e-5
+    log("scanner phi bounds per iterate: %s" % " ".join("%.1e" % b for b in bounds))
+    log("scanner map rel L2 (f, mu) after 5/10/15: %s (bounds %s)" % (
+        " ".join("(%.1e, %.1e)" % maps[k] for k in (5, 10, 15)), " ".join("(%.1e, %.1e)" % tuple(mb[k]) for k in (5, 10, 15))))
+    for e, b in zip(errs, bounds):
+        assert e <= b
     for k in (5, 10, 15):
-        assert maps[k][0] <= 5e-5 and maps[k][1] <= 5e-5
+        assert maps[k][0] <= mb[k][0] and maps[k][1] <= mb[k][1]
+
+
+GOLDEN_SCALED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "scanner9x9_n165_scaled_oracle.npz")
+
+
+def test_scanner_scaled_as_slice_of_batch64():
+    """The scanner benchmark's configuration (scaled active-set step, water
+    start, a batch of 64) against the stored oracle run of its first 3
+    iterations on slice 0: the first linearisation tightly (objective 1e-6,
+    gradient norm 1e-5, the first three CG residuals 1e-3 of the start),
+    then the objective per iterate and the maps within five times the
+    spread the oracle itself shows under 1e-6 relative perturbations of its
+    operator products (stored with it), and at least as close as 1e-5 /
+    5e-5 (the scanner grid's map bound above)."""
+    if not os.path.exists(GOLDEN_SCALED):
+        pytest.skip("stored oracle reconstruction not present")
+    ref = np.load(GOLDEN_SCALED)
+    og, pl = plans(1)
+    fine = plans(2)[1]
+    fscale = inputs.scanner_geometry(CFG, 2)["y_scale"] / inputs.scanner_geometry(CFG, 1)["y_scale"]
+    kinds = ("full", "missing", "replaced", "medium")
+    ys, f0s, m0s = [T(ref["y"])], [T(ref["f0"])], [T(ref["mu0"])]
+    one = torch.ones((CFG.n, CFG.n), device="cuda")
+    a1 = pl.forward(one, torch.zeros_like(one)).double()
+    for s_ in range(1, 64):   # the rest of the batch, as the benchmark draws it
+        ff, mf = inputs.scanner_phantom(CFG, s_, kinds[s_ % 4], 2)
+        y = inputs.gaussian_noise(fscale * fine.forward(T(ff), T(mf)).double().cpu().numpy(), CFG.noise, s_)
+        c0 = float((a1.cpu().numpy() * y).sum() / (a1 * a1).sum().item())
+        ys.append(T(y))
+        f0s.append(torch.full_like(one, c0))
+        m0s.append(T(ref["mu0"]))
+    outer = int(ref["outer"])
+    base = dict(max_outer=outer, n_cg=CFG.n_cg, alpha_f=CFG.alpha, alpha_mu=CFG.alpha,
+                w_mu=float(ref["w_mu"]), d_mu=float(ref["d_mu"]), active_set=1)
+    prm = [pget.SolverParams(replay=[int(v) for v in ref["accepted"]], **base)] + [pget.SolverParams(**base)] * 63
+    fs, ms, rbs = pl.lm_solve_batched(ys, f0s, m0s, prm)
+    rep = rbs[0].to_report()
+    assert rep.accepted == [int(v) for v in ref["accepted"]]
+    assert abs(rep.phi[0] - ref["phi"][0]) <= 1e-6 * ref["phi"][0]
+    assert abs(rep.gnorm[0] - ref["gnorm"][0]) <= 1e-5 * ref["gnorm"][0]
+    for m in range(3):
+        assert abs(rep.cg_rr[0][m] - ref["cg_rr0"][m]) <= 1e-3 * ref["cg_rr0"][0]
+    errs = [abs(rep.phi[k] - ref["phi"][k]) / ref["phi"][k] for k in range(len(ref["phi"]))]
+    bounds = [max(1e-5, 5 * v) for v in ref["spread_phi"]]
+    ef, em = rel(H(fs[0]), ref["f3"]), rel(H(ms[0]), ref["mu3"])
+    bf, bm = max(5e-5, 5 * float(ref["spread_f"])), max(5e-5, 5 * float(ref["spread_m"]))
+    log("scanner scaled batch64 slice 0 phi rel err per iterate: %s (bounds %s)" % (
+        " ".join("%.1e" % e for e in errs), " ".join("%.1e" % b for b in bounds)))
+    log("scanner scaled batch64 slice 0 maps after %d: f %.1e (bound %.1e) mu %.1e (bound %.1e)" % (
+        outer, ef, bf, em, bm))
+    for e, b in zip(errs, bounds):
+        assert e <= b
+    assert ef <= bf and em <= bm

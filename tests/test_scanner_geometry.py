@@ -1,11 +1,11 @@
-"""Scanner geometry (182 bins at 2 mm, 165 x 165 grid of 1 mm pixels, data on
+"""Scanner geometry (182 bins at 2 mm, 165 x 165 grid of 2 mm pixels, data on
 a grid twice as fine): the unit bookkeeping of ``inputs.scanner_geometry`` and
 the phantom generator, pinned through the oracle to things other than itself.
 
 * A uniform disk without attenuation projects to its chord lengths
   2 sqrt(R^2 - s^2) (mm) at bin offsets s = (j - 90.5) * 2 mm.
-* A smooth object projected on the fine grid (0.5 mm pixels, attenuation per
-  mm through atten_scale = 0.5, ray sums scaled by 0.5 mm) agrees with its
+* A smooth object projected on the fine grid (1 mm pixels, attenuation per
+  mm through atten_scale = 1, ray sums scaled by 1 mm) agrees with its
   projection on the reconstruction grid to the discretisation error
   (second order in the pixel size).
 * The phantom's total emission and attenuation agree across resolutions.
@@ -39,9 +39,9 @@ def test_uniform_disk_projects_to_chord_lengths():
     g, ys = geometry(1, n_angles=8, psf_sigma=0.0)
     X, Y = grid_mm(1)
     R = 40.0
-    # 8 x 8 supersampled disk (area-weighted pixels)
+    # 8 x 8 supersampled disk (area-weighted pixels; offsets in mm)
     sub = 8
-    off = ((np.arange(sub) + 0.5) / sub - 0.5)
+    off = ((np.arange(sub) + 0.5) / sub - 0.5) * CFG.pixel_mm
     f = np.zeros_like(X)
     for a in off:
         for b in off:
@@ -52,11 +52,11 @@ def test_uniform_disk_projects_to_chord_lengths():
     chord = 2.0 * np.sqrt(np.maximum(R * R - s * s, 0.0))
     inner = np.abs(s) < R - 3.0
     for a in range(8):
-        # mm: sampling an area-weighted edge every 1 mm along the ray moves the
-        # chord by a fraction of a sample; a wrong bin spacing would shift it
-        # by tens of mm
+        # mm: sampling an area-weighted edge every pixel (2 mm) along the ray
+        # moves the chord by a fraction of a sample; a wrong bin spacing would
+        # shift it by tens of mm
         err = np.abs(y[a, inner] - chord[inner]).max()
-        assert err < 0.5, (a, err)
+        assert err < 0.5 * CFG.pixel_mm, (a, err)
         assert np.linalg.norm(y[a, inner] - chord[inner]) / np.linalg.norm(chord[inner]) < 1e-2
     # total: every angle integrates the disk area (pi R^2 in mm^2) over bins of 2 mm
     assert abs(y.sum(axis=1).mean() * CFG.bin_mm - math.pi * R * R) / (math.pi * R * R) < 2e-3
@@ -74,9 +74,10 @@ def test_fine_grid_projection_matches_reconstruction_grid():
     y2 = s2 * O.forward(g2, *smooth(2))
     rel = np.linalg.norm(y2 - y1) / np.linalg.norm(y1)
     assert rel < 2e-3, rel
-    # dropping the pixel-size factor of the attenuation would be a gross mismatch
+    # attenuation per pixel of the coarse grid on the fine grid (a factor-2
+    # slip in the pixel size) would be a gross mismatch
     g2_wrong = O.Geometry(g2.n, g2.n_angles, g2.n_bins, bin_size=g2.bin_size, step=g2.step,
-                          psf_sigma=g2.psf_sigma, atten_scale=1.0)
+                          psf_sigma=g2.psf_sigma, atten_scale=2.0 * g2.atten_scale)
     y2_wrong = s2 * O.forward(g2_wrong, *smooth(2))
     assert np.linalg.norm(y2_wrong - y1) / np.linalg.norm(y1) > 20 * rel
 
@@ -102,7 +103,12 @@ def test_rod_prior_holds_for_every_phantom_kind():
     (water in the field of view) except on pixels the field-of-view circle
     cuts, for every kind and several seeds (rod jitter included)."""
     out, ref_f, ref_mu = inputs.scanner_rod_prior(CFG)
-    assert 0.4 < out.mean() < 0.7 and np.all(ref_f == 0.0)
+    # the region is the image minus 81 disks of radius rod + jitter + a pixel
+    # (to the pixel-centre discretisation of disks about 4 pixels across:
+    # a few percent of their area)
+    reach = CFG.rod_radius_mm + CFG.jitter_mm + CFG.pixel_mm
+    expect = 1.0 - CFG.n_rods ** 2 * math.pi * reach ** 2 / (CFG.n * CFG.pixel_mm) ** 2
+    assert abs(out.mean() - expect) < 0.02 and np.all(ref_f == 0.0)
     cc = np.arange(CFG.n) - 0.5 * (CFG.n - 1)
     X, Y = np.meshgrid(cc, cc)
     edge = np.abs(np.sqrt(X ** 2 + Y ** 2) - 0.5 * CFG.n) < 1.0
