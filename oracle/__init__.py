@@ -24,6 +24,8 @@ import os
 import subprocess
 from dataclasses import dataclass
 
+from typing import Optional, Tuple
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +58,7 @@ class _CGeometry(ctypes.Structure):
         ("step", ctypes.c_double),
         ("psf_sigma", ctypes.c_double),
         ("atten_scale", ctypes.c_double),
+        ("depth", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -102,12 +105,22 @@ class Geometry:
     psf_sigma: float = 1.5
     psf_radius: int = -1
     atten_scale: float = 1.0
+    # per-sample depth factor d_i of the attenuation path (n_samples values,
+    # sample 0 farthest from the detector), or None for d_i = 1
+    depth: Optional[Tuple[float, ...]] = None
 
     def _c(self) -> _CGeometry:
-        return _CGeometry(
+        c = _CGeometry(
             self.n, self.n_angles, self.n_bins, self.psf_radius, self.angle0,
-            self.arc, self.bin_size, self.step, self.psf_sigma, self.atten_scale,
+            self.arc, self.bin_size, self.step, self.psf_sigma, self.atten_scale, None,
         )
+        if self.depth is not None:
+            arr = (ctypes.c_double * len(self.depth))(*self.depth)
+            c.depth = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+            c._keep = arr
+            if len(self.depth) != _load().og_n_samples(ctypes.byref(c)):
+                raise ValueError("depth needs one value per sample along a ray")
+        return c
 
     @property
     def n_samples(self) -> int:

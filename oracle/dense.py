@@ -61,16 +61,18 @@ class DenseModel:
     """All matrices of one tiny geometry."""
 
     def __init__(self, n, n_angles, n_bins, psf_sigma=1.5, psf_radius=-1,
-                 angle0=0.0, arc=2.0 * math.pi, bin_size=1.0, step=1.0, atten_scale=1.0):
+                 angle0=0.0, arc=2.0 * math.pi, bin_size=1.0, step=1.0, atten_scale=1.0, depth=None):
         qx, qy, n_t = lattice(n, n_angles, n_bins, angle0, arc, bin_size, step)
         self.n, self.n_angles, self.n_bins, self.n_t = n, n_angles, n_bins, n_t
-        self.step, self.c = step, atten_scale
+        self.step = step
+        # path factor per sample: atten_scale times the depth factor d_i
+        self.c = atten_scale * (np.ones(n_t) if depth is None else np.asarray(depth, dtype=np.float64))
         self.W = interpolation_matrix(n, qx, qy)          # (A*J*T, n*n)
         self.U = beam_matrix(n_t)                          # (T, T)
         self.K = psf_matrix(n_bins, psf_sigma, psf_radius)  # (J, J)
 
     def forward(self, f, mu, xp=np):
-        """y = K [step * sum_i lam_i exp(-c * step * (U mu_hat)_i)], any array module."""
+        """y = K [step * sum_i lam_i exp(-c_i * step * (U mu_hat)_i)], any array module."""
         A, J, T = self.n_angles, self.n_bins, self.n_t
         W = xp.asarray(self.W) if xp is not np else self.W
         U = xp.asarray(self.U) if xp is not np else self.U
@@ -78,5 +80,6 @@ class DenseModel:
         lam = (W @ f.reshape(-1)).reshape(A, J, T)
         mh = (W @ mu.reshape(-1)).reshape(A, J, T)
         B = self.step * (mh @ U.T)                     # B[a,j,i] = step * sum_i' U[i,i'] mh[a,j,i']
-        p = self.step * (lam * xp.exp(-self.c * B)).sum(-1)   # (A, J)
+        c = xp.asarray(self.c) if xp is not np else self.c
+        p = self.step * (lam * xp.exp(-c * B)).sum(-1)   # (A, J)
         return p @ K.T                                  # y[a, j] = sum_j' K[j, j'] p[a, j']

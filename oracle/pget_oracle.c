@@ -16,7 +16,11 @@
  *             attenuation seen by a sample is the sum of the attenuation
  *             samples between it and the detector (midpoint rule: half of
  *             its own sample), and the collimator response r_{m,n} is a
- *             depth-independent Gaussian across detector bins.
+ *             depth-independent Gaussian across detector bins.  The factor
+ *             c_{m,n} >= 1 on an emitter's attenuation path is atten_scale
+ *             times an optional per-sample depth factor d_i (the vertical
+ *             correction: an emitter farther from the detector reaches it
+ *             along a steeper path), d_i = 1 when none is given.
  *   jvp       Sec. 2.1, eq. (frechet): D_lambda F[dl] = F(dl, mu) and
  *             D_mu F[dm] = -F(lambda * B(dm), mu), discretised the same way.
  *   vjp       the exact transpose of jvp (the adjoint F'^* that the gradient
@@ -47,8 +51,15 @@ typedef struct {
     double bin_size;  /* detector bin spacing (pixels)                  */
     double step;      /* sample spacing along a ray (pixels)            */
     double psf_sigma; /* Gaussian sigma in bins; 0 = no blur            */
-    double atten_scale; /* c_{m,n} of eq. (d_fwd_model), a constant     */
+    double atten_scale; /* c_{m,n} of eq. (d_fwd_model): this constant  */
+    const double* depth; /* times depth[i] for sample i (n_t values), or NULL */
 } og_geometry;
+
+/* c for an emitter at sample i of a ray */
+static double path_factor(const og_geometry* g, int i)
+{
+    return g->depth ? g->atten_scale * g->depth[i] : g->atten_scale;
+}
 
 /* number of samples along each ray */
 int og_n_samples(const og_geometry* g)
@@ -182,7 +193,7 @@ static void psf_apply_transpose(const og_geometry* g, const double* w, double* v
 /*
  * Per-ray quantities shared by the three operators: the sampled emission
  * lam[i], sampled attenuation mu[i], and the transmission
- * E[i] = exp(-c * B_i),  B_i = step * (mu[i]/2 + sum_{i' > i} mu[i']).
+ * E[i] = exp(-c_i * B_i),  B_i = step * (mu[i]/2 + sum_{i' > i} mu[i']).
  */
 static void ray_state(const og_geometry* g, const double* f, const double* mu, const ray_t* ray,
                       double* lam_s, double* mu_s, double* E)
@@ -197,7 +208,7 @@ static void ray_state(const og_geometry* g, const double* f, const double* mu, c
     double beyond = 0.0; /* sum of mu samples strictly closer to the detector */
     for (int i = nt - 1; i >= 0; --i) {
         double B = g->step * (0.5 * mu_s[i] + beyond);
-        E[i] = exp(-g->atten_scale * B);
+        E[i] = exp(-path_factor(g, i) * B);
         beyond += mu_s[i];
     }
 }
@@ -246,7 +257,7 @@ void og_psf_transpose(const og_geometry* g, const double* w, double* v) { psf_ap
 
 /*
  * jv = J [vf, vmu] = D_lambda F[vf] + D_mu F[vmu]:
- *   raw_{a,j} = step * sum_i E_i * (vf_i - c * lam_i * V_i),
+ *   raw_{a,j} = step * sum_i E_i * (vf_i - c_i * lam_i * V_i),
  *   V_i = step * (vmu_i/2 + sum_{i' > i} vmu_i')  (the beam transform of vmu),
  * followed by the same collimator blur as the forward map.
  */
@@ -274,7 +285,7 @@ void og_jvp(const og_geometry* g, const double* f, const double* mu, const doubl
             double acc = 0.0, beyond = 0.0;
             for (int i = nt - 1; i >= 0; --i) {
                 double V = g->step * (0.5 * vmu_s[i] + beyond);
-                acc += E[i] * (vf_s[i] - g->atten_scale * lam_s[i] * V);
+                acc += E[i] * (vf_s[i] - path_factor(g, i) * lam_s[i] * V);
                 beyond += vmu_s[i];
             }
             p[(size_t)a * g->n_bins + j] = g->step * acc;
@@ -286,7 +297,7 @@ void og_jvp(const og_geometry* g, const double* f, const double* mu, const doubl
 /*
  * [gf, gmu] = J^T w.  With wt = K^T w, every sample i of ray (a, j) carries
  *   d/d lam_i = step * E_i * wt,
- *   d/d mu_i  = -c * step^2 * wt * (lam_i E_i / 2 + sum_{i' < i} lam_i' E_i'),
+ *   d/d mu_i  = -step^2 * wt * (c_i lam_i E_i / 2 + sum_{i' < i} c_i' lam_i' E_i'),
  * (mu_i attenuates itself by half and every sample farther from the
  * detector fully), and these are spread back to the pixels with the same
  * bilinear weights that sampled them.
@@ -309,12 +320,12 @@ void og_vjp(const og_geometry* g, const double* f, const double* mu, const doubl
             double wr = wt[(size_t)a * g->n_bins + j];
             ray_t ray = make_ray(g, a, j);
             ray_state(g, f, mu, &ray, lam_s, mu_s, E);
-            double before = 0.0; /* sum of lam*E over samples farther from the detector */
+            double before = 0.0; /* sum of c*lam*E over samples farther from the detector */
             for (int i = 0; i < nt; ++i) {
-                double le = lam_s[i] * E[i];
+                double cle = path_factor(g, i) * lam_s[i] * E[i];
                 double d_lam = g->step * E[i] * wr;
-                double d_mu = -g->atten_scale * g->step * g->step * wr * (0.5 * le + before);
-                before += le;
+                double d_mu = -g->step * g->step * wr * (0.5 * cle + before);
+                before += cle;
                 double qx, qy;
                 int idx[4];
                 double bw[4];

@@ -261,3 +261,77 @@ def test_regulariser_gradient_and_nullspace():
     assert np.abs(O.reg_gradient(alpha, np.full((n, n), 3.0))).max() == 0.0
     ramp = np.tile(np.arange(n, dtype=float), (n, 1))
     assert abs(O.reg_energy(alpha, ramp) - 0.5 * alpha * n * (n - 1)) < 1e-12
+
+
+# ------------------------------------------------- depth factor of the path
+def _depth(n_t, seed):
+    """A smooth depth factor >= 1, largest far from the detector (sample 0)."""
+    rng = np.random.default_rng(seed)
+    t = np.linspace(1.0, 0.0, n_t)
+    return tuple(1.0 + 0.8 * t + 0.05 * rng.uniform(size=n_t))
+
+
+def test_depth_factor_matches_dense_and_autograd():
+    """With a per-sample factor d_i on the attenuation path (c_i = c d_i),
+    the oracle agrees with the dense formulation and its Jacobian products
+    with torch autograd of that formulation (where c_i enters the
+    exponential of every sample separately)."""
+    torch = pytest.importorskip("torch")
+    n, na, nb = 8, 8, 12
+    n_t = O.Geometry(n, na, nb).n_samples
+    d = _depth(n_t, 0)
+    g = O.Geometry(n, na, nb, psf_sigma=1.5, atten_scale=0.7, depth=d)
+    D = DenseModel(n, na, nb, psf_sigma=1.5, atten_scale=0.7, depth=d)
+    rng = np.random.default_rng(17)
+    f = rng.uniform(0, 1, (n, n))
+    mu = rng.uniform(0, 0.3, (n, n))
+    y = O.forward(g, f, mu)
+    assert np.abs(y - D.forward(f, mu)).max() <= 1e-13 * np.abs(y).max()
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal((na, nb))
+    fn = lambda a, b: D.forward(a, b, xp=torch)
+    T = lambda a: torch.tensor(a, dtype=torch.float64)
+    _, jt = torch.func.jvp(fn, (T(f), T(mu)), (T(vf), T(vm)))
+    jv = O.jvp(g, f, mu, vf, vm)
+    assert np.abs(jt.numpy() - jv).max() <= 1e-13 * np.abs(jv).max()
+    _, back = torch.func.vjp(fn, T(f), T(mu))
+    tf, tm = back(T(w))
+    gf, gm = O.vjp(g, f, mu, w)
+    assert np.abs(tf.numpy() - gf).max() <= 1e-13 * np.abs(gf).max()
+    assert np.abs(tm.numpy() - gm).max() <= 1e-13 * np.abs(gm).max()
+    # the factor matters: without it the attenuation part differs
+    g0 = O.Geometry(n, na, nb, psf_sigma=1.5, atten_scale=0.7)
+    assert np.abs(O.forward(g0, f, mu) - y).max() > 1e-3 * np.abs(y).max()
+
+
+def test_uniform_depth_is_a_scaled_attenuation():
+    """d_i = 2 everywhere is the constant factor c = 2 exactly."""
+    n, na, nb = 12, 10, 18
+    n_t = O.Geometry(n, na, nb).n_samples
+    g2 = O.Geometry(n, na, nb, atten_scale=2.0)
+    gd = O.Geometry(n, na, nb, depth=(2.0,) * n_t)
+    rng = np.random.default_rng(18)
+    f = rng.uniform(0, 1, (n, n))
+    mu = rng.uniform(0, 0.2, (n, n))
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal((na, nb))
+    assert np.array_equal(O.forward(g2, f, mu), O.forward(gd, f, mu))
+    assert np.array_equal(O.jvp(g2, f, mu, vf, vm), O.jvp(gd, f, mu, vf, vm))
+    for a, b in zip(O.vjp(g2, f, mu, w), O.vjp(gd, f, mu, w)):
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        O.Geometry(n, na, nb, depth=(1.0,) * (n_t - 1)).n_samples
+
+
+def test_depth_adjoint_identity():
+    n = 16
+    n_t = O.Geometry(n, 14, 23).n_samples
+    g = O.Geometry(n, 14, 23, psf_sigma=1.5, depth=_depth(n_t, 1))
+    rng = np.random.default_rng(19)
+    f = rng.uniform(0, 1, (n, n))
+    mu = rng.uniform(0, 0.15, (n, n))
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal(g.sino_shape)
+    lhs = np.sum(O.jvp(g, f, mu, vf, vm) * w)
+    gf, gm = O.vjp(g, f, mu, w)
+    assert abs(lhs - (np.sum(vf * gf) + np.sum(vm * gm))) <= 1e-12 * abs(lhs)
