@@ -107,6 +107,22 @@ int32_t pget_plan_psf_half_width(const pget_plan* plan);
 int64_t pget_plan_support_samples(const pget_plan* plan);
 
 /*
+ * Depth factor of the attenuation path (the vertical correction c_{m,n} >= 1
+ * of the discrete model, Sec. 2.1 eq. d_fwd_model: an emitter farther from
+ * the detector reaches it along a steeper path through the medium).  The
+ * transmission of sample i of every ray becomes exp(-atten_scale * d[i] *
+ * B_i), and the Jacobian products follow.  `depth` is a host array of
+ * pget_plan_n_samples(plan) values, sample 0 farthest from the detector
+ * (t_i = (i - (n_t - 1)/2) * step along the direction toward the detector);
+ * each must be finite and > 0.  NULL restores d = 1.  The values are copied
+ * to the device (a small allocation owned by the plan) before the call
+ * returns; calls enqueued afterwards use them, and no call of this plan may
+ * be in flight meanwhile.  Errors: INVALID_ARG (null plan, wrong count, bad
+ * value), HIP (allocation or copy failed).
+ */
+pget_status pget_plan_set_depth_factor(pget_plan* plan, const double* depth, int32_t n);
+
+/*
  * Device workspace needed by `op` for `batch` slices of this plan's shape
  * (batch >= 1; forward/jvp/vjp use batch 1).  0 on a bad argument.
  */

@@ -20,6 +20,7 @@ struct pget_plan {
     Geo g;
     Tables t;
     void* table_mem;     // one device allocation holding every table
+    float* depth_mem = nullptr;   // per-sample depth factor (set on demand)
     bool bf16;           // BF16 storage of staged maps and per-sample weights
     size_t px_bytes;     // bytes of one staged map pair (8 FP32, 4 BF16)
     size_t w_bytes;      // bytes of one per-sample weight pair
@@ -445,6 +446,7 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     P->t.clip = reinterpret_cast<const int2*>(base + o_clip);
     P->t.grange = reinterpret_cast<const int2*>(base + o_gr);
     P->t.taps = reinterpret_cast<const float*>(base + o_taps);
+    P->t.depth = nullptr;
 
     // ---- launch shapes
     // the ray march stages the FP32 map pair; the Jacobian product stages the
@@ -525,9 +527,10 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     return PGET_OK;
 }
 
-void pget_plan_destroy(pget_plan* plan)
+// Captured solver sequences that launch kernels of this plan (their kernel
+// arguments hold the plan's shapes and table pointers).
+static void drop_graphs(const pget_plan* plan)
 {
-    if (!plan) return;
     for (size_t k = 0; k < g_graphs.size();) {
         bool uses = false;
         for (auto& gk : g_graphs[k].key.groups) uses |= gk[0] == (long long)(intptr_t)plan;
@@ -538,8 +541,40 @@ void pget_plan_destroy(pget_plan* plan)
             ++k;
         }
     }
+}
+
+void pget_plan_destroy(pget_plan* plan)
+{
+    if (!plan) return;
+    drop_graphs(plan);
     (void)hipFree(plan->table_mem);
+    if (plan->depth_mem) (void)hipFree(plan->depth_mem);
     delete plan;
+}
+
+pget_status pget_plan_set_depth_factor(pget_plan* plan, const double* depth, int32_t n)
+{
+    if (!plan) return PGET_ERR_INVALID_ARG;
+    if (!depth) {
+        plan->t.depth = nullptr;
+        drop_graphs(plan);
+        return PGET_OK;
+    }
+    if (n != plan->g.n_t) return PGET_ERR_INVALID_ARG;
+    std::vector<float> d((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        if (!(depth[i] > 0.0) || !isfinite(depth[i])) return PGET_ERR_INVALID_ARG;
+        d[i] = (float)depth[i];
+    }
+    if (!plan->depth_mem && hipMalloc(&plan->depth_mem, (size_t)n * sizeof(float)) != hipSuccess) {
+        plan->depth_mem = nullptr;
+        return PGET_ERR_HIP;
+    }
+    if (hipMemcpy(plan->depth_mem, d.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return PGET_ERR_HIP;
+    plan->t.depth = plan->depth_mem;
+    drop_graphs(plan);
+    return PGET_OK;
 }
 
 int32_t pget_plan_n_samples(const pget_plan* plan) { return plan ? plan->g.n_t : -1; }
@@ -1328,16 +1363,7 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
     if (!P || batch < 1) return PGET_ERR_INVALID_ARG;
     if (!ws || ws_bytes < group_bytes(P, batch)) return PGET_ERR_WORKSPACE;
     // captured solver sequences of this plan used the old shapes
-    for (size_t k = 0; k < g_graphs.size();) {
-        bool uses = false;
-        for (auto& gk : g_graphs[k].key.groups) uses |= gk[0] == (long long)(intptr_t)P;
-        if (uses) {
-            (void)hipGraphExecDestroy(g_graphs[k].exec);
-            g_graphs.erase(g_graphs.begin() + k);
-        } else {
-            ++k;
-        }
-    }
+    drop_graphs(P);
     // drop an earlier choice for this batch so that the candidates below rule
     for (size_t k = 0; k < P->tuned.size(); ++k)
         if (P->tuned[k][0] == batch) {

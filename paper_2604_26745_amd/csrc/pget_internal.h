@@ -52,6 +52,7 @@ struct Tables {
     const int2* clip;     // [n_angles][n_bins]: samples [lo, hi] inside the support; lo > hi if none
     const int2* grange;   // [n_angles][n_groups]: union of the group's clip ranges
     const float* taps;    // [2K + 1]
+    const float* depth;   // [n_t]: depth factor of the attenuation path per sample, or nullptr (1)
 };
 
 // Per-slice LM parameters on the device.

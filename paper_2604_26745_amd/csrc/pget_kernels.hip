@@ -296,7 +296,8 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                 rb = A.t.rbase[(size_t)a * g.n_bins + j];
             }
             const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
-            float carry_mu = 0.0f, carry_le = 0.0f;
+            float carry_mu = 0.0f, carry_le = 0.0f, carry_dle = 0.0f;
+            const float* depth = A.t.depth;   // per-sample factor of the attenuation path, or none
             w_t* wrow = nullptr;
             if (MODE == MARCH_LIN)
                 wrow = static_cast<w_t*>(A.wts) + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
@@ -316,20 +317,36 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                 // B_i / step = carry + (samples nearer the detector) + mu_i / 2
                 const float bsum = carry_mu + (incl - hs * mu);
                 carry_mu += tot;
-                const float E = __builtin_amdgcn_exp2f(-g.ln2_scale * bsum);
-                const float le = lam * E;
                 float lincl, ltot;
-                quad_scan(le, q, lincl, ltot);
-                if (MODE == MARCH_LIN && act) {
-                    const float rprime = carry_le + (lincl - hs * le);
-                    wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, rprime);
+                if (!depth) {
+                    const float E = __builtin_amdgcn_exp2f(-g.ln2_scale * bsum);
+                    const float le = lam * E;
+                    quad_scan(le, q, lincl, ltot);
+                    if (MODE == MARCH_LIN && act) {
+                        const float rprime = carry_le + (lincl - hs * le);
+                        wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, rprime);
+                    }
+                } else {
+                    // E_i = exp(-c d_i B_i); the ray sum needs lam E, the
+                    // attenuation part of the Jacobian the sums of d lam E
+                    const float d = act ? depth[i] : 1.0f;
+                    const float E = __builtin_amdgcn_exp2f(-g.ln2_scale * (d * bsum));
+                    const float le = lam * E, dle = d * le;
+                    quad_scan(le, q, lincl, ltot);
+                    float dincl, dtot;
+                    quad_scan(dle, q, dincl, dtot);
+                    if (MODE == MARCH_LIN && act) {
+                        const float rprime = carry_dle + (dincl - hs * dle);
+                        wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, rprime);
+                    }
+                    carry_dle += dtot;
                 }
                 carry_le += ltot;
             }
             if (ray_ok && q == 0) {
                 rowp[j] = g.step * carry_le;
                 if (MODE == MARCH_LIN)
-                    A.tsum[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + j] = carry_le;
+                    A.tsum[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + j] = depth ? carry_dle : carry_le;
             }
         }
         __syncthreads();

@@ -95,6 +95,8 @@ def load_library():
     lib.pget_plan_psf_half_width.restype = ctypes.c_int32
     lib.pget_plan_support_samples.argtypes = [V]
     lib.pget_plan_support_samples.restype = ctypes.c_int64
+    lib.pget_plan_set_depth_factor.argtypes = [V, P(ctypes.c_double), ctypes.c_int32]
+    lib.pget_plan_set_depth_factor.restype = ctypes.c_int
     lib.pget_timing_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.pget_timing_enable.restype = ctypes.c_int
     lib.pget_timing_read.argtypes = [ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -384,6 +386,16 @@ class Plan:
         if sync:
             torch.cuda.current_stream().synchronize()
         return f, mu, rb
+
+    def set_depth_factor(self, depth=None):
+        """Per-sample depth factor d of the attenuation path (sample 0
+        farthest from the detector): exp(-atten_scale * d[i] * B_i).  None
+        restores d = 1."""
+        if depth is None:
+            _check(self.lib.pget_plan_set_depth_factor(self.handle, None, 0), "pget_plan_set_depth_factor")
+            return
+        arr = (ctypes.c_double * len(depth))(*[float(v) for v in depth])
+        _check(self.lib.pget_plan_set_depth_factor(self.handle, arr, len(depth)), "pget_plan_set_depth_factor")
 
     def autotune(self, batch: int = 1):
         """Pick the fastest launch shapes for solves of `batch` slices."""
