@@ -59,6 +59,8 @@ class _CGeometry(ctypes.Structure):
         ("psf_sigma", ctypes.c_double),
         ("atten_scale", ctypes.c_double),
         ("depth", ctypes.POINTER(ctypes.c_double)),
+        ("resp", ctypes.POINTER(ctypes.c_double)),
+        ("far_taps", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -108,18 +110,35 @@ class Geometry:
     # per-sample depth factor d_i of the attenuation path (n_samples values,
     # sample 0 farthest from the detector), or None for d_i = 1
     depth: Optional[Tuple[float, ...]] = None
+    # depth-dependent collimator response: sample i is seen through
+    # (1 - resp_i) times the Gaussian taps plus resp_i times far_taps
+    # (2K + 1 values); None for the same response at every depth
+    resp: Optional[Tuple[float, ...]] = None
+    far_taps: Optional[Tuple[float, ...]] = None
 
     def _c(self) -> _CGeometry:
         c = _CGeometry(
             self.n, self.n_angles, self.n_bins, self.psf_radius, self.angle0,
-            self.arc, self.bin_size, self.step, self.psf_sigma, self.atten_scale, None,
+            self.arc, self.bin_size, self.step, self.psf_sigma, self.atten_scale, None, None, None,
         )
-        if self.depth is not None:
-            arr = (ctypes.c_double * len(self.depth))(*self.depth)
-            c.depth = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
-            c._keep = arr
-            if len(self.depth) != _load().og_n_samples(ctypes.byref(c)):
-                raise ValueError("depth needs one value per sample along a ray")
+        keep = []
+        for name in ("depth", "resp", "far_taps"):
+            vals = getattr(self, name)
+            if vals is not None:
+                arr = (ctypes.c_double * len(vals))(*vals)
+                setattr(c, name, ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)))
+                keep.append(arr)
+        c._keep = keep
+        lib = _load()
+        if self.depth is not None and len(self.depth) != lib.og_n_samples(ctypes.byref(c)):
+            raise ValueError("depth needs one value per sample along a ray")
+        if (self.resp is None) != (self.far_taps is None):
+            raise ValueError("resp and far_taps go together")
+        if self.resp is not None:
+            if len(self.resp) != lib.og_n_samples(ctypes.byref(c)):
+                raise ValueError("resp needs one value per sample along a ray")
+            if len(self.far_taps) != 2 * lib.og_psf_half_width(ctypes.byref(c)) + 1:
+                raise ValueError("far_taps needs 2K + 1 values")
         return c
 
     @property

@@ -57,11 +57,23 @@ def psf_matrix(n_bins: int, sigma: float, radius: int = -1) -> np.ndarray:
     return M
 
 
+def banded_matrix(n_bins: int, taps) -> np.ndarray:
+    """M[j, j'] = taps[j - j' + R] for |j - j'| <= R, with 2R + 1 taps given."""
+    taps = np.asarray(taps, dtype=np.float64)
+    R = (len(taps) - 1) // 2
+    M = np.zeros((n_bins, n_bins))
+    for j in range(n_bins):
+        for jj in range(max(0, j - R), min(n_bins, j + R + 1)):
+            M[j, jj] = taps[j - jj + R]
+    return M
+
+
 class DenseModel:
     """All matrices of one tiny geometry."""
 
     def __init__(self, n, n_angles, n_bins, psf_sigma=1.5, psf_radius=-1,
-                 angle0=0.0, arc=2.0 * math.pi, bin_size=1.0, step=1.0, atten_scale=1.0, depth=None):
+                 angle0=0.0, arc=2.0 * math.pi, bin_size=1.0, step=1.0, atten_scale=1.0, depth=None,
+                 resp=None, far_taps=None):
         qx, qy, n_t = lattice(n, n_angles, n_bins, angle0, arc, bin_size, step)
         self.n, self.n_angles, self.n_bins, self.n_t = n, n_angles, n_bins, n_t
         self.step = step
@@ -70,6 +82,9 @@ class DenseModel:
         self.W = interpolation_matrix(n, qx, qy)          # (A*J*T, n*n)
         self.U = beam_matrix(n_t)                          # (T, T)
         self.K = psf_matrix(n_bins, psf_sigma, psf_radius)  # (J, J)
+        # depth response: sample i is seen through (1 - resp_i) K + resp_i K_far
+        self.resp = None if resp is None else np.asarray(resp, dtype=np.float64)
+        self.K_far = None if far_taps is None else banded_matrix(n_bins, far_taps)
 
     def forward(self, f, mu, xp=np):
         """y = K [step * sum_i lam_i exp(-c_i * step * (U mu_hat)_i)], any array module."""
@@ -81,5 +96,14 @@ class DenseModel:
         mh = (W @ mu.reshape(-1)).reshape(A, J, T)
         B = self.step * (mh @ U.T)                     # B[a,j,i] = step * sum_i' U[i,i'] mh[a,j,i']
         c = xp.asarray(self.c) if xp is not np else self.c
-        p = self.step * (lam * xp.exp(-c * B)).sum(-1)   # (A, J)
-        return p @ K.T                                  # y[a, j] = sum_j' K[j, j'] p[a, j']
+        if self.resp is None:
+            p = self.step * (lam * xp.exp(-c * B)).sum(-1)   # (A, J)
+            return p @ K.T                                  # y[a, j] = sum_j' K[j, j'] p[a, j']
+        # the response is linear in resp_i: split every ray sum into the part
+        # seen through K and the part seen through K_far
+        al = xp.asarray(self.resp) if xp is not np else self.resp
+        Kf = xp.asarray(self.K_far) if xp is not np else self.K_far
+        le = lam * xp.exp(-c * B)
+        p_near = self.step * ((1.0 - al) * le).sum(-1)
+        p_far = self.step * (al * le).sum(-1)
+        return p_near @ K.T + p_far @ Kf.T

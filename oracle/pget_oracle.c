@@ -16,7 +16,12 @@
  *             attenuation seen by a sample is the sum of the attenuation
  *             samples between it and the detector (midpoint rule: half of
  *             its own sample), and the collimator response r_{m,n} is a
- *             depth-independent Gaussian across detector bins.  The factor
+ *             Gaussian across detector bins, the same at every depth unless
+ *             a depth response is given: then the response to sample i is
+ *             (1 - alpha_i) times the Gaussian taps plus alpha_i times a
+ *             second set of taps (the response at the far side of the
+ *             field), so that it widens with the emitter's distance from
+ *             the detector.  The factor
  *             c_{m,n} >= 1 on an emitter's attenuation path is atten_scale
  *             times an optional per-sample depth factor d_i (the vertical
  *             correction: an emitter farther from the detector reaches it
@@ -53,6 +58,8 @@ typedef struct {
     double psf_sigma; /* Gaussian sigma in bins; 0 = no blur            */
     double atten_scale; /* c_{m,n} of eq. (d_fwd_model): this constant  */
     const double* depth; /* times depth[i] for sample i (n_t values), or NULL */
+    const double* resp;  /* depth weight alpha_i in [0, 1] of sample i (n_t values), or NULL */
+    const double* far_taps; /* with resp: the far response, 2K+1 taps for offsets -K..K */
 } og_geometry;
 
 /* c for an emitter at sample i of a ray */
@@ -85,6 +92,39 @@ void og_psf_taps(const og_geometry* g, double* taps)
         sum += taps[k + K];
     }
     for (int k = -K; k <= K; ++k) taps[k + K] /= sum;
+}
+
+/* Response of the collimator to sample i of a ray at bin offset k (-K..K)
+ * from the ray's own bin, given the Gaussian taps of the geometry. */
+static double response(const og_geometry* g, const double* taps, int K, int i, int k)
+{
+    if (!g->resp) return taps[k + K];
+    return (1.0 - g->resp[i]) * taps[k + K] + g->resp[i] * g->far_taps[k + K];
+}
+
+/* y[a][j + k] += r_i(k) * c over the bins inside [0, n_bins): the spread of
+ * the contribution c of sample i of ray (a, j). */
+static void spread_sample(const og_geometry* g, const double* taps, int K, int a, int j, int i, double c,
+                          double* y)
+{
+    for (int k = -K; k <= K; ++k) {
+        int jj = j + k;
+        if (jj < 0 || jj >= g->n_bins) continue;
+        y[(size_t)a * g->n_bins + jj] += response(g, taps, K, i, k) * c;
+    }
+}
+
+/* sum_k r_i(k) w[a][j + k]: the transposed spread, for the adjoint. */
+static double gather_sample(const og_geometry* g, const double* taps, int K, int a, int j, int i,
+                            const double* w)
+{
+    double acc = 0.0;
+    for (int k = -K; k <= K; ++k) {
+        int jj = j + k;
+        if (jj < 0 || jj >= g->n_bins) continue;
+        acc += response(g, taps, K, i, k) * w[(size_t)a * g->n_bins + jj];
+    }
+    return acc;
 }
 
 /* tent function of bilinear interpolation */
@@ -213,9 +253,31 @@ static void ray_state(const og_geometry* g, const double* f, const double* mu, c
     }
 }
 
+/* y = A(f, mu) with a depth response: every sample spreads its own
+ * contribution step * lam_i * E_i over the bins with its response r_i. */
+static void forward_depth_response(const og_geometry* g, const double* f, const double* mu, double* y)
+{
+    int nt = og_n_samples(g);
+    int K = og_psf_half_width(g);
+    double* taps = (double*)malloc(sizeof(double) * (size_t)(2 * K + 1));
+    double* lam_s = (double*)malloc(sizeof(double) * nt);
+    double* mu_s = (double*)malloc(sizeof(double) * nt);
+    double* E = (double*)malloc(sizeof(double) * nt);
+    og_psf_taps(g, taps);
+    memset(y, 0, sizeof(double) * (size_t)g->n_angles * g->n_bins);
+    for (int a = 0; a < g->n_angles; ++a)
+        for (int j = 0; j < g->n_bins; ++j) {
+            ray_t ray = make_ray(g, a, j);
+            ray_state(g, f, mu, &ray, lam_s, mu_s, E);
+            for (int i = 0; i < nt; ++i) spread_sample(g, taps, K, a, j, i, g->step * lam_s[i] * E[i], y);
+        }
+    free(taps); free(lam_s); free(mu_s); free(E);
+}
+
 /* y = A(f, mu): n_angles x n_bins, row-major. */
 void og_forward(const og_geometry* g, const double* f, const double* mu, double* y)
 {
+    if (g->resp) { forward_depth_response(g, f, mu, y); return; }
     int nt = og_n_samples(g);
     size_t nr = (size_t)g->n_angles * g->n_bins;
     double* p = (double*)malloc(sizeof(double) * nr);
@@ -259,12 +321,14 @@ void og_psf_transpose(const og_geometry* g, const double* w, double* v) { psf_ap
  * jv = J [vf, vmu] = D_lambda F[vf] + D_mu F[vmu]:
  *   raw_{a,j} = step * sum_i E_i * (vf_i - c_i * lam_i * V_i),
  *   V_i = step * (vmu_i/2 + sum_{i' > i} vmu_i')  (the beam transform of vmu),
- * followed by the same collimator blur as the forward map.
+ * followed by the same collimator blur as the forward map (with a depth
+ * response, each sample's term is spread with its own response).
  */
 void og_jvp(const og_geometry* g, const double* f, const double* mu, const double* vf,
             const double* vmu, double* jv)
 {
     int nt = og_n_samples(g);
+    int K = og_psf_half_width(g);
     size_t nr = (size_t)g->n_angles * g->n_bins;
     double* p = (double*)malloc(sizeof(double) * nr);
     double* lam_s = (double*)malloc(sizeof(double) * nt);
@@ -272,6 +336,9 @@ void og_jvp(const og_geometry* g, const double* f, const double* mu, const doubl
     double* E = (double*)malloc(sizeof(double) * nt);
     double* vf_s = (double*)malloc(sizeof(double) * nt);
     double* vmu_s = (double*)malloc(sizeof(double) * nt);
+    double* taps = (double*)malloc(sizeof(double) * (size_t)(2 * K + 1));
+    og_psf_taps(g, taps);
+    if (g->resp) memset(jv, 0, sizeof(double) * nr);
     for (int a = 0; a < g->n_angles; ++a)
         for (int j = 0; j < g->n_bins; ++j) {
             ray_t ray = make_ray(g, a, j);
@@ -285,19 +352,22 @@ void og_jvp(const og_geometry* g, const double* f, const double* mu, const doubl
             double acc = 0.0, beyond = 0.0;
             for (int i = nt - 1; i >= 0; --i) {
                 double V = g->step * (0.5 * vmu_s[i] + beyond);
-                acc += E[i] * (vf_s[i] - path_factor(g, i) * lam_s[i] * V);
+                double c = E[i] * (vf_s[i] - path_factor(g, i) * lam_s[i] * V);
+                if (g->resp) spread_sample(g, taps, K, a, j, i, g->step * c, jv);
+                else acc += c;
                 beyond += vmu_s[i];
             }
             p[(size_t)a * g->n_bins + j] = g->step * acc;
         }
-    psf_apply(g, p, jv);
-    free(p); free(lam_s); free(mu_s); free(E); free(vf_s); free(vmu_s);
+    if (!g->resp) psf_apply(g, p, jv);
+    free(p); free(lam_s); free(mu_s); free(E); free(vf_s); free(vmu_s); free(taps);
 }
 
 /*
- * [gf, gmu] = J^T w.  With wt = K^T w, every sample i of ray (a, j) carries
- *   d/d lam_i = step * E_i * wt,
- *   d/d mu_i  = -step^2 * wt * (c_i lam_i E_i / 2 + sum_{i' < i} c_i' lam_i' E_i'),
+ * [gf, gmu] = J^T w.  With wt_i = sum_k r_i(k) w[a][j + k] (K^T w when the
+ * response is the same at every depth), every sample i of ray (a, j) carries
+ *   d/d lam_i = step * E_i * wt_i,
+ *   d/d mu_i  = -step^2 * (c_i lam_i E_i wt_i / 2 + sum_{i' < i} c_i' lam_i' E_i' wt_i'),
  * (mu_i attenuates itself by half and every sample farther from the
  * detector fully), and these are spread back to the pixels with the same
  * bilinear weights that sampled them.
@@ -312,20 +382,33 @@ void og_vjp(const og_geometry* g, const double* f, const double* mu, const doubl
     double* lam_s = (double*)malloc(sizeof(double) * nt);
     double* mu_s = (double*)malloc(sizeof(double) * nt);
     double* E = (double*)malloc(sizeof(double) * nt);
+    int K = og_psf_half_width(g);
+    double* taps = (double*)malloc(sizeof(double) * (size_t)(2 * K + 1));
+    og_psf_taps(g, taps);
     psf_apply_transpose(g, w, wt);
     memset(gf, 0, sizeof(double) * (size_t)n2);
     memset(gmu, 0, sizeof(double) * (size_t)n2);
     for (int a = 0; a < g->n_angles; ++a)
         for (int j = 0; j < g->n_bins; ++j) {
-            double wr = wt[(size_t)a * g->n_bins + j];
             ray_t ray = make_ray(g, a, j);
             ray_state(g, f, mu, &ray, lam_s, mu_s, E);
-            double before = 0.0; /* sum of c*lam*E over samples farther from the detector */
+            /* sum over the samples farther from the detector of c*lam*E (times
+             * each one's own cotangent when the response depends on depth) */
+            double before = 0.0;
             for (int i = 0; i < nt; ++i) {
                 double cle = path_factor(g, i) * lam_s[i] * E[i];
+                double wr, d_mu;
+                if (g->resp) {
+                    /* the cotangent this sample sees through its own response */
+                    wr = gather_sample(g, taps, K, a, j, i, w);
+                    d_mu = -g->step * g->step * (0.5 * cle * wr + before);
+                    before += cle * wr;
+                } else {
+                    wr = wt[(size_t)a * g->n_bins + j];
+                    d_mu = -g->step * g->step * wr * (0.5 * cle + before);
+                    before += cle;
+                }
                 double d_lam = g->step * E[i] * wr;
-                double d_mu = -g->step * g->step * wr * (0.5 * cle + before);
-                before += cle;
                 double qx, qy;
                 int idx[4];
                 double bw[4];
@@ -337,7 +420,7 @@ void og_vjp(const og_geometry* g, const double* f, const double* mu, const doubl
                 }
             }
         }
-    free(wt); free(lam_s); free(mu_s); free(E);
+    free(wt); free(lam_s); free(mu_s); free(E); free(taps);
 }
 
 /*

@@ -335,3 +335,158 @@ def test_depth_adjoint_identity():
     lhs = np.sum(O.jvp(g, f, mu, vf, vm) * w)
     gf, gm = O.vjp(g, f, mu, w)
     assert abs(lhs - (np.sum(vf * gf) + np.sum(vm * gm))) <= 1e-12 * abs(lhs)
+
+
+# ------------------------------------- depth-dependent collimator response
+def _gauss_taps(sigma, K):
+    k = np.arange(-K, K + 1)
+    t = np.exp(-(k ** 2) / (2.0 * sigma ** 2))
+    return tuple(t / t.sum())
+
+
+def _alpha(n_t, seed=None):
+    """Weight of the far response: 1 at sample 0 (farthest from the
+    detector), 0 at the last sample, linear in between; optionally jittered."""
+    a = 1.0 - np.arange(n_t) / (n_t - 1)
+    if seed is not None:
+        a = np.clip(a + 0.1 * np.random.default_rng(seed).uniform(-1, 1, n_t), 0.0, 1.0)
+    return tuple(a)
+
+
+def test_depth_response_matches_dense_and_autograd():
+    """The oracle spreads every sample with its own response; the dense
+    formulation splits each ray sum into the parts seen through the near
+    and the far response.  They agree, and the oracle's Jacobian products
+    agree with torch autograd of the dense formulation, with and without a
+    depth factor on the attenuation path."""
+    torch = pytest.importorskip("torch")
+    n, na, nb = 8, 8, 14
+    n_t = O.Geometry(n, na, nb).n_samples
+    K = O.Geometry(n, na, nb, psf_sigma=1.5).psf_half_width
+    far = _gauss_taps(2.5, K)
+    al = _alpha(n_t, seed=3)
+    rng = np.random.default_rng(31)
+    f = rng.uniform(0, 1, (n, n))
+    mu = rng.uniform(0, 0.3, (n, n))
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal((na, nb))
+    T = lambda a: torch.tensor(a, dtype=torch.float64)
+    for depth in (None, _depth(n_t, 2)):
+        g = O.Geometry(n, na, nb, psf_sigma=1.5, atten_scale=0.7, depth=depth, resp=al, far_taps=far)
+        D = DenseModel(n, na, nb, psf_sigma=1.5, atten_scale=0.7, depth=depth, resp=al, far_taps=far)
+        y = O.forward(g, f, mu)
+        assert np.abs(y - D.forward(f, mu)).max() <= 1e-13 * np.abs(y).max()
+        fn = lambda a, b: D.forward(a, b, xp=torch)
+        _, jt = torch.func.jvp(fn, (T(f), T(mu)), (T(vf), T(vm)))
+        jv = O.jvp(g, f, mu, vf, vm)
+        assert np.abs(jt.numpy() - jv).max() <= 1e-13 * np.abs(jv).max()
+        _, back = torch.func.vjp(fn, T(f), T(mu))
+        tf, tm = back(T(w))
+        gf, gm = O.vjp(g, f, mu, w)
+        assert np.abs(tf.numpy() - gf).max() <= 1e-13 * np.abs(gf).max()
+        assert np.abs(tm.numpy() - gm).max() <= 1e-13 * np.abs(gm).max()
+        # the response matters
+        g0 = O.Geometry(n, na, nb, psf_sigma=1.5, atten_scale=0.7, depth=depth)
+        assert np.abs(O.forward(g0, f, mu) - y).max() > 1e-3 * np.abs(y).max()
+
+
+def test_depth_response_reduces_to_one_gaussian():
+    """alpha = 0 everywhere is the plain model; alpha = 1 everywhere is the
+    plain model whose Gaussian is the far one (same truncation)."""
+    n, na, nb = 12, 10, 20
+    g = O.Geometry(n, na, nb, psf_sigma=1.2)
+    n_t, K = g.n_samples, g.psf_half_width
+    far = _gauss_taps(2.0, K)
+    g_near = O.Geometry(n, na, nb, psf_sigma=1.2, resp=(0.0,) * n_t, far_taps=far)
+    g_far = O.Geometry(n, na, nb, psf_sigma=1.2, resp=(1.0,) * n_t, far_taps=far)
+    g_ref = O.Geometry(n, na, nb, psf_sigma=2.0, psf_radius=K)
+    rng = np.random.default_rng(32)
+    f = rng.uniform(0, 1, (n, n))
+    mu = rng.uniform(0, 0.2, (n, n))
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal((na, nb))
+    for a, b in ((g_near, g), (g_far, g_ref)):
+        y = O.forward(b, f, mu)
+        assert np.abs(O.forward(a, f, mu) - y).max() <= 1e-13 * np.abs(y).max()
+        jv = O.jvp(b, f, mu, vf, vm)
+        assert np.abs(O.jvp(a, f, mu, vf, vm) - jv).max() <= 1e-13 * np.abs(jv).max()
+        for p, q in zip(O.vjp(a, f, mu, w), O.vjp(b, f, mu, w)):
+            assert np.abs(p - q).max() <= 1e-13 * np.abs(q).max()
+
+
+def test_depth_response_is_affine_in_alpha():
+    """Every output is affine in the per-sample weights: the midpoint of two
+    weight profiles gives the mean of their outputs."""
+    n, na, nb = 10, 9, 16
+    g = O.Geometry(n, na, nb, psf_sigma=1.5)
+    n_t, K = g.n_samples, g.psf_half_width
+    far = _gauss_taps(3.0, K)
+    a1, a2 = np.array(_alpha(n_t, seed=4)), np.random.default_rng(5).uniform(0, 1, n_t)
+    gs = [O.Geometry(n, na, nb, psf_sigma=1.5, resp=tuple(a), far_taps=far) for a in (a1, a2, 0.5 * (a1 + a2))]
+    rng = np.random.default_rng(33)
+    f = rng.uniform(0, 1, (n, n))
+    mu = rng.uniform(0, 0.2, (n, n))
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal((na, nb))
+    y = [O.forward(x, f, mu) for x in gs]
+    assert np.abs(y[2] - 0.5 * (y[0] + y[1])).max() <= 1e-13 * np.abs(y[2]).max()
+    j = [O.jvp(x, f, mu, vf, vm) for x in gs]
+    assert np.abs(j[2] - 0.5 * (j[0] + j[1])).max() <= 1e-13 * np.abs(j[2]).max()
+    v = [O.vjp(x, f, mu, w) for x in gs]
+    for c in range(2):
+        assert np.abs(v[2][c] - 0.5 * (v[0][c] + v[1][c])).max() <= 1e-13 * np.abs(v[2][c]).max()
+
+
+def test_depth_response_point_emitter_width():
+    """A single emitting pixel at angle 0 without attenuation: pixel centres
+    fall on lattice points, so exactly one sample sees it, and its profile
+    across bins is that sample's response.  The profile keeps unit mass, and
+    its variance is (1 - alpha) Var(kappa) + alpha Var(kappa_far) with alpha
+    of the pixel's own depth: wider for the emitter far from the detector
+    (the detector lies toward +x at angle 0)."""
+    n, nb = 16, 24
+    g = O.Geometry(n, 4, nb, psf_sigma=1.0)
+    n_t, K = g.n_samples, g.psf_half_width
+    far = _gauss_taps(2.5, K)
+    al = _alpha(n_t)
+    gr = O.Geometry(n, 4, nb, psf_sigma=1.0, resp=al, far_taps=far)
+    k = np.arange(-K, K + 1)
+    var_near = float(np.sum(k ** 2 * np.array(O.psf_taps(g))))
+    var_far = float(np.sum(k ** 2 * np.array(far)))
+    widths = []
+    for c in (2, 13):                       # far from / near to the detector
+        f = np.zeros((n, n))
+        r = 8
+        f[r, c] = 1.0
+        y = O.forward(gr, f, np.zeros((n, n)))[0]
+        j0 = r - (n - 1) / 2 + (nb - 1) / 2     # bin whose centre is the pixel's row
+        i0 = int(c - (n - 1) / 2 + (n_t - 1) / 2)   # sample whose point is the pixel
+        a = al[i0]
+        var = float(np.sum((np.arange(nb) - j0) ** 2 * y))
+        assert abs(y.sum() - 1.0) <= 1e-13
+        assert abs(var - ((1 - a) * var_near + a * var_far)) <= 1e-12
+        widths.append((a, var))
+    (a_far, w_far), (a_near, w_near) = widths
+    assert a_far > a_near and w_far - w_near > 0.9 * (a_far - a_near) * (var_far - var_near)
+
+
+def test_depth_response_adjoint_identity_and_arguments():
+    n = 16
+    g0 = O.Geometry(n, 14, 23, psf_sigma=1.5)
+    n_t, K = g0.n_samples, g0.psf_half_width
+    g = O.Geometry(n, 14, 23, psf_sigma=1.5, depth=_depth(n_t, 1), resp=_alpha(n_t, seed=6),
+                   far_taps=_gauss_taps(2.8, K))
+    rng = np.random.default_rng(34)
+    f = rng.uniform(0, 1, (n, n))
+    mu = rng.uniform(0, 0.15, (n, n))
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal(g.sino_shape)
+    lhs = np.sum(O.jvp(g, f, mu, vf, vm) * w)
+    gf, gm = O.vjp(g, f, mu, w)
+    assert abs(lhs - (np.sum(vf * gf) + np.sum(vm * gm))) <= 1e-12 * abs(lhs)
+    with pytest.raises(ValueError):
+        O.Geometry(n, 14, 23, resp=(0.5,) * n_t).n_samples
+    with pytest.raises(ValueError):
+        O.Geometry(n, 14, 23, resp=(0.5,) * (n_t - 1), far_taps=_gauss_taps(2.0, K)).n_samples
+    with pytest.raises(ValueError):
+        O.Geometry(n, 14, 23, resp=(0.5,) * n_t, far_taps=_gauss_taps(2.0, K + 1)).n_samples
