@@ -123,6 +123,31 @@ int64_t pget_plan_support_samples(const pget_plan* plan);
 pget_status pget_plan_set_depth_factor(pget_plan* plan, const double* depth, int32_t n);
 
 /*
+ * Depth-dependent collimator response (the response r_{m,n} of the discrete
+ * model, Sec. 2.1 eq. d_fwd_model, which for a deep collimator widens with
+ * the emitter's distance from the detector).  The response to sample i of
+ * every ray becomes (1 - alpha[i]) * kappa + alpha[i] * far_taps: the plan's
+ * Gaussian taps kappa blended toward a second response, at offsets -K..K
+ * bins from the ray's own bin.  `alpha` is a host array of
+ * pget_plan_n_samples(plan) values in [0, 1], sample 0 farthest from the
+ * detector; `far_taps` a host array of n_taps = 2K + 1 finite values (K =
+ * pget_plan_psf_half_width(plan)), symmetric (far_taps[k] == far_taps[2K -
+ * k], as the adjoint applies the same taps).  NULL alpha restores the
+ * depth-independent response.  Forward, Jacobian products and every solver
+ * follow.  The workspace of every operation grows (one more float per
+ * lattice sample, a second plane of the per-ray sums): query
+ * pget_workspace_bytes / pget_workspace_bytes_multi again after the call.
+ * Values are copied to the device (a small allocation owned by the plan)
+ * before the call returns; no call of this plan may be in flight meanwhile.
+ * Errors: INVALID_ARG (null plan, wrong counts, alpha outside [0, 1], taps
+ * not finite or not symmetric), UNSUPPORTED (BF16 storage, or the extra
+ * rows of sums do not fit in the kernels' LDS for this shape), HIP
+ * (allocation or copy failed).
+ */
+pget_status pget_plan_set_depth_response(pget_plan* plan, const double* alpha, int32_t n, const double* far_taps,
+                                         int32_t n_taps);
+
+/*
  * Device workspace needed by `op` for `batch` slices of this plan's shape
  * (batch >= 1; forward/jvp/vjp use batch 1).  0 on a bad argument.
  */

@@ -21,6 +21,7 @@ struct pget_plan {
     Tables t;
     void* table_mem;     // one device allocation holding every table
     float* depth_mem = nullptr;   // per-sample depth factor (set on demand)
+    float* resp_mem = nullptr;    // depth response: alpha per sample, then the far taps
     bool bf16;           // BF16 storage of staged maps and per-sample weights
     size_t px_bytes;     // bytes of one staged map pair (8 FP32, 4 BF16)
     size_t w_bytes;      // bytes of one per-sample weight pair
@@ -30,6 +31,8 @@ struct pget_plan {
     int op_threads;      // threads per block of k_march
     size_t img_lds;      // LDS bytes of the staged map pair (0 if not staged)
     int max_japb;        // most angle slots per k_jvp_lin block that fit in LDS
+    int max_japb_dr;     // the same with a depth response (three rows per slot)
+    int vjp_resident_dr; // k_vjp_lin blocks per compute unit with a depth response
     int tiles_x;         // VJP tiles per edge
     int device;
     int n_cu;            // compute units of the device
@@ -86,6 +89,16 @@ int half_width(const pget_geometry* g)
     return (int)ceil(3.0 * g->psf_sigma);
 }
 
+// Dynamic LDS of a k_jvp_lin block of `japb` angle slots: the staged map
+// pair, and per sinogram row z and K z (plus the far part of z with a depth
+// response).
+size_t jvp_lds_for(const pget_plan* P, int japb)
+{
+    const size_t rows = P->t.resp ? 3 : 2;
+    return P->img_lds + rows * (size_t)japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+}
+int max_japb_of(const pget_plan* P) { return P->t.resp ? P->max_japb_dr : P->max_japb; }
+
 // Launch shapes for a batch of `batch` slices.
 struct Shapes {
     int apb;          // angles per block of k_march
@@ -119,10 +132,10 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.n_op_blocks = (P->g.n_angles + s.apb - 1) / s.apb;
     const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
     int jwant = std::max(1, (slots * batch) / (2 * cus));
-    s.japb = std::max(1, std::min(P->max_japb, jwant));
+    s.japb = std::max(1, std::min(max_japb_of(P), jwant));
     s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
     s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
-    s.jvp_lds = P->img_lds + 2 * (size_t)s.japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+    s.jvp_lds = jvp_lds_for(P, s.japb);
     // angle groups of the gather: the fewest launch rounds times the work of
     // one block (its angle slots plus about one slot of fixed cost), counted
     // against the resident blocks.  Small batches may split the angles finely
@@ -130,7 +143,7 @@ Shapes shapes_for(const pget_plan* P, int batch)
     const int tiles = P->tiles_x * P->tiles_x;
     const int vslots = vjp_slots(P);
     s.gcap = std::min(vslots, batch >= 16 ? 8 : 32);
-    const long long resident = (long long)cus * std::max(1, P->vjp_resident);
+    const long long resident = (long long)cus * std::max(1, P->t.resp ? P->vjp_resident_dr : P->vjp_resident);
     int g = 1;
     double best = 1e30;
     for (int c = 1; c <= s.gcap; ++c) {
@@ -142,10 +155,10 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.groups = g;
     for (const auto& t : P->tuned)
         if (t[0] == batch) {
-            s.japb = std::max(1, std::min(P->max_japb, t[1]));
+            s.japb = std::max(1, std::min(max_japb_of(P), t[1]));
             s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
             s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
-            s.jvp_lds = P->img_lds + 2 * (size_t)s.japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+            s.jvp_lds = jvp_lds_for(P, s.japb);
             g = std::max(1, std::min(t[2], s.gcap));
         }
     s.groups = g;
@@ -156,7 +169,8 @@ Shapes shapes_for(const pget_plan* P, int batch)
 
 // Workspace layout.  Every buffer is 256-byte aligned.
 struct Layout {
-    size_t wts, tsum, sino_a, sino_b, ymeas, gpart_grad, gpart_cg, gimg, part;
+    size_t wts, wq, tsum, sino_a, sino_b, ymeas, gpart_grad, gpart_cg, gimg, part;
+    long long far_off;   // depth response: elements from a sinogram plane to its far plane
     size_t u, ut, s, x, r, p, q, grad, fmask, state, params, repdev, reparr;
     size_t total;
 };
@@ -171,12 +185,18 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
     const size_t n2 = (size_t)g.n * g.n;
     const size_t sino = (size_t)g.n_angles * g.n_bins;
     const size_t lat = (size_t)g.n_angles * g.n_t * g.n_bins;
+    // with a depth response the ray totals and the blurred cotangents have a
+    // far plane B * sino elements after the near one, and the far prefix
+    // sums their own per-sample array
+    const size_t planes = P->t.resp ? 2 : 1;
+    L.far_off = (long long)(B * sino);
     if (op != PGET_OP_FORWARD) {
         L.wts = take(B * lat * P->w_bytes);
-        L.tsum = take(B * sino * sizeof(float));
+        if (P->t.resp) L.wq = take(B * lat * sizeof(float));
+        L.tsum = take(planes * B * sino * sizeof(float));
     }
-    L.sino_a = take(B * sino * sizeof(float));
-    L.sino_b = take(B * sino * sizeof(float));
+    L.sino_a = take(planes * B * sino * sizeof(float));
+    L.sino_b = take(planes * B * sino * sizeof(float));
     L.gimg = (P->lds_img && P->jvp_lds) ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
     L.part = take(B * (size_t)N_SLOTS * SLOT_WIDTH * sizeof(double));
     if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.gcap * B * 2 * n2 * sizeof(float));
@@ -242,7 +262,10 @@ template <bool LDS, int M>
 void launch_march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStream_t s)
 {
     Timed t(PGET_KC_MARCH, s);
-    if (P->bf16)
+    if (P->t.resp)   // one more row of ray sums (the far part)
+        hipLaunchKernelGGL((k_march<LDS, M, F32DR>), dim3(blocks, batch), dim3(P->op_threads),
+                           P->op_lds_bytes + P->g.n_bins * sizeof(float), s, A);
+    else if (P->bf16)
         hipLaunchKernelGGL((k_march<LDS, M, BF16S>), dim3(blocks, batch), dim3(P->op_threads), P->op_lds_bytes,
                            s, A);
     else
@@ -259,7 +282,10 @@ template <bool LDS, int M>
 void launch_jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
     Timed t(PGET_KC_JVP, s);
-    if (P->bf16)
+    if (P->t.resp)
+        hipLaunchKernelGGL((k_jvp_lin<LDS, M, F32DR>), dim3(sh.n_jvp_blocks, batch), dim3(sh.jvp_threads),
+                           sh.jvp_lds, s, A);
+    else if (P->bf16)
         hipLaunchKernelGGL((k_jvp_lin<LDS, M, BF16S>), dim3(sh.n_jvp_blocks, batch), dim3(sh.jvp_threads),
                            sh.jvp_lds, s, A);
     else
@@ -278,7 +304,10 @@ void jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipS
 void launch_vjp(const pget_plan* P, const VjpArgs& V, int batch, hipStream_t s)
 {
     const dim3 grid(P->tiles_x * P->tiles_x * V.groups, batch), block(VJP_THREADS);
-    if (P->bf16) {
+    if (P->t.resp) {
+        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<F32DR, true>), grid, block, 0, s, V);
+        else hipLaunchKernelGGL((k_vjp_lin<F32DR, false>), grid, block, 0, s, V);
+    } else if (P->bf16) {
         if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<BF16S, true>), grid, block, 0, s, V);
         else hipLaunchKernelGGL((k_vjp_lin<BF16S, false>), grid, block, 0, s, V);
     } else {
@@ -447,6 +476,8 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     P->t.grange = reinterpret_cast<const int2*>(base + o_gr);
     P->t.taps = reinterpret_cast<const float*>(base + o_taps);
     P->t.depth = nullptr;
+    P->t.resp = nullptr;
+    P->t.taps_far = nullptr;
 
     // ---- launch shapes
     // the ray march stages the FP32 map pair; the Jacobian product stages the
@@ -468,6 +499,7 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         P->jvp_lds = jimg_bytes + per_slot <= lds_budget;
         P->img_lds = P->jvp_lds ? jimg_bytes : 0;
         P->max_japb = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / per_slot);
+        P->max_japb_dr = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / (per_slot / 2 * 3));
         if (P->max_japb < 1) {
             (void)hipFree(P->table_mem);
             delete P;
@@ -502,6 +534,18 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
             attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_PLAIN, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
             attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_NORMAL, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
             attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_SQNORM, BF16S>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_FWD, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_LIN, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<true, MARCH_TRIAL, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_PLAIN, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_NORMAL, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<true, JVP_SQNORM, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_FWD, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_LIN, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_march<false, MARCH_TRIAL, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_PLAIN, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_NORMAL, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+            attr_ok &= hipFuncSetAttribute((const void*)k_jvp_lin<false, JVP_SQNORM, F32DR>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
         }
         if (!attr_ok) {
             (void)hipFree(P->table_mem);
@@ -511,17 +555,20 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     }
     P->tiles_x = (g.n + VT - 1) / VT;
     {
-        int occ = 0;
+        int occ = 0, occ_dr = 0;
         const void* vk = g.quad ? (P->bf16 ? (const void*)k_vjp_lin<BF16S, true> : (const void*)k_vjp_lin<F32S, true>)
                                 : (P->bf16 ? (const void*)k_vjp_lin<BF16S, false> : (const void*)k_vjp_lin<F32S, false>);
+        const void* vk_dr = g.quad ? (const void*)k_vjp_lin<F32DR, true> : (const void*)k_vjp_lin<F32DR, false>;
         if (hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vk, VJP_THREADS, 0) != hipSuccess) {
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vk, VJP_THREADS, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_dr, vk_dr, VJP_THREADS, 0) != hipSuccess) {
             (void)hipFree(P->table_mem);
             delete P;
             return PGET_ERR_HIP;
         }
         P->n_cu = std::max(1, P->n_cu);
         P->vjp_resident = std::max(1, occ);
+        P->vjp_resident_dr = std::max(1, occ_dr);
     }
     *out = P;
     return PGET_OK;
@@ -549,7 +596,46 @@ void pget_plan_destroy(pget_plan* plan)
     drop_graphs(plan);
     (void)hipFree(plan->table_mem);
     if (plan->depth_mem) (void)hipFree(plan->depth_mem);
+    if (plan->resp_mem) (void)hipFree(plan->resp_mem);
     delete plan;
+}
+
+pget_status pget_plan_set_depth_response(pget_plan* plan, const double* alpha, int32_t n, const double* far_taps,
+                                         int32_t n_taps)
+{
+    if (!plan) return PGET_ERR_INVALID_ARG;
+    if (!alpha) {
+        plan->t.resp = nullptr;
+        plan->t.taps_far = nullptr;
+        drop_graphs(plan);
+        return PGET_OK;
+    }
+    const Geo& g = plan->g;
+    if (n != g.n_t || !far_taps || n_taps != 2 * g.K + 1) return PGET_ERR_INVALID_ARG;
+    std::vector<float> h((size_t)n + n_taps);
+    for (int i = 0; i < n; ++i) {
+        if (!(alpha[i] >= 0.0 && alpha[i] <= 1.0)) return PGET_ERR_INVALID_ARG;
+        h[i] = (float)alpha[i];
+    }
+    for (int k = 0; k < n_taps; ++k) {
+        // the adjoint applies the same taps: the response must be symmetric
+        if (!isfinite(far_taps[k]) || far_taps[k] != far_taps[n_taps - 1 - k]) return PGET_ERR_INVALID_ARG;
+        h[(size_t)n + k] = (float)far_taps[k];
+    }
+    // BF16 storage has no variant with the far sums; the extra LDS row must fit
+    const size_t lds_budget = 160 * 1024 - 2048;
+    if (plan->bf16 || plan->max_japb_dr < 1 || plan->op_lds_bytes + g.n_bins * sizeof(float) > lds_budget)
+        return PGET_ERR_UNSUPPORTED;
+    if (!plan->resp_mem && hipMalloc(&plan->resp_mem, h.size() * sizeof(float)) != hipSuccess) {
+        plan->resp_mem = nullptr;
+        return PGET_ERR_HIP;
+    }
+    if (hipMemcpy(plan->resp_mem, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return PGET_ERR_HIP;
+    plan->t.resp = plan->resp_mem;
+    plan->t.taps_far = plan->resp_mem + n;
+    drop_graphs(plan);
+    return PGET_OK;
 }
 
 pget_status pget_plan_set_depth_factor(pget_plan* plan, const double* depth, int32_t n)
@@ -623,6 +709,8 @@ static void linearise(const pget_plan* P, const float* f, const float* mu, float
     A.src = planar_src(f, mu, 0);
     A.wts = at(ws, L.wts);
     A.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
+    A.wq = P->t.resp ? reinterpret_cast<float*>(at(ws, L.wq)) : nullptr;
+    A.far_off = L.far_off;
     A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
     A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
     A.yout = y_or_null;
@@ -630,6 +718,7 @@ static void linearise(const pget_plan* P, const float* f, const float* mu, float
     // samples outside the support are never written; the adjoint reads them
     // (with zero interpolation weight), so they must hold finite values
     fill_zero(at(ws, L.wts), (size_t)A.wts_stride * P->w_bytes, stream);
+    if (A.wq) fill_zero(A.wq, (size_t)A.wts_stride * sizeof(float), stream);
     if (!P->lds_img) {
         A.gimg = at(ws, L.gimg);
         pack(P, A.src, nullptr, at(ws, L.gimg), 1, nullptr, stream);
@@ -651,6 +740,8 @@ pget_status pget_jvp(const pget_plan* P, const float* f, const float* mu, const 
     A.src = planar_src(vf, vmu, 0);
     A.wts = at(ws, L.wts);
     A.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
+    A.wq = P->t.resp ? reinterpret_cast<const float*>(at(ws, L.wq)) : nullptr;
+    A.far_off = L.far_off;
     A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
     A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
     A.out = jv;
@@ -677,12 +768,17 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
         Timed t_(PGET_KC_CONTROL, stream);
         hipLaunchKernelGGL(k_psf, dim3(P->g.n_angles), dim3(256), P->g.n_bins * sizeof(float), stream, P->g,
                            P->t.taps, w, wt);
+        if (P->t.resp)   // the cotangent seen through the far response (symmetric taps)
+            hipLaunchKernelGGL(k_psf, dim3(P->g.n_angles), dim3(256), P->g.n_bins * sizeof(float), stream, P->g,
+                               P->t.taps_far, w, wt + L.far_off);
     }
     VjpArgs V = {};
     V.g = P->g;
     V.t = P->t;
     V.wts = at(ws, L.wts);
     V.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
+    V.wq = P->t.resp ? reinterpret_cast<const float*>(at(ws, L.wq)) : nullptr;
+    V.far_off = L.far_off;
     V.wt = wt;
     V.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
     V.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
@@ -780,6 +876,7 @@ void setup(Solve& S)
     LMState* st = reinterpret_cast<LMState*>(at(ws, S.L.state));
     void* wts = at(ws, S.L.wts);
     float* tsum = reinterpret_cast<float*>(at(ws, S.L.tsum));
+    float* wq = P->t.resp ? reinterpret_cast<float*>(at(ws, S.L.wq)) : nullptr;
     float* wt_res = reinterpret_cast<float*>(at(ws, S.L.sino_a));   // K (A(u) - y)
     float* wt_cg = reinterpret_cast<float*>(at(ws, S.L.sino_b));    // K K J p
     const float* ymeas = reinterpret_cast<float*>(at(ws, S.L.ymeas));
@@ -794,6 +891,8 @@ void setup(Solve& S)
     M.gimg_stride = (long long)g.pitch * g.pitch;
     M.wts = wts;
     M.tsum = tsum;
+    M.wq = wq;
+    M.far_off = S.L.far_off;
     M.wts_stride = lat;
     M.sino_stride = sino;
     M.ymeas = ymeas;
@@ -808,6 +907,7 @@ void setup(Solve& S)
     T.src = planar_src(ut, ut + n2, 2 * n2);
     T.wts = nullptr;
     T.tsum = nullptr;
+    T.wq = nullptr;
     T.wout = nullptr;
     T.slot = SLOT_PHI_DATA_T;
 
@@ -819,6 +919,8 @@ void setup(Solve& S)
     J.gimg_stride = (long long)g.pitch * g.pitch;
     J.wts = wts;
     J.tsum = tsum;
+    J.wq = wq;
+    J.far_off = S.L.far_off;
     J.wts_stride = lat;
     J.sino_stride = sino;
     J.out = wt_cg;
@@ -852,6 +954,8 @@ void setup(Solve& S)
     VG.t = P->t;
     VG.wts = wts;
     VG.tsum = tsum;
+    VG.wq = wq;
+    VG.far_off = S.L.far_off;
     VG.wt = wt_res;
     VG.wts_stride = lat;
     VG.sino_stride = sino;
@@ -1148,6 +1252,7 @@ void enqueue_group(Group& G, hipStream_t s)
     const int B = SS.B;
     hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, s, SS.V.st, SS.V.prm, B);
     fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * SS.P->w_bytes, s);
+    if (SS.lin.wq) fill_zero(SS.lin.wq, (size_t)B * SS.lin.wts_stride * sizeof(float), s);
     for (int k = 0; k < G.max_outer; ++k) {
         enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false);
         enqueue_commit(SS);
@@ -1191,6 +1296,7 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
         const int B = S.B;
         hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
         fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * S.P->w_bytes, stream);
+        if (S.lin.wq) fill_zero(S.lin.wq, (size_t)B * S.lin.wts_stride * sizeof(float), stream);
         for (int k = 0; k < G.max_outer; ++k) {
             enqueue_iteration(S, k, G.n_cg, G.need_beta0, true);
             pget_status rc = run_hook(S, hook, hook_user);
@@ -1401,12 +1507,12 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
     S.ws = ws;
     S.stream = stream;
     setup(S);
-    for (int japb = 1; japb <= P->max_japb; japb *= 2) {
+    for (int japb = 1; japb <= max_japb_of(P); japb *= 2) {
         Shapes sh = S.sh;
         sh.japb = japb;
         sh.n_jvp_blocks = (slots + japb - 1) / japb;
         sh.jvp_threads = std::min(16, japb * P->g.n_groups) * WAVE;
-        sh.jvp_lds = P->img_lds + 2 * (size_t)japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+        sh.jvp_lds = jvp_lds_for(P, japb);
         JvpArgs J = S.jcg;
         J.src = planar_src(S.V.u, S.V.u + (size_t)P->g.n * P->g.n, 2LL * P->g.n * P->g.n);
         J.st = nullptr;

@@ -53,6 +53,9 @@ struct Tables {
     const int2* grange;   // [n_angles][n_groups]: union of the group's clip ranges
     const float* taps;    // [2K + 1]
     const float* depth;   // [n_t]: depth factor of the attenuation path per sample, or nullptr (1)
+    const float* resp;    // [n_t]: weight alpha_i of the far collimator response per sample, or
+                          // nullptr (the response is taps at every depth)
+    const float* taps_far;  // [2K + 1] with resp: the far response (symmetric)
 };
 
 // Per-slice LM parameters on the device.
@@ -154,6 +157,8 @@ struct MarchArgs {
     long long gimg_stride;
     void* wts;              // MARCH_LIN: [n_angles][n_t][n_bins] (step*E, R') pairs
     float* tsum;            // MARCH_LIN: [n_angles][n_bins] sum of lambda*E
+    float* wq;              // depth response, MARCH_LIN: R' of the far response, as wts
+    long long far_off;      // depth response: elements from a sinogram plane (tsum, wout) to its far plane
     long long wts_stride, sino_stride;
     const float* ymeas;     // measured sinogram (residual modes) or null
     float* yout;            // MARCH_FWD: A(f, mu); MARCH_LIN: optional
@@ -172,6 +177,8 @@ struct JvpArgs {
     long long gimg_stride;
     const void* wts;
     const float* tsum;
+    const float* wq;        // depth response: R' of the far response per sample
+    long long far_off;      // depth response: far plane of tsum and (NORMAL) out
     long long wts_stride, sino_stride;
     float* out;             // PLAIN: K z;  NORMAL: K K z
     double* part;
@@ -187,6 +194,8 @@ struct VjpArgs {
     const void* wts;
     const float* tsum;
     const float* wt;        // blurred cotangent per ray [n_angles][n_bins]
+    const float* wq;        // depth response: R' of the far response per sample
+    long long far_off;      // depth response: far plane of tsum and wt
     long long wts_stride, sino_stride;
     float* gpart;           // [groups][slices][2][N][N]
     long long gpart_group_stride, gpart_slice_stride;
@@ -227,6 +236,7 @@ struct VecArgs {
 // either way.
 struct F32S;
 struct BF16S;
+struct F32DR;   // FP32 with a depth-dependent collimator response
 template <bool LDS_IMG, int MODE, typename S> __global__ void k_march(MarchArgs A);
 template <bool LDS_IMG, int MODE, typename S> __global__ void k_jvp_lin(JvpArgs A);
 template <typename S>

@@ -120,6 +120,7 @@ __device__ __forceinline__ uint32_t bf16_rne(float x)
 struct F32S {
     using px_t = float2;
     using w_t = float2;
+    static constexpr bool DR = false;     // no depth-dependent collimator response
     static constexpr int VJP_WAVES = 3;   // gather waves per SIMD (register budget 168)
     static constexpr int JVP_SPL = 4;     // Jacobian product: lanes per ray (16 rays x 8 B = a 128 B row)
     static __device__ __forceinline__ float2 px(px_t v) { return v; }
@@ -131,6 +132,7 @@ struct F32S {
 struct BF16S {
     using px_t = uint32_t;   // low half: first value, high half: second value
     using w_t = uint32_t;
+    static constexpr bool DR = false;
     static constexpr int VJP_WAVES = 4;   // half the staged weight registers (budget 128)
     static constexpr int JVP_SPL = 2;     // 32 rays x 4 B: a full 128 B row per load
     static __device__ __forceinline__ float2 px(px_t v)
@@ -140,6 +142,15 @@ struct BF16S {
     static __device__ __forceinline__ px_t to_px(float2 v) { return bf16_rne(v.x) | (bf16_rne(v.y) << 16); }
     static __device__ __forceinline__ float2 w(w_t v) { return px(v); }
     static __device__ __forceinline__ w_t to_w(float a, float b) { return bf16_rne(a) | (bf16_rne(b) << 16); }
+};
+
+// FP32 storage with a depth-dependent collimator response: the response to
+// sample i is (1 - alpha_i) K + alpha_i K_far.  The per-sample weight pair
+// holds (step*E, R'_near) and a second array the far prefix sums R'_far; the
+// ray totals and the blurred cotangents come in a near and a far plane.
+struct F32DR : F32S {
+    static constexpr bool DR = true;
+    static constexpr int VJP_WAVES = 2;   // the far sums double the staged registers
 };
 
 // Bilinear sample of the zero-bordered interleaved map pair at (col, row)
@@ -273,7 +284,12 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
     const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
     float* rowp = reinterpret_cast<float*>(simg + img_elems);   // raw ray sums  [n_bins]
     float* rowr = rowp + g.n_bins;                              // residual      [n_bins]
-    for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = A.t.taps[k];
+    float* rowpf = rowr + g.n_bins;    // depth response: ray sums seen through the far response
+    __shared__ float taps_f[S::DR ? MAX_TAPS : 1];
+    for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) {
+        taps[k] = A.t.taps[k];
+        if (S::DR) taps_f[k] = A.t.taps_far[k];
+    }
     if (LDS_IMG) stage_image<F32S>(simg, A.src, slice, g.n, g.pitch, 0.0f);
     const px_t* img = LDS_IMG ? simg : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
     __syncthreads();
@@ -297,10 +313,16 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
             }
             const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
             float carry_mu = 0.0f, carry_le = 0.0f, carry_dle = 0.0f;
+            // depth response: the sums split into the parts seen through the
+            // near and the far response (lambda E and, for the Jacobian, d lambda E)
+            float carry_lf = 0.0f, carry_dn = 0.0f, carry_df = 0.0f;
             const float* depth = A.t.depth;   // per-sample factor of the attenuation path, or none
             w_t* wrow = nullptr;
-            if (MODE == MARCH_LIN)
+            float* qrow = nullptr;
+            if (MODE == MARCH_LIN) {
                 wrow = static_cast<w_t*>(A.wts) + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
+                if (S::DR) qrow = A.wq + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
+            }
             for (int i0 = gr.y; i0 >= gr.x; i0 -= SPL) {
                 const int i = i0 - q;
                 const bool act = (i >= cl.x) && (i <= cl.y);
@@ -318,7 +340,33 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                 const float bsum = carry_mu + (incl - hs * mu);
                 carry_mu += tot;
                 float lincl, ltot;
-                if (!depth) {
+                if (S::DR) {
+                    // carry_le holds the near part; sample i splits lambda E
+                    // into (1 - alpha_i) and alpha_i shares
+                    const float d = (depth && act) ? depth[i] : 1.0f;
+                    const float al = act ? A.t.resp[i] : 0.0f;
+                    const float E = __builtin_amdgcn_exp2f(-g.ln2_scale * (d * bsum));
+                    const float le = lam * E;
+                    const float ln = (1.0f - al) * le, lf = al * le;
+                    float fincl, ftot;
+                    quad_scan(ln, q, lincl, ltot);
+                    quad_scan(lf, q, fincl, ftot);
+                    // the Jacobian's sums of d lambda E equal these without a depth factor
+                    float dn = ln, dfv = lf, dnincl = lincl, dntot = ltot, dfincl = fincl, dftot = ftot;
+                    if (depth) {
+                        dn = d * ln;
+                        dfv = d * lf;
+                        quad_scan(dn, q, dnincl, dntot);
+                        quad_scan(dfv, q, dfincl, dftot);
+                    }
+                    if (MODE == MARCH_LIN && act) {
+                        wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, carry_dn + (dnincl - hs * dn));
+                        qrow[(size_t)i * g.n_bins + j] = carry_df + (dfincl - hs * dfv);
+                    }
+                    carry_lf += ftot;
+                    carry_dn += dntot;
+                    carry_df += dftot;
+                } else if (!depth) {
                     const float E = __builtin_amdgcn_exp2f(-g.ln2_scale * bsum);
                     const float le = lam * E;
                     quad_scan(le, q, lincl, ltot);
@@ -345,15 +393,24 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
             }
             if (ray_ok && q == 0) {
                 rowp[j] = g.step * carry_le;
-                if (MODE == MARCH_LIN)
-                    A.tsum[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + j] = depth ? carry_dle : carry_le;
+                const size_t o = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins + j;
+                if (S::DR) {
+                    rowpf[j] = g.step * carry_lf;
+                    if (MODE == MARCH_LIN) {
+                        A.tsum[o] = carry_dn;
+                        A.tsum[o + A.far_off] = carry_df;
+                    }
+                } else if (MODE == MARCH_LIN) {
+                    A.tsum[o] = depth ? carry_dle : carry_le;
+                }
             }
         }
         __syncthreads();
         // collimator blur and epilogue over the bins of this angle
         const size_t srow = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
         for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) {
-            const float y = psf_at(rowp, taps, g.K, g.n_bins, j);
+            float y = psf_at(rowp, taps, g.K, g.n_bins, j);
+            if (S::DR) y += psf_at(rowpf, taps_f, g.K, g.n_bins, j);
             if (A.yout) A.yout[srow + j] = y;
             if (A.ymeas) {
                 const float r = y - A.ymeas[srow + j];
@@ -362,9 +419,12 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
             }
         }
         if (A.wout) {
+            // the transposed blurs; both responses are symmetric
             __syncthreads();
-            for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x)
+            for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) {
                 A.wout[srow + j] = psf_at(rowr, taps, g.K, g.n_bins, j);
+                if (S::DR) A.wout[srow + A.far_off + j] = psf_at(rowr, taps_f, g.K, g.n_bins, j);
+            }
         }
         __syncthreads();
     }
@@ -403,7 +463,12 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
     float* rowz = reinterpret_cast<float*>(simg + img_elems);   // [nrows][n_bins]
     float* rowy = rowz + A.angles_per_block * per_slot * g.n_bins;
-    for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) taps[k] = A.t.taps[k];
+    float* rowzf = rowy + A.angles_per_block * per_slot * g.n_bins;   // depth response: far part of z
+    __shared__ float taps_f[S::DR ? MAX_TAPS : 1];
+    for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) {
+        taps[k] = A.t.taps[k];
+        if (S::DR) taps_f[k] = A.t.taps_far[k];
+    }
     if (LDS_IMG) {
         const float beta = resolve_beta(A.src, A.part, slice, sh);
         stage_image<S>(simg, A.src, slice, g.n, g.pitch, beta);
@@ -440,12 +505,16 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         const bool ray_ok = j < g.n_bins;
         int2 cl = make_int2(1, 0);
         float2 rb = make_float2(0.0f, 0.0f);
-        float T = 0.0f, Tm = 0.0f;
+        float T = 0.0f, Tm = 0.0f, Tf = 0.0f, Tfm = 0.0f;
         if (ray_ok) {
             cl = A.t.clip[(size_t)a * g.n_bins + j];
             rb = A.t.rbase[(size_t)a * g.n_bins + j];
             T = tslice[(size_t)a * g.n_bins + j];
             if (g.paired) Tm = tslice[(size_t)am * g.n_bins + jm];
+            if (S::DR) {
+                Tf = tslice[A.far_off + (size_t)a * g.n_bins + j];
+                if (g.paired) Tfm = tslice[A.far_off + (size_t)am * g.n_bins + jm];
+            }
         }
         int2 gr = A.t.grange[(size_t)a * g.n_groups + grp * GPI];
 #pragma unroll
@@ -457,24 +526,34 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         }
         const w_t* wrow = wslice + (size_t)a * g.n_t * g.n_bins;
         const w_t* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
+        const float* qrow = S::DR ? A.wq + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins : nullptr;
+        const float* qrowm = S::DR ? A.wq + (size_t)slice * A.wts_stride + (size_t)am * g.n_t * g.n_bins : nullptr;
         float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
+        // depth response: accf / accq collect the near parts, these the far
+        float accff = 0.0f, accqf = 0.0f, accffm = 0.0f, accqfm = 0.0f;
         // The sample loop is software-pipelined: the weights of trip t+1 (JU
         // samples per lane) are loaded while trip t is computed; they stay in
         // their storage format until used.  Lanes outside their ray's support
         // load nothing and use (0, T), which makes both terms vanish.
-        constexpr int JU = 4;
+        constexpr int JU = S::DR ? 2 : 4;   // the far sums take the registers of two more trips
         constexpr int STEP = JU * JSPL;
+        constexpr int QU = S::DR ? JU : 1;
         w_t wa[JU], wma[JU], wb[JU], wmb[JU];
-        auto load = [&](int i0, w_t* w, w_t* wm) {
+        float qa[QU], qma[QU], qb[QU], qmb[QU];
+        auto load = [&](int i0, w_t* w, w_t* wm, float* qv, float* qm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
                 const int i = i0 - u * JSPL - q;
                 const bool ok = (i >= cl.x) && (i <= cl.y);
                 w[u] = ok ? wrow[(size_t)i * g.n_bins + j] : w_t{};
                 if (g.paired) wm[u] = ok ? wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : w_t{};
+                if constexpr (S::DR) {
+                    qv[u] = ok ? qrow[(size_t)i * g.n_bins + j] : 0.0f;
+                    if (g.paired) qm[u] = ok ? qrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : 0.0f;
+                }
             }
         };
-        auto compute = [&](int i0, const w_t* w, const w_t* wm) {
+        auto compute = [&](int i0, const w_t* w, const w_t* wm, const float* qv, const float* qm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
                 const int i = i0 - u * JSPL - q;
@@ -483,34 +562,63 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                 const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
                 const float2 v = bilerp<S>(img, g.pitch, g.n, col, row);
                 const float2 wv = S::w(w[u]);
-                accf = fmaf(wv.x, v.x, accf);
-                accq = fmaf(T - (ok ? wv.y : T), v.y, accq);
-                if (g.paired) {
-                    const float2 wmv = S::w(wm[u]);
-                    accfm = fmaf(wmv.x, v.x, accfm);
-                    accqm = fmaf(Tm - (ok ? wmv.y : Tm), v.y, accqm);
+                if constexpr (S::DR) {
+                    // sample i of this ray is sample n_t - 1 - i of the mirror ray
+                    const float al = ok ? A.t.resp[i] : 0.0f;
+                    const float ef = wv.x * v.x;
+                    accf = fmaf(1.0f - al, ef, accf);
+                    accff = fmaf(al, ef, accff);
+                    accq = fmaf(T - (ok ? wv.y : T), v.y, accq);
+                    accqf = fmaf(Tf - (ok ? qv[u] : Tf), v.y, accqf);
+                    if (g.paired) {
+                        const float2 wmv = S::w(wm[u]);
+                        const float alm = ok ? A.t.resp[g.n_t - 1 - i] : 0.0f;
+                        const float efm = wmv.x * v.x;
+                        accfm = fmaf(1.0f - alm, efm, accfm);
+                        accffm = fmaf(alm, efm, accffm);
+                        accqm = fmaf(Tm - (ok ? wmv.y : Tm), v.y, accqm);
+                        accqfm = fmaf(Tfm - (ok ? qm[u] : Tfm), v.y, accqfm);
+                    }
+                } else {
+                    accf = fmaf(wv.x, v.x, accf);
+                    accq = fmaf(T - (ok ? wv.y : T), v.y, accq);
+                    if (g.paired) {
+                        const float2 wmv = S::w(wm[u]);
+                        accfm = fmaf(wmv.x, v.x, accfm);
+                        accqm = fmaf(Tm - (ok ? wmv.y : Tm), v.y, accqm);
+                    }
                 }
             }
         };
         int i0 = gr.y;
-        if (i0 >= gr.x) load(i0, wa, wma);
+        if (i0 >= gr.x) load(i0, wa, wma, qa, qma);
         while (i0 >= gr.x) {
             const int i1 = i0 - STEP;
-            if (i1 >= gr.x) load(i1, wb, wmb);
-            compute(i0, wa, wma);
+            if (i1 >= gr.x) load(i1, wb, wmb, qb, qmb);
+            compute(i0, wa, wma, qa, qma);
             if (i1 < gr.x) break;
             const int i2 = i1 - STEP;
-            if (i2 >= gr.x) load(i2, wa, wma);
-            compute(i1, wb, wmb);
+            if (i2 >= gr.x) load(i2, wa, wma, qa, qma);
+            compute(i1, wb, wmb, qb, qmb);
             i0 = i2;
         }
         accf = ray_sum<JSPL>(accf);
         accq = ray_sum<JSPL>(accq);
         if (ray_ok && q == 0) rowz[sl * g.n_bins + j] = fmaf(g.kq, accq, accf);
+        if (S::DR) {
+            accff = ray_sum<JSPL>(accff);
+            accqf = ray_sum<JSPL>(accqf);
+            if (ray_ok && q == 0) rowzf[sl * g.n_bins + j] = fmaf(g.kq, accqf, accff);
+        }
         if (g.paired) {
             accfm = ray_sum<JSPL>(accfm);
             accqm = ray_sum<JSPL>(accqm);
             if (ray_ok && q == 0) rowz[(nslot + sl) * g.n_bins + jm] = fmaf(g.kq, accqm, accfm);
+            if (S::DR) {
+                accffm = ray_sum<JSPL>(accffm);
+                accqfm = ray_sum<JSPL>(accqfm);
+                if (ray_ok && q == 0) rowzf[(nslot + sl) * g.n_bins + jm] = fmaf(g.kq, accqfm, accffm);
+            }
         }
         int nxt = 0;
         if (lane == 0) nxt = atomicAdd(&next_item, 1);
@@ -523,7 +631,8 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     double acc2 = 0.0;
     for (int e = threadIdx.x; e < nel; e += blockDim.x) {
         const int r = e / g.n_bins, jb = e - r * g.n_bins;
-        const float y = psf_at(rowz + r * g.n_bins, taps, g.K, g.n_bins, jb);
+        float y = psf_at(rowz + r * g.n_bins, taps, g.K, g.n_bins, jb);
+        if (S::DR) y += psf_at(rowzf + r * g.n_bins, taps_f, g.K, g.n_bins, jb);
         const int a = r < nslot ? slot0 + r : slot0 + (r - nslot) + g.n_angles / 2;
         const size_t o = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins + jb;
         if (MODE == JVP_PLAIN) A.out[o] = y;
@@ -535,8 +644,9 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         for (int e = threadIdx.x; e < nel; e += blockDim.x) {
             const int r = e / g.n_bins, jb = e - r * g.n_bins;
             const int a = r < nslot ? slot0 + r : slot0 + (r - nslot) + g.n_angles / 2;
-            A.out[(size_t)slice * A.sino_stride + (size_t)a * g.n_bins + jb] =
-                psf_at(rowy + r * g.n_bins, taps, g.K, g.n_bins, jb);
+            const size_t o = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins + jb;
+            A.out[o] = psf_at(rowy + r * g.n_bins, taps, g.K, g.n_bins, jb);
+            if (S::DR) A.out[o + A.far_off] = psf_at(rowy + r * g.n_bins, taps_f, g.K, g.n_bins, jb);
         }
     }
     if (MODE == JVP_SQNORM) {
@@ -622,6 +732,14 @@ struct Stage {
     typename SP::w_t w[VROWS];
     typename SP::w_t wm[VROWS];   // mirror angle, same points (paired geometry)
     float wt, t, wtm, tm;
+    // depth response: R' of the far response per point, the far cotangent
+    // and total of the lane's column, and the window's first row (alpha of a
+    // row's sample is read when the row is staged: rows are wave-uniform,
+    // so that is a scalar load)
+    static constexpr int QR = SP::DR ? VROWS : 1;
+    float q[QR], qm[QR];
+    float wtf, tf, wtfm, tfm;
+    int ilo;
 };
 
 // Loads of one angle's window into registers (weight pair per point, and the
@@ -652,6 +770,22 @@ __device__ __forceinline__ void stage_load(Stage<SP>& S, const VjpArgs& A, const
         S.w[k] = typename SP::w_t{};     // zero in either format
         S.wm[k] = typename SP::w_t{};
     }
+    const float* qrow = nullptr;
+    const float* qrowm = nullptr;
+    if constexpr (SP::DR) {
+        S.wtf = jok ? A.wt[A.far_off + sbase + j] : 0.0f;
+        S.tf = jok ? A.tsum[A.far_off + sbase + j] : 0.0f;
+        S.wtfm = (jok && g.paired) ? A.wt[A.far_off + sbasem + jm] : 0.0f;
+        S.tfm = (jok && g.paired) ? A.tsum[A.far_off + sbasem + jm] : 0.0f;
+        qrow = A.wq + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
+        qrowm = A.wq + (size_t)slice * A.wts_stride + (size_t)am * g.n_t * g.n_bins;
+#pragma unroll
+        for (int k = 0; k < VROWS; ++k) {
+            S.q[k] = 0.0f;
+            S.qm[k] = 0.0f;
+        }
+        S.ilo = W.ilo;
+    }
     if (jok) {
 #pragma unroll
         for (int k = 0; k < VROWS; ++k) {
@@ -660,30 +794,58 @@ __device__ __forceinline__ void stage_load(Stage<SP>& S, const VjpArgs& A, const
             if (ii < W.wi && i >= 0 && i < g.n_t) {
                 S.w[k] = wrow[(size_t)i * g.n_bins + j];
                 if (g.paired) S.wm[k] = wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm];
+                if constexpr (SP::DR) {
+                    S.q[k] = qrow[(size_t)i * g.n_bins + j];
+                    if (g.paired) S.qm[k] = qrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm];
+                }
             }
         }
     }
 }
 
-// Staged value of a lattice point: the coefficients of f and mu it spreads
-// (step*E*wt and kq*(T - R')*wt), summed with those of the mirror angle's
-// sample at the same point when the geometry is paired.
+// Coefficients of f and mu that a staged point spreads: step*E*wt and
+// kq*(T - R')*wt, plus those of the mirror angle's sample at the same point
+// when the geometry is paired.  With a depth response the f coefficient sees
+// the cotangent blended between the near and far planes by the sample's
+// alpha, and the mu coefficient adds the far plane's term.
 template <typename SP>
-__device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, float kq)
+__device__ __forceinline__ float2 stage_coef(const Stage<SP>& S, int k, float kq, const Geo& g, const float* resp)
+{
+    const float2 w = SP::w(S.w[k]), wm = SP::w(S.wm[k]);
+    if constexpr (SP::DR) {
+        // sample i of the angle is sample n_t - 1 - i of its mirror; rows off
+        // the lattice hold zero weights, any alpha serves them
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int i = min(max(S.ilo + wave + 4 * k, 0), g.n_t - 1);
+        const float al = resp[i], alm = resp[g.n_t - 1 - i];
+        const float ct = fmaf(al, S.wtf - S.wt, S.wt);
+        const float ctm = fmaf(alm, S.wtfm - S.wtm, S.wtm);
+        const float cf = fmaf(wm.x, ctm, w.x * ct);
+        float sm = S.wt * (S.t - w.y);
+        sm = fmaf(S.wtf, S.tf - S.q[k], sm);
+        sm = fmaf(S.wtm, S.tm - wm.y, sm);
+        sm = fmaf(S.wtfm, S.tfm - S.qm[k], sm);
+        return make_float2(cf, kq * sm);
+    } else {
+        const float kw = kq * S.wt, kwm = kq * S.wtm;
+        const float cf = fmaf(wm.x, S.wtm, w.x * S.wt);
+        const float cm = fmaf(kwm, S.tm - wm.y, kw * (S.t - w.y));
+        return make_float2(cf, cm);
+    }
+}
+
+// Staged value of every lattice point of the window (stage_coef).
+template <typename SP>
+__device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, float kq, const Geo& g,
+                                            const float* resp)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (lane >= VFP) return;
-    const float kw = kq * S.wt, kwm = kq * S.wtm;
 #pragma unroll
     for (int k = 0; k < VROWS; ++k) {
         const int ii = wave + 4 * k;
-        if (ii < VFP) {
-            const float2 w = SP::w(S.w[k]), wm = SP::w(S.wm[k]);
-            const float cf = fmaf(wm.x, S.wtm, w.x * S.wt);
-            const float cm = fmaf(kwm, S.tm - wm.y, kw * (S.t - w.y));
-            lat[ii * LP + lane] = make_float2(cf, cm);
-        }
+        if (ii < VFP) lat[ii * LP + lane] = stage_coef(S, k, kq, g, resp);
     }
 }
 
@@ -692,23 +854,21 @@ __device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, flo
 // rotated column lane is W's row W.wi - 1 - lane, rotated row ii is W's column
 // ii.  Every point has one owner thread.
 template <typename SP>
-__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, float kq, const Window& W)
+__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, float kq, const Window& W,
+                                              const Geo& g, const float* resp)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (lane >= W.wi) return;
-    const float kw = kq * S.wt, kwm = kq * S.wtm;
     float2* row = lat + (W.wi - 1 - lane) * LP;
 #pragma unroll
     for (int k = 0; k < VROWS; ++k) {
         const int ii = wave + 4 * k;
         if (ii < W.wj) {
-            const float2 w = SP::w(S.w[k]), wm = SP::w(S.wm[k]);
-            const float cf = fmaf(wm.x, S.wtm, w.x * S.wt);
-            const float cm = fmaf(kwm, S.tm - wm.y, kw * (S.t - w.y));
+            const float2 c = stage_coef(S, k, kq, g, resp);
             float2 v = row[ii];
-            v.x += cf;
-            v.y += cm;
+            v.x += c.x;
+            v.y += c.y;
             row[ii] = v;
         }
     }
@@ -782,10 +942,10 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
     for (int a = a_begin; a < a_end; ++a) {
         const Window W = Wn;
         __syncthreads();   // the previous angle's gather is done with lat
-        stage_store(lat, S, g.kq);
+        stage_store(lat, S, g.kq, g, A.t.resp);
         if (QUAD) {
             __syncthreads();
-            stage_add_rot(lat, R, g.kq, W);
+            stage_add_rot(lat, R, g.kq, W, g, A.t.resp);
         }
         __syncthreads();
         if (a + 1 < a_end) {   // next angle's loads fly during this gather
@@ -1417,5 +1577,6 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
     template __global__ void k_pack<S>(Geo, PairSrc, const double*, void*, long long, const LMState*);
 INST_ALL(F32S)
 INST_ALL(BF16S)
+INST_ALL(F32DR)
 
 }  // namespace pget

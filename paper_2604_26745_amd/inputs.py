@@ -289,6 +289,20 @@ def lattice_rod_prior(cfg: SliceConfig, margin: float = 1.0):
     return out, np.zeros_like(out), np.where(can, cfg.bg_mu, 0.0)
 
 
+def collimator_depth_response(n_samples: int, half_width: int, sigma_far: float):
+    """A depth-dependent collimator response for the discrete model: the
+    response at the far side of the field is a Gaussian of ``sigma_far``
+    bins over the plan's 2K + 1 taps (normalised), and its weight alpha
+    grows linearly from 0 at the sample nearest the detector to 1 at the
+    farthest (sample 0), so the response widens with the emitter's
+    distance.  Returns (alpha, far_taps) as tuples."""
+    k = np.arange(-half_width, half_width + 1)
+    t = np.exp(-(k ** 2) / (2.0 * sigma_far ** 2))
+    t /= t.sum()
+    alpha = 1.0 - np.arange(n_samples) / max(n_samples - 1, 1)
+    return tuple(float(v) for v in alpha), tuple(float(v) for v in t)
+
+
 def fov_mask(cfg: ScannerConfig) -> np.ndarray:
     """Pixels of the reconstruction grid whose centre lies in the field-of-view disk."""
     cc = np.arange(cfg.n) - 0.5 * (cfg.n - 1)

@@ -97,6 +97,9 @@ def load_library():
     lib.pget_plan_support_samples.restype = ctypes.c_int64
     lib.pget_plan_set_depth_factor.argtypes = [V, P(ctypes.c_double), ctypes.c_int32]
     lib.pget_plan_set_depth_factor.restype = ctypes.c_int
+    lib.pget_plan_set_depth_response.argtypes = [V, P(ctypes.c_double), ctypes.c_int32, P(ctypes.c_double),
+                                                 ctypes.c_int32]
+    lib.pget_plan_set_depth_response.restype = ctypes.c_int
     lib.pget_timing_enable.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.pget_timing_enable.restype = ctypes.c_int
     lib.pget_timing_read.argtypes = [ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -396,6 +399,22 @@ class Plan:
             return
         arr = (ctypes.c_double * len(depth))(*[float(v) for v in depth])
         _check(self.lib.pget_plan_set_depth_factor(self.handle, arr, len(depth)), "pget_plan_set_depth_factor")
+
+    def set_depth_response(self, alpha=None, far_taps=None):
+        """Depth-dependent collimator response: sample i of every ray (sample
+        0 farthest from the detector) is seen through (1 - alpha[i]) times the
+        plan's Gaussian taps plus alpha[i] times ``far_taps`` (2K + 1
+        symmetric values).  None restores the depth-independent response.
+        The workspaces grow; the cached ones are dropped."""
+        self._ws.clear()
+        if alpha is None:
+            _check(self.lib.pget_plan_set_depth_response(self.handle, None, 0, None, 0),
+                   "pget_plan_set_depth_response")
+            return
+        a = (ctypes.c_double * len(alpha))(*[float(v) for v in alpha])
+        t = (ctypes.c_double * len(far_taps))(*[float(v) for v in far_taps])
+        _check(self.lib.pget_plan_set_depth_response(self.handle, a, len(alpha), t, len(far_taps)),
+               "pget_plan_set_depth_response")
 
     def autotune(self, batch: int = 1):
         """Pick the fastest launch shapes for solves of `batch` slices."""
