@@ -95,6 +95,10 @@ def parse():
     ap.add_argument("--dg-decay", type=float, default=1.0,
                     help="deepgn: divide the alphas by this factor per iteration (the paper uses 5)")
     ap.add_argument("--dg-decay-until", type=int, default=3, help="deepgn: iterations the decay runs for")
+    ap.add_argument("--full-model", action="store_true",
+                    help="scanner: the full discrete model (depth-dependent collimator response and "
+                         "vertical correction) for the data and the reconstruction; the plain model "
+                         "is timed beside it")
     ap.add_argument("--no-bf16-variant", action="store_true",
                     help="main workload: skip timing the BF16-storage variant beside FP32")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -317,12 +321,20 @@ def run_scanner(args, torch, np, inputs, pget):
     relative error of the maps inside the field of view."""
     import dataclasses
     cfg = dataclasses.replace(inputs.SCANNER_165, max_outer=args.outer, n_cg=args.cg)
+    full = args.full_model
+    if full and args.storage != "fp32":
+        sys.exit("bench: the full discrete model runs with FP32 storage only")
     geo = {}
     for o in (1, cfg.oversample):
-        d = inputs.scanner_geometry(cfg, o)
+        d = inputs.scanner_geometry(cfg, o, full_model=full)
         ys_ = d.pop("y_scale")
         n = d.pop("n")
-        geo[o] = (pget.Plan(n, d.pop("n_angles"), d.pop("n_bins"), storage=args.storage, **d), ys_)
+        pl = pget.Plan(n, d.pop("n_angles"), d.pop("n_bins"), storage=args.storage, **d)
+        if full:
+            dep, al, far = inputs.scanner_full_model(cfg, pl.n_samples)
+            pl.set_depth_factor(dep)
+            pl.set_depth_response(al, far)
+        geo[o] = (pl, ys_)
     plan, cscale = geo[1]
     fine, fscale = geo[cfg.oversample]
     T = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
@@ -358,17 +370,33 @@ def run_scanner(args, torch, np, inputs, pget):
     el = time.perf_counter() - t0
     reps = [r.to_report() for r in rbs]
     assert all(r.status == 0 for r in reps)
+    plain = None
+    if full:
+        # the same data and launch shapes reconstructed with the plain model
+        d = inputs.scanner_geometry(cfg, 1, full_model=True)
+        d.pop("y_scale")
+        p0 = pget.Plan(d.pop("n"), d.pop("n_angles"), d.pop("n_bins"), **d)
+        fs0, ms0, _ = p0.lm_solve_batched(ys, f0s, m0s, prm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            fs0, ms0, _ = p0.lm_solve_batched(ys, f0s, m0s, prm, sync=False)
+        torch.cuda.synchronize()
+        plain = (time.perf_counter() - t1, fs0, ms0)
     mask = inputs.fov_mask(cfg)
     ef = [np.linalg.norm((f.cpu().numpy() - t[0])[mask]) / np.linalg.norm(t[0][mask]) for f, t in zip(fs, truth)]
     em = [np.linalg.norm((m.cpu().numpy() - t[1])[mask]) / np.linalg.norm(t[1][mask]) for m, t in zip(ms, truth)]
+    model = ", full discrete model" if full else ""
     out = {
-        "metric": "LM reconstructions/s, scanner geometry 165^2 x 360 angles x 182 bins (%s)" % args.storage.upper(),
+        "metric": "LM reconstructions/s, scanner geometry 165^2 x 360 angles x 182 bins (%s%s)"
+                  % (args.storage.upper(), model),
         "value": round(B * args.steps / el, 4), "unit": "reconstructions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.storage == "fp32" else "bf16-storage/f32-compute",
         "data": "synthetic: 9x9 assemblies on a 1 mm grid, 2% Gaussian noise",
-        "config": {"workload": "%s_batch%d" % (cfg.name, B), "outer": cfg.max_outer, "cg": cfg.n_cg,
+        "config": {"workload": "%s_batch%d" % (cfg.name, B) + ("_full_model" if full else ""),
+                   "outer": cfg.max_outer, "cg": cfg.n_cg,
                    "pixel_mm": cfg.pixel_mm, "bin_mm": cfg.bin_mm, "oversample": cfg.oversample,
                    "solver": dict({"name": args.solver, "prior_gamma": args.prior}, **opts),
                    "mu0": "water in the field of view" if args.solver == "scaled" else "zero"},
@@ -377,6 +405,15 @@ def run_scanner(args, torch, np, inputs, pget):
                         [np.linalg.norm((f0.cpu().numpy() - t[0])[mask]) / np.linalg.norm(t[0][mask])
                          for f0, t in zip(f0s, truth)])), 4)},
     }
+    if full:
+        out["config"]["full_model"] = {"psf_sigma_far_bins": cfg.psf_sigma_far_bins,
+                                       "depth_factor_far": cfg.depth_factor_far}
+        el0, fs0, ms0 = plain
+        ef0 = [np.linalg.norm((f.cpu().numpy() - t[0])[mask]) / np.linalg.norm(t[0][mask]) for f, t in zip(fs0, truth)]
+        em0 = [np.linalg.norm((m.cpu().numpy() - t[1])[mask]) / np.linalg.norm(t[1][mask]) for m, t in zip(ms0, truth)]
+        out["plain_model"] = {"value": round(B * args.steps / el0, 4), "ms_per_step": round(1e3 * el0 / args.steps, 3),
+                              "f_rel_err_fov": round(float(np.mean(ef0)), 4),
+                              "mu_rel_err_fov": round(float(np.mean(em0)), 4)}
     print(json.dumps(out), flush=True)
 
 

@@ -90,12 +90,13 @@ int half_width(const pget_geometry* g)
 }
 
 // Dynamic LDS of a k_jvp_lin block of `japb` angle slots: the staged map
-// pair, and per sinogram row z and K z (plus the far part of z with a depth
-// response).
+// pair, and per sinogram row z and K z (plus, with a depth response, the far
+// part of z, and alpha per sample).
 size_t jvp_lds_for(const pget_plan* P, int japb)
 {
     const size_t rows = P->t.resp ? 3 : 2;
-    return P->img_lds + rows * (size_t)japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+    const size_t alpha = P->t.resp ? (size_t)P->g.n_t * sizeof(float) : 0;
+    return P->img_lds + rows * (size_t)japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float) + alpha;
 }
 int max_japb_of(const pget_plan* P) { return P->t.resp ? P->max_japb_dr : P->max_japb; }
 
@@ -114,11 +115,12 @@ struct Shapes {
 };
 
 // Angle slots of the adjoint gather: one slot takes an angle with its mirror
-// (paired) and the quarter-turn pair (quad).
+// (paired) and the quarter-turn pair (quad; not with a depth response, whose
+// far sums leave no registers for a second staged angle).
 int vjp_slots(const pget_plan* P)
 {
     const Geo& g = P->g;
-    return g.quad ? g.n_angles / 4 : g.paired ? g.n_angles / 2 : g.n_angles;
+    return (g.quad && !P->t.resp) ? g.n_angles / 4 : g.paired ? g.n_angles / 2 : g.n_angles;
 }
 
 Shapes shapes_for(const pget_plan* P, int batch)
@@ -305,8 +307,7 @@ void launch_vjp(const pget_plan* P, const VjpArgs& V, int batch, hipStream_t s)
 {
     const dim3 grid(P->tiles_x * P->tiles_x * V.groups, batch), block(VJP_THREADS);
     if (P->t.resp) {
-        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<F32DR, true>), grid, block, 0, s, V);
-        else hipLaunchKernelGGL((k_vjp_lin<F32DR, false>), grid, block, 0, s, V);
+        hipLaunchKernelGGL((k_vjp_lin<F32DR, false>), grid, block, 0, s, V);
     } else if (P->bf16) {
         if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<BF16S, true>), grid, block, 0, s, V);
         else hipLaunchKernelGGL((k_vjp_lin<BF16S, false>), grid, block, 0, s, V);
@@ -499,7 +500,10 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         P->jvp_lds = jimg_bytes + per_slot <= lds_budget;
         P->img_lds = P->jvp_lds ? jimg_bytes : 0;
         P->max_japb = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / per_slot);
-        P->max_japb_dr = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / (per_slot / 2 * 3));
+        const size_t alpha_bytes = (size_t)nt * sizeof(float);
+        P->max_japb_dr = lds_budget >= P->img_lds + alpha_bytes
+                             ? (int)std::min<size_t>(16, (lds_budget - P->img_lds - alpha_bytes) / (per_slot / 2 * 3))
+                             : 0;
         if (P->max_japb < 1) {
             (void)hipFree(P->table_mem);
             delete P;
@@ -558,7 +562,7 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         int occ = 0, occ_dr = 0;
         const void* vk = g.quad ? (P->bf16 ? (const void*)k_vjp_lin<BF16S, true> : (const void*)k_vjp_lin<F32S, true>)
                                 : (P->bf16 ? (const void*)k_vjp_lin<BF16S, false> : (const void*)k_vjp_lin<F32S, false>);
-        const void* vk_dr = g.quad ? (const void*)k_vjp_lin<F32DR, true> : (const void*)k_vjp_lin<F32DR, false>;
+        const void* vk_dr = (const void*)k_vjp_lin<F32DR, false>;
         if (hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, vk, VJP_THREADS, 0) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_dr, vk_dr, VJP_THREADS, 0) != hipSuccess) {

@@ -464,11 +464,14 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     float* rowz = reinterpret_cast<float*>(simg + img_elems);   // [nrows][n_bins]
     float* rowy = rowz + A.angles_per_block * per_slot * g.n_bins;
     float* rowzf = rowy + A.angles_per_block * per_slot * g.n_bins;   // depth response: far part of z
+    float* alpha = rowzf + A.angles_per_block * per_slot * g.n_bins;  // depth response: alpha per sample
     __shared__ float taps_f[S::DR ? MAX_TAPS : 1];
     for (int k = threadIdx.x; k < 2 * g.K + 1; k += blockDim.x) {
         taps[k] = A.t.taps[k];
         if (S::DR) taps_f[k] = A.t.taps_far[k];
     }
+    if (S::DR)
+        for (int i = threadIdx.x; i < g.n_t; i += blockDim.x) alpha[i] = A.t.resp[i];
     if (LDS_IMG) {
         const float beta = resolve_beta(A.src, A.part, slice, sh);
         stage_image<S>(simg, A.src, slice, g.n, g.pitch, beta);
@@ -564,7 +567,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                 const float2 wv = S::w(w[u]);
                 if constexpr (S::DR) {
                     // sample i of this ray is sample n_t - 1 - i of the mirror ray
-                    const float al = ok ? A.t.resp[i] : 0.0f;
+                    const float al = ok ? alpha[i] : 0.0f;
                     const float ef = wv.x * v.x;
                     accf = fmaf(1.0f - al, ef, accf);
                     accff = fmaf(al, ef, accff);
@@ -572,7 +575,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                     accqf = fmaf(Tf - (ok ? qv[u] : Tf), v.y, accqf);
                     if (g.paired) {
                         const float2 wmv = S::w(wm[u]);
-                        const float alm = ok ? A.t.resp[g.n_t - 1 - i] : 0.0f;
+                        const float alm = ok ? alpha[g.n_t - 1 - i] : 0.0f;
                         const float efm = wmv.x * v.x;
                         accfm = fmaf(1.0f - alm, efm, accfm);
                         accffm = fmaf(alm, efm, accffm);
@@ -733,13 +736,13 @@ struct Stage {
     typename SP::w_t wm[VROWS];   // mirror angle, same points (paired geometry)
     float wt, t, wtm, tm;
     // depth response: R' of the far response per point, the far cotangent
-    // and total of the lane's column, and the window's first row (alpha of a
-    // row's sample is read when the row is staged: rows are wave-uniform,
-    // so that is a scalar load)
+    // and total of the lane's column, and alpha of window row `lane` for the
+    // angle and its mirror (a staged row takes its value by readlane: rows
+    // are wave-uniform)
     static constexpr int QR = SP::DR ? VROWS : 1;
     float q[QR], qm[QR];
     float wtf, tf, wtfm, tfm;
-    int ilo;
+    float al, alm;
 };
 
 // Loads of one angle's window into registers (weight pair per point, and the
@@ -784,7 +787,11 @@ __device__ __forceinline__ void stage_load(Stage<SP>& S, const VjpArgs& A, const
             S.q[k] = 0.0f;
             S.qm[k] = 0.0f;
         }
-        S.ilo = W.ilo;
+        // sample i of the angle is sample n_t - 1 - i of its mirror; rows off
+        // the lattice hold zero weights, any alpha serves them
+        const int i = min(max(W.ilo + lane, 0), g.n_t - 1);
+        S.al = A.t.resp[i];
+        S.alm = A.t.resp[g.n_t - 1 - i];
     }
     if (jok) {
 #pragma unroll
@@ -809,15 +816,13 @@ __device__ __forceinline__ void stage_load(Stage<SP>& S, const VjpArgs& A, const
 // the cotangent blended between the near and far planes by the sample's
 // alpha, and the mu coefficient adds the far plane's term.
 template <typename SP>
-__device__ __forceinline__ float2 stage_coef(const Stage<SP>& S, int k, float kq, const Geo& g, const float* resp)
+__device__ __forceinline__ float2 stage_coef(const Stage<SP>& S, int k, float kq)
 {
     const float2 w = SP::w(S.w[k]), wm = SP::w(S.wm[k]);
     if constexpr (SP::DR) {
-        // sample i of the angle is sample n_t - 1 - i of its mirror; rows off
-        // the lattice hold zero weights, any alpha serves them
-        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int i = min(max(S.ilo + wave + 4 * k, 0), g.n_t - 1);
-        const float al = resp[i], alm = resp[g.n_t - 1 - i];
+        const int row = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) + 4 * k;
+        const float al = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(S.al), row));
+        const float alm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(S.alm), row));
         const float ct = fmaf(al, S.wtf - S.wt, S.wt);
         const float ctm = fmaf(alm, S.wtfm - S.wtm, S.wtm);
         const float cf = fmaf(wm.x, ctm, w.x * ct);
@@ -836,8 +841,7 @@ __device__ __forceinline__ float2 stage_coef(const Stage<SP>& S, int k, float kq
 
 // Staged value of every lattice point of the window (stage_coef).
 template <typename SP>
-__device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, float kq, const Geo& g,
-                                            const float* resp)
+__device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, float kq)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -845,7 +849,7 @@ __device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, flo
 #pragma unroll
     for (int k = 0; k < VROWS; ++k) {
         const int ii = wave + 4 * k;
-        if (ii < VFP) lat[ii * LP + lane] = stage_coef(S, k, kq, g, resp);
+        if (ii < VFP) lat[ii * LP + lane] = stage_coef(S, k, kq);
     }
 }
 
@@ -854,8 +858,7 @@ __device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, flo
 // rotated column lane is W's row W.wi - 1 - lane, rotated row ii is W's column
 // ii.  Every point has one owner thread.
 template <typename SP>
-__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, float kq, const Window& W,
-                                              const Geo& g, const float* resp)
+__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, float kq, const Window& W)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -865,7 +868,7 @@ __device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, f
     for (int k = 0; k < VROWS; ++k) {
         const int ii = wave + 4 * k;
         if (ii < W.wj) {
-            const float2 c = stage_coef(S, k, kq, g, resp);
+            const float2 c = stage_coef(S, k, kq);
             float2 v = row[ii];
             v.x += c.x;
             v.y += c.y;
@@ -942,10 +945,10 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
     for (int a = a_begin; a < a_end; ++a) {
         const Window W = Wn;
         __syncthreads();   // the previous angle's gather is done with lat
-        stage_store(lat, S, g.kq, g, A.t.resp);
+        stage_store(lat, S, g.kq);
         if (QUAD) {
             __syncthreads();
-            stage_add_rot(lat, R, g.kq, W, g, A.t.resp);
+            stage_add_rot(lat, R, g.kq, W);
         }
         __syncthreads();
         if (a + 1 < a_end) {   // next angle's loads fly during this gather

@@ -146,7 +146,10 @@ class ScannerConfig:
     angles, collimator response a Gaussian of 1 bin (2 mm) standard
     deviation, a 9 x 9 lattice at 14.4 mm pitch with 5.5 mm rod radius, rod
     centres perturbed by U(-0.5, 0.5) mm per axis, water filling the
-    field-of-view disk."""
+    field-of-view disk.  The full discrete model (``scanner_full_model``)
+    adds a response widening to a Gaussian of 2 bins at the far side of the
+    field and a vertical correction of the attenuation path growing to 1.05
+    there, both linear in depth."""
 
     name: str = "scanner9x9_n165_a360_b182"
     n: int = 165
@@ -155,6 +158,8 @@ class ScannerConfig:
     n_bins: int = 182
     bin_mm: float = 2.0
     psf_sigma_bins: float = 1.0
+    psf_sigma_far_bins: float = 2.0     # full model: response at the far side of the field
+    depth_factor_far: float = 1.05      # full model: vertical correction there
     oversample: int = 2
     n_rods: int = 9
     pitch_mm: float = 14.4
@@ -172,15 +177,30 @@ class ScannerConfig:
 SCANNER_165 = ScannerConfig()
 
 
-def scanner_geometry(cfg: ScannerConfig, oversample: int = 1) -> dict:
+def scanner_geometry(cfg: ScannerConfig, oversample: int = 1, full_model: bool = False) -> dict:
     """Plan arguments of the device geometry on a grid `oversample` times
     finer than cfg.n: pixel size p = pixel_mm / oversample, bins and samples
     in pixel units, attenuation per mm (atten_scale = p), and the factor p
-    that turns the plan's ray sums (step of one pixel) into millimetres."""
+    that turns the plan's ray sums (step of one pixel) into millimetres.
+    With the full model the collimator taps span 3 far-response sigmas."""
     p = cfg.pixel_mm / oversample
-    return dict(n=cfg.n * oversample, n_angles=cfg.n_angles, n_bins=cfg.n_bins,
-                bin_size=cfg.bin_mm / p, step=1.0, psf_sigma=cfg.psf_sigma_bins,
-                atten_scale=p, y_scale=p)
+    d = dict(n=cfg.n * oversample, n_angles=cfg.n_angles, n_bins=cfg.n_bins,
+             bin_size=cfg.bin_mm / p, step=1.0, psf_sigma=cfg.psf_sigma_bins,
+             atten_scale=p, y_scale=p)
+    if full_model:
+        d["psf_radius"] = int(math.ceil(3.0 * cfg.psf_sigma_far_bins))
+    return d
+
+
+def scanner_full_model(cfg: ScannerConfig, n_samples: int):
+    """Per-sample tables of the full discrete model for a plan of the device
+    geometry with ``n_samples`` samples per ray: (depth factor, alpha of the
+    far response, far taps), linear in depth from the detector side (1, 0)
+    to the far side (depth_factor_far, 1)."""
+    K = int(math.ceil(3.0 * cfg.psf_sigma_far_bins))
+    alpha, far = collimator_depth_response(n_samples, K, cfg.psf_sigma_far_bins)
+    depth = tuple(1.0 + (cfg.depth_factor_far - 1.0) * a for a in alpha)
+    return depth, alpha, far
 
 
 def scanner_phantom(cfg: ScannerConfig, seed: int = 0, kind: str = "missing", oversample: int = 1):
