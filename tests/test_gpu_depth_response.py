@@ -226,3 +226,13 @@ def test_bad_depth_response_rejected():
     with pytest.raises(pget.PgetError) as e:
         bf.set_depth_response(al, far)
     assert e.value.status == -5
+    # 8192 bins: three rows of sums per angle slot exceed a J v block's LDS;
+    # the plan is refused the response and keeps working without it
+    wide = pget.Plan(16, 8, 8192)
+    aw, fw = inputs.collimator_depth_response(wide.n_samples, wide.psf_half_width, 2.0)
+    with pytest.raises(pget.PgetError) as e:
+        wide.set_depth_response(aw, fw)
+    assert e.value.status == -5
+    f = torch.ones((16, 16), device="cuda")
+    y = wide.forward(f, torch.zeros_like(f))
+    assert torch.isfinite(y).all() and float(y.sum()) > 0
