@@ -4,8 +4,9 @@ times a far response) on the GPU against the FP64 oracle, which spreads
 every sample with its own response:
 
 * the operators with and without the quarter-turn fold of the gather, over
-  a half turn (no mirror pairing), and together with the depth factor of
-  the attenuation path (relative L2 <= 1e-5, max-abs / max-ref <= 1e-4);
+  a half turn (no mirror pairing), with maps too large for LDS (read from
+  HBM), and together with the depth factor of the attenuation path
+  (relative L2 <= 1e-5, max-abs / max-ref <= 1e-4);
 * an LM trajectory of the full discrete model (depth factor and response)
   with the oracle's decisions replayed (objective per iterate 1e-4, maps
   1e-3, as for the plain model);
@@ -72,7 +73,8 @@ def phantom(n, seed, mu_rod=0.08):
 
 @pytest.mark.parametrize("with_depth", [False, True], ids=["response", "response_and_depth"])
 @pytest.mark.parametrize("n,na,nb,arc", [(64, 120, 96, 2 * np.pi), (48, 90, 70, 2 * np.pi),
-                                         (40, 45, 60, np.pi)], ids=["quad", "paired", "half_turn"])
+                                         (40, 45, 60, np.pi), (150, 24, 220, 2 * np.pi)],
+                         ids=["quad", "paired", "half_turn", "maps_in_hbm"])
 def test_operators_with_depth_response(n, na, nb, arc, with_depth):
     plan = pget.Plan(n, na, nb, arc=arc)
     n_t, K = plan.n_samples, plan.psf_half_width
@@ -141,7 +143,7 @@ def test_batched_and_mixed_match_single_solves():
     """Slices of a batch and of a mixed-size call index the far planes of
     the per-ray sums by their own offsets: each equals its single-slice
     solve (same decisions replayed) to FP32 rounding of the launch shapes."""
-    shapes = [(24, 36, 36), (32, 48, 44)]
+    shapes = [(24, 36, 36), (32, 48, 44), (150, 16, 216)]   # the last: maps read from HBM
     plans, cases = {}, []
     for (n, na, nb) in shapes:
         plan = pget.Plan(n, na, nb)
