@@ -1576,10 +1576,12 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
     INST_JVP(true, JVP_PLAIN, S) INST_JVP(true, JVP_NORMAL, S) INST_JVP(true, JVP_SQNORM, S)  \
     INST_JVP(false, JVP_PLAIN, S) INST_JVP(false, JVP_NORMAL, S) INST_JVP(false, JVP_SQNORM, S) \
     template __global__ void k_vjp_lin<S, false>(VjpArgs);                                    \
-    template __global__ void k_vjp_lin<S, true>(VjpArgs);                                     \
     template __global__ void k_pack<S>(Geo, PairSrc, const double*, void*, long long, const LMState*);
 INST_ALL(F32S)
 INST_ALL(BF16S)
 INST_ALL(F32DR)
+// the quarter-turn fold; not with a depth response (one staged angle only)
+template __global__ void k_vjp_lin<F32S, true>(VjpArgs);
+template __global__ void k_vjp_lin<BF16S, true>(VjpArgs);
 
 }  // namespace pget
