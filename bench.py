@@ -548,9 +548,39 @@ def run_serve(args, torch, pget):
     print("bench: serve warm-up (graph capture per size and batch)", file=sys.stderr, flush=True)
     srv.warm()
     reqs = serve.make_trace(args.rate, args.duration, pool, seed=0)
+    # keep every request's result for the check against solves of the slice alone
+    outputs = {}
+    launch = ex.launch
+
+    def keep(size, rs, slot):
+        h = launch(size, rs, slot)
+        for i, r in enumerate(rs):
+            outputs[r.rid] = (h[1][0][i], h[1][1][i], h[1][2][i])
+        return h
+
+    ex.launch = keep
     print("bench: serving %d requests at %.0f/s" % (len(reqs), args.rate), file=sys.stderr, flush=True)
     st = serve.run_trace(srv, reqs)
     print("bench: served %s" % st, file=sys.stderr, flush=True)
+    import numpy as np
+    picks = np.random.default_rng([0, 7]).choice(len(reqs), size=min(16, len(reqs)), replace=False)
+    worst = [0.0, 0.0]
+    worst_same = [0.0, 0.0]   # over the requests whose decisions equal those of the solve alone
+    same = 0
+    for k in picks:
+        r = reqs[int(k)]
+        sl = pool[r.slot]
+        fa, ma, ra = plans[r.size].lm_solve(sl.y, sl.f0, sl.mu0, prm)
+        f, m, rb = outputs[r.rid]
+        e = (float(torch.linalg.norm(f - fa) / torch.linalg.norm(fa)),
+             float(torch.linalg.norm(m - ma) / torch.linalg.norm(ma)))
+        worst = [max(worst[0], e[0]), max(worst[1], e[1])]
+        if rb.to_report().accepted == ra.to_report().accepted:
+            same += 1
+            worst_same = [max(worst_same[0], e[0]), max(worst_same[1], e[1])]
+    print("bench: served vs alone, %d requests: max rel f %.2e mu %.2e; %d with the same decisions: "
+          "max rel f %.2e mu %.2e" % (len(picks), worst[0], worst[1], same, worst_same[0], worst_same[1]),
+          file=sys.stderr, flush=True)
     reqs2 = serve.make_trace(args.rate, args.duration, pool, seed=0)
     pl = serve.run_plain(plans, pool, prm, reqs2)
     print("bench: plain %s" % pl, file=sys.stderr, flush=True)
@@ -571,6 +601,9 @@ def run_serve(args, torch, pget):
         "peak_in_flight_gb": round(st["peak_in_flight_gb"], 3),
         "plain_per_slice": {"recon_per_s": round(pl["recon_per_s"], 4),
                             "p50_ms": round(pl["p50_ms"], 2), "p99_ms": round(pl["p99_ms"], 2)},
+        "check_vs_alone": {"requests": int(len(picks)), "max_rel_l2_f": float("%.3g" % worst[0]),
+                           "max_rel_l2_mu": float("%.3g" % worst[1]), "same_decisions": same,
+                           "same_decisions_max_rel_l2": [float("%.3g" % v) for v in worst_same]},
     }
     print(json.dumps(out), flush=True)
 
