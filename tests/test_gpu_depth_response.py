@@ -5,8 +5,9 @@ every sample with its own response:
 
 * the operators with and without the quarter-turn fold of the gather, over
   a half turn (no mirror pairing), with maps too large for LDS (read from
-  HBM), and together with the depth factor of the attenuation path
-  (relative L2 <= 1e-5, max-abs / max-ref <= 1e-4);
+  HBM) up to the largest map, and together with the depth factor of the
+  attenuation path (relative L2 <= 1e-5, 2e-5 above 256 px as for the plain
+  model; max-abs / max-ref <= 1e-4);
 * an LM trajectory of the full discrete model (depth factor and response)
   with the oracle's decisions replayed (objective per iterate 1e-4, maps
   1e-3, as for the plain model);
@@ -73,8 +74,9 @@ def phantom(n, seed, mu_rod=0.08):
 
 @pytest.mark.parametrize("with_depth", [False, True], ids=["response", "response_and_depth"])
 @pytest.mark.parametrize("n,na,nb,arc", [(64, 120, 96, 2 * np.pi), (48, 90, 70, 2 * np.pi),
-                                         (40, 45, 60, np.pi), (150, 24, 220, 2 * np.pi)],
-                         ids=["quad", "paired", "half_turn", "maps_in_hbm"])
+                                         (40, 45, 60, np.pi), (150, 24, 220, 2 * np.pi),
+                                         (512, 8, 730, 2 * np.pi)],
+                         ids=["quad", "paired", "half_turn", "maps_in_hbm", "max_size"])
 def test_operators_with_depth_response(n, na, nb, arc, with_depth):
     plan = pget.Plan(n, na, nb, arc=arc)
     n_t, K = plan.n_samples, plan.psf_half_width
@@ -97,7 +99,8 @@ def test_operators_with_depth_response(n, na, nb, arc, with_depth):
     gf_ref, gm_ref = O.vjp(og, f, mu, w)
     errs = (rel(y, y_ref), rel(jv, jv_ref), rel(H(gf), gf_ref), rel(H(gm), gm_ref))
     log("  forward %.2e jvp %.2e vjp f %.2e mu %.2e" % errs)
-    assert max(errs) <= 1e-5
+    # sample positions beyond ~256 px carry FP32 rounding of their coordinates
+    assert max(errs) <= (1e-5 if n <= 256 else 2e-5)
     assert maxrel(y, y_ref) <= 1e-4 and maxrel(jv, jv_ref) <= 1e-4
     assert maxrel(H(gf), gf_ref) <= 1e-4 and maxrel(H(gm), gm_ref) <= 1e-4
     # the response is in effect
