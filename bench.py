@@ -611,7 +611,7 @@ def run_serve(args, torch, pget):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+        print("bench.py measures one GPU only; --gpus %d is not supported "
               "(independent slices would shard across GPUs with no communication)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
