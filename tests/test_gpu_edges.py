@@ -126,3 +126,52 @@ def test_empty_and_mismatched_batches():
     # the C entry point itself rejects n_slices < 1 before touching any pointer
     rc = lib.pget_lm_solve_batched(plan.handle, 0, None, None, None, None, None, None, None)
     assert rc == -1
+
+
+@pytest.mark.parametrize("n,na,nb,sigma", [(2, 1, 1, 0.0), (2, 4, 4, 1.5), (3, 5, 1, 1.0), (16, 1, 24, 1.5),
+                                           (5, 7, 9, 0.0)],
+                         ids=["n2_a1_b1_nopsf", "n2_a4_b4", "n3_one_bin", "one_angle", "n5_nopsf"])
+def test_smallest_shapes(n, na, nb, sigma):
+    """The smallest map, one angle, one bin, and no collimator blur (one tap):
+    random positive maps and random directions against the oracle."""
+    og = O.Geometry(n, na, nb, psf_sigma=sigma)
+    plan = pget.Plan(n, na, nb, psf_sigma=sigma)
+    rng = np.random.default_rng(n * 100 + na)
+    f = rng.uniform(0.2, 1.0, (n, n))
+    mu = rng.uniform(0.0, 0.2, (n, n))
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal((na, nb))
+    log("case n=%d na=%d nb=%d sigma=%g" % (n, na, nb, sigma))
+    y, y_ref = H(plan.forward(T(f), T(mu))), O.forward(og, f, mu)
+    jv, jv_ref = H(plan.jvp(T(f), T(mu), T(vf), T(vm))), O.jvp(og, f, mu, vf, vm)
+    gf, gm = plan.vjp(T(f), T(mu), T(w))
+    gf_ref, gm_ref = O.vjp(og, f, mu, w)
+    errs = (rel(y, y_ref), rel(jv, jv_ref), rel(H(gf), gf_ref), rel(H(gm), gm_ref))
+    log("  forward %.2e jvp %.2e vjp f %.2e mu %.2e" % errs)
+    assert max(errs) <= 1e-5
+    assert maxrel(y, y_ref) <= 1e-4 and maxrel(jv, jv_ref) <= 1e-4
+
+
+def test_tiny_lm_replayed():
+    """A 4 x 4 slice, 8 angles, 6 bins: the whole solver on a problem smaller
+    than one tile of every kernel, decisions replayed from the oracle.  The
+    noise is 1 % of the data, so the final residual is about 1.3 % of ||y||
+    and Phi's relative error is the maps' FP32 differences (bound 1e-3 as
+    elsewhere) amplified by ||y|| / ||r||: Phi is held to 1e-3 here."""
+    from oracle import lm as OLM
+    n, na, nb = 4, 8, 6
+    og = O.Geometry(n, na, nb, psf_sigma=1.0)
+    rng = np.random.default_rng(3)
+    f_true = rng.uniform(0.5, 1.0, (n, n))
+    mu_true = rng.uniform(0.0, 0.1, (n, n))
+    y = O.forward(og, f_true, mu_true) * (1 + 0.01 * rng.standard_normal((na, nb)))
+    f0, mu0 = OLM.initial_guess(og, y)
+    p = OLM.LMParams(max_outer=5, n_cg=4)
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p)
+    plan = pget.Plan(n, na, nb, psf_sigma=1.0)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(max_outer=5, n_cg=4, replay=orep.accepted))
+    rep = rb.to_report()
+    assert rep.status == 0 and rep.accepted == orep.accepted
+    e = max(abs(a - b) / b for a, b in zip(rep.phi[:rep.iters_run + 1], orep.phi[:rep.iters_run + 1]))
+    log("tiny LM: phi %.1e f %.1e mu %.1e" % (e, rel(H(f), of), rel(H(mu), om)))
+    assert e <= 1e-3 and rel(H(f), of) <= 1e-3 and rel(H(mu), om) <= 1e-3
