@@ -312,3 +312,32 @@ def test_serving_results_equal_alone():
         fa, ma, _ = plans[r.size].lm_solve(sl.y, sl.f0, sl.mu0, prm)
         f, m = outputs[r.rid]
         assert rel(H(f), H(fa)) <= 1e-5 and rel(H(m), H(ma)) <= 1e-5
+
+
+@pytest.mark.parametrize("scaled", [False, True], ids=["plain", "scaled_active_set"])
+def test_checkpoint_and_resume(scaled):
+    """Snapshot and resume: after an accepted step the solver's state is the
+    iterate and the damping beta (Nielsen's nu is back at 2), so a solve
+    started from a snapshot (f, mu, beta_final as beta0) continues the
+    uninterrupted run exactly: same decisions, bitwise equal maps."""
+    _, y, f0, mu0, _, _ = problem(SMALL, seed=2)
+    opts = dict(w_mu=0.05 ** 2, d_mu=1 / 0.05 ** 2, active_set=1) if scaled else {}
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    total = 10
+    fa, ma, ra = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(max_outer=total, n_cg=6, **opts))
+    rep_a = ra.to_report()
+    assert rep_a.iters_run == total
+    # snapshot after the last accepted step among the first six iterations
+    k = max(i for i in range(6) if rep_a.accepted[i]) + 1
+    fs, ms, rs = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(max_outer=k, n_cg=6, **opts))
+    rep_s = rs.to_report()
+    assert rep_s.accepted == rep_a.accepted[:k]
+    # the checkpoint, kept on the host: FP32 maps and the damping
+    f_host, m_host, beta = fs.cpu(), ms.cpu(), rep_s.beta_final
+    fr, mr, rr = plan.lm_solve(T(y), f_host.cuda(), m_host.cuda(),
+                               pget.SolverParams(max_outer=total - k, n_cg=6, beta0=beta, **opts))
+    rep_r = rr.to_report()
+    log("resume after %d: decisions %s + %s vs %s" % (k, rep_s.accepted, rep_r.accepted, rep_a.accepted))
+    assert rep_s.accepted + rep_r.accepted == rep_a.accepted
+    assert abs(rep_r.phi[0] - rep_a.phi[k]) <= 1e-12 * rep_a.phi[k]
+    assert torch.equal(fr, fa) and torch.equal(mr, ma)
