@@ -36,6 +36,7 @@ class Request:
     admit: float = math.nan
     done: float = math.nan
     batch: int = 0
+    cancelled: bool = False
 
 
 @dataclass
@@ -147,6 +148,23 @@ class Server:
     def warm(self):
         self.ex.warm(self.batch_sizes)
 
+    def cancel(self, rid: int, now: float) -> int:
+        """Cancel request `rid`.  A queued request leaves the queue at once
+        (returns 1: it will not complete through poll); an admitted one runs
+        to the end of its batch's solve, which cannot be interrupted, and its
+        result is dropped (returns 0: poll still completes it).  Unknown or
+        finished requests are left alone (returns 0)."""
+        for r in self.queue:
+            if r.rid == rid:
+                self.queue.remove(r)
+                r.cancelled, r.done = True, now
+                return 1
+        for job in self.in_flight:
+            for r in job.reqs:
+                if r.rid == rid:
+                    r.cancelled = True
+        return 0
+
     def poll(self, now: float) -> int:
         done = 0
         still = []
@@ -229,10 +247,12 @@ def run_plain(plans, pool, params, reqs: List[Request], timeout: float = 600.0) 
 
 
 def summarize(reqs: List[Request], makespan: float, batches: List[int], peak_bytes: int) -> dict:
-    lat = np.array([r.done - r.arrival for r in reqs])
+    served = [r for r in reqs if not r.cancelled]
+    lat = np.array([r.done - r.arrival for r in served]) if served else np.zeros(1)
     return {
-        "requests": len(reqs),
-        "recon_per_s": len(reqs) / makespan,
+        "requests": len(served),
+        "cancelled": len(reqs) - len(served),
+        "recon_per_s": len(served) / makespan,
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_ms": float(lat.mean() * 1e3),

@@ -112,3 +112,30 @@ def test_trace_is_seeded():
     b = serve.make_trace(50.0, 2.0, pool, seed=3)
     assert [(r.arrival, r.size) for r in a] == [(r.arrival, r.size) for r in b]
     assert 60 <= len(a) <= 140
+
+
+def test_cancelled_requests():
+    """A queued request leaves at once and is never launched; an admitted one
+    finishes with its batch (a solve cannot be interrupted) and is left out of
+    the served statistics; unknown ids are ignored."""
+    ex = FakeExecutor({64: 0.01}, {64: 1})
+    srv = serve.Server(ex, hbm_budget=1e9, n_slots=1, max_batch=1)
+    reqs = [R(k, 0.0, 64) for k in range(4)]
+    for r in reqs:
+        srv.queue.append(r)
+    srv.admit(0.0)                       # request 0 is in flight, 1..3 queued
+    assert srv.cancel(2, 0.0) == 1       # queued: gone now
+    assert srv.cancel(0, 0.0) == 0       # in flight: completes through poll
+    assert srv.cancel(99, 0.0) == 0
+    done, t = 1, 0.0                     # request 2 counts as finished
+    while done < len(reqs):
+        t += 1e-3
+        ex.now = t
+        done += srv.poll(t)
+        srv.admit(t)
+        assert t < 10
+    launched = [rid for l in ex.launches for rid in l[2]]
+    assert launched == [0, 1, 3]
+    assert reqs[0].cancelled and reqs[2].cancelled and not reqs[1].cancelled
+    st = serve.summarize(reqs, t, srv.batches, 0)
+    assert st["requests"] == 2 and st["cancelled"] == 2
