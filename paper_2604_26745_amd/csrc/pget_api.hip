@@ -809,6 +809,7 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
 // ------------------------------------------------------------------ solver
 namespace {
 
+// Range checks of the solver parameters (the ranges pget.h states).
 bool params_ok(const pget_lm_params* p)
 {
     if (!p) return false;
@@ -822,6 +823,7 @@ bool params_ok(const pget_lm_params* p)
     return true;
 }
 
+// The per-slice parameters as the kernels read them.
 LMParamsDev to_dev(const pget_lm_params& p)
 {
     LMParamsDev d = {};
@@ -866,6 +868,10 @@ struct Solve {
     void* gimg;
 };
 
+// Argument blocks of every launch of a solve, pointing into its workspace:
+// the linearising and trial marches, the Jacobian products (CG normal
+// operator, ||J s||^2, ||J 1||^2), the two gathers (gradient and CG) and the
+// vector kernels.
 void setup(Solve& S)
 {
     const pget_plan* P = S.P;
@@ -1001,6 +1007,8 @@ void setup(Solve& S)
     V.rep = reinterpret_cast<ReportDev*>(at(ws, S.L.repdev));
 }
 
+// A ray march over every slice of the solve (through a bordered copy in HBM
+// when the map pair does not fit in LDS).
 void enqueue_march(Solve& S, const MarchArgs& A, int mode)
 {
     if (!S.P->lds_img) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream);
@@ -1008,6 +1016,7 @@ void enqueue_march(Solve& S, const MarchArgs& A, int mode)
     else march<MARCH_TRIAL>(S.P, A, S.sh.n_op_blocks, S.B, S.stream);
 }
 
+// A Jacobian product over every slice of the solve (the same fallback).
 void enqueue_jvp(Solve& S, const JvpArgs& A, int mode)
 {
     if (!S.P->jvp_lds) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream, true);
@@ -1023,6 +1032,12 @@ void enqueue_step_eval(Solve& S)
     enqueue_march(S, S.trial, MARCH_TRIAL);
 }
 
+// One outer LM iteration (Sec. 2.2): linearise at u (weights, Phi, the
+// blurred residual); at k = 0 the initial damping unless given; the gradient
+// g = J^T r + R u; n_cg CG steps on (J^T J + beta D + R) x = -g, each a
+// product K^T K J p, a gather and the q / x updates; the trial point
+// u' = clamp(u + x); the model decrease and Phi(u'); the decision (rho, beta).
+// Every decision is taken on the device.
 void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_present)
 {
     const dim3 ew(S.sh.n_ew_blocks, S.B);
@@ -1071,14 +1086,15 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
         Timed t_(PGET_KC_VECTOR, S.stream);
         hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vt);
     }
-    enqueue_jvp(S, S.jpred, JVP_SQNORM);
-    enqueue_march(S, S.trial, MARCH_TRIAL);
+    enqueue_step_eval(S);
     {
         Timed t_(PGET_KC_CONTROL, S.stream);
         hipLaunchKernelGGL(k_decide, dim3(S.B), dim3(256), 0, S.stream, S.V, hook_present ? 1 : 0);
     }
 }
 
+// Apply the iteration's decision: the trial point replaces u where it was
+// accepted, and every slice's state advances.
 void enqueue_commit(Solve& S)
 {
     const dim3 ew(S.sh.n_ew_blocks, S.B);
@@ -1126,6 +1142,7 @@ pget_status run_hook(Solve& S, pget_refine_fn hook, void* user)
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
 }
 
+// The device report arrays of one slice into the caller's report (on `s`).
 void copy_report(const ReportDev& R, const pget_lm_report* out, int max_outer, int n_cg, hipStream_t s)
 {
     if (!out) return;
@@ -1184,6 +1201,7 @@ struct StreamPool {
 } g_pool;
 
 
+// Workspace of B slices of one plan (report arrays for the largest solve).
 size_t group_bytes(const pget_plan* P, int B)
 {
     Shapes sh = shapes_for(P, B);
@@ -1350,6 +1368,7 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
 }
 
+// B slices of one plan in the same launches.
 pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* const* f,
                        float* const* mu, const pget_lm_params* params, const pget_lm_report* reports,
                        pget_refine_fn hook, void* hook_user, void* ws, hipStream_t stream)
@@ -1372,6 +1391,7 @@ pget_status solve_impl(const pget_plan* P, int B, const float* const* y, float* 
     return solve_groups(groups, hook, hook_user, ws, stream);
 }
 
+// Slices of several plans: one group per plan, on forked streams.
 pget_status solve_multi(int n, const pget_plan* const* plans, const float* const* y, float* const* f,
                         float* const* mu, const pget_lm_params* params, const pget_lm_report* reports,
                         void* ws, size_t ws_bytes, hipStream_t stream)

@@ -1010,7 +1010,6 @@ __global__ void __launch_bounds__(256) k_fill_zero(float4* p, long long n4)
         p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// Sum of the angle-group partial images (fixed order) into gf / gmu.
 // Sum over the angle groups of the gather's partial images at element m of
 // a slice (f block at m, mu block at n2 + m), in group order; the loads of
 // eight groups are issued before their adds so that they overlap.
@@ -1038,6 +1037,7 @@ __device__ __forceinline__ float2 sum_groups(const float* gp, long long group_st
     return make_float2(sf, sm);
 }
 
+// Sum of the angle-group partial images (fixed order) into gf / gmu.
 __global__ void __launch_bounds__(256) k_sum_groups(int n2, int groups, const float* gpart,
                                                     long long group_stride, float* gf, float* gm)
 {
@@ -1374,6 +1374,8 @@ __global__ void __launch_bounds__(256) k_beta0(VecArgs V)
     }
 }
 
+// Per-slice solver state at the start of a solve: beta from the parameters
+// (or left for k_beta0), nu = 2, k = 0, the iterate marked for linearising.
 __global__ void k_lm_init(LMState* st, const LMParamsDev* prm, int n_slices)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1515,8 +1517,8 @@ __global__ void k_commit(LMState* st, int n_slices)
     if (st[s].done_next) st[s].done = 1;
 }
 
-// Final report: Phi of the returned maps with the alphas of iteration
-// iters_run; one block per slice, plus the scalar fields.
+// Regulariser energy of the returned maps with the alphas of iteration
+// iters_run (partials for k_finish).
 __global__ void __launch_bounds__(EW_THREADS) k_final_reg(VecArgs V)
 {
     __shared__ double sh[16];
@@ -1546,6 +1548,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_final_reg(VecArgs V)
     if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_PHI_REG_U)[blockIdx.x] = s;
 }
 
+// Final report: Phi of the returned maps with the alphas of iteration
+// iters_run; one block per slice, plus the scalar fields.
 __global__ void __launch_bounds__(256) k_finish(VecArgs V)
 {
     __shared__ double sh[16];
