@@ -234,6 +234,50 @@ def traffic_from_profile(kernel: str, workload: str):
         return None
 
 
+def instrumented_roofline(pget, torch, run_step, max_outer, n_cg, units, workload):
+    """One more step with HIP events bracketing every launch of the heavy
+    kernel classes on the launch stream (direct launches: events are not
+    recorded inside a replayed graph), and the roofline object of the
+    dominant class: its algorithmic lane-operations per launch over its
+    average launch time, with the committed counter bytes of the workload
+    when they were taken from the current kernel sources."""
+    classes = (1 << pget.KC_VJP) | (1 << pget.KC_JVP) | (1 << pget.KC_MARCH) | \
+              (1 << pget.KC_VECTOR) | (1 << pget.KC_GRADIENT)
+    # timed launches per outer iteration: n_cg J^T, n_cg + 2 J, 2 n_cg + 6
+    # vector kernels, 2 marches and the gradient; room to spare
+    per_step = max_outer * (5 * n_cg + 24) + 16
+    pget.timing_enable(classes, per_step + 64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    run_step()
+    torch.cuda.synchronize()
+    instrumented_s = time.perf_counter() - t2
+    kt = {pget.KERNEL_CLASS_NAMES[c]: pget.timing_read(c) for c in
+          (pget.KC_VJP, pget.KC_JVP, pget.KC_MARCH, pget.KC_VECTOR, pget.KC_GRADIENT)}
+    pget.timing_enable(0, 0)
+    print("bench: instrumented step %.3f s; kernel ms (total, launches): %s" % (
+        instrumented_s, {k: (round(v[0], 2), v[1]) for k, v in kt.items()}), file=sys.stderr,
+        flush=True)
+    dom = max(kt, key=lambda k: kt[k][0])
+    tot_ms, launches = kt[dom]
+    avg_s = tot_ms / 1e3 / max(launches, 1)
+    achieved = LANE_OPS_PER_SAMPLE[dom] * units / avg_s / 1e12
+    kernel_name = {"vjp": "k_vjp_lin", "gradient": "k_vjp_lin", "jvp": "k_jvp_lin",
+                   "march": "k_march"}.get(dom, dom)
+    roofline = {
+        "bound": "alu", "kernel": kernel_name, "achieved": round(achieved, 3),
+        "peak": round(PEAK_VALU_TLANEOPS, 3), "unit": "Tlane-op/s", "frac": round(achieved / PEAK_VALU_TLANEOPS, 4),
+        "traffic": traffic_from_profile(kernel_name, workload),
+        "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+        "lane_ops_per_unit": LANE_OPS_PER_SAMPLE[dom], "units_per_launch": units,
+    }
+    if roofline["traffic"]:
+        # counter-measured HBM rate of the same launches (the weight stream)
+        roofline["hbm_gbs"] = round(roofline["traffic"] / avg_s / 1e9, 1)
+        roofline["hbm_frac"] = round(roofline["traffic"] / avg_s / 1e9 / PEAK_HBM_GBS, 4)
+    return roofline, kt, instrumented_s
+
+
 def run_mixed(args, torch, np, inputs, pget):
     """64 slices with grid sizes drawn from {64, 96, 128, 192, 256}^2, 360
     angles, 1.5x grid bins, 9x9 or 17x17 lattices, Poisson peak 10^U(3,5);
@@ -370,6 +414,9 @@ def run_scanner(args, torch, np, inputs, pget):
     el = time.perf_counter() - t0
     reps = [r.to_report() for r in rbs]
     assert all(r.status == 0 for r in reps)
+    wl = "%s_batch%d" % (cfg.name, B) + ("_full_model" if full else "")
+    roofline, _, _ = instrumented_roofline(pget, torch, lambda: plan.lm_solve_batched(ys, f0s, m0s, prm, sync=False),
+                                           cfg.max_outer, cfg.n_cg, plan.support_samples * B, wl)
     plain = None
     if full:
         # the same data and launch shapes reconstructed with the plain model
@@ -383,6 +430,9 @@ def run_scanner(args, torch, np, inputs, pget):
             fs0, ms0, _ = p0.lm_solve_batched(ys, f0s, m0s, prm, sync=False)
         torch.cuda.synchronize()
         plain = (time.perf_counter() - t1, fs0, ms0)
+        roofline0, _, _ = instrumented_roofline(pget, torch, lambda: p0.lm_solve_batched(ys, f0s, m0s, prm, sync=False),
+                                                cfg.max_outer, cfg.n_cg, p0.support_samples * B,
+                                                "%s_batch%d" % (cfg.name, B))
     mask = inputs.fov_mask(cfg)
     ef = [np.linalg.norm((f.cpu().numpy() - t[0])[mask]) / np.linalg.norm(t[0][mask]) for f, t in zip(fs, truth)]
     em = [np.linalg.norm((m.cpu().numpy() - t[1])[mask]) / np.linalg.norm(t[1][mask]) for m, t in zip(ms, truth)]
@@ -395,7 +445,7 @@ def run_scanner(args, torch, np, inputs, pget):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.storage == "fp32" else "bf16-storage/f32-compute",
         "data": "synthetic: 9x9 assemblies on a 1 mm grid, 2% Gaussian noise",
-        "config": {"workload": "%s_batch%d" % (cfg.name, B) + ("_full_model" if full else ""),
+        "config": {"workload": wl,
                    "outer": cfg.max_outer, "cg": cfg.n_cg,
                    "pixel_mm": cfg.pixel_mm, "bin_mm": cfg.bin_mm, "oversample": cfg.oversample,
                    "solver": dict({"name": args.solver, "prior_gamma": args.prior}, **opts),
@@ -405,6 +455,7 @@ def run_scanner(args, torch, np, inputs, pget):
                         [np.linalg.norm((f0.cpu().numpy() - t[0])[mask]) / np.linalg.norm(t[0][mask])
                          for f0, t in zip(f0s, truth)])), 4)},
     }
+    out["roofline"] = roofline
     if full:
         out["config"]["full_model"] = {"psf_sigma_far_bins": cfg.psf_sigma_far_bins,
                                        "depth_factor_far": cfg.depth_factor_far}
@@ -413,7 +464,7 @@ def run_scanner(args, torch, np, inputs, pget):
         em0 = [np.linalg.norm((m.cpu().numpy() - t[1])[mask]) / np.linalg.norm(t[1][mask]) for m, t in zip(ms0, truth)]
         out["plain_model"] = {"value": round(B * args.steps / el0, 4), "ms_per_step": round(1e3 * el0 / args.steps, 3),
                               "f_rel_err_fov": round(float(np.mean(ef0)), 4),
-                              "mu_rel_err_fov": round(float(np.mean(em0)), 4)}
+                              "mu_rel_err_fov": round(float(np.mean(em0)), 4), "roofline": roofline0}
     print(json.dumps(out), flush=True)
 
 
@@ -680,47 +731,10 @@ def main():
     assert all(r.status == 0 for r in reps), "solver reported a failure"
     print("bench: timed %.3f s (%d steps)" % (elapsed, args.steps), file=sys.stderr, flush=True)
 
-    # instrumented region: one more step with HIP events bracketing every
-    # launch of the heavy kernel classes on the launch stream (direct
-    # launches: events are not recorded inside a replayed graph)
-    classes = (1 << pget.KC_VJP) | (1 << pget.KC_JVP) | (1 << pget.KC_MARCH) | \
-              (1 << pget.KC_VECTOR) | (1 << pget.KC_GRADIENT)
-    # timed launches per outer iteration: n_cg J^T, n_cg + 2 J, 2 n_cg + 6
-    # vector kernels, 2 marches and the gradient; room to spare
-    per_step = cfg.max_outer * (5 * cfg.n_cg + 24) + 16
-    pget.timing_enable(classes, per_step + 64)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    plan.lm_solve_batched(ys, f0s, m0s, prm, sync=False)
-    torch.cuda.synchronize()
-    instrumented_s = time.perf_counter() - t2
-    kt = {pget.KERNEL_CLASS_NAMES[c]: pget.timing_read(c) for c in
-          (pget.KC_VJP, pget.KC_JVP, pget.KC_MARCH, pget.KC_VECTOR, pget.KC_GRADIENT)}
-    pget.timing_enable(0, 0)
-    print("bench: instrumented step %.3f s; kernel ms (total, launches): %s" % (
-        instrumented_s, {k: (round(v[0], 2), v[1]) for k, v in kt.items()}), file=sys.stderr,
-        flush=True)
-
-    # roofline of the dominant kernel class
-    dom = max(kt, key=lambda k: kt[k][0])
-    tot_ms, launches = kt[dom]
-    avg_s = tot_ms / 1e3 / max(launches, 1)
-    units = plan.support_samples * B
-    achieved = LANE_OPS_PER_SAMPLE[dom] * units / avg_s / 1e12
     workload = "%s_batch%d" % (cfg.name, B) + ("_bf16" if args.storage == "bf16" else "")
-    kernel_name = {"vjp": "k_vjp_lin", "gradient": "k_vjp_lin", "jvp": "k_jvp_lin",
-                   "march": "k_march"}.get(dom, dom)
-    roofline = {
-        "bound": "alu", "kernel": kernel_name, "achieved": round(achieved, 3),
-        "peak": round(PEAK_VALU_TLANEOPS, 3), "unit": "Tlane-op/s", "frac": round(achieved / PEAK_VALU_TLANEOPS, 4),
-        "traffic": traffic_from_profile(kernel_name, workload),
-        "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
-        "lane_ops_per_unit": LANE_OPS_PER_SAMPLE[dom], "units_per_launch": units,
-    }
-    if roofline["traffic"]:
-        # counter-measured HBM rate of the same launches (the weight stream)
-        roofline["hbm_gbs"] = round(roofline["traffic"] / avg_s / 1e9, 1)
-        roofline["hbm_frac"] = round(roofline["traffic"] / avg_s / 1e9 / PEAK_HBM_GBS, 4)
+    roofline, kt, instrumented_s = instrumented_roofline(
+        pget, torch, lambda: plan.lm_solve_batched(ys, f0s, m0s, prm, sync=False), cfg.max_outer, cfg.n_cg,
+        plan.support_samples * B, workload)
     # HBM GB/s of the projector (A, the ray march) and both Jacobian products:
     # committed counter bytes per launch over this run's average launch time
     kernel_gbs = {}
