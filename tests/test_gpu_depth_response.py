@@ -73,12 +73,13 @@ def phantom(n, seed, mu_rod=0.08):
 
 
 @pytest.mark.parametrize("with_depth", [False, True], ids=["response", "response_and_depth"])
-@pytest.mark.parametrize("n,na,nb,arc", [(64, 120, 96, 2 * np.pi), (48, 90, 70, 2 * np.pi),
-                                         (40, 45, 60, np.pi), (150, 24, 220, 2 * np.pi),
-                                         (512, 8, 730, 2 * np.pi)],
-                         ids=["quad", "paired", "half_turn", "maps_in_hbm", "max_size"])
-def test_operators_with_depth_response(n, na, nb, arc, with_depth):
-    plan = pget.Plan(n, na, nb, arc=arc)
+@pytest.mark.parametrize("n,na,nb,arc,bin_size,step", [
+    (64, 120, 96, 2 * np.pi, 1.0, 1.0), (48, 90, 70, 2 * np.pi, 1.0, 1.0), (40, 45, 60, np.pi, 1.0, 1.0),
+    (150, 24, 220, 2 * np.pi, 1.0, 1.0), (512, 8, 730, 2 * np.pi, 1.0, 1.0),
+    (60, 36, 46, 2 * np.pi, 2.0, 1.0), (48, 40, 70, 2 * np.pi, 1.0, 1.5)],
+    ids=["quad", "paired", "half_turn", "maps_in_hbm", "max_size", "bins_of_2px", "step_1p5"])
+def test_operators_with_depth_response(n, na, nb, arc, bin_size, step, with_depth):
+    plan = pget.Plan(n, na, nb, arc=arc, bin_size=bin_size, step=step)
     n_t, K = plan.n_samples, plan.psf_half_width
     _, far = inputs.collimator_depth_response(n_t, K, 3.0)
     al = jittered_alpha(n_t, 7)
@@ -86,13 +87,13 @@ def test_operators_with_depth_response(n, na, nb, arc, with_depth):
     if d is not None:
         plan.set_depth_factor(d)
     plan.set_depth_response(al, far)
-    og = O.Geometry(n, na, nb, arc=arc, depth=d, resp=al, far_taps=far)
+    og = O.Geometry(n, na, nb, arc=arc, bin_size=bin_size, step=step, depth=d, resp=al, far_taps=far)
     f, mu = phantom(n, 3)
     rng = np.random.default_rng(5)
     vf, vm = rng.standard_normal((2, n, n))
     vm *= 0.05
     w = rng.standard_normal((na, nb))
-    log("case n=%d na=%d nb=%d arc=%.3f depth=%s" % (n, na, nb, arc, with_depth))
+    log("case n=%d na=%d nb=%d arc=%.3f bin=%g step=%g depth=%s" % (n, na, nb, arc, bin_size, step, with_depth))
     y, y_ref = H(plan.forward(T(f), T(mu))), O.forward(og, f, mu)
     jv, jv_ref = H(plan.jvp(T(f), T(mu), T(vf), T(vm))), O.jvp(og, f, mu, vf, vm)
     gf, gm = plan.vjp(T(f), T(mu), T(w))
@@ -104,7 +105,7 @@ def test_operators_with_depth_response(n, na, nb, arc, with_depth):
     assert maxrel(y, y_ref) <= 1e-4 and maxrel(jv, jv_ref) <= 1e-4
     assert maxrel(H(gf), gf_ref) <= 1e-4 and maxrel(H(gm), gm_ref) <= 1e-4
     # the response is in effect
-    assert rel(y, O.forward(O.Geometry(n, na, nb, arc=arc, depth=d), f, mu)) > 1e-3
+    assert rel(y, O.forward(O.Geometry(n, na, nb, arc=arc, bin_size=bin_size, step=step, depth=d), f, mu)) > 1e-3
 
 
 def lattice_case():
