@@ -242,3 +242,45 @@ def test_bad_depth_response_rejected():
     f = torch.ones((16, 16), device="cuda")
     y = wide.forward(f, torch.zeros_like(f))
     assert torch.isfinite(y).all() and float(y.sum()) > 0
+
+
+def test_hook_with_full_model_matches_oracle():
+    """The learned step's safeguard under the full discrete model: a hook
+    that moves halfway from the LM trial point to the phantom, on the GPU and
+    in the oracle (same decisions replayed): the same proposals kept, and
+    m(0) - m(s~) and rho(s~) of every proposal within the tolerance of the
+    maps (the proposals follow the FP32 iterates)."""
+    cfg = lattice_case()
+    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins)
+    d, al, far = full_model(plan)
+    og = O.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, depth=d, resp=al, far_taps=far)
+    f_true, mu_true = inputs.rod_lattice(cfg, 0)
+    y = inputs.poisson_counts(O.forward(og, f_true, mu_true), cfg.peak_counts, 0)
+    f0, mu0 = OLM.initial_guess(og, y)
+    p = OLM.LMParams(max_outer=6, n_cg=6)
+
+    def blend_np(f, mu, sf, sm):
+        return (f + sf + 0.5 * (f_true - (f + sf)), mu + sm + 0.5 * (mu_true - (mu + sm)))
+
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p, hook=blend_np)
+    ft, mt = T(f_true), T(mu_true)
+
+    def blend(f, mu, sf, sm):
+        return (f + sf + 0.5 * (ft - (f + sf)), mu + sm + 0.5 * (mt - (mu + sm)))
+
+    plan.set_depth_factor(d)
+    plan.set_depth_response(al, far)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(max_outer=6, n_cg=6, replay=orep.accepted),
+                              hook=blend)
+    rep = rb.to_report()
+    log("hook kept %s (oracle %s); maps f %.1e mu %.1e" % (rep.hook_accepted, orep.hook_accepted,
+                                                          rel(H(f), of), rel(H(mu), om)))
+    assert rep.hook_accepted == orep.hook_accepted
+    assert rel(H(f), of) <= 1e-3 and rel(H(mu), om) <= 1e-3
+    assert np.array_equal(np.isnan(rep.hook_pred), np.isnan(orep.hook_pred))
+    for a, b in zip(rep.hook_pred, orep.hook_pred):
+        if not np.isnan(b):
+            assert abs(a - b) <= 1e-3 * abs(b)
+    for a, b in zip(rep.hook_rho, orep.hook_rho):
+        if not np.isnan(b) and np.isfinite(b):
+            assert abs(a - b) <= 1e-3 * max(1.0, abs(b))
