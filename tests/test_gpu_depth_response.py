@@ -284,3 +284,27 @@ def test_hook_with_full_model_matches_oracle():
     for a, b in zip(rep.hook_rho, orep.hook_rho):
         if not np.isnan(b) and np.isfinite(b):
             assert abs(a - b) <= 1e-3 * max(1.0, abs(b))
+
+
+def test_autotune_with_depth_response_keeps_results():
+    """The autotuner times the depth-response kernels within their own LDS
+    limit (three rows of sums per angle slot, alpha in LDS); the tuned shapes
+    change the summation order only."""
+    n, na, nb = 64, 120, 96
+    plan = pget.Plan(n, na, nb)
+    d, al, far = full_model(plan)
+    plan.set_depth_factor(d)
+    plan.set_depth_response(al, far)
+    og = O.Geometry(n, na, nb, depth=d, resp=al, far_taps=far)
+    f_true, mu_true = phantom(n, 5)
+    y = inputs.poisson_counts(O.forward(og, f_true, mu_true), 1e4, 5)
+    f0, mu0 = OLM.initial_guess(og, y)
+    prm = pget.SolverParams(max_outer=3, n_cg=5)
+    ys, f0s, m0s = [T(y)] * 4, [T(f0)] * 4, [T(mu0)] * 4
+    fa, ma, _ = plan.lm_solve_batched(ys, f0s, m0s, [prm] * 4)
+    shape = plan.autotune(4)
+    log("tuned shape with the depth response: %s" % shape)
+    assert shape["tuned"] and shape["jvp_angle_slots"] >= 1 and shape["vjp_angle_groups"] >= 1
+    fb, mb, _ = plan.lm_solve_batched(ys, f0s, m0s, [prm] * 4)
+    for k in range(4):
+        assert rel(H(fb[k]), H(fa[k])) <= 1e-5 and rel(H(mb[k]), H(ma[k])) <= 1e-5
