@@ -248,3 +248,27 @@ def test_prior_in_batch_equal_alone_and_checked():
         plan.lm_solve(ys[0], f0s[0], m0s[0], pget.SolverParams(prior_w=pa[0][:1], **base))
     with pytest.raises(ValueError):
         plan.lm_solve(ys[0], f0s[0], m0s[0], pget.SolverParams(prior_w=pa[0].double(), **base))
+
+
+def test_upper_bounds_with_replay():
+    """Box constraints with finite upper bounds that bind within the six
+    iterations (emission at 0.7 of the phantom's peak, attenuation at 0.004,
+    below what the unbounded solve reaches): the clamp and the active set act
+    at the upper bound too (8 and 25 pixels end on it in the oracle's run).
+    Decisions replayed from the oracle; tolerances as for the other
+    trajectories."""
+    og, y, f0, mu0 = problem(SMALL)
+    f_true, _ = inputs.rod_lattice(SMALL, 0)
+    f_hi, mu_hi = 0.7 * float(f_true.max()), 0.004
+    p = OLM.LMParams(max_outer=SMALL.max_outer, n_cg=SMALL.n_cg, w_mu=W_MU, active_set=True,
+                     f_hi=f_hi, mu_hi=mu_hi)
+    of, om, orep = OLM.lm_solve(og, y, f0, mu0, p)
+    assert (of == f_hi).sum() >= 4 and (om == mu_hi).sum() >= 4     # both upper bounds bind
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    f, mu, rb = plan.lm_solve(T(y), T(f0), T(mu0), pget.SolverParams(
+        max_outer=SMALL.max_outer, n_cg=SMALL.n_cg, w_mu=W_MU, active_set=1, f_hi=f_hi, mu_hi=mu_hi,
+        replay=orep.accepted))
+    rep = rb.to_report()
+    assert rep.status == 0
+    compare(rep, orep, f, mu, of, om)
+    assert float(f.max()) <= np.float32(f_hi) and float(mu.max()) <= np.float32(mu_hi)
