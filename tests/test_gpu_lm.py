@@ -341,3 +341,25 @@ def test_checkpoint_and_resume(scaled):
     assert rep_s.accepted + rep_r.accepted == rep_a.accepted
     assert abs(rep_r.phi[0] - rep_a.phi[k]) <= 1e-12 * rep_a.phi[k]
     assert torch.equal(fr, fa) and torch.equal(mr, ma)
+
+
+def test_nonfinite_slice_leaves_its_batch_unaffected():
+    """A NaN in one slice's starting map and an Inf in another's data: those
+    two slices stop with the non-finite status, while the healthy slice of
+    the same batch gives the result of its solve alone (to FP32 rounding of
+    the launch shapes, which depend on the batch size)."""
+    _, y, f0, mu0, _, _ = problem(SMALL, seed=0)
+    _, y2, f02, mu02, _, _ = problem(SMALL, seed=1)
+    plan = pget.Plan(SMALL.n, SMALL.n_angles, SMALL.n_bins)
+    prm = pget.SolverParams(max_outer=4, n_cg=5)
+    f_bad = f0.copy()
+    f_bad[5, 6] = np.nan
+    y_bad = y2.copy()
+    y_bad[2, 3] = np.inf
+    fs, ms, rbs = plan.lm_solve_batched([T(y2), T(y), T(y_bad)], [T(f02), T(f_bad), T(f02)],
+                                        [T(mu02), T(mu0), T(mu02)], [prm] * 3)
+    reps = [r.to_report() for r in rbs]
+    log("statuses %s" % [r.status for r in reps])
+    assert reps[0].status == 0 and reps[1].status == -4 and reps[2].status == -4
+    fa, ma, _ = plan.lm_solve_batched([T(y2)], [T(f02)], [T(mu02)], [prm])
+    assert rel(H(fs[0]), H(fa[0])) <= 1e-6 and rel(H(ms[0]), H(ma[0])) <= 1e-6
