@@ -308,3 +308,36 @@ def test_autotune_with_depth_response_keeps_results():
     fb, mb, _ = plan.lm_solve_batched(ys, f0s, m0s, [prm] * 4)
     for k in range(4):
         assert rel(H(fb[k]), H(fa[k])) <= 1e-5 and rel(H(mb[k]), H(ma[k])) <= 1e-5
+
+
+def test_graph_replay_with_full_model_matches_eager():
+    """The captured solver sequence of the full discrete model (the far
+    planes and the far prefix sums cleared by fill kernels, not memsets)
+    replayed several times with eager work in between gives the eager result
+    bit for bit, batched."""
+    cfg = lattice_case()
+    plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins)
+    d, al, far = full_model(plan)
+    plan.set_depth_factor(d)
+    plan.set_depth_response(al, far)
+    og = O.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, depth=d, resp=al, far_taps=far)
+    ys, f0s, m0s = [], [], []
+    for seed in range(3):
+        f_true, mu_true = inputs.rod_lattice(cfg, seed)
+        y = inputs.poisson_counts(O.forward(og, f_true, mu_true), cfg.peak_counts, seed)
+        f0, mu0 = OLM.initial_guess(og, y)
+        ys.append(T(y))
+        f0s.append(T(f0))
+        m0s.append(T(mu0))
+    prm = [pget.SolverParams(max_outer=4, n_cg=5, w_mu=0.05 ** 2, active_set=1)] * 3
+    pget.set_graphs(False)
+    try:
+        fe, me, _ = plan.lm_solve_batched(ys, f0s, m0s, prm)
+    finally:
+        pget.set_graphs(True)
+    for rep_i in range(3):
+        fg, mg, _ = plan.lm_solve_batched(ys, f0s, m0s, prm)
+        for k in range(3):
+            assert torch.equal(fg[k], fe[k]) and torch.equal(mg[k], me[k]), (rep_i, k)
+        plan.forward(f0s[0], m0s[0])
+        torch.cuda.synchronize()
