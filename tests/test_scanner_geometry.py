@@ -131,3 +131,29 @@ def test_lattice_rod_prior_holds():
         f, mu = inputs.rod_lattice(cfg, seed)
         assert f[out > 0].max() == 0.0
         assert np.abs(mu - ref_mu)[out > 0].max() <= 1e-12
+
+
+def test_full_model_tables():
+    """The full discrete model's per-sample tables for the scanner plans:
+    alpha linear from 1 (sample 0, farthest from the detector) to 0, the
+    vertical correction 1 + 0.05 alpha, the far taps a normalised symmetric
+    Gaussian of 2 bins over the taps the full-model plan uses."""
+    import math
+    import numpy as np
+    from paper_2604_26745_amd import inputs
+    cfg = inputs.SCANNER_165
+    for o in (1, cfg.oversample):
+        d = inputs.scanner_geometry(cfg, o, full_model=True)
+        K = d["psf_radius"]
+        assert K == math.ceil(3 * cfg.psf_sigma_far_bins)
+        n_t = 2 * math.ceil(d["n"] / math.sqrt(2.0) + 1.0)
+        depth, alpha, far = inputs.scanner_full_model(cfg, n_t)
+        a = np.array(alpha)
+        assert len(alpha) == len(depth) == n_t and len(far) == 2 * K + 1
+        assert a[0] == 1.0 and a[-1] == 0.0 and np.allclose(np.diff(a), -1.0 / (n_t - 1))
+        assert np.allclose(depth, 1.0 + (cfg.depth_factor_far - 1.0) * a)
+        t = np.array(far)
+        assert abs(t.sum() - 1.0) < 1e-12 and np.array_equal(t, t[::-1])
+        k = np.arange(-K, K + 1)
+        var = float((k ** 2 * t).sum())
+        assert 0.8 * cfg.psf_sigma_far_bins ** 2 < var < cfg.psf_sigma_far_bins ** 2
