@@ -341,3 +341,28 @@ def test_graph_replay_with_full_model_matches_eager():
             assert torch.equal(fg[k], fe[k]) and torch.equal(mg[k], me[k]), (rep_i, k)
         plan.forward(f0s[0], m0s[0])
         torch.cuda.synchronize()
+
+
+def test_single_tap_response_is_a_depth_gain():
+    """Without a blur (one tap) the response is a gain per sample,
+    (1 - alpha_i) + alpha_i * far: here 1 at the detector side falling to 0.5
+    at the far side.  Operators against the oracle."""
+    n, na, nb = 32, 40, 48
+    plan = pget.Plan(n, na, nb, psf_sigma=0.0)
+    assert plan.psf_half_width == 0
+    n_t = plan.n_samples
+    al = tuple(1.0 - i / (n_t - 1) for i in range(n_t))
+    plan.set_depth_response(al, (0.5,))
+    og = O.Geometry(n, na, nb, psf_sigma=0.0, resp=al, far_taps=(0.5,))
+    f, mu = phantom(n, 6)
+    rng = np.random.default_rng(8)
+    vf, vm = rng.standard_normal((2, n, n))
+    w = rng.standard_normal((na, nb))
+    y, y_ref = H(plan.forward(T(f), T(mu))), O.forward(og, f, mu)
+    jv, jv_ref = H(plan.jvp(T(f), T(mu), T(vf), T(vm))), O.jvp(og, f, mu, vf, vm)
+    gf, gm = plan.vjp(T(f), T(mu), T(w))
+    gf_ref, gm_ref = O.vjp(og, f, mu, w)
+    errs = (rel(y, y_ref), rel(jv, jv_ref), rel(H(gf), gf_ref), rel(H(gm), gm_ref))
+    log("one tap: forward %.2e jvp %.2e vjp f %.2e mu %.2e" % errs)
+    assert max(errs) <= 1e-5
+    assert rel(y, O.forward(O.Geometry(n, na, nb, psf_sigma=0.0), f, mu)) > 1e-2
