@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=64, help="slices reconstructed per step")
+    ap.add_argument("--grid", type=int, default=128, choices=[64, 128, 256],
+                    help="main workload: 64 (9x9 lattice, 120 x 96; C1 uses --cg 20), 128 (9x9 lattice, "
+                         "360 x 192) or 256 (17x17 lattice, 360 x 256)")
     ap.add_argument("--outer", type=int, default=15)
     ap.add_argument("--prior", type=float, default=0.0,
                     help="geometry prior weight gamma (main and scanner workloads): gamma on "
@@ -693,7 +696,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cfg = inputs.scaled(inputs.MAIN_128, max_outer=args.outer, n_cg=args.cg)
+    base = {64: inputs.SMALL_64, 128: inputs.MAIN_128, 256: inputs.LARGE_256}[args.grid]
+    cfg = inputs.scaled(base, max_outer=args.outer, n_cg=args.cg)
     plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, storage=args.storage)
     B = args.batch
     if args.autotune:
@@ -785,7 +789,7 @@ def main():
         cpu = cpu_baseline(cfg, workers)
 
     out = {
-        "metric": "LM reconstructions/s at 128^2 x 360 angles (%s)" % args.storage.upper(),
+        "metric": "LM reconstructions/s at %d^2 x %d angles (%s)" % (cfg.n, cfg.n_angles, args.storage.upper()),
         "value": round(value, 4),
         "unit": "reconstructions/s",
         "n_gpus": 1,
@@ -805,7 +809,8 @@ def main():
             "grid": cfg.n, "angles": cfg.n_angles, "bins": cfg.n_bins, "psf_sigma": cfg.psf_sigma,
             "outer": cfg.max_outer, "cg": cfg.n_cg, "alpha": cfg.alpha,
             "solver": dict({"name": args.solver, "prior_gamma": args.prior}, **SOLVER_OPTIONS[args.solver]),
-            "phantom": "9x9 rod lattice, r=4 px, pitch 12 px, 5 empty rods, Poisson peak 1e4",
+            "phantom": "%dx%d rod lattice, r=%g px, pitch %g px, %d empty rods, Poisson peak %g" % (
+                cfg.n_rods, cfg.n_rods, cfg.rod_radius, cfg.pitch, cfg.n_empty, cfg.peak_counts),
         },
         "quality": dict(quality(fs, ms, cfg, inputs, np),
                         start=quality(f0s, m0s, cfg, inputs, np)),
