@@ -39,12 +39,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# FP32 work per in-support lattice sample of one operator pass (algorithmic
-# count, see the measurement section of the design notes): the adjoint
-# spreads two coefficients to the four bilinear neighbours (28 FLOP), the
-# linearised Jacobian product gathers two fields from four neighbours and
-# weights them (26 FLOP), the ray march adds the attenuation sums and one exp
-# (30 FLOP).
 # Algorithmic VALU work of one operator pass per in-support sample of the
 # rotated lattice (the method's arithmetic: bilinear taps, the attenuation
 # exponential, the per-ray sums and the tent gather), in lane-operations.
@@ -186,12 +180,25 @@ def cpu_baseline(cfg, workers: int):
     per_recon = K * (2 * t_fwd + (M + 1) * t_jvp + (M + 1) * t_vjp) + t_jvp
     return {
         "value": workers / per_recon, "unit": "reconstructions/s", "cores": workers,
-        "kind": "oracle",
+        "kind": "oracle", "cpu_model": cpu_model(),
         "sample": ("FP64 C oracle, one forward + one J v + one J^T w per worker at %dx%d, %d angles, "
                    "%d bins (%.1f s wall on %d workers), scaled to %d x (%d CG) passes per "
                    "reconstruction: %.1f s per reconstruction per core"
                    % (cfg.n, cfg.n, cfg.n_angles, cfg.n_bins, wall, workers, K, M, per_recon)),
     }
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def _oracle_sample(arg):

@@ -296,7 +296,10 @@ pget_status pget_lm_solve(const pget_plan* plan, const float* y, float* f_inout,
  * together (every kernel launch covers all slices).  y, f_inout, mu_inout
  * are arrays of n_slices device pointers (host arrays of pointers);
  * params and reports are arrays of n_slices entries (reports may be NULL).
- * Each slice's result is the one pget_lm_solve gives for it alone.
+ * Each slice's result is the one pget_lm_solve gives for it alone, bit for
+ * bit: every order of additions (per-angle partials of the squared norms,
+ * fixed-order sums of partials, the adjoint's fine angle groups) depends on
+ * the plan only, never on the batch.
  * ws: PGET_OP_LM with batch n_slices.
  */
 pget_status pget_lm_solve_batched(const pget_plan* plan, int32_t n_slices, const float* const* y,
@@ -343,7 +346,8 @@ pget_status pget_set_graphs(int32_t enable);
  * on).  Arguments as for pget_lm_solve_batched, per slice; within a group all
  * slices must share max_outer and n_cg.  ws must hold
  * pget_workspace_bytes_multi(n_slices, plans) bytes; ws_bytes is its size.
- * Each slice's result is the one pget_lm_solve gives for it alone.
+ * Each slice's result is the one pget_lm_solve gives for it alone, bit for
+ * bit (as for pget_lm_solve_batched).
  */
 size_t pget_workspace_bytes_multi(int32_t n_slices, const pget_plan* const* plans);
 pget_status pget_lm_solve_multi(int32_t n_slices, const pget_plan* const* plans, const float* const* y,
@@ -354,16 +358,16 @@ pget_status pget_lm_solve_multi(int32_t n_slices, const pget_plan* const* plans,
 /*
  * Autotuner of launch shapes: times the candidate shapes of the Jacobian
  * product (angle slots per block: 1, 2, 4, ...) and of the adjoint gather
- * (angle groups split across blocks: 1, 2, 4, ...) for `batch` slices of this
- * plan's shape on zero-filled data, and keeps the fastest pair in the plan
- * for later solves of that batch size.  ws: at least
- * pget_workspace_bytes(plan, PGET_OP_LM, batch) bytes (its contents are
- * overwritten).  Synchronises `stream`.  The Jacobian product's shape does
- * not change any result bit; the adjoint's angle grouping changes the order in
- * which per-angle contributions are added (rounding-level differences between
- * shapes); a given shape is bitwise reproducible.
- * pget_tuned_shape reports the shape a solve of `batch` slices will use and
- * returns 1 if it came from the autotuner, 0 if from the default heuristic.
+ * (blocks per pixel tile, each running a run of the plan's fine angle
+ * groups) for `batch` slices of this plan's shape on zero-filled data, and
+ * keeps the fastest pair in the plan for later solves of that batch size.
+ * ws: at least pget_workspace_bytes(plan, PGET_OP_LM, batch) bytes (its
+ * contents are overwritten).  Synchronises `stream`.  No shape changes any
+ * result bit: the fine angle groups, whose partial images are added in
+ * order, are fixed by the plan.
+ * pget_tuned_shape reports the shape a solve of `batch` slices will use
+ * (vjp_groups: gather blocks per tile and slice) and returns 1 if it came
+ * from the autotuner, 0 if from the default heuristic.
  */
 pget_status pget_autotune(pget_plan* plan, int32_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
 int32_t pget_tuned_shape(const pget_plan* plan, int32_t batch, int32_t* japb, int32_t* vjp_groups);

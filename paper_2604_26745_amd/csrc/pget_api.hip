@@ -52,8 +52,14 @@ struct GraphKey {
 struct GraphEntry {
     GraphKey key;
     hipGraphExec_t exec;
+    unsigned long long used;   // last replay (a counter), for eviction
 };
 static std::vector<GraphEntry> g_graphs;
+static unsigned long long g_graph_clock = 0;
+// Executable graphs kept at once; the least recently replayed one is
+// destroyed to make room (a caller that passes a fresh workspace per solve
+// pays a capture per call but no growing set of graphs).
+constexpr size_t GRAPH_CACHE = 32;
 
 namespace {
 
@@ -108,8 +114,14 @@ struct Shapes {
     int n_jvp_blocks; // blocks per slice of k_jvp_lin
     int jvp_threads;
     size_t jvp_lds;
-    int groups;       // angle groups of the adjoint gather
-    int gcap;         // angle groups the partial-image buffers hold
+    int groups;       // blocks per tile and slice of the adjoint gather
+    int fine;         // fine angle groups of the gather (plan only)
+    int spf;          // angle slots per fine group
+    int gs;           // fine groups per super group (plan only)
+    int fpb;          // fine groups per gather block: 1 or a multiple of gs
+    int super_out;    // the gather writes super-group partials (else fine ones)
+    int n_part;       // partial images per slice the gather writes
+    int gfold;        // partials per super group in the consumer's sum
     int n_vjp_blocks; // blocks per slice of k_vjp_lin
     int n_ew_blocks;  // blocks per slice of the element-wise kernels
 };
@@ -121,6 +133,69 @@ int vjp_slots(const pget_plan* P)
 {
     const Geo& g = P->g;
     return (g.quad && !P->t.resp) ? g.n_angles / 4 : g.paired ? g.n_angles / 2 : g.n_angles;
+}
+
+// Angle groups of the adjoint gather.  The angle slots are cut into fine
+// groups of spf consecutive slots (about FINE_GROUPS of them), and runs of gs
+// fine groups form super groups.  A pixel's value is the sum of its slots in
+// order within a fine group, of the fine groups in order within a super
+// group, and of the super groups in order: fine and super groups depend on
+// the plan alone, so a slice gets the same bits alone, in a batch or in a
+// mixed call.  A launch either runs one fine group per block (small batches:
+// many blocks) and leaves the folds to the consumer, or whole super groups
+// per block (large batches: few partial images).
+constexpr int FINE_GROUPS = 32;
+constexpr int REF_BATCH = 64;   // the batch the super-group size is chosen for
+
+// Launch rounds times the work of one block (its angle slots plus about one
+// slot of fixed cost), counted against the resident gather blocks.
+double gather_cost(const pget_plan* P, int batch, int fine, int spf, int fpb)
+{
+    const long long resident =
+        (long long)P->n_cu * std::max(1, P->t.resp ? P->vjp_resident_dr : P->vjp_resident);
+    const int c = (fine + fpb - 1) / fpb;
+    const long long blocks = (long long)P->tiles_x * P->tiles_x * batch * c;
+    const double rounds = (double)((blocks + resident - 1) / resident);
+    return rounds * ((double)(std::min(fpb, fine) * spf) + 1.0);
+}
+
+void fine_groups(const pget_plan* P, int& fine, int& spf, int& gs)
+{
+    const int vslots = vjp_slots(P);
+    spf = std::max(1, (vslots + FINE_GROUPS - 1) / FINE_GROUPS);
+    fine = std::max(1, (vslots + spf - 1) / spf);
+    gs = 1;
+    double best = 1e30;
+    for (int f = 1; f <= fine; ++f) {
+        const double cost = gather_cost(P, REF_BATCH, fine, spf, f);
+        if (cost < best * (1.0 - 1e-9)) { best = cost; gs = f; }
+    }
+}
+
+// Gather blocks per tile and slice that run `fpb` fine groups each.
+inline int coarse_of(int fine, int fpb) { return (fine + fpb - 1) / fpb; }
+
+// Candidate fine groups per block: 1, or whole super groups.
+std::vector<int> fpb_candidates(int fine, int gs)
+{
+    std::vector<int> c{1};
+    for (int f = gs; f < fine + gs; f += gs)
+        if (f > 1) c.push_back(f);
+    return c;
+}
+
+// The gather's block count and output layout for `fpb` fine groups per block.
+void set_fpb(Shapes& s, int fpb)
+{
+    // blocks never straddle a super group: whole super groups (or all fine
+    // groups in one block), else one fine group each
+    s.fpb = std::max(1, std::min(fpb, s.fine));
+    const bool whole = s.fpb % s.gs == 0 || s.fpb == s.fine;
+    if (!whole) s.fpb = 1;
+    s.groups = coarse_of(s.fine, s.fpb);
+    s.super_out = (s.fpb % s.gs == 0 || s.fpb == s.fine) ? 1 : 0;
+    s.n_part = s.super_out ? coarse_of(s.fine, s.gs) : s.fine;
+    s.gfold = s.super_out ? 1 : s.gs;
 }
 
 Shapes shapes_for(const pget_plan* P, int batch)
@@ -138,33 +213,28 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
     s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
     s.jvp_lds = jvp_lds_for(P, s.japb);
-    // angle groups of the gather: the fewest launch rounds times the work of
-    // one block (its angle slots plus about one slot of fixed cost), counted
-    // against the resident blocks.  Small batches may split the angles finely
-    // to fill the chip; the partial-image buffers hold gcap groups.
+    // blocks of the gather: the fewest launch rounds times the work of one
+    // block (its angle slots plus about one slot of fixed cost), counted
+    // against the resident blocks.  Small batches run one fine group per
+    // block to fill the chip.
     const int tiles = P->tiles_x * P->tiles_x;
-    const int vslots = vjp_slots(P);
-    s.gcap = std::min(vslots, batch >= 16 ? 8 : 32);
-    const long long resident = (long long)cus * std::max(1, P->t.resp ? P->vjp_resident_dr : P->vjp_resident);
-    int g = 1;
+    fine_groups(P, s.fine, s.spf, s.gs);
+    int fpb = 1;
     double best = 1e30;
-    for (int c = 1; c <= s.gcap; ++c) {
-        const long long blocks = (long long)tiles * batch * c;
-        const double rounds = (double)((blocks + resident - 1) / resident);
-        const double cost = rounds * ((double)((vslots + c - 1) / c) + 1.0);
-        if (cost < best * (1.0 - 1e-9)) { best = cost; g = c; }
+    for (int f : fpb_candidates(s.fine, s.gs)) {
+        const double cost = gather_cost(P, batch, s.fine, s.spf, f);
+        if (cost < best * (1.0 - 1e-9)) { best = cost; fpb = f; }
     }
-    s.groups = g;
     for (const auto& t : P->tuned)
         if (t[0] == batch) {
             s.japb = std::max(1, std::min(max_japb_of(P), t[1]));
             s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
             s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
             s.jvp_lds = jvp_lds_for(P, s.japb);
-            g = std::max(1, std::min(t[2], s.gcap));
+            fpb = t[2];
         }
-    s.groups = g;
-    s.n_vjp_blocks = tiles * g;
+    set_fpb(s, fpb);
+    s.n_vjp_blocks = tiles * s.groups;
     s.n_ew_blocks = (P->g.n * P->g.n + EW_THREADS - 1) / EW_THREADS;
     return s;
 }
@@ -201,9 +271,9 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
     L.sino_b = take(planes * B * sino * sizeof(float));
     L.gimg = (P->lds_img && P->jvp_lds) ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
     L.part = take(B * (size_t)N_SLOTS * SLOT_WIDTH * sizeof(double));
-    if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.gcap * B * 2 * n2 * sizeof(float));
+    if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.fine * B * 2 * n2 * sizeof(float));
     if (op == PGET_OP_LM) {
-        L.gpart_grad = take((size_t)sh.gcap * B * 2 * n2 * sizeof(float));
+        L.gpart_grad = take((size_t)sh.fine * B * 2 * n2 * sizeof(float));
         L.ymeas = take(B * sino * sizeof(float));
         L.u = take(B * 2 * n2 * sizeof(float));
         L.ut = take(B * 2 * n2 * sizeof(float));
@@ -341,6 +411,17 @@ void fill_zero(void* p, size_t bytes, hipStream_t s)
         Timed t_(PGET_KC_CONTROL, s);
         hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, reinterpret_cast<float4*>(p), n4);
     }
+}
+
+// Block and group counts of a gather launch.
+void set_groups(VjpArgs& V, const Shapes& sh)
+{
+    V.groups = sh.groups;
+    V.fine = sh.fine;
+    V.spf = sh.spf;
+    V.fpb = sh.fpb;
+    V.gs = sh.gs;
+    V.super_out = sh.super_out;
 }
 
 PairSrc planar_src(const float* f, const float* mu, long long stride)
@@ -791,7 +872,7 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     V.gpart_group_stride = 2 * n2;
     V.gpart_slice_stride = 0;
     V.tiles_x = P->tiles_x;
-    V.groups = sh.groups;
+    set_groups(V, sh);
     {
         Timed t_(PGET_KC_VJP, stream);
         launch_vjp(P, V, 1, stream);
@@ -799,7 +880,7 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     {
         Timed t_(PGET_KC_VECTOR, stream);
         hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, stream, (int)n2,
-                           sh.groups, V.gpart, (long long)V.gpart_group_stride, gf, gmu);
+                           sh.n_part, sh.gfold, V.gpart, (long long)V.gpart_group_stride, gf, gmu);
     }
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
 }
@@ -973,7 +1054,7 @@ void setup(Solve& S)
     VG.gpart_group_stride = (long long)S.B * 2 * n2;
     VG.gpart_slice_stride = 2 * n2;
     VG.tiles_x = P->tiles_x;
-    VG.groups = S.sh.groups;
+    set_groups(VG, S.sh);
     VG.st = st;
     VG.skip_if_clean = 1;
     S.vcg = VG;
@@ -997,11 +1078,11 @@ void setup(Solve& S)
     V.gpart = S.vcg.gpart;
     V.gpart_group_stride = S.vcg.gpart_group_stride;
     V.gpart_slice_stride = S.vcg.gpart_slice_stride;
-    V.groups = S.sh.groups;
+    V.groups = S.sh.n_part;
+    V.gfold = S.sh.gfold;
     V.part = part;
-    V.n_jvp_blocks = S.sh.n_jvp_blocks;
     V.n_ew_blocks = S.sh.n_ew_blocks;
-    V.n_march_blocks = S.sh.n_op_blocks;
+    V.n_angle_parts = g.n_angles;
     V.st = st;
     V.prm = reinterpret_cast<LMParamsDev*>(at(ws, S.L.params));
     V.rep = reinterpret_cast<ReportDev*>(at(ws, S.L.repdev));
@@ -1337,9 +1418,23 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
             key.groups.push_back({(long long)(intptr_t)G.S.P, G.S.B, G.max_outer, G.n_cg, (long long)G.need_beta0,
                                   (long long)((char*)G.S.ws - (char*)ws)});
         hipGraphExec_t exec = nullptr;
+        ++g_graph_clock;
         for (auto& e : g_graphs)
-            if (e.key == key) exec = e.exec;
+            if (e.key == key) {
+                exec = e.exec;
+                e.used = g_graph_clock;
+            }
         if (!exec) {
+            if (g_graphs.size() >= GRAPH_CACHE) {
+                // earlier replays of the evicted graph may still run on
+                // some stream: wait for the device before destroying it
+                HIP_TRY(hipDeviceSynchronize());
+                size_t lru = 0;
+                for (size_t k = 1; k < g_graphs.size(); ++k)
+                    if (g_graphs[k].used < g_graphs[lru].used) lru = k;
+                (void)hipGraphExecDestroy(g_graphs[lru].exec);
+                g_graphs.erase(g_graphs.begin() + lru);
+            }
             hipStream_t cs = g_pool.get(0);
             if (!cs) return PGET_ERR_HIP;
             hipGraph_t graph = nullptr;
@@ -1351,7 +1446,7 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
             hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) return PGET_ERR_HIP;
-            g_graphs.push_back(GraphEntry{key, exec});
+            g_graphs.push_back(GraphEntry{key, exec, g_graph_clock});
         }
         HIP_TRY(hipGraphLaunch(exec, stream));
     }
@@ -1547,15 +1642,17 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
         });
         if (t < best_j) { best_j = t; best_japb = japb; }
     }
-    // the adjoint's partial images live in a buffer sized for S.sh.gcap
-    for (int grp = 1; grp <= S.sh.gcap; ++grp) {
+    // the partial-image buffers hold the fine groups, the most any layout writes
+    for (int fpb : fpb_candidates(S.sh.fine, S.sh.gs)) {
+        Shapes sh = S.sh;
+        set_fpb(sh, fpb);
         VjpArgs V = S.vcg;
         V.st = nullptr;
-        V.groups = grp;
+        set_groups(V, sh);
         const float t = time_it([&] {
             launch_vjp(P, V, batch, stream);
         });
-        if (t < best_v) { best_v = t; best_groups = grp; }
+        if (t < best_v) { best_v = t; best_groups = sh.fpb; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

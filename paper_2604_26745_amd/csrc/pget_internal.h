@@ -197,10 +197,16 @@ struct VjpArgs {
     const float* wq;        // depth response: R' of the far response per sample
     long long far_off;      // depth response: far plane of tsum and wt
     long long wts_stride, sino_stride;
-    float* gpart;           // [groups][slices][2][N][N]
+    float* gpart;           // [fine][slices][2][N][N]
     long long gpart_group_stride, gpart_slice_stride;
     int tiles_x;            // ceil(N / VT)
-    int groups;             // angle groups
+    int groups;             // blocks per tile and slice, each running fpb fine groups
+    int fine;               // fine angle groups (fixed by the plan)
+    int spf;                // angle slots per fine group
+    int fpb;                // fine groups per block: fine <= groups * fpb
+    int gs;                 // fine groups per super group (fixed by the plan)
+    int super_out;          // 1: a block sums whole super groups and writes one partial
+                            // image per super group (fpb a multiple of gs); 0: one per fine group
     const LMState* st;
     int skip_if_clean;
 };
@@ -217,13 +223,13 @@ struct VecArgs {
     float* q;               // (J^T J + beta D + R) p
     float* grad;            // gradient g
     uint8_t* fmask;         // 1 where a variable is free (active set on)
-    const float* gpart;     // angle-group partials of the adjoint
+    const float* gpart;     // group partials of the adjoint
     long long gpart_group_stride, gpart_slice_stride;
-    int groups;
+    int groups;             // partial images (fine or super groups), summed in order
+    int gfold;              // partials per super group: gs for fine partials, 1 for super ones
     double* part;
-    int n_jvp_blocks;       // partials of SLOT_JS / J1 / PHI_DATA_*
     int n_ew_blocks;        // partials of element-wise slots
-    int n_march_blocks;
+    int n_angle_parts;      // partials of SLOT_JS / J1 / PHI_DATA_* (one per angle)
     LMState* st;
     const LMParamsDev* prm;
     ReportDev* rep;
@@ -245,8 +251,8 @@ __global__ void k_pack(Geo g, PairSrc s, const double* part, void* out, long lon
 __global__ void k_psf(Geo g, const float* taps_g, const float* in, float* out);
 template <typename S, bool QUAD> __global__ void k_vjp_lin(VjpArgs A);
 __global__ void k_fill_zero(float4* p, long long n4);
-__global__ void k_sum_groups(int n2, int groups, const float* gpart, long long group_stride, float* gf,
-                             float* gm);
+__global__ void k_sum_groups(int n2, int groups, int gfold, const float* gpart, long long group_stride,
+                             float* gf, float* gm);
 __global__ void k_grad_init(VecArgs V);
 __global__ void k_cg_q(VecArgs V);
 __global__ void k_cg_x(VecArgs V);

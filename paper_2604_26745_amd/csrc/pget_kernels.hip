@@ -91,13 +91,21 @@ __device__ double block_sum(double v, double* sh)
     return s;
 }
 
-// Sum of n partials (one per producing block) in fixed order; every thread
-// of the block gets the result.
+// Sum of n partials (one per producing block or angle); every thread of the
+// block gets the result.  The first wave adds them (lane l takes l, l + 64,
+// ..., then a fixed butterfly), so the order does not depend on the size of
+// the consuming block.
 __device__ double sum_partials(const double* p, int n, double* sh)
 {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
-    return block_sum(v, sh);
+    __syncthreads();   // sh may still be read by an earlier call
+    if (threadIdx.x < WAVE) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < n; i += WAVE) v += p[i];
+        v = wave_sum(v);
+        if (threadIdx.x == 0) sh[0] = v;
+    }
+    __syncthreads();
+    return sh[0];
 }
 
 __device__ __forceinline__ double* slot_ptr(double* part, int slice, int slot)
@@ -268,7 +276,6 @@ template <bool LDS_IMG, int MODE, typename S>
 __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 {
     extern __shared__ float4 smem_raw[];
-    __shared__ double sh[16];
     __shared__ float taps[MAX_TAPS];
     const Geo& g = A.g;
     const int slice = blockIdx.y;
@@ -296,7 +303,6 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int q = lane & (SPL - 1), jj = lane >> 2;
-    double acc_r2 = 0.0;
     const float hs = 0.5f;
     for (int ab = 0; ab < A.angles_per_block; ++ab) {
         const int a = blockIdx.x * A.angles_per_block + ab;
@@ -412,25 +418,29 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
             float y = psf_at(rowp, taps, g.K, g.n_bins, j);
             if (S::DR) y += psf_at(rowpf, taps_f, g.K, g.n_bins, j);
             if (A.yout) A.yout[srow + j] = y;
-            if (A.ymeas) {
-                const float r = y - A.ymeas[srow + j];
-                rowr[j] = r;
-                acc_r2 += (double)r * (double)r;
-            }
+            if (A.ymeas) rowr[j] = y - A.ymeas[srow + j];
         }
-        if (A.wout) {
-            // the transposed blurs; both responses are symmetric
+        if (A.ymeas) {
             __syncthreads();
-            for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) {
-                A.wout[srow + j] = psf_at(rowr, taps, g.K, g.n_bins, j);
-                if (S::DR) A.wout[srow + A.far_off + j] = psf_at(rowr, taps_f, g.K, g.n_bins, j);
+            // the transposed blurs; both responses are symmetric
+            if (A.wout)
+                for (int j = threadIdx.x; j < g.n_bins; j += blockDim.x) {
+                    A.wout[srow + j] = psf_at(rowr, taps, g.K, g.n_bins, j);
+                    if (S::DR) A.wout[srow + A.far_off + j] = psf_at(rowr, taps_f, g.K, g.n_bins, j);
+                }
+            // ||A - y||^2 of this angle, one partial per angle in a fixed
+            // order (the same whatever the angles per block)
+            if (A.part && wave == 0) {
+                double v = 0.0;
+                for (int j = lane; j < g.n_bins; j += WAVE) {
+                    const double r = rowr[j];
+                    v += r * r;
+                }
+                v = wave_sum(v);
+                if (lane == 0) slot_ptr(A.part, slice, A.slot)[a] = v;
             }
         }
         __syncthreads();
-    }
-    if (A.part && A.ymeas) {
-        double s = block_sum(acc_r2, sh);
-        if (threadIdx.x == 0) slot_ptr(A.part, slice, A.slot)[blockIdx.x] = s;
     }
 }
 
@@ -631,7 +641,6 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     // collimator epilogue over every (row, bin) of the block; row r < nslot is
     // angle slot0 + r, row nslot + r its mirror
     const int nel = nrows * g.n_bins;
-    double acc2 = 0.0;
     for (int e = threadIdx.x; e < nel; e += blockDim.x) {
         const int r = e / g.n_bins, jb = e - r * g.n_bins;
         float y = psf_at(rowz + r * g.n_bins, taps, g.K, g.n_bins, jb);
@@ -639,8 +648,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         const int a = r < nslot ? slot0 + r : slot0 + (r - nslot) + g.n_angles / 2;
         const size_t o = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins + jb;
         if (MODE == JVP_PLAIN) A.out[o] = y;
-        if (MODE == JVP_NORMAL) rowy[e] = y;
-        if (MODE == JVP_SQNORM) acc2 += (double)y * (double)y;
+        if (MODE != JVP_PLAIN) rowy[e] = y;
     }
     if (MODE == JVP_NORMAL) {
         __syncthreads();
@@ -653,8 +661,19 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         }
     }
     if (MODE == JVP_SQNORM) {
-        double s = block_sum(acc2, sh);
-        if (threadIdx.x == 0) slot_ptr(A.part, slice, A.slot)[blockIdx.x] = s;
+        // ||K z||^2 per angle: row r by wave r mod nwaves, in a fixed order
+        // (the same whatever the angle slots per block)
+        __syncthreads();
+        for (int r = wave; r < nrows; r += nwaves) {
+            const int a = r < nslot ? slot0 + r : slot0 + (r - nslot) + g.n_angles / 2;
+            double v = 0.0;
+            for (int jb = lane; jb < g.n_bins; jb += WAVE) {
+                const double y = rowy[r * g.n_bins + jb];
+                v += y * y;
+            }
+            v = wave_sum(v);
+            if (lane == 0) slot_ptr(A.part, slice, A.slot)[a] = v;
+        }
     }
 }
 
@@ -914,26 +933,83 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
         if (A.skip_if_clean && !A.st[slice].dirty) return;
     }
     const int tr0 = (tile / A.tiles_x) * VT, tc0 = (tile % A.tiles_x) * VT;
-    // a slot gathers angle a, its mirror (paired) and the quarter-turn pair (QUAD)
+    // a slot gathers angle a, its mirror (paired) and the quarter-turn pair
+    // (QUAD).  The slots form A.fine groups of A.spf consecutive slots, each
+    // summed into its own partial image (the plan fixes them, so a pixel's
+    // additions run in the same order at every batch size); this block runs
+    // the fine groups [grp * A.fpb, (grp + 1) * A.fpb).
     const int n_slots = QUAD ? g.n_angles / 4 : g.paired ? g.n_angles / 2 : g.n_angles;
-    const int apg = (n_slots + A.groups - 1) / A.groups;
-    const int a_begin = grp * apg, a_end = min(n_slots, a_begin + apg);
+    const int f_begin = grp * A.fpb, f_end = min(A.fine, f_begin + A.fpb);
+    const int a_begin = f_begin * A.spf, a_end = min(n_slots, f_end * A.spf);
     const int qa = g.n_angles / 4;
 
     // this thread's 4 pixels: the same position in the four 8x8 blocks of its
     // wave's 16x16 quarter (a wave touches one compact 8x8 block per step)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int qr = tr0 + (wave >> 1) * 16, qc = tc0 + (wave & 1) * 16;
-    int prow[4], pcol[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        prow[b] = qr + (b >> 1) * 8 + (lane >> 3);
-        pcol[b] = qc + (b & 1) * 8 + (lane & 7);
-    }
+    // pixel b sits at (row0 + 8 (b >> 1), col0 + 8 (b & 1)); x, y centred
+    const float x0 = (float)(qc + (lane & 7)) - g.half, y0 = (float)(qr + (lane >> 3)) - g.half;
     float accf[4] = {0.f, 0.f, 0.f, 0.f}, accm[4] = {0.f, 0.f, 0.f, 0.f};
     const float SQ2 = 1.41421356f;
     const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
     const typename SP::w_t* wbase = static_cast<const typename SP::w_t*>(A.wts) + (size_t)slice * A.wts_stride;
+
+    // End of fine group fg: its sum (this thread's 4 pixels, both maps) goes
+    // either to its own partial image or, when the block runs whole super
+    // groups, onto the running super-group sum kept in LDS (each thread its
+    // own entries), written out at the super group's end.  Either way the
+    // additions per pixel are: slots in order within a fine group, fine
+    // groups in order within a super group, super groups in order (the last
+    // two by the consumer for fine partials).
+    __shared__ float2 tot[4 * VJP_THREADS];
+    auto write_out = [&](int idx, const float* vf, const float* vm) {
+        float* out = A.gpart + (size_t)idx * A.gpart_group_stride + (size_t)slice * A.gpart_slice_stride;
+        const int n2 = g.n * g.n;
+        // an empty asm on the thread index keeps the offset arithmetic here:
+        // hoisted out of the loop it would hold registers across the gather
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int l = tid & 63, wv = tid >> 6;
+        const int r0 = tr0 + (wv >> 1) * 16 + (l >> 3), c0 = tc0 + (wv & 1) * 16 + (l & 7);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int rr = r0 + (b >> 1) * 8, cc = c0 + (b & 1) * 8;
+            if (rr < g.n && cc < g.n) {
+                out[rr * g.n + cc] = vf[b];
+                out[n2 + rr * g.n + cc] = vm[b];
+            }
+        }
+    };
+    if (A.super_out) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) tot[b * VJP_THREADS + threadIdx.x] = make_float2(0.0f, 0.0f);
+    }
+    auto flush = [&](int fg) {
+        if (!A.super_out) {
+            write_out(fg, accf, accm);
+        } else {
+            float tf[4], tm[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                float2 t = tot[b * VJP_THREADS + threadIdx.x];
+                t.x += accf[b];
+                t.y += accm[b];
+                tf[b] = t.x;
+                tm[b] = t.y;
+                tot[b * VJP_THREADS + threadIdx.x] = t;
+            }
+            if ((fg + 1) % A.gs == 0 || fg + 1 == A.fine) {
+                write_out(fg / A.gs, tf, tm);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) tot[b * VJP_THREADS + threadIdx.x] = make_float2(0.0f, 0.0f);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            accf[b] = 0.0f;
+            accm[b] = 0.0f;
+        }
+    };
 
     Stage<SP> S, R;
     Window Wn = {0, 0, 0, 0};
@@ -942,6 +1018,7 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
         stage_load<SP>(S, A, wbase, slice, a_begin, Wn);
         if (QUAD) stage_load<SP>(R, A, wbase, slice, a_begin + qa, rot_window(g, Wn));
     }
+    int fg = f_begin, left = A.spf;   // fine group being summed, its slots still to come
     for (int a = a_begin; a < a_end; ++a) {
         const Window W = Wn;
         __syncthreads();   // the previous angle's gather is done with lat
@@ -951,6 +1028,12 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
             stage_add_rot(lat, R, g.kq, W);
         }
         __syncthreads();
+        // the previous fine group is complete: write it out here, where the
+        // staged registers are consumed and the next ones not yet loaded
+        if (left == 0) {
+            flush(fg++);
+            left = A.spf;
+        }
         if (a + 1 < a_end) {   // next angle's loads fly during this gather
             Wn = tile_window(g, A.t.trig[a + 1], tr0, tc0);
             stage_load<SP>(S, A, wbase, slice, a + 1, Wn);
@@ -966,7 +1049,7 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
         const float oyj[3] = {0.0f, A3, A3 + A3}, oyi[3] = {0.0f, A4, A4 + A4};
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const float x = (float)pcol[b] - g.half, y = (float)prow[b] - g.half;
+            const float x = x0 + (float)((b & 1) * 8), y = y0 + (float)((b >> 1) * 8);
             const float u = fmaf(-x * sn + y * cs, inv_ds, g.s_off);
             const float v = fmaf(x * cs + y * sn, inv_dt, g.t_off);
             const float ju = floorf(u - SQ2) + 1.0f, iv = floorf(v - SQ2) + 1.0f;
@@ -990,16 +1073,9 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
             accf[b] += sf;
             accm[b] += sm;
         }
+        --left;
     }
-    float* out = A.gpart + (size_t)grp * A.gpart_group_stride + (size_t)slice * A.gpart_slice_stride;
-    const int n2 = g.n * g.n;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        if (prow[b] < g.n && pcol[b] < g.n) {
-            out[prow[b] * g.n + pcol[b]] = accf[b];
-            out[n2 + prow[b] * g.n + pcol[b]] = accm[b];
-        }
-    }
+    flush(fg);
 }
 
 // Zero fill (kernels, not memset, so that captured graphs stay clean).
@@ -1010,12 +1086,28 @@ __global__ void __launch_bounds__(256) k_fill_zero(float4* p, long long n4)
         p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// Sum over the angle groups of the gather's partial images at element m of
-// a slice (f block at m, mu block at n2 + m), in group order; the loads of
-// eight groups are issued before their adds so that they overlap.
-__device__ __forceinline__ float2 sum_groups(const float* gp, long long group_stride, int groups, int m, int n2)
+// Sum of the gather's partial images at element m of a slice (f block at
+// m, mu block at n2 + m): runs of gfold partials (the fine groups of one
+// super group; 1 when the partials are super-group sums) are added in
+// order, then the runs in order -- the order the gather itself uses when it
+// sums whole super groups, so both layouts give the same bits.  The loads
+// of eight partials are issued before their adds so that they overlap.
+__device__ __forceinline__ float2 sum_groups(const float* gp, long long group_stride, int groups, int gfold,
+                                             int m, int n2)
 {
-    float sf = 0.0f, sm = 0.0f;
+    float sf = 0.0f, sm = 0.0f, tf = 0.0f, tm = 0.0f;
+    int in_run = 0;
+    auto add = [&](float vf, float vm) {
+        tf += vf;
+        tm += vm;
+        if (++in_run == gfold) {
+            sf += tf;
+            sm += tm;
+            tf = 0.0f;
+            tm = 0.0f;
+            in_run = 0;
+        }
+    };
     int k = 0;
     for (; k + 8 <= groups; k += 8) {
         float vf[8], vm[8];
@@ -1025,25 +1117,23 @@ __device__ __forceinline__ float2 sum_groups(const float* gp, long long group_st
             vm[u] = gp[(size_t)(k + u) * group_stride + n2 + m];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            sf += vf[u];
-            sm += vm[u];
-        }
+        for (int u = 0; u < 8; ++u) add(vf[u], vm[u]);
     }
-    for (; k < groups; ++k) {
-        sf += gp[(size_t)k * group_stride + m];
-        sm += gp[(size_t)k * group_stride + n2 + m];
+    for (; k < groups; ++k) add(gp[(size_t)k * group_stride + m], gp[(size_t)k * group_stride + n2 + m]);
+    if (in_run > 0) {
+        sf += tf;
+        sm += tm;
     }
     return make_float2(sf, sm);
 }
 
-// Sum of the angle-group partial images (fixed order) into gf / gmu.
-__global__ void __launch_bounds__(256) k_sum_groups(int n2, int groups, const float* gpart,
+// Sum of the gather's partial images (fixed order) into gf / gm.
+__global__ void __launch_bounds__(256) k_sum_groups(int n2, int groups, int gfold, const float* gpart,
                                                     long long group_stride, float* gf, float* gm)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n2) return;
-    const float2 s = sum_groups(gpart, group_stride, groups, idx, n2);
+    const float2 s = sum_groups(gpart, group_stride, groups, gfold, idx, n2);
     gf[idx] = s.x;
     gm[idx] = s.y;
 }
@@ -1120,7 +1210,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
         const int r = m / n, c = m - r * n;
         const float* uf = V.u + vo;
         const float* um = uf + n2;
-        const float2 gs = sum_groups(gp, V.gpart_group_stride, V.groups, m, n2);
+        const float2 gs = sum_groups(gp, V.gpart_group_stride, V.groups, V.gfold, m, n2);
         float gf = gs.x, gm = gs.y;
         gf = fmaf(af, lap(uf, n, r, c), gf);
         gm = fmaf(am, lap(um, n, r, c), gm);
@@ -1214,7 +1304,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_q(VecArgs V)
         if (c + 1 < n) { lf += pfc - PF(m + 1); lm += pmc - PM(m + 1); }
         if (r > 0) { lf += pfc - PF(m - n); lm += pmc - PM(m - n); }
         if (r + 1 < n) { lf += pfc - PF(m + n); lm += pmc - PM(m + n); }
-        const float2 gs = sum_groups(gp, V.gpart_group_stride, V.groups, m, n2);
+        const float2 gs = sum_groups(gp, V.gpart_group_stride, V.groups, V.gfold, m, n2);
         const float gf = gs.x, gm = gs.y;
         float qf = fmaf(af, lf, fmaf(bdf, pfc, gf));
         float qm = fmaf(am, lm, fmaf(bdm, pmc, gm));
@@ -1361,7 +1451,7 @@ __global__ void __launch_bounds__(256) k_beta0(VecArgs V)
     const int slice = blockIdx.x;
     LMState& st = V.st[slice];
     const LMParamsDev& P = V.prm[slice];
-    double j1 = sum_partials(slot_ptr(V.part, slice, SLOT_J1), V.n_jvp_blocks, sh);
+    double j1 = sum_partials(slot_ptr(V.part, slice, SLOT_J1), V.n_angle_parts, sh);
     if (threadIdx.x == 0 && P.beta0 <= 0.0) {
         const double n2 = (double)V.g.n * V.g.n;
         st.beta = P.tau * j1 / (2.0 * n2);
@@ -1397,13 +1487,13 @@ __global__ void __launch_bounds__(256) k_decide(VecArgs V, int hook_present)
     LMState& st = V.st[slice];
     if (st.done) return;
     const LMParamsDev& P = V.prm[slice];
-    const double phid_u = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_U), V.n_march_blocks, sh);
+    const double phid_u = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_U), V.n_angle_parts, sh);
     const double regu = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_U), V.n_ew_blocks, sh);
-    const double phid_t = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_T), V.n_march_blocks, sh);
+    const double phid_t = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_T), V.n_angle_parts, sh);
     const double regt = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_T), V.n_ew_blocks, sh);
     const double gs = sum_partials(slot_ptr(V.part, slice, SLOT_GS), V.n_ew_blocks, sh);
     const double srs = sum_partials(slot_ptr(V.part, slice, SLOT_SRS), V.n_ew_blocks, sh);
-    const double js = sum_partials(slot_ptr(V.part, slice, SLOT_JS), V.n_jvp_blocks, sh);
+    const double js = sum_partials(slot_ptr(V.part, slice, SLOT_JS), V.n_angle_parts, sh);
     const double ss = sum_partials(slot_ptr(V.part, slice, SLOT_SNORM), V.n_ew_blocks, sh);
     const double uu = sum_partials(slot_ptr(V.part, slice, SLOT_UNORM), V.n_ew_blocks, sh);
     if (threadIdx.x != 0) return;
@@ -1472,11 +1562,11 @@ __global__ void __launch_bounds__(256) k_hook_decide(VecArgs V)
     LMState& st = V.st[slice];
     if (st.done || !st.accepted) return;
     const LMParamsDev& P = V.prm[slice];
-    const double phid_h = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_H), V.n_march_blocks, sh);
+    const double phid_h = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_DATA_H), V.n_angle_parts, sh);
     const double regt = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_T), V.n_ew_blocks, sh);
     const double gs = sum_partials(slot_ptr(V.part, slice, SLOT_GS), V.n_ew_blocks, sh);
     const double srs = sum_partials(slot_ptr(V.part, slice, SLOT_SRS), V.n_ew_blocks, sh);
-    const double js = sum_partials(slot_ptr(V.part, slice, SLOT_JS), V.n_jvp_blocks, sh);
+    const double js = sum_partials(slot_ptr(V.part, slice, SLOT_JS), V.n_angle_parts, sh);
     if (threadIdx.x != 0) return;
     const double phi_h = 0.5 * phid_h + 0.5 * regt;
     const double pred_h = -(gs + 0.5 * (js + srs));
@@ -1558,7 +1648,7 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
     // Phi_data of the final iterate: the trial's if the last step was
     // accepted, else the linearisation point's.
     const int slot = st.final_slot;
-    const double phid = sum_partials(slot_ptr(V.part, slice, slot), V.n_march_blocks, sh);
+    const double phid = sum_partials(slot_ptr(V.part, slice, slot), V.n_angle_parts, sh);
     const double reg = sum_partials(slot_ptr(V.part, slice, SLOT_PHI_REG_U), V.n_ew_blocks, sh);
     if (threadIdx.x != 0 || !V.rep) return;
     ReportDev& R = V.rep[slice];

@@ -187,6 +187,9 @@ class SolverParams:
             setattr(p, k, getattr(self, k))
         keep = []
         if self.replay is not None:
+            # the library reads max_outer entries
+            if len(self.replay) < self.max_outer:
+                raise ValueError("replay holds %d decisions, max_outer is %d" % (len(self.replay), self.max_outer))
             arr = (ctypes.c_int8 * len(self.replay))(*[int(v) for v in self.replay])
             keep.append(arr)
             p.replay = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int8))

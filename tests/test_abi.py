@@ -86,3 +86,14 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for field, _ in cls._fields_:
             assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
+def test_short_replay_is_refused_on_the_host():
+    """The library reads max_outer replay decisions: a shorter list is an
+    argument error before anything reaches the C ABI."""
+    import pytest
+    from paper_2604_26745_amd import pget
+    with pytest.raises(ValueError, match="replay"):
+        pget.SolverParams(max_outer=5, replay=[1, 0, 1]).to_c()
+    p, keep = pget.SolverParams(max_outer=3, replay=[1, 0, 1]).to_c()
+    assert [p.replay[k] for k in range(3)] == [1, 0, 1] and keep

@@ -289,7 +289,7 @@ def test_hook_with_full_model_matches_oracle():
 def test_autotune_with_depth_response_keeps_results():
     """The autotuner times the depth-response kernels within their own LDS
     limit (three rows of sums per angle slot, alpha in LDS); the tuned shapes
-    change the summation order only."""
+    change no bit of the result."""
     n, na, nb = 64, 120, 96
     plan = pget.Plan(n, na, nb)
     d, al, far = full_model(plan)
@@ -307,7 +307,7 @@ def test_autotune_with_depth_response_keeps_results():
     assert shape["tuned"] and shape["jvp_angle_slots"] >= 1 and shape["vjp_angle_groups"] >= 1
     fb, mb, _ = plan.lm_solve_batched(ys, f0s, m0s, [prm] * 4)
     for k in range(4):
-        assert rel(H(fb[k]), H(fa[k])) <= 1e-5 and rel(H(mb[k]), H(ma[k])) <= 1e-5
+        assert torch.equal(fb[k], fa[k]) and torch.equal(mb[k], ma[k])
 
 
 def test_graph_replay_with_full_model_matches_eager():

@@ -478,3 +478,56 @@ def test_prior_decays_with_the_alphas():
         wf, wm, rf, rm = L.prior_at(p, k)
         assert np.allclose(wf, 10.0 / d) and np.all(wm == 0.0) and np.all(rf == 0.0) and np.all(rm == 0.0)
     assert L.prior_at(params(), 0) is None
+
+
+def test_initial_damping_is_rayleigh_quotient_of_dense_jacobian():
+    """beta0 = tau * 1^T (J^T J) 1 / 1^T 1 over both blocks (the reading of
+    'beta_k tuned accordingly', Sec. 2.2): J is built column by column from
+    torch autograd of the dense formulation, not from the oracle's J v."""
+    torch = pytest.importorskip("torch")
+    from oracle.dense import DenseModel
+    n, na, nb = 8, 10, 14
+    g = O.Geometry(n, na, nb, psf_sigma=1.5)
+    D = DenseModel(n, na, nb, psf_sigma=1.5)
+    rng = np.random.default_rng(5)
+    f = rng.uniform(0.2, 1.0, (n, n))
+    mu = rng.uniform(0.0, 0.1, (n, n))
+    T = lambda a: torch.tensor(a, dtype=torch.float64)
+    Jf, Jm = torch.autograd.functional.jacobian(lambda a, b: D.forward(a, b, xp=torch), (T(f), T(mu)))
+    J = np.concatenate([Jf.numpy().reshape(na * nb, n * n), Jm.numpy().reshape(na * nb, n * n)], axis=1)
+    one = np.ones(2 * n * n)
+    for tau in (1e-3, 0.37):
+        want = tau * float(one @ (J.T @ J) @ one) / float(one @ one)
+        got = L.initial_damping(g, f, mu, params(tau=tau))
+        assert abs(got - want) <= 1e-12 * want, (got, want)
+    assert L.initial_damping(g, f, mu, params(beta0=2.5)) == 2.5    # a given beta0 is kept
+
+
+def test_continuation_alphas():
+    """alpha_k = alpha / decay^min(k, until) (the alpha/5^k continuation of
+    Sec. 3.1, halted after `until` divisions)."""
+    p = params(alpha_f=1e-2, alpha_mu=3e-2, alpha_decay=5.0, alpha_decay_until=3)
+    want = {0: (1e-2, 3e-2), 1: (2e-3, 6e-3), 2: (4e-4, 1.2e-3), 3: (8e-5, 2.4e-4),
+            4: (8e-5, 2.4e-4), 9: (8e-5, 2.4e-4)}
+    for k, (wf, wm) in want.items():
+        af, am = L.alphas_at(p, k)
+        assert abs(af - wf) <= 1e-15 * wf and abs(am - wm) <= 1e-15 * wm, (k, af, am)
+    assert L.alphas_at(params(alpha_f=0.2, alpha_mu=0.1), 7) == (0.2, 0.1)   # decay 1: constant
+
+
+def test_damping_overflow_stops_the_solve():
+    """Every step rejected: Nielsen's rule multiplies beta by 2, 4, 8, ...,
+    so after k rejections beta = beta0 * 2^(k(k+1)/2).  The solve stops once
+    beta exceeds 1e16 beta0 (2^53.15): after the 10th rejection (2^55), with
+    the iterate unchanged."""
+    g, y, _, _ = small_problem()
+    f0, mu0 = L.initial_guess(g, y)
+    p = params(max_outer=15, n_cg=3, beta0=0.5)
+    f, mu, rep = L.lm_solve(g, y, f0, mu0, p, replay=[0] * 15)
+    assert rep.stop_reason == "beta_overflow" and rep.iters_run == 10
+    assert rep.beta == [0.5 * 2.0 ** (k * (k + 1) // 2) for k in range(10)]
+    assert rep.beta_final == 0.5 * 2.0 ** 55
+    assert np.array_equal(f, f0) and np.array_equal(mu, mu0)
+    # nine rejections stay below the bound (2^45): the solve runs on
+    f, mu, rep = L.lm_solve(g, y, f0, mu0, params(max_outer=9, n_cg=3, beta0=0.5), replay=[0] * 9)
+    assert rep.stop_reason == "max_outer" and rep.iters_run == 9

@@ -9,8 +9,12 @@ formulation, J v and J^T w against torch autograd of it, the regulariser's
 gradient against central differences of its energy.  Solver pins: the gain
 ratio of an emission-only step is exactly 1 (the data term is linear in f,
 the penalty and the prior quadratic), preconditioned CG reaches the direct
-solve in as many steps as unknowns, and Nielsen's damping factor at
-rho = 0.75 is 1 - 0.5^3."""
+solve in as many steps as unknowns, Nielsen's damping factor at
+rho = 0.75 is 1 - 0.5^3, the initial damping equals tau times the Rayleigh
+quotient of J^T J at the all-ones vector with J from torch autograd of the
+dense formulation, the continuation's alphas after its halt are alpha /
+decay^until, and ten rejections in a row (beta0 * 2^55 > 1e16 beta0) stop
+the solve."""
 import ctypes
 import os
 import subprocess
@@ -64,6 +68,11 @@ LM_MUTANTS = {
                                    "phi = float(np.dot(r.ravel(), r.ravel()))"),
     "prior gradient sign": ("gf, gm = gf + wf * (f - rf), gm + wm * (mu - rm)",
                             "gf, gm = gf - wf * (f - rf), gm - wm * (mu - rm)"),
+    "beta0 over N^2 instead of the 2 N^2 unknowns": ("/ (2.0 * g.n * g.n)", "/ (g.n * g.n)"),
+    "beta0 from the emission block only": ("j1 = jvp(g, f, mu, one, one)", "j1 = jvp(g, f, mu, one, 0.0 * one)"),
+    "continuation without its halt": ("decay = p.alpha_decay ** min(k, p.alpha_decay_until)\n    return",
+                                      "decay = p.alpha_decay ** k\n    return"),
+    "damping overflow never stops": ("if beta > 1e16 * beta_init:", "if beta > 1e16 * beta:"),
 }
 
 
@@ -213,6 +222,22 @@ def lm_pins(L):
     pins["CG vs direct solve"] = (float(np.abs(got - x).max() / np.abs(x).max()), 1e-8)
     beta, _ = L.nielsen_update(1.0, 2.0, True, 0.75)
     pins["Nielsen factor at rho = 0.75"] = (abs(beta - (1.0 - 0.5 ** 3)), 1e-15)
+    # initial damping against the dense Jacobian (torch autograd of the
+    # dense formulation, both blocks, all-ones direction)
+    torch = pytest.importorskip("torch")
+    D = DenseModel(n, na, nb, psf_sigma=1.5)
+    T = lambda a: torch.tensor(a, dtype=torch.float64)
+    Jf, Jm = torch.autograd.functional.jacobian(lambda a, b: D.forward(a, b, xp=torch), (T(f), T(mu)))
+    J = np.concatenate([Jf.numpy().reshape(na * nb, n * n), Jm.numpy().reshape(na * nb, n * n)], axis=1)
+    p0 = L.LMParams(tau=1e-3)
+    want = 1e-3 * float(np.sum((J @ np.ones(2 * n * n)) ** 2)) / (2 * n * n)
+    pins["beta0 vs dense Rayleigh quotient"] = (abs(L.initial_damping(g, f, mu, p0) / want - 1.0), 1e-12)
+    pc = L.LMParams(alpha_f=1e-2, alpha_mu=1e-2, alpha_decay=5.0, alpha_decay_until=3)
+    pins["alpha after the continuation's halt"] = (abs(L.alphas_at(pc, 5)[0] / 8e-5 - 1.0), 1e-15)
+    # ten rejections in a row end the solve (beta0 * 2^55 > 1e16 beta0)
+    po = L.LMParams(max_outer=12, n_cg=2, beta0=1.0)
+    rep = L.lm_solve(g, y, f, mu, po, replay=[0] * 12)[2]
+    pins["damping overflow after ten rejections"] = (float(abs(rep.iters_run - 10)), 0.0)
     return pins
 
 
