@@ -212,6 +212,12 @@ pget_status pget_vjp(const pget_plan* plan, const float* f, const float* mu, con
  * prior_w = NULL: no prior; prior_ref = NULL: zero reference.  Weights must
  * be >= 0 (not checked: the solver reads them on the device); they are
  * divided by the same continuation factor as the alphas.
+ * trace_u, trace_t (optional, for step-by-step checks against a reference
+ * implementation): device buffers of max_outer x 2 N^2 floats owned by the
+ * caller; outer iteration k writes the iterate u_k it linearises at (f
+ * block then mu block) to trace_u + k 2 N^2 and its trial point
+ * u'_k = clamp(u_k + x_k) to trace_t + k 2 N^2 (with a hook, before the
+ * proposal is evaluated).  Iterations not run leave their rows untouched.
  */
 typedef struct {
     int32_t max_outer;        /* >= 1                                        */
@@ -229,6 +235,8 @@ typedef struct {
     int32_t active_set;       /* 0 or 1                                      */
     const float* prior_w;     /* device, 2 N^2, or NULL                      */
     const float* prior_ref;   /* device, 2 N^2, or NULL                      */
+    float* trace_u;           /* device, max_outer x 2 N^2, or NULL          */
+    float* trace_t;           /* device, max_outer x 2 N^2, or NULL          */
 } pget_lm_params;
 
 /*

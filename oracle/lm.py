@@ -352,3 +352,52 @@ def lm_solve(
     rep.phi.append(objective(g, y, f, mu, af, am, prior_at(p, rep.iters_run))[0])
     rep.beta_final = beta
     return f, mu, rep
+
+
+def step_quantities(g: Geometry, y, f, mu, f_trial, mu_trial, p: LMParams, k: int) -> dict:
+    """The gain-ratio quantities of outer iteration k evaluated at a given
+    iterate u = (f, mu) and trial point u' (eqs. m-function and
+    rho_agreement): Phi(u), ||g(u)||, pred = m(0) - m(s) with s = u' - u,
+    ared = Phi(u) - Phi(u'), and rho = ared / pred (-inf if pred <= 0).
+    For checking another implementation step by step at its own iterates."""
+    f, mu = np.asarray(f, np.float64), np.asarray(mu, np.float64)
+    ft, mt = np.asarray(f_trial, np.float64), np.asarray(mu_trial, np.float64)
+    y = np.asarray(y, np.float64)
+    af, am = alphas_at(p, k)
+    pr = prior_at(p, k)
+    phi, r = objective(g, y, f, mu, af, am, pr)
+    gf, gm = gradient(g, f, mu, r, af, am, pr)
+    pred = model_decrease(g, f, mu, gf, gm, ft - f, mt - mu, af, am, pr)
+    phi_t = objective(g, y, ft, mt, af, am, pr)[0]
+    ared = phi - phi_t
+    return {"phi": phi, "gnorm": float(np.sqrt(np.sum(gf ** 2) + np.sum(gm ** 2))), "pred": pred,
+            "ared": ared, "phi_trial": phi_t, "rho": ared / pred if pred > 0.0 else -np.inf}
+
+
+def step_quantities_job(args):
+    """step_quantities from plain arguments (geometry keywords, arrays, the
+    parameters, k), or with beta given the whole iteration from u (its CG
+    solve included) as lm_iteration computes it: for process pools.  With a
+    noise seed, every normal-operator product of that CG solve is multiplied
+    elementwise by (1 + 1e-6 N(0, 1)): the solve's sensitivity to rounding
+    of FP32 size."""
+    geom_kw, y, f, mu, ft, mt, p, k, beta, noise_seed = args
+    g = Geometry(**geom_kw)
+    if beta is None:
+        return step_quantities(g, y, f, mu, ft, mt, p, k)
+    global normal_matvec
+    exact = normal_matvec
+    if noise_seed is not None:
+        rng = np.random.default_rng(noise_seed)
+
+        def normal_matvec(*a, **kw):
+            qf, qm = exact(*a, **kw)
+            return (qf * (1.0 + 1e-6 * rng.standard_normal(qf.shape)),
+                    qm * (1.0 + 1e-6 * rng.standard_normal(qm.shape)))
+    try:
+        it = lm_iteration(g, np.asarray(y, np.float64), np.asarray(f, np.float64), np.asarray(mu, np.float64),
+                          beta, p, k)
+    finally:
+        normal_matvec = exact
+    return {"f_trial": it.f_trial, "mu_trial": it.mu_trial, "pred": it.pred, "ared": it.ared, "rho": it.rho,
+            "cg_rr": list(it.cg_rr)}

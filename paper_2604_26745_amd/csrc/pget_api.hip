@@ -46,7 +46,7 @@ static bool g_use_graphs = true;
 // Instantiated solver sequences, keyed by workspace and the groups solved.
 struct GraphKey {
     void* ws;
-    std::vector<std::array<long long, 6>> groups;   // plan, batch, outer, cg, beta0, offset
+    std::vector<std::array<long long, 6>> groups;   // plan, batch, outer, cg, beta0 | trace << 1, offset
     bool operator==(const GraphKey& o) const { return ws == o.ws && groups == o.groups; }
 };
 struct GraphEntry {
@@ -377,13 +377,13 @@ void launch_vjp(const pget_plan* P, const VjpArgs& V, int batch, hipStream_t s)
 {
     const dim3 grid(P->tiles_x * P->tiles_x * V.groups, batch), block(VJP_THREADS);
     if (P->t.resp) {
-        hipLaunchKernelGGL((k_vjp_lin<F32DR, false>), grid, block, 0, s, V);
+        hipLaunchKernelGGL((k_vjp_lin<F32DR, false>), grid, block, 0, s, V, V.t.trig);
     } else if (P->bf16) {
-        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<BF16S, true>), grid, block, 0, s, V);
-        else hipLaunchKernelGGL((k_vjp_lin<BF16S, false>), grid, block, 0, s, V);
+        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<BF16S, true>), grid, block, 0, s, V, V.t.trig);
+        else hipLaunchKernelGGL((k_vjp_lin<BF16S, false>), grid, block, 0, s, V, V.t.trig);
     } else {
-        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<F32S, true>), grid, block, 0, s, V);
-        else hipLaunchKernelGGL((k_vjp_lin<F32S, false>), grid, block, 0, s, V);
+        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<F32S, true>), grid, block, 0, s, V, V.t.trig);
+        else hipLaunchKernelGGL((k_vjp_lin<F32S, false>), grid, block, 0, s, V, V.t.trig);
     }
 }
 
@@ -762,13 +762,14 @@ size_t pget_workspace_bytes(const pget_plan* plan, int32_t op, int32_t batch)
     return L.total;
 }
 
-pget_status pget_forward(const pget_plan* P, const float* f, const float* mu, float* y, void* ws,
-                         hipStream_t stream)
+}  // extern "C"
+
+// The forward map with the bordered copy of the map pair (used when the pair
+// does not fit in LDS) in `gimg`.
+static pget_status forward_into(const pget_plan* P, const float* f, const float* mu, float* y, void* gimg,
+                                hipStream_t stream)
 {
-    if (!P || !f || !mu || !y) return PGET_ERR_INVALID_ARG;
-    if (!ws) return PGET_ERR_WORKSPACE;
     Shapes sh = shapes_for(P, 1);
-    Layout L = layout_for(P, PGET_OP_FORWARD, 1, sh, 256, 256);
     MarchArgs A = {};
     A.g = P->g;
     A.t = P->t;
@@ -777,12 +778,25 @@ pget_status pget_forward(const pget_plan* P, const float* f, const float* mu, fl
     A.yout = y;
     A.angles_per_block = sh.apb;
     if (!P->lds_img) {
-        A.gimg = at(ws, L.gimg);
-        pack(P, A.src, nullptr, at(ws, L.gimg), 1, nullptr, stream);
+        A.gimg = gimg;
+        pack(P, A.src, nullptr, gimg, 1, nullptr, stream);
     }
     march<MARCH_FWD>(P, A, sh.n_op_blocks, 1, stream);
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
 }
+
+extern "C" {
+
+pget_status pget_forward(const pget_plan* P, const float* f, const float* mu, float* y, void* ws,
+                         hipStream_t stream)
+{
+    if (!P || !f || !mu || !y) return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    Shapes sh = shapes_for(P, 1);
+    Layout L = layout_for(P, PGET_OP_FORWARD, 1, sh, 256, 256);
+    return forward_into(P, f, mu, y, at(ws, L.gimg), stream);
+}
+
 
 // Linearise at (f, mu): per-sample weights and ray totals into the workspace.
 static void linearise(const pget_plan* P, const float* f, const float* mu, float* y_or_null,
@@ -929,6 +943,8 @@ LMParamsDev to_dev(const pget_lm_params& p)
     d.active_set = p.active_set;
     d.prior_w = p.prior_w;
     d.prior_ref = p.prior_w ? p.prior_ref : nullptr;
+    d.trace_u = p.trace_u;
+    d.trace_t = p.trace_t;
     d.has_replay = p.replay != nullptr;
     if (p.replay)
         for (int k = 0; k < p.max_outer; ++k) d.replay[k] = p.replay[k];
@@ -1119,7 +1135,7 @@ void enqueue_step_eval(Solve& S)
 // product K^T K J p, a gather and the q / x updates; the trial point
 // u' = clamp(u + x); the model decrease and Phi(u'); the decision (rho, beta).
 // Every decision is taken on the device.
-void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_present)
+void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_present, bool trace)
 {
     const dim3 ew(S.sh.n_ew_blocks, S.B);
     enqueue_march(S, S.lin, MARCH_LIN);
@@ -1166,6 +1182,10 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
     {
         Timed t_(PGET_KC_VECTOR, S.stream);
         hipLaunchKernelGGL(k_trial, ew, dim3(EW_THREADS), 0, S.stream, Vt);
+    }
+    if (trace) {
+        Timed t_(PGET_KC_VECTOR, S.stream);
+        hipLaunchKernelGGL(k_trace, ew, dim3(EW_THREADS), 0, S.stream, S.V);
     }
     enqueue_step_eval(S);
     {
@@ -1250,6 +1270,7 @@ struct Group {
     Solve S;
     int max_outer = 0, n_cg = 0;
     bool need_beta0 = false;
+    bool trace = false;      // some slice records its iterates
     std::vector<LMParamsDev> prm;
     std::vector<ReportDev> rep;
     std::vector<const float*> y;
@@ -1297,10 +1318,12 @@ pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStre
     G.max_outer = G.prm.empty() ? 0 : G.prm[0].max_outer;
     G.n_cg = G.prm.empty() ? 0 : G.prm[0].n_cg;
     G.need_beta0 = false;
+    G.trace = false;
     for (int b = 0; b < B; ++b) {
         if (G.prm[b].max_outer != G.max_outer || G.prm[b].n_cg != G.n_cg) return PGET_ERR_INVALID_ARG;
         if (!G.y[b] || !G.f[b] || !G.mu[b]) return PGET_ERR_INVALID_ARG;
         if (G.prm[b].beta0 <= 0.0) G.need_beta0 = true;
+        if (G.prm[b].trace_u || G.prm[b].trace_t) G.trace = true;
     }
     Solve& S = G.S;
     S.P = P;
@@ -1357,7 +1380,7 @@ void enqueue_group(Group& G, hipStream_t s)
     fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * SS.P->w_bytes, s);
     if (SS.lin.wq) fill_zero(SS.lin.wq, (size_t)B * SS.lin.wts_stride * sizeof(float), s);
     for (int k = 0; k < G.max_outer; ++k) {
-        enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false);
+        enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false, G.trace);
         enqueue_commit(SS);
     }
     hipLaunchKernelGGL(k_final_reg, dim3(SS.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, s, SS.V);
@@ -1401,7 +1424,7 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
         fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * S.P->w_bytes, stream);
         if (S.lin.wq) fill_zero(S.lin.wq, (size_t)B * S.lin.wts_stride * sizeof(float), stream);
         for (int k = 0; k < G.max_outer; ++k) {
-            enqueue_iteration(S, k, G.n_cg, G.need_beta0, true);
+            enqueue_iteration(S, k, G.n_cg, G.need_beta0, true, G.trace);
             pget_status rc = run_hook(S, hook, hook_user);
             if (rc != PGET_OK) return rc;
             enqueue_commit(S);
@@ -1415,7 +1438,8 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
         GraphKey key;
         key.ws = ws;
         for (auto& G : groups)
-            key.groups.push_back({(long long)(intptr_t)G.S.P, G.S.B, G.max_outer, G.n_cg, (long long)G.need_beta0,
+            key.groups.push_back({(long long)(intptr_t)G.S.P, G.S.B, G.max_outer, G.n_cg,
+                                  (long long)G.need_beta0 | ((long long)G.trace << 1),
                                   (long long)((char*)G.S.ws - (char*)ws)});
         hipGraphExec_t exec = nullptr;
         ++g_graph_clock;

@@ -69,6 +69,8 @@ struct LMParamsDev {
     int active_set;         // 1: CG on the free variables only
     const float* prior_w;   // geometry prior weights (2 N^2, f then mu) or nullptr
     const float* prior_ref; // its reference maps (2 N^2) or nullptr (zero)
+    float* trace_u;         // [max_outer][2 N^2]: iterate of each outer iteration, or nullptr
+    float* trace_t;         // [max_outer][2 N^2]: its trial point, or nullptr
     int has_replay;
     int8_t replay[256];
 };
@@ -249,7 +251,7 @@ template <typename S>
 __global__ void k_pack(Geo g, PairSrc s, const double* part, void* out, long long out_stride,
                        const LMState* st);
 __global__ void k_psf(Geo g, const float* taps_g, const float* in, float* out);
-template <typename S, bool QUAD> __global__ void k_vjp_lin(VjpArgs A);
+template <typename S, bool QUAD> __global__ void k_vjp_lin(VjpArgs A, const float4* trig);
 __global__ void k_fill_zero(float4* p, long long n4);
 __global__ void k_sum_groups(int n2, int groups, int gfold, const float* gpart, long long group_stride,
                              float* gf, float* gm);
@@ -257,6 +259,7 @@ __global__ void k_grad_init(VecArgs V);
 __global__ void k_cg_q(VecArgs V);
 __global__ void k_cg_x(VecArgs V);
 __global__ void k_trial(VecArgs V);
+__global__ void k_trace(VecArgs V);
 __global__ void k_beta0(VecArgs V);
 __global__ void k_lm_init(LMState* st, const LMParamsDev* prm, int n_slices);
 __global__ void k_decide(VecArgs V, int hook_present);

@@ -916,7 +916,8 @@ __device__ __forceinline__ float tent(float d)
 }
 
 template <typename SP, bool QUAD>
-__global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_eu(SP::VJP_WAVES))) k_vjp_lin(VjpArgs A)
+__global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_eu(SP::VJP_WAVES))) k_vjp_lin(VjpArgs A,
+                                                                      const float4* __restrict__ trig)
 {
     __shared__ float2 lat[VFP * LP];
     const Geo& g = A.g;
@@ -1011,10 +1012,14 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
         }
     };
 
+    // `trig` is the plan's angle table (A.t.trig) as a restrict argument: the
+    // compiler may then keep its loads scalar despite the partial-image
+    // stores inside the loop (a vector load here would wait for the next
+    // angle's weight loads in flight).
     Stage<SP> S, R;
     Window Wn = {0, 0, 0, 0};
     if (a_begin < a_end) {
-        Wn = tile_window(g, A.t.trig[a_begin], tr0, tc0);
+        Wn = tile_window(g, trig[a_begin], tr0, tc0);
         stage_load<SP>(S, A, wbase, slice, a_begin, Wn);
         if (QUAD) stage_load<SP>(R, A, wbase, slice, a_begin + qa, rot_window(g, Wn));
     }
@@ -1035,11 +1040,11 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
             left = A.spf;
         }
         if (a + 1 < a_end) {   // next angle's loads fly during this gather
-            Wn = tile_window(g, A.t.trig[a + 1], tr0, tc0);
+            Wn = tile_window(g, trig[a + 1], tr0, tc0);
             stage_load<SP>(S, A, wbase, slice, a + 1, Wn);
             if (QUAD) stage_load<SP>(R, A, wbase, slice, a + 1 + qa, rot_window(g, Wn));
         }
-        const float4 tr = A.t.trig[a];
+        const float4 tr = trig[a];
         const float cs = tr.z, sn = tr.w;
         // displacement (pixel -> lattice point) per unit lattice step, and its
         // value at the 3x3 candidate offsets (built from sums: no 0*x or 2*x)
@@ -1444,6 +1449,30 @@ __global__ void __launch_bounds__(EW_THREADS) k_trial(VecArgs V)
     v = block_sum(regt, sh); if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_PHI_REG_T)[blockIdx.x] = v;
 }
 
+// Iterate trace (optional, per slice): u_k and the trial point u'_k of the
+// current outer iteration into rows k of the caller's buffers.
+__global__ void __launch_bounds__(EW_THREADS) k_trace(VecArgs V)
+{
+    const int slice = blockIdx.y;
+    const LMState& st = V.st[slice];
+    const LMParamsDev& P = V.prm[slice];
+    if (st.done || (!P.trace_u && !P.trace_t)) return;
+    const long long n2x2 = V.vstride;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= V.g.n * V.g.n) return;
+    const size_t vo = (size_t)slice * n2x2;
+    const size_t row = (size_t)st.k * n2x2;
+    const int n2 = V.g.n * V.g.n;
+    if (P.trace_u) {
+        P.trace_u[row + m] = V.u[vo + m];
+        P.trace_u[row + n2 + m] = V.u[vo + n2 + m];
+    }
+    if (P.trace_t) {
+        P.trace_t[row + m] = V.ut[vo + m];
+        P.trace_t[row + n2 + m] = V.ut[vo + n2 + m];
+    }
+}
+
 // Initial damping: beta0 = tau ||J 1||^2 / (2 N^2) unless given.
 __global__ void __launch_bounds__(256) k_beta0(VecArgs V)
 {
@@ -1669,13 +1698,13 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
     INST_MARCH(false, MARCH_TRIAL, S)                                                         \
     INST_JVP(true, JVP_PLAIN, S) INST_JVP(true, JVP_NORMAL, S) INST_JVP(true, JVP_SQNORM, S)  \
     INST_JVP(false, JVP_PLAIN, S) INST_JVP(false, JVP_NORMAL, S) INST_JVP(false, JVP_SQNORM, S) \
-    template __global__ void k_vjp_lin<S, false>(VjpArgs);                                    \
+    template __global__ void k_vjp_lin<S, false>(VjpArgs, const float4*);                                    \
     template __global__ void k_pack<S>(Geo, PairSrc, const double*, void*, long long, const LMState*);
 INST_ALL(F32S)
 INST_ALL(BF16S)
 INST_ALL(F32DR)
 // the quarter-turn fold; not with a depth response (one staged angle only)
-template __global__ void k_vjp_lin<F32S, true>(VjpArgs);
-template __global__ void k_vjp_lin<BF16S, true>(VjpArgs);
+template __global__ void k_vjp_lin<F32S, true>(VjpArgs, const float4*);
+template __global__ void k_vjp_lin<BF16S, true>(VjpArgs, const float4*);
 
 }  // namespace pget

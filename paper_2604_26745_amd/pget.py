@@ -54,6 +54,7 @@ class LMParams(ctypes.Structure):
         ("tol", ctypes.c_double), ("replay", ctypes.POINTER(ctypes.c_int8)),
         ("w_f", ctypes.c_double), ("w_mu", ctypes.c_double), ("active_set", ctypes.c_int32),
         ("prior_w", ctypes.c_void_p), ("prior_ref", ctypes.c_void_p),
+        ("trace_u", ctypes.c_void_p), ("trace_t", ctypes.c_void_p),
     ]
 
 
@@ -178,11 +179,13 @@ class SolverParams:
     active_set: int = 0       # 1: CG on the variables not held at a bound
     prior_w: object = None    # geometry prior: CUDA float32 (2, N, N) weights, or None
     prior_ref: object = None  # its reference maps (2, N, N), or None (zero)
+    trace_u: object = None    # iterate trace: CUDA float32 (max_outer, 2, N, N) receiving u_k, or None
+    trace_t: object = None    # the same receiving the trial points u'_k, or None
 
     def to_c(self, n: Optional[int] = None):
         p = LMParams()
         for k, _ in LMParams._fields_:
-            if k in ("replay", "prior_w", "prior_ref"):
+            if k in ("replay", "prior_w", "prior_ref", "trace_u", "trace_t"):
                 continue
             setattr(p, k, getattr(self, k))
         keep = []
@@ -201,6 +204,16 @@ class SolverParams:
                 raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
             if n is not None and t.numel() != 2 * n * n:
                 raise ValueError("%s must hold 2 x %d x %d values" % (name, n, n))
+            keep.append(t)
+            setattr(p, name, t.data_ptr())
+        for name in ("trace_u", "trace_t"):
+            t = getattr(self, name)
+            if t is None:
+                continue
+            if not (t.is_cuda and t.dtype == _torch().float32 and t.is_contiguous()):
+                raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
+            if n is not None and t.numel() != self.max_outer * 2 * n * n:
+                raise ValueError("%s must hold max_outer x 2 x %d x %d values" % (name, n, n))
             keep.append(t)
             setattr(p, name, t.data_ptr())
         return p, keep

@@ -531,3 +531,26 @@ def test_damping_overflow_stops_the_solve():
     # nine rejections stay below the bound (2^45): the solve runs on
     f, mu, rep = L.lm_solve(g, y, f0, mu0, params(max_outer=9, n_cg=3, beta0=0.5), replay=[0] * 9)
     assert rep.stop_reason == "max_outer" and rep.iters_run == 9
+
+
+def test_step_quantities_reproduce_an_iteration():
+    """The step-by-step evaluator gives, at an iteration's own iterate and
+    trial point, the objective, gradient norm, model and actual decrease and
+    gain ratio the iteration computed."""
+    import dataclasses
+    g, y, _, _ = small_problem()
+    f0, mu0 = L.initial_guess(g, y)
+    p = params(n_cg=6, w_mu=0.05 ** 2, d_mu=400.0, active_set=True)
+    it = L.lm_iteration(g, y, f0, mu0, 0.3, p, 0)
+    q = L.step_quantities(g, y, f0, mu0, it.f_trial, it.mu_trial, p, 0)
+    for key, want in (("phi", it.phi), ("pred", it.pred), ("ared", it.ared), ("rho", it.rho),
+                      ("gnorm", float(np.sqrt(np.sum(it.gf ** 2) + np.sum(it.gm ** 2))))):
+        assert abs(q[key] - want) <= 1e-12 * abs(want), key
+    job = L.step_quantities_job((dataclasses.asdict(g), y, f0, mu0, None, None, p, 0, 0.3, None))
+    assert np.array_equal(job["f_trial"], it.f_trial) and job["rho"] == it.rho
+    # perturbed products move the step a little, and the exact product is restored
+    noisy = L.step_quantities_job((dataclasses.asdict(g), y, f0, mu0, None, None, p, 0, 0.3, 1))
+    d = np.linalg.norm(noisy["f_trial"] - it.f_trial) / np.linalg.norm(it.f_trial - f0)
+    assert 0.0 < d < 1e-4
+    again = L.step_quantities_job((dataclasses.asdict(g), y, f0, mu0, None, None, p, 0, 0.3, None))
+    assert np.array_equal(again["f_trial"], it.f_trial)
