@@ -162,6 +162,23 @@ pget_status pget_forward(const pget_plan* plan, const float* f, const float* mu,
                          void* ws, hipStream_t stream);
 
 /*
+ * pget_forward without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and the same result bit for bit.
+ * The bordered copy of the map pair that the ray march reads when the pair
+ * does not fit in LDS (N > 136: (N + 2)^2 * 8 bytes) lives in a static
+ * device array of 2.25 MiB that the library holds on each device until the
+ * process ends; sizes beyond it return PGET_ERR_UNSUPPORTED (no plan within
+ * the N <= 512 limit reaches it).  Calls on one device share that array:
+ * calls that overlap in time on one device (several streams or threads)
+ * race and must be serialised by the caller.  The current device must be
+ * the plan's (else PGET_ERR_INVALID_ARG).  Nothing is allocated, freed or
+ * set with memset.
+ */
+pget_status pget_forward_noalloc(const pget_plan* plan, const float* f, const float* mu, float* y,
+                                 hipStream_t stream);
+
+/*
  * jv = J(f, mu) [vf, vmu] = D_lambda F[vf] + D_mu F[vmu] with
  * D_lambda F[v] = F(v, mu) and D_mu F[v] = -F(lambda * B v, mu) (Sec. 2.1,
  * eq. frechet), in the same discretisation as pget_forward.  y_or_null, if

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -40,6 +41,33 @@ struct pget_plan {
     int64_t support;     // lattice samples inside the support
     std::vector<std::array<int, 3>> tuned;   // (batch, japb, vjp groups) picked by pget_autotune
 };
+
+// Scratch of the allocation-free forward map (pget_forward_noalloc): the
+// zero-bordered map pair ((N + 2)^2 float2) that the ray march reads when the
+// pair does not fit in LDS; at most 514^2 * 8 B for N = 512.  Each device
+// the library runs on holds its own copy for the life of the process.  Host
+// code uses only the device address looked up per device (g_scratch), never
+// this name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 2304u * 1024u;   // 2.25 MiB
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static void* g_scratch[MAX_DEVICES];
+static std::mutex g_scratch_mutex;
+
+// Device address of `scratch` on the current device `device`, looked up on
+// the first call for that device (plan creation is the set-up call).
+static pget_status scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return PGET_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PGET_ERR_HIP;
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return PGET_OK;
+}
 
 static bool g_use_graphs = true;
 
@@ -638,6 +666,14 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
             return PGET_ERR_HIP;
         }
     }
+    {
+        void* scr = nullptr;
+        if (scratch_address(P->device, &scr) != PGET_OK) {
+            (void)hipFree(P->table_mem);
+            delete P;
+            return PGET_ERR_HIP;
+        }
+    }
     P->tiles_x = (g.n + VT - 1) / VT;
     {
         int occ = 0, occ_dr = 0;
@@ -797,6 +833,20 @@ pget_status pget_forward(const pget_plan* P, const float* f, const float* mu, fl
     return forward_into(P, f, mu, y, at(ws, L.gimg), stream);
 }
 
+pget_status pget_forward_noalloc(const pget_plan* P, const float* f, const float* mu, float* y,
+                                 hipStream_t stream)
+{
+    if (!P || !f || !mu || !y) return PGET_ERR_INVALID_ARG;
+    const size_t need = P->lds_img ? 0 : (size_t)P->g.pitch * P->g.pitch * sizeof(float2);
+    if (need > NOALLOC_SCRATCH_BYTES) return PGET_ERR_UNSUPPORTED;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PGET_ERR_HIP;
+    if (dev != P->device) return PGET_ERR_INVALID_ARG;   // the plan's tables live on its device
+    void* scr = nullptr;
+    pget_status rc = scratch_address(dev, &scr);
+    if (rc != PGET_OK) return rc;
+    return forward_into(P, f, mu, y, scr, stream);
+}
 
 // Linearise at (f, mu): per-sample weights and ray totals into the workspace.
 static void linearise(const pget_plan* P, const float* f, const float* mu, float* y_or_null,

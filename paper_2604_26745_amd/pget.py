@@ -120,6 +120,8 @@ def load_library():
     lib.pget_workspace_bytes.restype = ctypes.c_size_t
     lib.pget_forward.argtypes = [V, V, V, V, V, V]
     lib.pget_forward.restype = ctypes.c_int
+    lib.pget_forward_noalloc.argtypes = [V, V, V, V, V]
+    lib.pget_forward_noalloc.restype = ctypes.c_int
     lib.pget_jvp.argtypes = [V, V, V, V, V, V, V, V, V]
     lib.pget_jvp.restype = ctypes.c_int
     lib.pget_vjp.argtypes = [V, V, V, V, V, V, V, V]
@@ -351,6 +353,14 @@ class Plan:
         ws = self.workspace(OP_FORWARD)
         _check(self.lib.pget_forward(self.handle, _ptr(f), _ptr(mu), _ptr(y), _ptr(ws), _stream()),
                "pget_forward")
+        return y
+
+    def forward_noalloc(self, f, mu, y):
+        """pget_forward_noalloc into the caller's y (n_angles x n_bins): the
+        library allocates nothing for it."""
+        f, mu, y = self._img(f), self._img(mu), self._sino(y)
+        _check(self.lib.pget_forward_noalloc(self.handle, _ptr(f), _ptr(mu), _ptr(y), _stream()),
+               "pget_forward_noalloc")
         return y
 
     def jvp(self, f, mu, vf, vmu, want_y: bool = False):
