@@ -21,9 +21,15 @@ Measured alongside:
 * the FP64 CPU oracle, timed on the host cores on a bounded sample of the
   same workload.
 
-Other workloads (--workload): mixed grid sizes, serving with p50/p99
-latency, the scanner geometry, and the safeguarded Deep Gauss-Newton
-comparison.
+* the serving half of the metric: a 10 s Poisson trace (30 requests/s)
+  over the mixed grid sizes {64..256}^2 through the iteration-level
+  continuous-batching server, with p50/p99 latency, the plain per-slice
+  solver on the same trace, and a bitwise check of served results against
+  the same slices solved alone.
+
+Other workloads (--workload): mixed grid sizes, serving alone (rate and
+server selectable), the scanner geometry, and the safeguarded Deep
+Gauss-Newton comparison.
 """
 from __future__ import annotations
 
@@ -78,7 +84,16 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=5.0, help="serve: seconds of arrivals")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct request payloads")
-    ap.add_argument("--streams", type=int, default=4, help="serve: concurrent solves")
+    ap.add_argument("--streams", type=int, default=4, help="serve (--server batch): concurrent solves")
+    ap.add_argument("--server", default="iter", choices=["iter", "batch"],
+                    help="serve: iter = per-size slot pools admitting requests at every outer-iteration "
+                         "boundary; batch = whole batched solves on --streams streams")
+    ap.add_argument("--capacity", type=int, default=8, help="serve (--server iter): slots per size")
+    ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain per-slice solver")
+    ap.add_argument("--serve-rate", type=float, default=30.0,
+                    help="main workload: arrival rate of the serving leg (0 = skip it)")
+    ap.add_argument("--serve-duration", type=float, default=10.0,
+                    help="main workload: seconds of arrivals of the serving leg")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: in-flight workspace cap")
     ap.add_argument("--autotune", action="store_true", help="autotune launch shapes first")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16"],
@@ -598,73 +613,96 @@ def run_deepgn(args, torch, np, inputs, pget):
     print(json.dumps(out), flush=True)
 
 
-def run_serve(args, torch, pget):
-    """Continuous batching of mixed-size requests (Poisson arrivals, early exit
-    at tolerance 1e-4) against the plain per-slice solver on the same trace."""
+def serving_measure(torch, pget, rate, duration, pool_n, outer, cg, solver, server="iter", capacity=8,
+                    streams=4, hbm_budget_gb=64.0, check=16, plain=True):
+    """Mixed-size requests (Poisson arrivals over the {64..256}^2 mix,
+    early exit at tolerance 1e-4) through the continuous-batching server --
+    "iter": per-size slot pools with admission at every outer-iteration
+    boundary; "batch": whole batched solves on `streams` streams -- and the
+    same trace through the plain per-slice solver.  `check` seeded requests
+    are compared with their slice solved alone (bitwise)."""
+    import numpy as np
     from paper_2604_26745_amd import serve
-    plans, pool = serve.make_pool(args.pool, args.outer, args.cg)
-    prm = pget.SolverParams(max_outer=args.outer, n_cg=args.cg, tol=1e-4, **SOLVER_OPTIONS[args.solver])
-    ex = serve.GpuExecutor(plans, pool, prm, n_slots=args.streams)
-    srv = serve.Server(ex, hbm_budget=args.hbm_budget_gb * 1e9, n_slots=args.streams)
-    print("bench: serve warm-up (graph capture per size and batch)", file=sys.stderr, flush=True)
-    srv.warm()
-    reqs = serve.make_trace(args.rate, args.duration, pool, seed=0)
-    # keep every request's result for the check against solves of the slice alone
+    plans, pool = serve.make_pool(pool_n, outer, cg)
+    prm = pget.SolverParams(max_outer=outer, n_cg=cg, tol=1e-4, **SOLVER_OPTIONS[solver])
     outputs = {}
-    launch = ex.launch
+    if server == "iter":
+        pools = serve.make_pools(plans, pool, prm, {n: capacity for n in plans})
+        for gp in pools.values():
+            gp.keep_outputs = True
+        srv = serve.IterServer(pools, hbm_budget=hbm_budget_gb * 1e9)
+    else:
+        ex = serve.GpuExecutor(plans, pool, prm, n_slots=streams)
+        srv = serve.Server(ex, hbm_budget=hbm_budget_gb * 1e9, n_slots=streams)
+        print("bench: serve warm-up (graph capture per size and batch)", file=sys.stderr, flush=True)
+        srv.warm()
+        launch = ex.launch
 
-    def keep(size, rs, slot):
-        h = launch(size, rs, slot)
-        for i, r in enumerate(rs):
-            outputs[r.rid] = (h[1][0][i], h[1][1][i], h[1][2][i])
-        return h
-
-    ex.launch = keep
-    print("bench: serving %d requests at %.0f/s" % (len(reqs), args.rate), file=sys.stderr, flush=True)
+        def keep(size, rs, slot):
+            h = launch(size, rs, slot)
+            for i, r in enumerate(rs):
+                outputs[r.rid] = (h[1][0][i], h[1][1][i])
+            return h
+        ex.launch = keep
+    reqs = serve.make_trace(rate, duration, pool, seed=0)
+    print("bench: serving %d requests at %.0f/s (%s server)" % (len(reqs), rate, server), file=sys.stderr,
+          flush=True)
     st = serve.run_trace(srv, reqs)
     print("bench: served %s" % st, file=sys.stderr, flush=True)
-    import numpy as np
-    picks = np.random.default_rng([0, 7]).choice(len(reqs), size=min(16, len(reqs)), replace=False)
-    worst = [0.0, 0.0]
-    worst_same = [0.0, 0.0]   # over the requests whose decisions equal those of the solve alone
-    same = 0
+    if server == "iter":
+        for gp in pools.values():
+            outputs.update(gp.outputs)
+    torch.cuda.synchronize()
+    picks = np.random.default_rng([0, 7]).choice(len(reqs), size=min(check, len(reqs)), replace=False)
+    worst, bitwise = [0.0, 0.0], 0
     for k in picks:
         r = reqs[int(k)]
         sl = pool[r.slot]
-        fa, ma, ra = plans[r.size].lm_solve(sl.y, sl.f0, sl.mu0, prm)
-        f, m, rb = outputs[r.rid]
-        e = (float(torch.linalg.norm(f - fa) / torch.linalg.norm(fa)),
-             float(torch.linalg.norm(m - ma) / torch.linalg.norm(ma)))
-        worst = [max(worst[0], e[0]), max(worst[1], e[1])]
-        if rb.to_report().accepted == ra.to_report().accepted:
-            same += 1
-            worst_same = [max(worst_same[0], e[0]), max(worst_same[1], e[1])]
-    print("bench: served vs alone, %d requests: max rel f %.2e mu %.2e; %d with the same decisions: "
-          "max rel f %.2e mu %.2e" % (len(picks), worst[0], worst[1], same, worst_same[0], worst_same[1]),
-          file=sys.stderr, flush=True)
-    reqs2 = serve.make_trace(args.rate, args.duration, pool, seed=0)
-    pl = serve.run_plain(plans, pool, prm, reqs2)
-    print("bench: plain %s" % pl, file=sys.stderr, flush=True)
+        fa, ma, _ = plans[r.size].lm_solve(sl.y, sl.f0, sl.mu0, prm)
+        f, m = outputs[r.rid]
+        worst = [max(worst[0], float(torch.linalg.norm(f - fa) / torch.linalg.norm(fa))),
+                 max(worst[1], float(torch.linalg.norm(m - ma) / torch.linalg.norm(ma)))]
+        bitwise += int(torch.equal(f, fa) and torch.equal(m, ma))
+    print("bench: served vs alone, %d requests: %d bitwise equal, max rel f %.2e mu %.2e"
+          % (len(picks), bitwise, worst[0], worst[1]), file=sys.stderr, flush=True)
+    if server == "iter":
+        del pools, srv
+    pl = {"recon_per_s": math.nan, "p50_ms": math.nan, "p99_ms": math.nan}
+    if plain:
+        reqs2 = serve.make_trace(rate, duration, pool, seed=0)
+        pl = serve.run_plain(plans, pool, prm, reqs2)
+        print("bench: plain %s" % pl, file=sys.stderr, flush=True)
+    return {
+        "server": server, "rate_per_s": rate, "arrival_window_s": duration, "requests": len(reqs),
+        "recon_per_s": round(st["recon_per_s"], 3),
+        "latency_ms": {"p50": round(st["p50_ms"], 1), "p99": round(st["p99_ms"], 1),
+                       "mean": round(st["mean_ms"], 1)},
+        "makespan_s": round(st["makespan_s"], 3),
+        "mean_occupancy" if server == "iter" else "mean_batch": round(st["mean_batch"], 3),
+        "workspace_gb": round(st["peak_in_flight_gb"], 3),
+        "plain_per_slice": {"recon_per_s": round(pl["recon_per_s"], 3), "p50_ms": round(pl["p50_ms"], 1),
+                            "p99_ms": round(pl["p99_ms"], 1)},
+        "check_vs_alone": {"requests": int(len(picks)), "bitwise_equal": bitwise,
+                           "max_rel_l2_f": float("%.3g" % worst[0]), "max_rel_l2_mu": float("%.3g" % worst[1])},
+        "config": {"solver": dict({"name": solver}, **SOLVER_OPTIONS[solver]), "pool": pool_n, "tol": 1e-4,
+                   "outer": outer, "cg": cg, "capacity_per_size" if server == "iter" else "streams":
+                   capacity if server == "iter" else streams},
+    }
+
+
+def run_serve(args, torch, pget):
+    """The serving workload alone, as its own JSON line."""
+    sv = serving_measure(torch, pget, args.rate, args.duration, args.pool, args.outer, args.cg, args.solver,
+                         server=args.server, capacity=args.capacity, streams=args.streams,
+                         hbm_budget_gb=args.hbm_budget_gb, plain=not args.no_plain)
     out = {
         "metric": "serving: LM reconstructions/s with p50/p99 latency, mixed sizes {64..256}^2",
-        "value": round(st["recon_per_s"], 4), "unit": "reconstructions/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * st["makespan_s"], 3),
+        "value": sv["recon_per_s"], "unit": "reconstructions/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * sv["makespan_s"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "serve_poisson_%g_per_s_%gs" % (args.rate, args.duration),
-                   "solver": dict({"name": args.solver}, **SOLVER_OPTIONS[args.solver]),
-                   "requests": len(reqs), "pool": args.pool, "streams": args.streams,
-                   "hbm_budget_gb": args.hbm_budget_gb, "tol": 1e-4, "outer": args.outer,
-                   "cg": args.cg},
-        "latency_ms": {"p50": round(st["p50_ms"], 2), "p99": round(st["p99_ms"], 2),
-                       "mean": round(st["mean_ms"], 2)},
-        "mean_batch": round(st["mean_batch"], 3),
-        "peak_in_flight_gb": round(st["peak_in_flight_gb"], 3),
-        "plain_per_slice": {"recon_per_s": round(pl["recon_per_s"], 4),
-                            "p50_ms": round(pl["p50_ms"], 2), "p99_ms": round(pl["p99_ms"], 2)},
-        "check_vs_alone": {"requests": int(len(picks)), "max_rel_l2_f": float("%.3g" % worst[0]),
-                           "max_rel_l2_mu": float("%.3g" % worst[1]), "same_decisions": same,
-                           "same_decisions_max_rel_l2": [float("%.3g" % v) for v in worst_same]},
+        "config": dict({"workload": "serve_poisson_%g_per_s_%gs" % (args.rate, args.duration)}, **sv["config"]),
+        "serving": sv,
     }
     print(json.dumps(out), flush=True)
 
@@ -789,6 +827,15 @@ def main():
         print("bench: BF16 storage %.2f recon/s" % bf16["value"], file=sys.stderr, flush=True)
         del plan_b
 
+    # the serving half of the metric: a Poisson trace over the mixed sizes
+    # through the iteration-level continuous-batching server, beside the
+    # plain per-slice solver on the same trace
+    serving = None
+    if args.serve_rate > 0 and args.grid == 128 and args.storage == "fp32":
+        serving = serving_measure(torch, pget, args.serve_rate, args.serve_duration, args.pool, args.outer,
+                                  args.cg, args.solver, server="iter", capacity=args.capacity,
+                                  hbm_budget_gb=args.hbm_budget_gb)
+
     cpu = None
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
@@ -827,6 +874,7 @@ def main():
         "kernel_time_share": kernel_share,
         "instrumented_step_ms": round(1e3 * instrumented_s, 3),
         "single_slice": single,
+        "serving": serving,
         "final_phi_mean": float(np.mean([r.phi[-1] for r in reps])),
     }
     print(json.dumps(out), flush=True)

@@ -397,6 +397,41 @@ pget_status pget_lm_solve_multi(int32_t n_slices, const pget_plan* const* plans,
 pget_status pget_autotune(pget_plan* plan, int32_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
 int32_t pget_tuned_shape(const pget_plan* plan, int32_t batch, int32_t* japb, int32_t* vjp_groups);
 
+/*
+ * Slot pools: continuous batching at outer-iteration boundaries (Sec. 2.2's
+ * outer LM iteration is the unit of admission and retirement).  A pool
+ * keeps `capacity` slots of one plan's shape, each holding one slice's
+ * whole LM state on the device; slots at different outer iterations run in
+ * the same launches.  pget_lm_pool_load puts a slice into a free slot;
+ * pget_lm_pool_step runs ONE outer iteration of every loaded, unfinished
+ * slot (its initial damping at its first iteration) and writes, to
+ * `finished` (capacity int32, host or device memory of the caller, written
+ * asynchronously), 1 for every slot whose solve has stopped (max_outer,
+ * tolerance, damping overflow, non-finite) or that is free, else 0;
+ * pget_lm_pool_fetch copies a slot's maps and report out and frees the slot
+ * (fetching an unfinished slot cancels its solve at the iteration boundary:
+ * the maps are its current iterate).  Each slice's result is the one
+ * pget_lm_solve gives for it alone, bit for bit, whatever the other slots
+ * hold.  Rules: params->n_cg must equal the pool's n_cg and
+ * params->max_outer be at most the pool's; no hook; every call of a pool on
+ * one stream (or ordered by the caller); a pool is not thread-safe.  The
+ * step is captured as a HIP graph on its first call and replayed (unless
+ * graphs are off or timing is on).  ws: pget_lm_pool_workspace_bytes bytes,
+ * owned by the caller, alive until pget_lm_pool_destroy; the pool object
+ * itself holds only host-side bookkeeping.  Errors: INVALID_ARG (bad slot,
+ * slot busy on load or free on fetch, parameters), WORKSPACE, HIP.
+ */
+typedef struct pget_lm_pool pget_lm_pool;
+size_t pget_lm_pool_workspace_bytes(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg);
+pget_status pget_lm_pool_create(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg,
+                                void* ws, size_t ws_bytes, hipStream_t stream, pget_lm_pool** out);
+void pget_lm_pool_destroy(pget_lm_pool* pool);
+pget_status pget_lm_pool_load(pget_lm_pool* pool, int32_t slot, const float* y, const float* f0, const float* mu0,
+                              const pget_lm_params* params, hipStream_t stream);
+pget_status pget_lm_pool_step(pget_lm_pool* pool, int32_t* finished, hipStream_t stream);
+pget_status pget_lm_pool_fetch(pget_lm_pool* pool, int32_t slot, float* f_out, float* mu_out,
+                               const pget_lm_report* report, hipStream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char* pget_status_string(pget_status status);
 

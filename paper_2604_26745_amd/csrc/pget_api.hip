@@ -1185,12 +1185,17 @@ void enqueue_step_eval(Solve& S)
 // product K^T K J p, a gather and the q / x updates; the trial point
 // u' = clamp(u + x); the model decrease and Phi(u'); the decision (rho, beta).
 // Every decision is taken on the device.
-void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_present, bool trace)
+void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_present, bool trace,
+                       bool pool = false)
 {
     const dim3 ew(S.sh.n_ew_blocks, S.B);
     enqueue_march(S, S.lin, MARCH_LIN);
-    if (k == 0 && need_beta0) {
-        enqueue_jvp(S, S.jones, JVP_SQNORM);
+    // the initial damping: at k = 0 of a solve, or in a slot pool (slots at
+    // different iterations) for the slices at iteration 0
+    if ((k == 0 && need_beta0) || pool) {
+        JvpArgs J1 = S.jones;
+        J1.only_k0 = pool ? 1 : 0;
+        enqueue_jvp(S, J1, JVP_SQNORM);
         {
             Timed t_(PGET_KC_CONTROL, S.stream);
             hipLaunchKernelGGL(k_beta0, dim3(S.B), dim3(256), 0, S.stream, S.V);
@@ -1255,7 +1260,7 @@ void enqueue_commit(Solve& S)
     }
     {
         Timed t_(PGET_KC_CONTROL, S.stream);
-        hipLaunchKernelGGL(k_commit, dim3((S.B + 63) / 64), dim3(64), 0, S.stream, S.V.st, S.B);
+        hipLaunchKernelGGL(k_commit, dim3((S.B + 63) / 64), dim3(64), 0, S.stream, S.V.st, S.V.prm, S.B);
     }
 }
 
@@ -1360,6 +1365,32 @@ size_t group_bytes(const pget_plan* P, int B)
     return align_up(layout_for(P, PGET_OP_LM, B, sh, 256, 256).total);
 }
 
+// Device report arrays of every slice of a solve, in its workspace.
+void report_arrays(const Solve& S, int max_outer, int n_cg, std::vector<ReportDev>& rep)
+{
+    rep.assign(S.B, ReportDev{});
+    const size_t per = align_up((size_t)(max_outer + 1) * 8 * sizeof(double) + 2 * (size_t)max_outer +
+                                (size_t)max_outer * n_cg * sizeof(double) + 4 * sizeof(double) + 64);
+    for (int b = 0; b < S.B; ++b) {
+        char* base = at(S.ws, S.L.reparr + (size_t)b * per);
+        size_t o = 0;
+        auto take = [&](size_t bytes) { char* p = base + o; o += (bytes + 7) / 8 * 8; return p; };
+        ReportDev& R = rep[b];
+        R.phi = reinterpret_cast<double*>(take((max_outer + 1) * sizeof(double)));
+        R.rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.beta = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.ared = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.gnorm = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.cg_rr = reinterpret_cast<double*>(take((size_t)max_outer * n_cg * sizeof(double)));
+        R.hook_rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.hook_pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
+        R.scalars = reinterpret_cast<double*>(take(4 * sizeof(double)));
+        R.accepted = reinterpret_cast<int8_t*>(take(max_outer));
+        R.hook_accepted = reinterpret_cast<int8_t*>(take(max_outer));
+    }
+}
+
 // Validate, lay out and upload one group (uploads on `stream`).
 pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStream_t stream)
 {
@@ -1386,27 +1417,7 @@ pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStre
     const Geo& g = P->g;
     const size_t n2 = (size_t)g.n * g.n, sino = (size_t)g.n_angles * g.n_bins;
     const int max_outer = G.max_outer, n_cg = G.n_cg;
-    G.rep.assign(B, ReportDev{});
-    const size_t per = align_up((size_t)(max_outer + 1) * 8 * sizeof(double) + 2 * (size_t)max_outer +
-                                (size_t)max_outer * n_cg * sizeof(double) + 4 * sizeof(double) + 64);
-    for (int b = 0; b < B; ++b) {
-        char* base = at(ws, S.L.reparr + (size_t)b * per);
-        size_t o = 0;
-        auto take = [&](size_t bytes) { char* p = base + o; o += (bytes + 7) / 8 * 8; return p; };
-        ReportDev& R = G.rep[b];
-        R.phi = reinterpret_cast<double*>(take((max_outer + 1) * sizeof(double)));
-        R.rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        R.beta = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        R.pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        R.ared = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        R.gnorm = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        R.cg_rr = reinterpret_cast<double*>(take((size_t)max_outer * n_cg * sizeof(double)));
-        R.hook_rho = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        R.hook_pred = reinterpret_cast<double*>(take(max_outer * sizeof(double)));
-        R.scalars = reinterpret_cast<double*>(take(4 * sizeof(double)));
-        R.accepted = reinterpret_cast<int8_t*>(take(max_outer));
-        R.hook_accepted = reinterpret_cast<int8_t*>(take(max_outer));
-    }
+    report_arrays(S, max_outer, n_cg, G.rep);
     HIP_TRY(hipMemcpyAsync(const_cast<LMParamsDev*>(S.V.prm), G.prm.data(), B * sizeof(LMParamsDev),
                            hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(S.V.rep, G.rep.data(), B * sizeof(ReportDev), hipMemcpyHostToDevice, stream));
@@ -1779,6 +1790,174 @@ pget_status pget_lm_solve_batched(const pget_plan* plan, int32_t n_slices, const
                                   void* ws, hipStream_t stream)
 {
     return solve_impl(plan, n_slices, y, f_inout, mu_inout, params, reports, nullptr, nullptr, ws, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ slot pools
+// Continuous batching at outer-iteration boundaries: `cap` slots of one
+// plan share every launch of an outer iteration; each slot holds one
+// slice's whole LM state on the device and runs at its own iteration count.
+struct pget_lm_pool {
+    const pget_plan* P = nullptr;
+    int cap = 0, max_outer = 0, n_cg = 0;
+    Solve S;
+    std::vector<LMParamsDev> prm;   // host copies of the slots' parameters
+    std::vector<ReportDev> rep;     // the slots' device report arrays
+    std::vector<char> loaded;       // host view: slot holds a slice
+    int* flags = nullptr;           // device: 1 where a slot's solve has finished
+    hipGraphExec_t step_graph = nullptr;
+};
+
+namespace {
+
+size_t pool_bytes(const pget_plan* P, int cap, int max_outer, int n_cg, Layout* out)
+{
+    Shapes sh = shapes_for(P, cap);
+    Layout L = layout_for(P, PGET_OP_LM, cap, sh, max_outer, n_cg);
+    if (out) *out = L;
+    return L.total + align_up((size_t)cap * sizeof(int));
+}
+
+// One outer iteration of every unfinished slot, then the report's objective
+// and scalars of every slot and the finished flags.
+void enqueue_pool_step(pget_lm_pool* Q, hipStream_t s)
+{
+    Solve S = Q->S;
+    S.stream = s;
+    enqueue_iteration(S, 1, Q->n_cg, true, false, true, true);
+    enqueue_commit(S);
+    hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, S.B), dim3(EW_THREADS), 0, s, S.V);
+    hipLaunchKernelGGL(k_finish, dim3(S.B), dim3(256), 0, s, S.V);
+    hipLaunchKernelGGL(k_pool_flags, dim3((S.B + 63) / 64), dim3(64), 0, s, S.V.st, Q->flags, S.B);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pget_lm_pool_workspace_bytes(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg)
+{
+    if (!plan || capacity < 1 || max_outer < 1 || max_outer > 256 || n_cg < 1 || n_cg > 256) return 0;
+    return pool_bytes(plan, capacity, max_outer, n_cg, nullptr);
+}
+
+pget_status pget_lm_pool_create(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg, void* ws,
+                                size_t ws_bytes, hipStream_t stream, pget_lm_pool** out)
+{
+    if (!out) return PGET_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!plan || capacity < 1 || max_outer < 1 || max_outer > 256 || n_cg < 1 || n_cg > 256)
+        return PGET_ERR_INVALID_ARG;
+    if (!ws) return PGET_ERR_WORKSPACE;
+    Layout L;
+    const size_t need = pool_bytes(plan, capacity, max_outer, n_cg, &L);
+    if (ws_bytes < need) return PGET_ERR_WORKSPACE;
+    pget_lm_pool* Q = new (std::nothrow) pget_lm_pool();
+    if (!Q) return PGET_ERR_HIP;
+    Q->P = plan;
+    Q->cap = capacity;
+    Q->max_outer = max_outer;
+    Q->n_cg = n_cg;
+    Solve& S = Q->S;
+    S.P = plan;
+    S.B = capacity;
+    S.sh = shapes_for(plan, capacity);
+    S.L = L;
+    S.ws = ws;
+    S.stream = stream;
+    setup(S);
+    Q->flags = reinterpret_cast<int*>(at(ws, L.total));
+    Q->prm.assign(capacity, LMParamsDev{});
+    Q->loaded.assign(capacity, 0);
+    report_arrays(S, max_outer, n_cg, Q->rep);
+    // weights outside the support are never written and must read as zero;
+    // every slot starts free (finished)
+    fill_zero(S.lin.wts, (size_t)capacity * S.lin.wts_stride * plan->w_bytes, stream);
+    if (S.lin.wq) fill_zero(S.lin.wq, (size_t)capacity * S.lin.wts_stride * sizeof(float), stream);
+    hipLaunchKernelGGL(k_pool_clear, dim3((capacity + 63) / 64), dim3(64), 0, stream, S.V.st, capacity);
+    hipLaunchKernelGGL(k_pool_flags, dim3((capacity + 63) / 64), dim3(64), 0, stream, S.V.st, Q->flags, capacity);
+    bool ok = hipMemcpyAsync(S.V.rep, Q->rep.data(), capacity * sizeof(ReportDev), hipMemcpyHostToDevice, stream) ==
+                  hipSuccess &&
+              hipStreamSynchronize(stream) == hipSuccess && hipGetLastError() == hipSuccess;
+    if (!ok) {
+        delete Q;
+        return PGET_ERR_HIP;
+    }
+    *out = Q;
+    return PGET_OK;
+}
+
+void pget_lm_pool_destroy(pget_lm_pool* pool)
+{
+    if (!pool) return;
+    if (pool->step_graph) (void)hipGraphExecDestroy(pool->step_graph);
+    delete pool;
+}
+
+pget_status pget_lm_pool_load(pget_lm_pool* Q, int32_t slot, const float* y, const float* f0, const float* mu0,
+                              const pget_lm_params* params, hipStream_t stream)
+{
+    if (!Q || slot < 0 || slot >= Q->cap || !y || !f0 || !mu0 || !params_ok(params)) return PGET_ERR_INVALID_ARG;
+    if (Q->loaded[slot] || params->max_outer > Q->max_outer || params->n_cg != Q->n_cg) return PGET_ERR_INVALID_ARG;
+    Solve& S = Q->S;
+    const Geo& g = Q->P->g;
+    const size_t n2 = (size_t)g.n * g.n, sino = (size_t)g.n_angles * g.n_bins;
+    Q->prm[slot] = to_dev(*params);
+    LMParamsDev* prm_dev = const_cast<LMParamsDev*>(S.V.prm) + slot;
+    float* ymeas = reinterpret_cast<float*>(at(S.ws, S.L.ymeas));
+    HIP_TRY(hipMemcpyAsync(prm_dev, &Q->prm[slot], sizeof(LMParamsDev), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ymeas + slot * sino, y, sino * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(S.V.u + slot * 2 * n2, f0, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(S.V.u + slot * 2 * n2 + n2, mu0, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    hipLaunchKernelGGL(k_lm_init, dim3(1), dim3(64), 0, stream, S.V.st + slot, prm_dev, 1);
+    HIP_TRY(hipGetLastError());
+    Q->loaded[slot] = 1;
+    return PGET_OK;
+}
+
+pget_status pget_lm_pool_step(pget_lm_pool* Q, int32_t* finished, hipStream_t stream)
+{
+    if (!Q) return PGET_ERR_INVALID_ARG;
+    const bool graph_ok = g_use_graphs && g_timing.classes == 0;
+    if (!graph_ok) {
+        enqueue_pool_step(Q, stream);
+    } else {
+        if (!Q->step_graph) {
+            hipStream_t cs = g_pool.get(0);
+            if (!cs) return PGET_ERR_HIP;
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            enqueue_pool_step(Q, cs);
+            HIP_TRY(hipStreamEndCapture(cs, &graph));
+            hipError_t e = hipGraphInstantiate(&Q->step_graph, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                Q->step_graph = nullptr;
+                return PGET_ERR_HIP;
+            }
+        }
+        HIP_TRY(hipGraphLaunch(Q->step_graph, stream));
+    }
+    if (finished)
+        HIP_TRY(hipMemcpyAsync(finished, Q->flags, Q->cap * sizeof(int), hipMemcpyDefault, stream));
+    return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+pget_status pget_lm_pool_fetch(pget_lm_pool* Q, int32_t slot, float* f_out, float* mu_out,
+                               const pget_lm_report* report, hipStream_t stream)
+{
+    if (!Q || slot < 0 || slot >= Q->cap || !Q->loaded[slot]) return PGET_ERR_INVALID_ARG;
+    Solve& S = Q->S;
+    const size_t n2 = (size_t)Q->P->g.n * Q->P->g.n;
+    if (f_out) HIP_TRY(hipMemcpyAsync(f_out, S.V.u + slot * 2 * n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    if (mu_out)
+        HIP_TRY(hipMemcpyAsync(mu_out, S.V.u + slot * 2 * n2 + n2, n2 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    if (report) copy_report(Q->rep[slot], report, Q->prm[slot].max_outer, Q->n_cg, stream);
+    hipLaunchKernelGGL(k_pool_release, dim3(1), dim3(64), 0, stream, S.V.st, slot);
+    HIP_TRY(hipGetLastError());
+    Q->loaded[slot] = 0;
+    return PGET_OK;
 }
 
 }  // extern "C"

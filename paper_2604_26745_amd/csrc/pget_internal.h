@@ -186,7 +186,7 @@ struct JvpArgs {
     double* part;
     int slot;               // SQNORM: slot of ||K z||^2
     const LMState* st;
-    int skip_if_clean;      // for the initial-damping probe: run only when dirty
+    int only_k0;            // initial-damping probe of a slot pool: only slices at iteration 0
     int angles_per_block;   // angle slots per block (a slot is an angle pair when paired)
 };
 
@@ -267,6 +267,9 @@ __global__ void k_hook_decide(VecArgs V);
 __global__ void k_accept(VecArgs V);
 __global__ void k_final_reg(VecArgs V);
 __global__ void k_finish(VecArgs V);
-__global__ void k_commit(LMState* st, int n_slices);
+__global__ void k_commit(LMState* st, const LMParamsDev* prm, int n_slices);
+__global__ void k_pool_clear(LMState* st, int n_slices);
+__global__ void k_pool_release(LMState* st, int slot);
+__global__ void k_pool_flags(const LMState* st, int* flags, int n_slices);
 
 }  // namespace pget

@@ -462,6 +462,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const Geo& g = A.g;
     const int slice = blockIdx.y;
     if (A.st && A.st[slice].done) return;
+    if (A.only_k0 && A.st && A.st[slice].k != 0) return;   // initial-damping probe of a slot pool
     const int per_slot = g.paired ? 2 : 1;
     const int n_slots = g.paired ? g.n_angles / 2 : g.n_angles;
     const int slot0 = blockIdx.x * A.angles_per_block;
@@ -1480,6 +1481,7 @@ __global__ void __launch_bounds__(256) k_beta0(VecArgs V)
     const int slice = blockIdx.x;
     LMState& st = V.st[slice];
     const LMParamsDev& P = V.prm[slice];
+    if (st.done || st.k != 0) return;   // block-uniform
     double j1 = sum_partials(slot_ptr(V.part, slice, SLOT_J1), V.n_angle_parts, sh);
     if (threadIdx.x == 0 && P.beta0 <= 0.0) {
         const double n2 = (double)V.g.n * V.g.n;
@@ -1628,12 +1630,36 @@ __global__ void __launch_bounds__(EW_THREADS) k_accept(VecArgs V)
     }
 }
 
-// End of an outer iteration: apply a stop decided in k_decide.
-__global__ void k_commit(LMState* st, int n_slices)
+// End of an outer iteration: apply a stop decided in k_decide, or the end
+// of the slice's max_outer iterations.
+__global__ void k_commit(LMState* st, const LMParamsDev* prm, int n_slices)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_slices) return;
-    if (st[s].done_next) st[s].done = 1;
+    if (st[s].done_next || st[s].k >= prm[s].max_outer) st[s].done = 1;
+}
+
+// Slot pool: every slot finished (free slots are kept finished).
+__global__ void k_pool_clear(LMState* st, int n_slices)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slices) return;
+    LMState z = {};
+    z.done = 1;
+    st[s] = z;
+}
+
+// Slot pool: stop slot `slot` (its result was fetched, or it was cancelled).
+__global__ void k_pool_release(LMState* st, int slot)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[slot].done = 1;
+}
+
+// Slot pool: 1 where a slot's solve has finished, else 0.
+__global__ void k_pool_flags(const LMState* st, int* flags, int n_slices)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_slices) flags[s] = st[s].done ? 1 : 0;
 }
 
 // Regulariser energy of the returned maps with the alphas of iteration

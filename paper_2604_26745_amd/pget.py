@@ -131,6 +131,19 @@ def load_library():
     lib.pget_lm_solve_batched.argtypes = [V, ctypes.c_int32, P(V), P(V), P(V), P(LMParams),
                                           P(LMReportC), V, V]
     lib.pget_lm_solve_batched.restype = ctypes.c_int
+    lib.pget_lm_pool_workspace_bytes.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.pget_lm_pool_workspace_bytes.restype = ctypes.c_size_t
+    lib.pget_lm_pool_create.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, V, ctypes.c_size_t, V,
+                                        P(V)]
+    lib.pget_lm_pool_create.restype = ctypes.c_int
+    lib.pget_lm_pool_destroy.argtypes = [V]
+    lib.pget_lm_pool_destroy.restype = None
+    lib.pget_lm_pool_load.argtypes = [V, ctypes.c_int32, V, V, V, P(LMParams), V]
+    lib.pget_lm_pool_load.restype = ctypes.c_int
+    lib.pget_lm_pool_step.argtypes = [V, V, V]
+    lib.pget_lm_pool_step.restype = ctypes.c_int
+    lib.pget_lm_pool_fetch.argtypes = [V, ctypes.c_int32, V, V, P(LMReportC), V]
+    lib.pget_lm_pool_fetch.restype = ctypes.c_int
     lib.pget_status_string.argtypes = [ctypes.c_int]
     lib.pget_status_string.restype = ctypes.c_char_p
     _lib = lib
@@ -589,3 +602,66 @@ def pget_lm_solve(plan: Plan, y, f0, mu0, params: SolverParams, hook=None):
 
 def pget_lm_solve_batched(plan: Plan, ys, f0s, mu0s, params):
     return plan.lm_solve_batched(ys, f0s, mu0s, params)
+
+
+class LMPool:
+    """A slot pool of one plan (pget_lm_pool_*): continuous batching at
+    outer-iteration boundaries.  All calls go to the stream current at
+    construction (or `stream`).  Argument marshalling only."""
+
+    def __init__(self, plan: "Plan", capacity: int, max_outer: int, n_cg: int, stream=None):
+        torch = _torch()
+        self.plan, self.lib = plan, plan.lib
+        self.capacity, self.max_outer, self.n_cg = capacity, max_outer, n_cg
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nbytes = self.lib.pget_lm_pool_workspace_bytes(plan.handle, capacity, max_outer, n_cg)
+        if nbytes == 0:
+            raise PgetError(-1, "pget_lm_pool_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.finished = torch.zeros(capacity, dtype=torch.int32).pin_memory()
+        self.keep = [None] * capacity      # per slot: inputs, parameters, report buffers
+        self.handle = ctypes.c_void_p()
+        _check(self.lib.pget_lm_pool_create(plan.handle, capacity, max_outer, n_cg, _ptr(self.ws), nbytes,
+                                            self.stream.cuda_stream, ctypes.byref(self.handle)),
+               "pget_lm_pool_create")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and getattr(self, "lib", None) is not None:
+            self.lib.pget_lm_pool_destroy(h)
+            self.handle = ctypes.c_void_p()
+
+    def load(self, slot: int, y, f0, mu0, params: SolverParams):
+        p = self.plan
+        y, f0, mu0 = p._sino(y), p._img(f0), p._img(mu0)
+        prm, keep = params.to_c(p.n)
+        self.keep[slot] = (y, f0, mu0, prm, keep)
+        _check(self.lib.pget_lm_pool_load(self.handle, slot, _ptr(y), _ptr(f0), _ptr(mu0), ctypes.byref(prm),
+                                          self.stream.cuda_stream), "pget_lm_pool_load")
+
+    def step(self):
+        """Enqueue one outer iteration; returns an event recorded after it
+        (the `finished` flags are valid once it has completed)."""
+        torch = _torch()
+        _check(self.lib.pget_lm_pool_step(self.handle, ctypes.c_void_p(self.finished.data_ptr()),
+                                          self.stream.cuda_stream), "pget_lm_pool_step")
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    def fetch(self, slot: int, report: bool = True):
+        """Maps (and report buffers) of a slot, which becomes free."""
+        torch = _torch()
+        n = self.plan.n
+        f = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        mu = torch.empty_like(f)
+        held = self.keep[slot] if 0 <= slot < self.capacity else None
+        mo = held[3].max_outer if held is not None else self.max_outer
+        rb = _ReportBuffers(mo, self.n_cg, "cuda") if report else None
+        rc = rb.c() if rb is not None else None
+        _check(self.lib.pget_lm_pool_fetch(self.handle, slot, _ptr(f), _ptr(mu),
+                                           ctypes.byref(rc) if rc is not None else None, self.stream.cuda_stream),
+               "pget_lm_pool_fetch")
+        if 0 <= slot < self.capacity:
+            self.keep[slot] = None
+        return f, mu, rb

@@ -217,7 +217,8 @@ def run_trace(server: Server, reqs: List[Request], timeout: float = 600.0) -> di
             i += 1
         done += server.poll(now)
         server.admit(now)
-        if not server.in_flight and i < n and not server.queue:
+        queued = server.queued() if hasattr(server, "queued") else len(server.queue)
+        if not server.in_flight and i < n and not queued:
             time.sleep(max(0.0, min(0.002, reqs[i].arrival - now)))
         else:
             time.sleep(0.0002)
@@ -267,3 +268,154 @@ def make_trace(rate: float, duration: float, pool: List[Slice], seed: int = 0) -
     rng = np.random.default_rng([seed, 4])
     picks = rng.integers(0, len(pool), size=len(arr))
     return [Request(k, float(t), pool[int(p)].cfg.n, int(p)) for k, (t, p) in enumerate(zip(arr, picks))]
+
+
+# ---------------------------------------------------------------------------
+# Continuous batching at outer-iteration boundaries.
+#
+# Each grid size has a slot pool (pget_lm_pool) on its own stream: one step
+# is one outer LM iteration of every occupied slot.  Between steps, slots
+# whose solve has stopped (max_outer, early-exit tolerance, damping
+# overflow, non-finite) are retired and queued requests of that size take
+# the free slots at once, so a request waits at most one outer iteration of
+# its size for admission and never for a whole batch to finish.  Pools of
+# different sizes step concurrently on their streams.
+
+
+class GpuPool:
+    """One size's slot pool on the GPU (pget.LMPool) behind the interface
+    the iteration-level server drives: capacity, load, step, done,
+    finished, fetch."""
+
+    def __init__(self, plan: pget.Plan, pool: List[Slice], params: pget.SolverParams, capacity: int):
+        import torch
+        self.torch = torch
+        self.pool, self.params = pool, params
+        self.stream = torch.cuda.Stream()   # default priority
+        with torch.cuda.stream(self.stream):
+            self.p = pget.LMPool(plan, capacity, params.max_outer, params.n_cg, stream=self.stream)
+        self.capacity = capacity
+        self.nbytes = int(self.p.ws.numel())
+        self.outputs: Dict[int, tuple] = {}   # rid -> (f, mu) of served requests (kept if keep_outputs)
+        self.keep_outputs = False
+
+    def load(self, slot: int, req: Request):
+        sl = self.pool[req.slot]
+        self.p.load(slot, sl.y, sl.f0, sl.mu0, self.params)
+
+    def step(self):
+        return self.p.step()
+
+    def done(self, handle) -> bool:
+        return handle.query()
+
+    def finished(self) -> List[int]:
+        return self.p.finished.tolist()
+
+    def fetch(self, slot: int, req: Request):
+        f, mu, _ = self.p.fetch(slot, report=False)
+        if self.keep_outputs:
+            self.outputs[req.rid] = (f, mu)
+
+
+class IterServer:
+    """Admission at outer-iteration boundaries into per-size slot pools.
+    Same driving interface as Server (queue, poll, admit, in_flight,
+    batches, max_in_flight_bytes), executor-agnostic: `pools` maps a grid
+    size to an object with capacity, load(slot, req), step() -> handle,
+    done(handle), finished() -> per-slot flags, fetch(slot, req)."""
+
+    def __init__(self, pools: Dict[int, object], hbm_budget: float = 64e9):
+        self.pools = pools
+        total = sum(getattr(p, "nbytes", 0) for p in pools.values())
+        if total > hbm_budget:
+            raise ValueError("slot pools need %.1f GB, over the %.1f GB budget" % (total / 1e9, hbm_budget / 1e9))
+        self.max_in_flight_bytes = total
+        self.queue: deque = deque()       # inbox (arrival order); sorted into per-size queues
+        self.waiting: Dict[int, deque] = {s: deque() for s in pools}
+        self.slots: Dict[int, List[Optional[Request]]] = {s: [None] * p.capacity for s, p in pools.items()}
+        self.step_handle: Dict[int, object] = {s: None for s in pools}
+        self.batches: List[int] = []      # occupied slots per step
+        self.cancelled_rids: set = set()
+
+    @property
+    def in_flight(self):
+        return [s for s, held in self.slots.items() if any(r is not None for r in held)]
+
+    def queued(self) -> int:
+        return len(self.queue) + sum(len(q) for q in self.waiting.values())
+
+    def cancel(self, rid: int, now: float) -> int:
+        """A queued request leaves at once (returns 1); an admitted one is
+        fetched at its pool's next iteration boundary and dropped from the
+        statistics (returns 0: poll completes it)."""
+        self._sort_inbox()
+        for q in self.waiting.values():
+            for r in q:
+                if r.rid == rid:
+                    q.remove(r)
+                    r.cancelled, r.done = True, now
+                    return 1
+        for held in self.slots.values():
+            for r in held:
+                if r is not None and r.rid == rid:
+                    r.cancelled = True
+        return 0
+
+    def _sort_inbox(self):
+        while self.queue:
+            r = self.queue.popleft()
+            self.waiting[r.size].append(r)
+
+    def poll(self, now: float) -> int:
+        """Retire finished (or cancelled) slots of every pool whose last step
+        has completed; returns the number of requests completed."""
+        done = 0
+        for size, pool in self.pools.items():
+            h = self.step_handle[size]
+            if h is None or not pool.done(h):
+                continue
+            self.step_handle[size] = None
+            flags = pool.finished()
+            for slot, r in enumerate(self.slots[size]):
+                if r is not None and (flags[slot] or r.cancelled):
+                    pool.fetch(slot, r)
+                    r.done = now
+                    self.slots[size][slot] = None
+                    done += 1
+        return done
+
+    def admit(self, now: float):
+        """Load queued requests (arrival order) into the free slots of their
+        size's pool, then start the next step of every idle pool that holds
+        work."""
+        self._sort_inbox()
+        for size, pool in self.pools.items():
+            if self.step_handle[size] is not None:
+                continue
+            held, q = self.slots[size], self.waiting[size]
+            for slot in range(pool.capacity):
+                if held[slot] is not None:
+                    continue
+                if not q:
+                    break
+                req = q.popleft()
+                pool.load(slot, req)
+                req.admit, req.batch = now, pool.capacity
+                held[slot] = req
+            busy = sum(r is not None for r in held)
+            if busy:
+                self.step_handle[size] = pool.step()
+                self.batches.append(busy)
+
+
+def make_pools(plans: Dict[int, pget.Plan], pool: List[Slice], params: pget.SolverParams,
+               capacity: Dict[int, int]) -> Dict[int, GpuPool]:
+    """A GPU slot pool per size, warmed (its step graph captured) before
+    the trace starts."""
+    import torch
+    pools = {n: GpuPool(plans[n], pool, params, capacity[n]) for n in plans}
+    for n, gp in pools.items():
+        gp.step().synchronize()     # captures the step graph on empty slots
+    torch.cuda.synchronize()
+    return pools

@@ -141,3 +141,29 @@ def test_autotuned_shapes_keep_every_bit(mixed_pool):
     log("tuned shape %s" % shape)
     f2, m2, r2 = plan.lm_solve(sl.y, sl.f0, sl.mu0, prm)
     assert torch.equal(f1, f2) and torch.equal(m1, m2) and same_report(r1, r2)
+
+
+def test_iteration_level_served_requests_equal_alone(mixed_pool):
+    """The same, served by per-size slot pools that admit requests at every
+    outer-iteration boundary (slots at different iterations share launches)."""
+    plans, pool = mixed_pool
+    prm = pget.SolverParams(max_outer=5, n_cg=10, tol=1e-4, **SCALED)
+    pools = serve.make_pools(plans, pool, prm, {n: 3 for n in plans})
+    for gp in pools.values():
+        gp.keep_outputs = True
+    srv = serve.IterServer(pools, hbm_budget=1e12)
+    reqs = [serve.Request(k, 0.003 * k, pool[k % len(pool)].cfg.n, k % len(pool)) for k in range(24)]
+    st = serve.run_trace(srv, reqs, timeout=300)
+    log("served %d requests through slot pools, mean occupancy %.2f" % (st["requests"], st["mean_batch"]))
+    assert st["requests"] == 24
+    outputs = {}
+    for gp in pools.values():
+        outputs.update(gp.outputs)
+    torch.cuda.synchronize()
+    alone = {}
+    for r in reqs:
+        if r.slot not in alone:
+            sl = pool[r.slot]
+            alone[r.slot] = plans[r.size].lm_solve(sl.y, sl.f0, sl.mu0, prm)
+        f, m = outputs[r.rid]
+        assert torch.equal(f, alone[r.slot][0]) and torch.equal(m, alone[r.slot][1]), r.rid

@@ -139,3 +139,110 @@ def test_cancelled_requests():
     assert reqs[0].cancelled and reqs[2].cancelled and not reqs[1].cancelled
     st = serve.summarize(reqs, t, srv.batches, 0)
     assert st["requests"] == 2 and st["cancelled"] == 2
+
+
+class FakePool:
+    """A slot pool whose slots finish after `iters[slot]` steps; a step takes
+    `dt` simulated seconds."""
+
+    def __init__(self, capacity, iters_of, dt, clock):
+        self.capacity, self.iters_of, self.dt, self.clock = capacity, iters_of, dt, clock
+        self.left = [None] * capacity
+        self.loads, self.fetches, self.steps = [], [], []
+
+    def load(self, slot, req):
+        assert self.left[slot] is None
+        self.left[slot] = self.iters_of(req)
+        self.loads.append((self.clock[0], slot, req.rid))
+
+    def step(self):
+        busy = [s for s in range(self.capacity) if self.left[s] is not None]
+        self.steps.append(busy)
+        for s in busy:
+            self.left[s] = max(0, self.left[s] - 1)
+        return self.clock[0] + self.dt
+
+    def done(self, h):
+        return self.clock[0] >= h
+
+    def finished(self):
+        return [1 if (x is None or x == 0) else 0 for x in self.left]
+
+    def fetch(self, slot, req):
+        self.fetches.append((self.clock[0], slot, req.rid))
+        self.left[slot] = None
+
+
+def drive_iter(server, clock, reqs, dt=1e-3, horizon=100.0):
+    i, done, n = 0, 0, len(reqs)
+    t = 0.0
+    while done < n:
+        assert t < horizon
+        clock[0] = t
+        while i < n and reqs[i].arrival <= t:
+            server.queue.append(reqs[i])
+            i += 1
+        done += server.poll(t)
+        server.admit(t)
+        t += dt
+    return t
+
+
+def test_iteration_level_admission_refills_slots_at_step_boundaries():
+    """A request arriving while a long solve runs joins the same pool at the
+    next step boundary and leaves as soon as its own iterations are done,
+    before the long solve ends; freed slots take queued requests at once."""
+    clock = [0.0]
+    iters = {0: 15, 1: 3, 2: 3, 3: 2}
+    pool = FakePool(2, lambda r: iters[r.rid], 0.01, clock)
+    srv = serve.IterServer({64: pool}, hbm_budget=1e9)
+    reqs = [R(0, 0.0, 64), R(1, 0.0305, 64), R(2, 0.0305, 64), R(3, 0.0306, 64)]
+    drive_iter(srv, clock, reqs)
+    # request 1 is loaded at the first boundary after its arrival, into the free slot
+    t_load1 = next(t for t, s, rid in pool.loads if rid == 1)
+    assert 0.0305 <= t_load1 <= 0.041
+    # 1 finishes after its 3 steps, long before request 0 (15 steps)
+    assert reqs[1].done < reqs[0].done
+    assert reqs[0].done == pytest.approx(0.15, abs=0.011)
+    # 2 takes the slot 1 left; 3 follows 2
+    assert reqs[1].done <= next(t for t, s, rid in pool.loads if rid == 2) + 1e-9
+    assert reqs[2].done < reqs[3].done < reqs[0].done
+    # every step ran on at most 2 slots, never idle while work was loaded
+    assert max(len(b) for b in pool.steps) == 2
+    assert srv.batches and max(srv.batches) == 2
+
+
+def test_iteration_level_pools_per_size_and_cancel():
+    clock = [0.0]
+    a = FakePool(1, lambda r: 4, 0.01, clock)
+    b = FakePool(1, lambda r: 2, 0.02, clock)
+    srv = serve.IterServer({64: a, 128: b}, hbm_budget=1e9)
+    reqs = [R(0, 0.0, 64), R(1, 0.0, 128), R(2, 0.001, 64), R(3, 0.002, 64)]
+    i = 0
+    t = 0.0
+    cancelled_queued = False
+    done = 0
+    while done < 4:
+        clock[0] = t
+        while i < 4 and reqs[i].arrival <= t:
+            srv.queue.append(reqs[i])
+            i += 1
+        if t >= 0.003 and not cancelled_queued:
+            done += srv.cancel(3, t)          # still queued: leaves at once
+            srv.cancel(0, t)                  # running: fetched at the next boundary
+            cancelled_queued = True
+        done += srv.poll(t)
+        srv.admit(t)
+        t += 1e-3
+        assert t < 10
+    assert reqs[3].cancelled and reqs[0].cancelled and not reqs[2].cancelled
+    assert reqs[0].done < 0.03              # cut short at the first boundary after the cancel
+    assert [rid for _, _, rid in b.fetches] == [1]
+    assert [rid for _, _, rid in a.fetches] == [0, 2]
+
+
+def test_iteration_level_budget():
+    class P:
+        capacity, nbytes = 4, 5e9
+    with pytest.raises(ValueError):
+        serve.IterServer({64: P(), 128: P()}, hbm_budget=8e9)
