@@ -229,6 +229,19 @@ pget_status pget_vjp(const pget_plan* plan, const float* f, const float* mu, con
  * prior_w = NULL: no prior; prior_ref = NULL: zero reference.  Weights must
  * be >= 0 (not checked: the solver reads them on the device); they are
  * divided by the same continuation factor as the alphas.
+ * step selects the solver of the damped step.  PGET_STEP_CG: n_cg CG steps
+ * on the normal equations as above, then the clamp into the box.
+ * PGET_STEP_SGP: the paper's scaled gradient projection (Sec. 2.2, after
+ * Bonettini, Zanella and Zanni) of the box-constrained step: n_cg
+ * iterations, each y = P_box(s - alpha W grad q(s)), d = y - s, an Armijo
+ * backtracking factor lambda (1, 0.4, 0.16, ...; sufficient decrease 1e-4,
+ * exact for the quadratic q), s += lambda d, and the next alpha from the two
+ * scaled Barzilai-Borwein rules with alternation (threshold 0.5, memory 3,
+ * alpha in [1e-10, 1e5], alpha_0 = 1); W = diag(w_f I, w_mu I) is the
+ * scaling, active_set is ignored, and cg_rr reports q(s) after each
+ * iteration.  One normal-operator product per iteration either way.  All
+ * slices of one batched or mixed call that share a plan must use the same
+ * step solver.
  * trace_u, trace_t (optional, for step-by-step checks against a reference
  * implementation): device buffers of max_outer x 2 N^2 floats owned by the
  * caller; outer iteration k writes the iterate u_k it linearises at (f
@@ -254,7 +267,11 @@ typedef struct {
     const float* prior_ref;   /* device, 2 N^2, or NULL                      */
     float* trace_u;           /* device, max_outer x 2 N^2, or NULL          */
     float* trace_t;           /* device, max_outer x 2 N^2, or NULL          */
+    int32_t step;             /* PGET_STEP_CG (0) or PGET_STEP_SGP (1)       */
 } pget_lm_params;
+
+/* Solvers of the damped step (pget_lm_params.step). */
+enum { PGET_STEP_CG = 0, PGET_STEP_SGP = 1 };
 
 /*
  * Per-solve report.  Every pointer is caller-owned and may be NULL (not
@@ -412,7 +429,8 @@ int32_t pget_tuned_shape(const pget_plan* plan, int32_t batch, int32_t* japb, in
  * (fetching an unfinished slot cancels its solve at the iteration boundary:
  * the maps are its current iterate).  Each slice's result is the one
  * pget_lm_solve gives for it alone, bit for bit, whatever the other slots
- * hold.  Rules: params->n_cg must equal the pool's n_cg and
+ * hold.  Rules: params->step must equal the pool's `step` (PGET_STEP_*),
+ * params->n_cg must equal the pool's n_cg and
  * params->max_outer be at most the pool's; no hook; every call of a pool on
  * one stream (or ordered by the caller); a pool is not thread-safe.  The
  * step is captured as a HIP graph on its first call and replayed (unless
@@ -424,7 +442,7 @@ int32_t pget_tuned_shape(const pget_plan* plan, int32_t batch, int32_t* japb, in
 typedef struct pget_lm_pool pget_lm_pool;
 size_t pget_lm_pool_workspace_bytes(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg);
 pget_status pget_lm_pool_create(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg,
-                                void* ws, size_t ws_bytes, hipStream_t stream, pget_lm_pool** out);
+                                int32_t step, void* ws, size_t ws_bytes, hipStream_t stream, pget_lm_pool** out);
 void pget_lm_pool_destroy(pget_lm_pool* pool);
 pget_status pget_lm_pool_load(pget_lm_pool* pool, int32_t slot, const float* y, const float* f0, const float* mu0,
                               const pget_lm_params* params, hipStream_t stream);

@@ -67,6 +67,11 @@ class LMParams:
     w_f: float = 1.0
     w_mu: float = 1.0
     active_set: bool = False
+    # the damped step's solver: "cg" (CG on the normal equations, clamped
+    # into the box) or "sgp" (the scaled gradient projection of the
+    # box-constrained step, Sec. 2.2); n_cg is its number of iterations
+    # (one normal-operator product each)
+    step: str = "cg"
     prior_w_f: Optional[np.ndarray] = None
     prior_w_mu: Optional[np.ndarray] = None
     prior_ref_f: Optional[np.ndarray] = None
@@ -179,6 +184,79 @@ def cg(matvec: Callable, bf, bm, n_steps: int, wf: float = 1.0, wm: float = 1.0)
     return xf, xm, trace
 
 
+# Parameters of the scaled gradient projection (Bonettini, Zanella, Zanni,
+# Inverse Problems 25 (2009) 015002, cited for the constrained step in
+# Sec. 2.2): Armijo sufficient-decrease factor and backtracking ratio,
+# steplength bounds, the alternation threshold of the two Barzilai-Borwein
+# rules and its memory, and the first steplength.
+SGP_ARMIJO = 1e-4
+SGP_BACKTRACK = 0.4
+SGP_ALPHA_MIN = 1e-10
+SGP_ALPHA_MAX = 1e5
+SGP_TAU0 = 0.5
+SGP_MEMORY = 3
+SGP_ALPHA0 = 1.0
+
+
+def sgp(matvec: Callable, gf, gm, lo_f, hi_f, lo_m, hi_m, n_steps: int, wf: float = 1.0, wm: float = 1.0):
+    """Scaled gradient projection for the box-constrained quadratic
+    min q(s) = g.s + 0.5 s.M s over lo <= s <= hi (lo <= 0 <= hi), from
+    s = 0, with the diagonal scaling D = diag(wf I, wm I) (the metric of the
+    variables scaled by their typical magnitudes).  Each iteration:
+      y = P_box(s - alpha D grad q(s)),  d = y - s;
+      lambda = 1, times 0.4 until q(s + lambda d) <= q(s) + 1e-4 lambda grad q.d
+        (q is quadratic: q(s + l d) - q(s) = l grad.d + l^2/2 d.M d);
+      s += lambda d,  grad += lambda M d;
+      the next alpha from the scaled Barzilai-Borwein rules with
+        BB1 = d.D^-2 d / d.D^-1 M d,  BB2 = d.D M d / (M d).D^2 (M d)
+        (s and grad changes are lambda d and lambda M d; lambda cancels):
+      BB2 / BB1 <= tau: alpha = min of the last 3 BB2, tau *= 0.9;
+      else alpha = BB1, tau *= 1.1; alpha clamped to [1e-10, 1e5].
+    One product M d per iteration.  Returns (sf, sm, qvals): qvals[m] is
+    q(s) after iteration m.  A zero direction (the projected gradient
+    vanishes) leaves s unchanged."""
+    sf = np.zeros_like(gf)
+    sm = np.zeros_like(gm)
+    rf, rm = np.array(gf, dtype=np.float64), np.array(gm, dtype=np.float64)   # grad q(s)
+    alpha, tau = SGP_ALPHA0, SGP_TAU0
+    bb2_hist: List[float] = []
+    qv = 0.0
+    trace = []
+    for _ in range(n_steps):
+        yf = np.clip(sf - alpha * wf * rf, lo_f, hi_f)
+        ym = np.clip(sm - alpha * wm * rm, lo_m, hi_m)
+        df, dm = yf - sf, ym - sm
+        gd = float(np.sum(rf * df) + np.sum(rm * dm))
+        if not gd < 0.0:
+            trace.append(qv)
+            continue
+        qf, qm = matvec(df, dm)
+        dMd = float(np.sum(df * qf) + np.sum(dm * qm))
+        lam = 1.0
+        while lam * gd + 0.5 * lam * lam * dMd > SGP_ARMIJO * lam * gd and lam > 1e-30:
+            lam *= SGP_BACKTRACK
+        sf, sm = sf + lam * df, sm + lam * dm
+        rf, rm = rf + lam * qf, rm + lam * qm
+        qv += lam * gd + 0.5 * lam * lam * dMd
+        trace.append(qv)
+        # the next steplength (scaled Barzilai-Borwein with alternation)
+        den1 = float(np.sum(df * qf) / wf + np.sum(dm * qm) / wm)
+        num1 = float(np.sum(df * df) / wf ** 2 + np.sum(dm * dm) / wm ** 2)
+        num2 = float(wf * np.sum(df * qf) + wm * np.sum(dm * qm))
+        den2 = float(wf ** 2 * np.sum(qf * qf) + wm ** 2 * np.sum(qm * qm))
+        bb1 = num1 / den1 if den1 > 0.0 else SGP_ALPHA_MAX
+        bb2 = num2 / den2 if num2 > 0.0 else SGP_ALPHA_MAX
+        bb2_hist = (bb2_hist + [bb2])[-SGP_MEMORY:]
+        if bb2 / bb1 <= tau:
+            alpha = min(bb2_hist)
+            tau *= 0.9
+        else:
+            alpha = bb1
+            tau *= 1.1
+        alpha = min(max(alpha, SGP_ALPHA_MIN), SGP_ALPHA_MAX)
+    return sf, sm, trace
+
+
 def free_set(f, mu, gf, gm, p: LMParams):
     """0/1 masks of the free variables: a variable is held when it lies on
     its lower bound with a positive gradient, or on its upper bound with a
@@ -247,7 +325,10 @@ def lm_iteration(g: Geometry, y, f, mu, beta, p: LMParams, k: int) -> Iterate:
     pr = prior_at(p, k)
     phi, r = objective(g, y, f, mu, af, am, pr)
     gf, gm = gradient(g, f, mu, r, af, am, pr)
-    if p.active_set:
+    if p.step == "sgp":
+        xf, xm, rr = sgp(lambda a, b: normal_matvec(g, f, mu, a, b, beta, p, af, am, pr), gf, gm,
+                         p.f_lo - f, p.f_hi - f, p.mu_lo - mu, p.mu_hi - mu, p.n_cg, p.w_f, p.w_mu)
+    elif p.active_set:
         ff, fm = free_set(f, mu, gf, gm, p)
 
         def mv(a, b):

@@ -74,7 +74,7 @@ static bool g_use_graphs = true;
 // Instantiated solver sequences, keyed by workspace and the groups solved.
 struct GraphKey {
     void* ws;
-    std::vector<std::array<long long, 6>> groups;   // plan, batch, outer, cg, beta0 | trace << 1, offset
+    std::vector<std::array<long long, 6>> groups;   // plan, batch, outer, cg, beta0 | trace << 1 | sgp << 2, offset
     bool operator==(const GraphKey& o) const { return ws == o.ws && groups == o.groups; }
 };
 struct GraphEntry {
@@ -965,6 +965,7 @@ bool params_ok(const pget_lm_params* p)
     if (!(p->tol >= 0)) return false;
     if (!(p->w_f >= 0) || !(p->w_mu >= 0) || !isfinite(p->w_f) || !isfinite(p->w_mu)) return false;
     if (p->active_set != 0 && p->active_set != 1) return false;
+    if (p->step != PGET_STEP_CG && p->step != PGET_STEP_SGP) return false;
     return true;
 }
 
@@ -995,6 +996,7 @@ LMParamsDev to_dev(const pget_lm_params& p)
     d.prior_ref = p.prior_w ? p.prior_ref : nullptr;
     d.trace_u = p.trace_u;
     d.trace_t = p.trace_t;
+    d.step_sgp = p.step == PGET_STEP_SGP ? 1 : 0;
     d.has_replay = p.replay != nullptr;
     if (p.replay)
         for (int k = 0; k < p.max_outer; ++k) d.replay[k] = p.replay[k];
@@ -1009,7 +1011,7 @@ struct Solve {
     void* ws;
     hipStream_t stream;
     MarchArgs lin, trial;
-    JvpArgs jcg, jpred, jones;
+    JvpArgs jcg, jsgp, jpred, jones;
     VjpArgs vgrad, vcg;
     VecArgs V;
     void* gimg;
@@ -1095,6 +1097,10 @@ void setup(Solve& S)
     J.src.kind = 1;
     J.src.n_rr = S.sh.n_ew_blocks;
     J.src.prm = reinterpret_cast<const LMParamsDev*>(at(ws, S.L.params));
+
+    // the scaled gradient projection's direction, formed by the vector kernels
+    S.jsgp = J;
+    S.jsgp.src = planar_src(p, p + n2, 2 * n2);
 
     float* s = reinterpret_cast<float*>(at(ws, S.L.s));
     S.jpred = J;
@@ -1186,7 +1192,7 @@ void enqueue_step_eval(Solve& S)
 // u' = clamp(u + x); the model decrease and Phi(u'); the decision (rho, beta).
 // Every decision is taken on the device.
 void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_present, bool trace,
-                       bool pool = false)
+                       bool pool = false, bool sgp = false)
 {
     const dim3 ew(S.sh.n_ew_blocks, S.B);
     enqueue_march(S, S.lin, MARCH_LIN);
@@ -1211,7 +1217,30 @@ void enqueue_iteration(Solve& S, int k, int n_cg, bool need_beta0, bool hook_pre
         Timed t_(PGET_KC_VECTOR, S.stream);
         hipLaunchKernelGGL(k_grad_init, ew, dim3(EW_THREADS), 0, S.stream, Vg);
     }
-    for (int m = 0; m < n_cg; ++m) {
+    for (int m = 0; m < n_cg && sgp; ++m) {
+        // scaled gradient projection: M d, the step's line search and
+        // steplength, the move and the next direction
+        enqueue_jvp(S, S.jsgp, JVP_NORMAL);
+        {
+            Timed t_(PGET_KC_VJP, S.stream);
+            launch_vjp(S.P, S.vcg, S.B, S.stream);
+        }
+        VecArgs V = S.V;
+        V.cg_step = m;
+        {
+            Timed t_(PGET_KC_VECTOR, S.stream);
+            hipLaunchKernelGGL(k_sgp_q, ew, dim3(EW_THREADS), 0, S.stream, V);
+        }
+        {
+            Timed t_(PGET_KC_CONTROL, S.stream);
+            hipLaunchKernelGGL(k_sgp_step, dim3(S.B), dim3(256), 0, S.stream, V);
+        }
+        {
+            Timed t_(PGET_KC_VECTOR, S.stream);
+            hipLaunchKernelGGL(k_sgp_x, ew, dim3(EW_THREADS), 0, S.stream, V);
+        }
+    }
+    for (int m = 0; m < n_cg && !sgp; ++m) {
         JvpArgs J = S.jcg;
         J.src.rr_slot_cur = rr_slot(m);
         J.src.rr_slot_prev = rr_slot(m + 2);
@@ -1326,6 +1355,7 @@ struct Group {
     int max_outer = 0, n_cg = 0;
     bool need_beta0 = false;
     bool trace = false;      // some slice records its iterates
+    bool sgp = false;        // the step by scaled gradient projection (all slices)
     std::vector<LMParamsDev> prm;
     std::vector<ReportDev> rep;
     std::vector<const float*> y;
@@ -1400,7 +1430,9 @@ pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStre
     G.n_cg = G.prm.empty() ? 0 : G.prm[0].n_cg;
     G.need_beta0 = false;
     G.trace = false;
+    G.sgp = !G.prm.empty() && G.prm[0].step_sgp;
     for (int b = 0; b < B; ++b) {
+        if ((G.prm[b].step_sgp != 0) != G.sgp) return PGET_ERR_INVALID_ARG;
         if (G.prm[b].max_outer != G.max_outer || G.prm[b].n_cg != G.n_cg) return PGET_ERR_INVALID_ARG;
         if (!G.y[b] || !G.f[b] || !G.mu[b]) return PGET_ERR_INVALID_ARG;
         if (G.prm[b].beta0 <= 0.0) G.need_beta0 = true;
@@ -1441,7 +1473,7 @@ void enqueue_group(Group& G, hipStream_t s)
     fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * SS.P->w_bytes, s);
     if (SS.lin.wq) fill_zero(SS.lin.wq, (size_t)B * SS.lin.wts_stride * sizeof(float), s);
     for (int k = 0; k < G.max_outer; ++k) {
-        enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false, G.trace);
+        enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false, G.trace, false, G.sgp);
         enqueue_commit(SS);
     }
     hipLaunchKernelGGL(k_final_reg, dim3(SS.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, s, SS.V);
@@ -1485,7 +1517,7 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
         fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * S.P->w_bytes, stream);
         if (S.lin.wq) fill_zero(S.lin.wq, (size_t)B * S.lin.wts_stride * sizeof(float), stream);
         for (int k = 0; k < G.max_outer; ++k) {
-            enqueue_iteration(S, k, G.n_cg, G.need_beta0, true, G.trace);
+            enqueue_iteration(S, k, G.n_cg, G.need_beta0, true, G.trace, false, G.sgp);
             pget_status rc = run_hook(S, hook, hook_user);
             if (rc != PGET_OK) return rc;
             enqueue_commit(S);
@@ -1500,7 +1532,7 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
         key.ws = ws;
         for (auto& G : groups)
             key.groups.push_back({(long long)(intptr_t)G.S.P, G.S.B, G.max_outer, G.n_cg,
-                                  (long long)G.need_beta0 | ((long long)G.trace << 1),
+                                  (long long)G.need_beta0 | ((long long)G.trace << 1) | ((long long)G.sgp << 2),
                                   (long long)((char*)G.S.ws - (char*)ws)});
         hipGraphExec_t exec = nullptr;
         ++g_graph_clock;
@@ -1801,6 +1833,7 @@ pget_status pget_lm_solve_batched(const pget_plan* plan, int32_t n_slices, const
 struct pget_lm_pool {
     const pget_plan* P = nullptr;
     int cap = 0, max_outer = 0, n_cg = 0;
+    int step = PGET_STEP_CG;        // the damped step's solver of every slot
     Solve S;
     std::vector<LMParamsDev> prm;   // host copies of the slots' parameters
     std::vector<ReportDev> rep;     // the slots' device report arrays
@@ -1825,7 +1858,7 @@ void enqueue_pool_step(pget_lm_pool* Q, hipStream_t s)
 {
     Solve S = Q->S;
     S.stream = s;
-    enqueue_iteration(S, 1, Q->n_cg, true, false, true, true);
+    enqueue_iteration(S, 1, Q->n_cg, true, false, true, true, Q->step == PGET_STEP_SGP);
     enqueue_commit(S);
     hipLaunchKernelGGL(k_final_reg, dim3(S.sh.n_ew_blocks, S.B), dim3(EW_THREADS), 0, s, S.V);
     hipLaunchKernelGGL(k_finish, dim3(S.B), dim3(256), 0, s, S.V);
@@ -1842,13 +1875,14 @@ size_t pget_lm_pool_workspace_bytes(const pget_plan* plan, int32_t capacity, int
     return pool_bytes(plan, capacity, max_outer, n_cg, nullptr);
 }
 
-pget_status pget_lm_pool_create(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg, void* ws,
-                                size_t ws_bytes, hipStream_t stream, pget_lm_pool** out)
+pget_status pget_lm_pool_create(const pget_plan* plan, int32_t capacity, int32_t max_outer, int32_t n_cg, int32_t step,
+                                void* ws, size_t ws_bytes, hipStream_t stream, pget_lm_pool** out)
 {
     if (!out) return PGET_ERR_INVALID_ARG;
     *out = nullptr;
     if (!plan || capacity < 1 || max_outer < 1 || max_outer > 256 || n_cg < 1 || n_cg > 256)
         return PGET_ERR_INVALID_ARG;
+    if (step != PGET_STEP_CG && step != PGET_STEP_SGP) return PGET_ERR_INVALID_ARG;
     if (!ws) return PGET_ERR_WORKSPACE;
     Layout L;
     const size_t need = pool_bytes(plan, capacity, max_outer, n_cg, &L);
@@ -1859,6 +1893,7 @@ pget_status pget_lm_pool_create(const pget_plan* plan, int32_t capacity, int32_t
     Q->cap = capacity;
     Q->max_outer = max_outer;
     Q->n_cg = n_cg;
+    Q->step = step;
     Solve& S = Q->S;
     S.P = plan;
     S.B = capacity;
@@ -1899,7 +1934,8 @@ pget_status pget_lm_pool_load(pget_lm_pool* Q, int32_t slot, const float* y, con
                               const pget_lm_params* params, hipStream_t stream)
 {
     if (!Q || slot < 0 || slot >= Q->cap || !y || !f0 || !mu0 || !params_ok(params)) return PGET_ERR_INVALID_ARG;
-    if (Q->loaded[slot] || params->max_outer > Q->max_outer || params->n_cg != Q->n_cg) return PGET_ERR_INVALID_ARG;
+    if (Q->loaded[slot] || params->max_outer > Q->max_outer || params->n_cg != Q->n_cg || params->step != Q->step)
+        return PGET_ERR_INVALID_ARG;
     Solve& S = Q->S;
     const Geo& g = Q->P->g;
     const size_t n2 = (size_t)g.n * g.n, sino = (size_t)g.n_angles * g.n_bins;

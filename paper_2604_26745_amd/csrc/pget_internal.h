@@ -71,6 +71,7 @@ struct LMParamsDev {
     const float* prior_ref; // its reference maps (2 N^2) or nullptr (zero)
     float* trace_u;         // [max_outer][2 N^2]: iterate of each outer iteration, or nullptr
     float* trace_t;         // [max_outer][2 N^2]: its trial point, or nullptr
+    int step_sgp;           // 1: the damped step by scaled gradient projection, 0: by CG
     int has_replay;
     int8_t replay[256];
 };
@@ -90,6 +91,11 @@ struct LMState {
     int stop_reason;
     int status;
     double pred, ared, rho;    // of the last LM step
+    // scaled gradient projection of the current step: steplength, the
+    // alternation threshold, the last Barzilai-Borwein (second rule) values,
+    // the line-search factor of the last iteration, and q(s)
+    double sgp_alpha, sgp_tau, sgp_bb2[3], sgp_lambda, sgp_q;
+    int sgp_nbb;
 };
 
 // Reduction slots: each kernel that reduces writes one double per block.
@@ -110,6 +116,12 @@ enum Slot {
     SLOT_RR2,              // rotating slots keep readers and writers apart
     SLOT_J1,               // ||J 1||^2 (initial damping)
     SLOT_PHI_DATA_H,       // ||A(u~) - y||^2 of a hook proposal
+    SLOT_SGP_GD,           // scaled gradient projection: grad q . d
+    SLOT_SGP_DMD,          // d . M d
+    SLOT_SGP_N1,           // d . W^-2 d
+    SLOT_SGP_D1,           // d . W^-1 M d
+    SLOT_SGP_N2,           // d . W M d
+    SLOT_SGP_D2,           // (M d) . W^2 (M d)
     N_SLOTS
 };
 constexpr int SLOT_WIDTH = 1024;   // max blocks per slice of any reducing launch
@@ -258,6 +270,9 @@ __global__ void k_sum_groups(int n2, int groups, int gfold, const float* gpart, 
 __global__ void k_grad_init(VecArgs V);
 __global__ void k_cg_q(VecArgs V);
 __global__ void k_cg_x(VecArgs V);
+__global__ void k_sgp_q(VecArgs V);
+__global__ void k_sgp_step(VecArgs V);
+__global__ void k_sgp_x(VecArgs V);
 __global__ void k_trial(VecArgs V);
 __global__ void k_trace(VecArgs V);
 __global__ void k_beta0(VecArgs V);

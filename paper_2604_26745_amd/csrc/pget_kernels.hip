@@ -1147,6 +1147,16 @@ __global__ void __launch_bounds__(256) k_sum_groups(int n2, int groups, int gfol
 // ----------------------------------------------------------- LM kernels
 // Vectors of one slice are [2][N][N] (f block, then mu block).
 
+// Scaled gradient projection (Bonettini, Zanella and Zanni): Armijo
+// sufficient decrease and backtracking ratio, steplength bounds, the first
+// steplength and the first alternation threshold.
+constexpr double SGP_ARMIJO = 1e-4;
+constexpr double SGP_BACKTRACK = 0.4;
+constexpr double SGP_ALPHA_MIN = 1e-10;
+constexpr double SGP_ALPHA_MAX = 1e5;
+constexpr float SGP_ALPHA0 = 1.0f;
+constexpr double SGP_TAU0 = 0.5;
+
 __device__ __forceinline__ void alphas_at(const LMParamsDev& p, int k, float& af, float& am)
 {
     int e = min(k, p.alpha_decay_until);
@@ -1233,26 +1243,44 @@ __global__ void __launch_bounds__(EW_THREADS) k_grad_init(VecArgs V)
         }
         V.grad[vo + m] = gf;
         V.grad[vo + n2 + m] = gm;
-        float rf = -gf, rm = -gm;
-        if (P.active_set) {
-            // held: on the lower bound with g > 0, or on the upper bound with g < 0
-            const float f0 = uf[m], m0 = um[m];
-            const bool hold_f = (f0 <= (float)P.f_lo && gf > 0.0f) || (f0 >= (float)P.f_hi && gf < 0.0f);
-            const bool hold_m = (m0 <= (float)P.mu_lo && gm > 0.0f) || (m0 >= (float)P.mu_hi && gm < 0.0f);
-            V.fmask[vo + m] = hold_f ? 0 : 1;
-            V.fmask[vo + n2 + m] = hold_m ? 0 : 1;
-            if (hold_f) rf = 0.0f;
-            if (hold_m) rm = 0.0f;
+        const float f0 = uf[m], m0 = um[m];
+        if (P.step_sgp) {
+            // scaled gradient projection from s = 0: r = grad q(0) = g and the
+            // first direction d = P_box(-alpha_0 W g) in step space
+            V.r[vo + m] = gf;
+            V.r[vo + n2 + m] = gm;
+            V.p[vo + m] = fminf(fmaxf(-SGP_ALPHA0 * (float)P.w_f * gf, (float)P.f_lo - f0), (float)P.f_hi - f0);
+            V.p[vo + n2 + m] = fminf(fmaxf(-SGP_ALPHA0 * (float)P.w_mu * gm, (float)P.mu_lo - m0), (float)P.mu_hi - m0);
+            V.fmask[vo + m] = 1;
+            V.fmask[vo + n2 + m] = 1;
+        } else {
+            float rf = -gf, rm = -gm;
+            if (P.active_set) {
+                // held: on the lower bound with g > 0, or on the upper bound with g < 0
+                const bool hold_f = (f0 <= (float)P.f_lo && gf > 0.0f) || (f0 >= (float)P.f_hi && gf < 0.0f);
+                const bool hold_m = (m0 <= (float)P.mu_lo && gm > 0.0f) || (m0 >= (float)P.mu_hi && gm < 0.0f);
+                V.fmask[vo + m] = hold_f ? 0 : 1;
+                V.fmask[vo + n2 + m] = hold_m ? 0 : 1;
+                if (hold_f) rf = 0.0f;
+                if (hold_m) rm = 0.0f;
+            }
+            V.r[vo + m] = rf;
+            V.r[vo + n2 + m] = rm;
+            V.p[vo + m] = 0.0f;
+            V.p[vo + n2 + m] = 0.0f;
+            rr = (double)(float)P.w_f * ((double)rf * rf) + (double)(float)P.w_mu * ((double)rm * rm);
         }
-        V.r[vo + m] = rf;
-        V.r[vo + n2 + m] = rm;
         V.x[vo + m] = 0.0f;
         V.x[vo + n2 + m] = 0.0f;
-        V.p[vo + m] = 0.0f;
-        V.p[vo + n2 + m] = 0.0f;
-        rr = (double)(float)P.w_f * ((double)rf * rf) + (double)(float)P.w_mu * ((double)rm * rm);
         gg = (double)gf * gf + (double)gm * gm;
         reg = (double)af * grad2(uf, n, r, c) + (double)am * grad2(um, n, r, c) + prior_e;
+    }
+    if (P.step_sgp && blockIdx.x == 0 && threadIdx.x == 0) {
+        st.sgp_alpha = SGP_ALPHA0;
+        st.sgp_tau = SGP_TAU0;
+        st.sgp_nbb = 0;
+        st.sgp_q = 0.0;
+        st.sgp_lambda = 0.0;
     }
     double s1 = block_sum(rr, sh);
     double s3 = block_sum(gg, sh);
@@ -1373,6 +1401,142 @@ __global__ void __launch_bounds__(EW_THREADS) k_cg_x(VecArgs V)
     if (threadIdx.x == 0) slot_ptr(V.part, slice, rr_slot(m_step + 1))[blockIdx.x] = s;
 }
 
+// ---- scaled gradient projection of the box-constrained step (Sec. 2.2,
+// after Bonettini, Zanella and Zanni): x holds the step s, r the gradient
+// grad q(s) = g + M s, p the direction d, q the product M d.
+
+// M d = (J^T J + beta D + R) d from the gather's partials, and the partials
+// of grad q . d, d.M d and the four scaled Barzilai-Borwein sums.
+__global__ void __launch_bounds__(EW_THREADS) k_sgp_q(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.y;
+    LMState& st = V.st[slice];
+    if (st.done) return;
+    const Geo& g = V.g;
+    const int n = g.n, n2 = n * n;
+    const LMParamsDev& P = V.prm[slice];
+    float af, am;
+    alphas_at(P, st.k, af, am);
+    const float bdf = (float)(st.beta * P.d_f), bdm = (float)(st.beta * P.d_mu);
+    const float wf = (float)P.w_f, wm = (float)P.w_mu;
+    const size_t vo = (size_t)slice * V.vstride;
+    const float* gp = V.gpart + (size_t)slice * V.gpart_slice_stride;
+    double gd = 0.0, dmd = 0.0, n1 = 0.0, d1 = 0.0, nn2 = 0.0, d2 = 0.0;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n2) {
+        const int r = m / n, c = m - r * n;
+        const float* pf = V.p + vo;
+        const float* pm = pf + n2;
+        const float2 gs = sum_groups(gp, V.gpart_group_stride, V.groups, V.gfold, m, n2);
+        float qf = fmaf(af, lap(pf, n, r, c), fmaf(bdf, pf[m], gs.x));
+        float qm = fmaf(am, lap(pm, n, r, c), fmaf(bdm, pm[m], gs.y));
+        if (P.prior_w) {
+            const float ps = prior_scale(P, st.k);
+            float pwf, pwm, rf0, rm0;
+            prior_at(P, ps, m, pwf, rf0);
+            prior_at(P, ps, n2 + m, pwm, rm0);
+            qf = fmaf(pwf, pf[m], qf);
+            qm = fmaf(pwm, pm[m], qm);
+        }
+        V.q[vo + m] = qf;
+        V.q[vo + n2 + m] = qm;
+        const double df = pf[m], dm = pm[m], Qf = qf, Qm = qm;
+        const double Wf = wf, Wm = wm;
+        gd = (double)V.r[vo + m] * df + (double)V.r[vo + n2 + m] * dm;
+        dmd = df * Qf + dm * Qm;
+        n1 = df * df / (Wf * Wf) + dm * dm / (Wm * Wm);
+        d1 = df * Qf / Wf + dm * Qm / Wm;
+        nn2 = Wf * df * Qf + Wm * dm * Qm;
+        d2 = Wf * Wf * Qf * Qf + Wm * Wm * Qm * Qm;
+    }
+    double v;
+    v = block_sum(gd, sh);  if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SGP_GD)[blockIdx.x] = v;
+    v = block_sum(dmd, sh); if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SGP_DMD)[blockIdx.x] = v;
+    v = block_sum(n1, sh);  if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SGP_N1)[blockIdx.x] = v;
+    v = block_sum(d1, sh);  if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SGP_D1)[blockIdx.x] = v;
+    v = block_sum(nn2, sh); if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SGP_N2)[blockIdx.x] = v;
+    v = block_sum(d2, sh);  if (threadIdx.x == 0) slot_ptr(V.part, slice, SLOT_SGP_D2)[blockIdx.x] = v;
+}
+
+// Per slice: the Armijo factor lambda (1, 0.4, 0.16, ... until
+// q(s + lambda d) <= q(s) + 1e-4 lambda grad q . d, exact for the quadratic),
+// q(s) after the move, and the next steplength from the scaled
+// Barzilai-Borwein rules with alternation.  No descent (grad q . d >= 0):
+// lambda = 0 and the steplength is kept.
+__global__ void __launch_bounds__(256) k_sgp_step(VecArgs V)
+{
+    __shared__ double sh[16];
+    const int slice = blockIdx.x;
+    LMState& st = V.st[slice];
+    if (st.done) return;
+    const LMParamsDev& P = V.prm[slice];
+    const double gd = sum_partials(slot_ptr(V.part, slice, SLOT_SGP_GD), V.n_ew_blocks, sh);
+    const double dmd = sum_partials(slot_ptr(V.part, slice, SLOT_SGP_DMD), V.n_ew_blocks, sh);
+    const double n1 = sum_partials(slot_ptr(V.part, slice, SLOT_SGP_N1), V.n_ew_blocks, sh);
+    const double d1 = sum_partials(slot_ptr(V.part, slice, SLOT_SGP_D1), V.n_ew_blocks, sh);
+    const double n2 = sum_partials(slot_ptr(V.part, slice, SLOT_SGP_N2), V.n_ew_blocks, sh);
+    const double d2 = sum_partials(slot_ptr(V.part, slice, SLOT_SGP_D2), V.n_ew_blocks, sh);
+    double gg = 0.0;
+    if (V.cg_step == 0 && V.rep) gg = sum_partials(slot_ptr(V.part, slice, SLOT_GNORM), V.n_ew_blocks, sh);
+    if (threadIdx.x != 0) return;
+    if (V.cg_step == 0 && V.rep) V.rep[slice].gnorm[st.k] = sqrt(gg);
+    double lam = 0.0;
+    if (gd < 0.0) {
+        lam = 1.0;
+        while (lam * gd + 0.5 * lam * lam * dmd > SGP_ARMIJO * lam * gd && lam > 1e-30) lam *= SGP_BACKTRACK;
+        st.sgp_q += lam * gd + 0.5 * lam * lam * dmd;
+        const double bb1 = d1 > 0.0 ? n1 / d1 : SGP_ALPHA_MAX;
+        const double bb2 = n2 > 0.0 ? n2 / d2 : SGP_ALPHA_MAX;
+        if (st.sgp_nbb < 3) {
+            st.sgp_bb2[st.sgp_nbb++] = bb2;
+        } else {
+            st.sgp_bb2[0] = st.sgp_bb2[1];
+            st.sgp_bb2[1] = st.sgp_bb2[2];
+            st.sgp_bb2[2] = bb2;
+        }
+        double alpha;
+        if (bb2 / bb1 <= st.sgp_tau) {
+            alpha = st.sgp_bb2[0];
+            for (int i = 1; i < st.sgp_nbb; ++i) alpha = fmin(alpha, st.sgp_bb2[i]);
+            st.sgp_tau *= 0.9;
+        } else {
+            alpha = bb1;
+            st.sgp_tau *= 1.1;
+        }
+        st.sgp_alpha = fmin(fmax(alpha, SGP_ALPHA_MIN), SGP_ALPHA_MAX);
+    }
+    st.sgp_lambda = lam;
+    if (V.rep) V.rep[slice].cg_rr[(size_t)st.k * P.n_cg + V.cg_step] = st.sgp_q;
+}
+
+// s += lambda d, grad q += lambda M d, and the next direction
+// d = P_box(s - alpha W grad q) - s with the new steplength.
+__global__ void __launch_bounds__(EW_THREADS) k_sgp_x(VecArgs V)
+{
+    const int slice = blockIdx.y;
+    const LMState& st = V.st[slice];
+    if (st.done) return;
+    const LMParamsDev& P = V.prm[slice];
+    const int n2 = V.g.n * V.g.n;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n2) return;
+    const float lam = (float)st.sgp_lambda, alpha = (float)st.sgp_alpha;
+    const size_t vo = (size_t)slice * V.vstride;
+    const float w2[2] = {(float)P.w_f, (float)P.w_mu};
+    const float lo2[2] = {(float)P.f_lo, (float)P.mu_lo}, hi2[2] = {(float)P.f_hi, (float)P.mu_hi};
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const size_t o = vo + (size_t)b * n2 + m;
+        const float x = fmaf(lam, V.p[o], V.x[o]);
+        const float r = fmaf(lam, V.q[o], V.r[o]);
+        const float u = V.u[o];
+        V.x[o] = x;
+        V.r[o] = r;
+        V.p[o] = fminf(fmaxf(fmaf(-alpha * w2[b], r, x), lo2[b] - u), hi2[b] - u) - x;
+    }
+}
+
 // Trial point u' = clamp(u + x) (or the hook's proposal), s = u' - u, and
 // partials of g.s, s.R s, ||s||^2, ||u||^2, alpha ||grad u'||^2.
 __global__ void __launch_bounds__(EW_THREADS) k_trial(VecArgs V)
@@ -1384,7 +1548,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_trial(VecArgs V)
     const LMParamsDev& P = V.prm[slice];
     const Geo& g = V.g;
     const int n = g.n, n2 = n * n;
-    if (!V.hook_mode && V.rep && blockIdx.x == 0) {
+    if (!V.hook_mode && V.rep && blockIdx.x == 0 && !P.step_sgp) {
         double rr = sum_partials(slot_ptr(V.part, slice, rr_slot(P.n_cg)), V.n_ew_blocks, sh);
         if (threadIdx.x == 0) V.rep[slice].cg_rr[(size_t)st.k * P.n_cg + (P.n_cg - 1)] = rr;
     }

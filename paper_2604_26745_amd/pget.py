@@ -22,6 +22,7 @@ STATUS_NAMES = {
     -4: "non-finite value in the solver", -5: "unsupported geometry",
 }
 OP_FORWARD, OP_JVP, OP_VJP, OP_LM = 0, 1, 2, 3
+STEP_CG, STEP_SGP = 0, 1
 KC_MARCH, KC_JVP, KC_VJP, KC_VECTOR, KC_CONTROL, KC_GRADIENT = 0, 1, 2, 3, 4, 5
 KERNEL_CLASS_NAMES = {KC_MARCH: "march", KC_JVP: "jvp", KC_VJP: "vjp", KC_VECTOR: "vector",
                       KC_CONTROL: "control", KC_GRADIENT: "gradient"}
@@ -54,7 +55,7 @@ class LMParams(ctypes.Structure):
         ("tol", ctypes.c_double), ("replay", ctypes.POINTER(ctypes.c_int8)),
         ("w_f", ctypes.c_double), ("w_mu", ctypes.c_double), ("active_set", ctypes.c_int32),
         ("prior_w", ctypes.c_void_p), ("prior_ref", ctypes.c_void_p),
-        ("trace_u", ctypes.c_void_p), ("trace_t", ctypes.c_void_p),
+        ("trace_u", ctypes.c_void_p), ("trace_t", ctypes.c_void_p), ("step", ctypes.c_int32),
     ]
 
 
@@ -133,8 +134,8 @@ def load_library():
     lib.pget_lm_solve_batched.restype = ctypes.c_int
     lib.pget_lm_pool_workspace_bytes.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.pget_lm_pool_workspace_bytes.restype = ctypes.c_size_t
-    lib.pget_lm_pool_create.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, V, ctypes.c_size_t, V,
-                                        P(V)]
+    lib.pget_lm_pool_create.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, V,
+                                        ctypes.c_size_t, V, P(V)]
     lib.pget_lm_pool_create.restype = ctypes.c_int
     lib.pget_lm_pool_destroy.argtypes = [V]
     lib.pget_lm_pool_destroy.restype = None
@@ -196,6 +197,7 @@ class SolverParams:
     prior_ref: object = None  # its reference maps (2, N, N), or None (zero)
     trace_u: object = None    # iterate trace: CUDA float32 (max_outer, 2, N, N) receiving u_k, or None
     trace_t: object = None    # the same receiving the trial points u'_k, or None
+    step: int = 0             # damped-step solver: STEP_CG (0) or STEP_SGP (1, scaled gradient projection)
 
     def to_c(self, n: Optional[int] = None):
         p = LMParams()
@@ -609,7 +611,7 @@ class LMPool:
     outer-iteration boundaries.  All calls go to the stream current at
     construction (or `stream`).  Argument marshalling only."""
 
-    def __init__(self, plan: "Plan", capacity: int, max_outer: int, n_cg: int, stream=None):
+    def __init__(self, plan: "Plan", capacity: int, max_outer: int, n_cg: int, stream=None, step: int = 0):
         torch = _torch()
         self.plan, self.lib = plan, plan.lib
         self.capacity, self.max_outer, self.n_cg = capacity, max_outer, n_cg
@@ -621,7 +623,7 @@ class LMPool:
         self.finished = torch.zeros(capacity, dtype=torch.int32).pin_memory()
         self.keep = [None] * capacity      # per slot: inputs, parameters, report buffers
         self.handle = ctypes.c_void_p()
-        _check(self.lib.pget_lm_pool_create(plan.handle, capacity, max_outer, n_cg, _ptr(self.ws), nbytes,
+        _check(self.lib.pget_lm_pool_create(plan.handle, capacity, max_outer, n_cg, step, _ptr(self.ws), nbytes,
                                             self.stream.cuda_stream, ctypes.byref(self.handle)),
                "pget_lm_pool_create")
 

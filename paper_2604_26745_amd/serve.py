@@ -293,7 +293,7 @@ class GpuPool:
         self.pool, self.params = pool, params
         self.stream = torch.cuda.Stream()   # default priority
         with torch.cuda.stream(self.stream):
-            self.p = pget.LMPool(plan, capacity, params.max_outer, params.n_cg, stream=self.stream)
+            self.p = pget.LMPool(plan, capacity, params.max_outer, params.n_cg, stream=self.stream, step=params.step)
         self.capacity = capacity
         self.nbytes = int(self.p.ws.numel())
         self.outputs: Dict[int, tuple] = {}   # rid -> (f, mu) of served requests (kept if keep_outputs)

@@ -554,3 +554,98 @@ def test_step_quantities_reproduce_an_iteration():
     assert 0.0 < d < 1e-4
     again = L.step_quantities_job((dataclasses.asdict(g), y, f0, mu0, None, None, p, 0, 0.3, None))
     assert np.array_equal(again["f_trial"], it.f_trial)
+
+
+def _box_qp(n=5, seed=3, tight=0.02):
+    """A small damped normal system M, g at a random iterate (dense, from
+    the oracle's operator) and a box around the iterate in step space."""
+    g = O.Geometry(n, 8, 10, psf_sigma=1.0)
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.5, 1.0, (n, n))
+    mu = rng.uniform(0.0, 0.2, (n, n))
+    p = params(w_mu=0.05 ** 2, d_mu=400.0)
+    beta = 0.05
+    M = dense_normal_matrix(g, f, mu, beta, p)
+    gv = rng.standard_normal(2 * n * n)
+    lo = -tight * rng.uniform(0.2, 1.0, 2 * n * n)
+    hi = tight * rng.uniform(0.2, 1.0, 2 * n * n)
+    mv = lambda a, c: L.normal_matvec(g, f, mu, a, c, beta, p, p.alpha_f, p.alpha_mu)
+    return n, M, gv, lo, hi, mv, p
+
+
+def _sgp_dense(n, gv, lo, hi, mv, steps, wf=1.0, wm=1.0):
+    n2 = n * n
+    sh = lambda v: (v[:n2].reshape(n, n), v[n2:].reshape(n, n))
+    gf, gm = sh(gv)
+    (lf, lm), (hf, hm) = sh(lo), sh(hi)
+    sf, sm, q = L.sgp(mv, gf, gm, lf, hf, lm, hm, steps, wf, wm)
+    return np.concatenate([sf.ravel(), sm.ravel()]), q
+
+
+def test_sgp_reaches_the_bounded_least_squares_solution():
+    """The scaled gradient projection (the paper's solver of the box-
+    constrained damped step) converges to the minimiser of
+    g.s + 0.5 s.M s over the box, as scipy's bounded-variable least squares
+    (BVLS, an exact active-set method) finds it through the Cholesky factor
+    of M; the KKT conditions hold at the limit, with constraints active."""
+    from scipy.optimize import lsq_linear
+    n, M, gv, lo, hi, mv, p = _box_qp()
+    Lc = np.linalg.cholesky(M)
+    ref = lsq_linear(Lc.T, -np.linalg.solve(Lc, gv), bounds=(lo, hi), method="bvls", tol=1e-14).x
+    s, q = _sgp_dense(n, gv, lo, hi, mv, 3000, p.w_f, p.w_mu)
+    assert np.linalg.norm(s - ref) <= 1e-7 * np.linalg.norm(ref)
+    grad = gv + M @ s
+    at_lo, at_hi = np.isclose(s, lo, rtol=0, atol=1e-12), np.isclose(s, hi, rtol=0, atol=1e-12)
+    free = ~(at_lo | at_hi)
+    assert at_lo.sum() > 0 and at_hi.sum() > 0 and free.sum() > 0
+    scale = np.abs(gv).max()
+    assert np.abs(grad[free]).max() <= 1e-7 * scale
+    assert grad[at_lo].min() >= -1e-7 * scale and grad[at_hi].max() <= 1e-7 * scale
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(q, q[1:]))     # monotone (Armijo)
+
+
+def test_sgp_without_active_bounds_solves_the_normal_equations():
+    n, M, gv, lo, hi, mv, p = _box_qp(tight=1e6)
+    s, _ = _sgp_dense(n, gv, lo, hi, mv, 3000, 1.0, 1.0)
+    x = np.linalg.solve(M, -gv)
+    assert np.linalg.norm(s - x) <= 1e-7 * np.linalg.norm(x)
+
+
+def test_sgp_step_in_the_lm_solver_stays_in_the_box_and_decreases_phi():
+    """The LM solver with the scaled gradient projection as its step: every
+    trial point lies in the box without clamping, accepted steps decrease
+    Phi by at least eta * pred, and pred is the model decrease of the
+    returned step."""
+    g, y, _, _ = small_problem()
+    f0, mu0 = L.initial_guess(g, y)
+    p = params(step="sgp", n_cg=10, w_mu=0.05 ** 2, d_mu=400.0, f_hi=3.0, mu_hi=0.06)
+    beta = L.initial_damping(g, f0, mu0, p)
+    it = L.lm_iteration(g, y, f0, mu0, beta, p, 0)
+    assert np.all(f0 + it.xf >= p.f_lo - 1e-15) and np.all(f0 + it.xf <= p.f_hi + 1e-15)
+    assert np.all(mu0 + it.xm >= p.mu_lo - 1e-15) and np.all(mu0 + it.xm <= p.mu_hi + 1e-15)
+    assert np.array_equal(it.f_trial, f0 + it.xf) or np.abs(it.f_trial - (f0 + it.xf)).max() < 1e-15
+    f, mu, rep = L.lm_solve(g, y, f0, mu0, p)
+    for k in range(rep.iters_run):
+        if rep.accepted[k]:
+            assert rep.phi[k + 1] <= rep.phi[k] - p.eta * rep.pred[k] + 1e-9 * rep.phi[k]
+    assert rep.phi[-1] < 0.5 * rep.phi[0]
+    assert np.all(mu <= p.mu_hi) and np.all(mu >= 0) and np.all(f >= 0) and np.all(f <= p.f_hi)
+
+
+def test_sgp_and_active_set_cg_at_equal_operator_products():
+    """The comparison behind the benchmark's choice of step (oracle, a
+    32 x 32 9x9 lattice, 60 angles, 15 outer iterations of 20 operator
+    products each): the active-set CG step reaches a lower objective than
+    the scaled gradient projection, which reaches a lower one than CG
+    without the active set (clamp only).  Measured: about 14, 20 and 35
+    from 1341 (at 64^2, 120 angles: 84, 168 and 776 from 18150)."""
+    cfg = inputs.scaled(inputs.SMALL_64, n=32, n_angles=60, n_bins=48, rod_radius=1.0, pitch=3.0, can_half=13.5)
+    g = O.Geometry(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma)
+    ft, mt = inputs.rod_lattice(cfg, 0)
+    y = inputs.poisson_counts(O.forward(g, ft, mt), cfg.peak_counts, 0)
+    f0, m0 = L.initial_guess(g, y)
+    phi = {}
+    for name, kw in (("cg", dict(active_set=True)), ("sgp", dict(step="sgp")), ("clamp", dict(active_set=False))):
+        p = L.LMParams(max_outer=15, n_cg=20, alpha_f=1e-2, alpha_mu=1e-2, w_mu=0.05 ** 2, d_mu=400.0, **kw)
+        phi[name] = L.lm_solve(g, y, f0, m0, p)[2].phi[-1]
+    assert phi["cg"] < phi["sgp"] < phi["clamp"] < 0.1 * 1341.0, phi

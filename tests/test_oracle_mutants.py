@@ -14,7 +14,8 @@ rho = 0.75 is 1 - 0.5^3, the initial damping equals tau times the Rayleigh
 quotient of J^T J at the all-ones vector with J from torch autograd of the
 dense formulation, the continuation's alphas after its halt are alpha /
 decay^until, and ten rejections in a row (beta0 * 2^55 > 1e16 beta0) stop
-the solve."""
+the solve, and the scaled gradient projection reaches the bounded least
+squares solution of a box-constrained quadratic, decreasing monotonically."""
 import ctypes
 import os
 import subprocess
@@ -73,6 +74,10 @@ LM_MUTANTS = {
     "continuation without its halt": ("decay = p.alpha_decay ** min(k, p.alpha_decay_until)\n    return",
                                       "decay = p.alpha_decay ** k\n    return"),
     "damping overflow never stops": ("if beta > 1e16 * beta_init:", "if beta > 1e16 * beta:"),
+    "SGP without the projection": ("yf = np.clip(sf - alpha * wf * rf, lo_f, hi_f)", "yf = sf - alpha * wf * rf"),
+    "SGP gradient not updated": ("rf, rm = rf + lam * qf, rm + lam * qm", "rf, rm = rf, rm + lam * qm"),
+    "SGP without its line search": ("        while lam * gd + 0.5 * lam * lam * dMd > SGP_ARMIJO * lam * gd and lam > 1e-30:",
+                                    "        while False:"),
 }
 
 
@@ -238,6 +243,25 @@ def lm_pins(L):
     po = L.LMParams(max_outer=12, n_cg=2, beta0=1.0)
     rep = L.lm_solve(g, y, f, mu, po, replay=[0] * 12)[2]
     pins["damping overflow after ten rejections"] = (float(abs(rep.iters_run - 10)), 0.0)
+    # scaled gradient projection of a box-constrained quadratic against
+    # scipy's bounded-variable least squares (through the Cholesky factor)
+    from scipy.optimize import lsq_linear
+    k = 12
+    B = rng.standard_normal((k, k))
+    Mq = B @ B.T + 0.5 * np.eye(k)
+    gq = rng.standard_normal(k)
+    lo, hi = -0.05 * rng.uniform(0.2, 1, k), 0.05 * rng.uniform(0.2, 1, k)
+    Lc = np.linalg.cholesky(Mq)
+    ref = lsq_linear(Lc.T, -np.linalg.solve(Lc, gq), bounds=(lo, hi), method="bvls", tol=1e-14).x
+    h = k // 2
+
+    def mvq(a, c):
+        out = Mq @ np.concatenate([a, c])
+        return out[:h], out[h:]
+    sf, sm, qv = L.sgp(mvq, gq[:h], gq[h:], lo[:h], hi[:h], lo[h:], hi[h:], 500, 0.5, 2.0)
+    got = np.concatenate([sf, sm])
+    pins["SGP vs bounded least squares"] = (float(np.abs(got - ref).max() / np.abs(ref).max()), 1e-8)
+    pins["SGP monotone"] = (max([0.0] + [b - a for a, b in zip(qv, qv[1:])]), 1e-12)
     return pins
 
 
