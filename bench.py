@@ -83,7 +83,7 @@ def parse():
                          "server vs the plain per-slice solver")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=5.0, help="serve: seconds of arrivals")
-    ap.add_argument("--pool", type=int, default=64, help="serve: distinct request payloads")
+    ap.add_argument("--pool", type=int, default=256, help="serve: distinct request payloads")
     ap.add_argument("--streams", type=int, default=4, help="serve (--server batch): concurrent solves")
     ap.add_argument("--server", default="iter", choices=["iter", "batch"],
                     help="serve: iter = per-size slot pools admitting requests at every outer-iteration "
