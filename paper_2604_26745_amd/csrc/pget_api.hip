@@ -284,7 +284,7 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
     const size_t B = (size_t)batch;
     const size_t n2 = (size_t)g.n * g.n;
     const size_t sino = (size_t)g.n_angles * g.n_bins;
-    const size_t lat = (size_t)g.n_angles * g.n_t * g.n_bins;
+    const size_t lat = (size_t)P->support;   // compacted per-sample arrays: in-support samples only
     // with a depth response the ray totals and the blurred cotangents have a
     // far plane B * sino elements after the near one, and the far prefix
     // sums their own per-sample array
@@ -405,13 +405,13 @@ void launch_vjp(const pget_plan* P, const VjpArgs& V, int batch, hipStream_t s)
 {
     const dim3 grid(P->tiles_x * P->tiles_x * V.groups, batch), block(VJP_THREADS);
     if (P->t.resp) {
-        hipLaunchKernelGGL((k_vjp_lin<F32DR, false>), grid, block, 0, s, V, V.t.trig);
+        hipLaunchKernelGGL((k_vjp_lin<F32DR, false>), grid, block, 0, s, V, V.t.trig, V.t.gcol);
     } else if (P->bf16) {
-        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<BF16S, true>), grid, block, 0, s, V, V.t.trig);
-        else hipLaunchKernelGGL((k_vjp_lin<BF16S, false>), grid, block, 0, s, V, V.t.trig);
+        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<BF16S, true>), grid, block, 0, s, V, V.t.trig, V.t.gcol);
+        else hipLaunchKernelGGL((k_vjp_lin<BF16S, false>), grid, block, 0, s, V, V.t.trig, V.t.gcol);
     } else {
-        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<F32S, true>), grid, block, 0, s, V, V.t.trig);
-        else hipLaunchKernelGGL((k_vjp_lin<F32S, false>), grid, block, 0, s, V, V.t.trig);
+        if (P->g.quad) hipLaunchKernelGGL((k_vjp_lin<F32S, true>), grid, block, 0, s, V, V.t.trig, V.t.gcol);
+        else hipLaunchKernelGGL((k_vjp_lin<F32S, false>), grid, block, 0, s, V, V.t.trig, V.t.gcol);
     }
 }
 
@@ -541,13 +541,53 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
             }
             if (hi < lo) { lo = 1; hi = 0; }
             clip[(size_t)a * nb + j] = make_int2(lo, hi);
-            if (hi >= lo) P->support += hi - lo + 1;
-            if (hi >= lo) {
-                int2& gr = grange[(size_t)a * ng + j / RG];
-                if (gr.y < gr.x) gr = make_int2(lo, hi);
-                else gr = make_int2(std::min(gr.x, lo), std::max(gr.y, hi));
-            }
         }
+    }
+    // A full turn with an even angle count: ray n_b-1-j of angle a + n/2
+    // visits ray j's points in reverse; its clip range is taken from ray j's
+    // (exact symmetry, whatever the rounding of the two FP64 tests), so that
+    // a sample and its mirror are in the support together.
+    if (g.paired)
+        for (int a = 0; a < na / 2; ++a)
+            for (int j = 0; j < nb; ++j) {
+                const int2 c = clip[(size_t)a * nb + j];
+                clip[(size_t)(a + na / 2) * nb + (nb - 1 - j)] =
+                    c.y >= c.x ? make_int2(nt - 1 - c.y, nt - 1 - c.x) : make_int2(1, 0);
+            }
+    // ray offsets of the compacted per-sample arrays: a ray's in-support
+    // samples contiguous, rays in (angle, bin) order, except that in paired
+    // geometry ray (a + n_a/2, n_b-1-j) follows ray (a, j) (the adjoint then
+    // finds the mirror's samples from the ray's own offset)
+    std::vector<int> roff((size_t)na * nb);
+    auto place = [&](size_t r) {
+        const int2 c = clip[r];
+        roff[r] = (int)std::min<int64_t>(P->support, INT32_MAX);
+        if (c.y >= c.x) P->support += c.y - c.x + 1;
+    };
+    for (int a = 0; a < (g.paired ? na / 2 : na); ++a)
+        for (int j = 0; j < nb; ++j) {
+            place((size_t)a * nb + j);
+            if (g.paired) place((size_t)(a + na / 2) * nb + (nb - 1 - j));
+        }
+    if (P->support >= ((int64_t)1 << 29)) {
+        delete P;
+        return PGET_ERR_UNSUPPORTED;   // the adjoint's byte offsets (8 B per sample) are 32-bit
+    }
+    // the groups' unions of clip ranges
+    for (int a = 0; a < na; ++a)
+        for (int j = 0; j < nb; ++j) {
+            const int2 c = clip[(size_t)a * nb + j];
+            if (c.y < c.x) continue;
+            int2& gr = grange[(size_t)a * ng + j / RG];
+            if (gr.y < gr.x) gr = c;
+            else gr = make_int2(std::min(gr.x, c.x), std::max(gr.y, c.y));
+        }
+    // the adjoint's column table: (lo | len << 16, offset of sample 0); empty
+    // rays (0, 0).  n_t <= 728 (n <= 512, step >= 1) fits 16 bits.
+    std::vector<int2> gcol((size_t)na * nb);
+    for (size_t r = 0; r < gcol.size(); ++r) {
+        const int2 c = clip[r];
+        gcol[r] = c.y >= c.x ? make_int2(c.x | ((c.y - c.x + 1) << 16), roff[r] - c.x) : make_int2(0, 0);
     }
     if (K == 0) taps[0] = 1.0f;
     else {
@@ -564,7 +604,9 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     size_t o_clip = align_up(o_rbase + rbase.size() * sizeof(float2));
     size_t o_gr = align_up(o_clip + clip.size() * sizeof(int2));
     size_t o_taps = align_up(o_gr + grange.size() * sizeof(int2));
-    size_t total = align_up(o_taps + taps.size() * sizeof(float));
+    size_t o_roff = align_up(o_taps + taps.size() * sizeof(float));
+    size_t o_gcol = align_up(o_roff + roff.size() * sizeof(int));
+    size_t total = align_up(o_gcol + gcol.size() * sizeof(int2));
     if (hipGetDevice(&P->device) != hipSuccess || hipMalloc(&P->table_mem, total) != hipSuccess) {
         delete P;
         return PGET_ERR_HIP;
@@ -574,7 +616,9 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
               hipMemcpy(base + o_rbase, rbase.data(), rbase.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(base + o_clip, clip.data(), clip.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(base + o_gr, grange.data(), grange.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(base + o_taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(base + o_taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + o_roff, roff.data(), roff.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + o_gcol, gcol.data(), gcol.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         (void)hipFree(P->table_mem);
         delete P;
@@ -585,6 +629,8 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     P->t.clip = reinterpret_cast<const int2*>(base + o_clip);
     P->t.grange = reinterpret_cast<const int2*>(base + o_gr);
     P->t.taps = reinterpret_cast<const float*>(base + o_taps);
+    P->t.roff = reinterpret_cast<const int*>(base + o_roff);
+    P->t.gcol = reinterpret_cast<const int2*>(base + o_gcol);
     P->t.depth = nullptr;
     P->t.resp = nullptr;
     P->t.taps_far = nullptr;
@@ -861,13 +907,9 @@ static void linearise(const pget_plan* P, const float* f, const float* mu, float
     A.wq = P->t.resp ? reinterpret_cast<float*>(at(ws, L.wq)) : nullptr;
     A.far_off = L.far_off;
     A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
-    A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
+    A.wts_stride = P->support;
     A.yout = y_or_null;
     A.angles_per_block = sh.apb;
-    // samples outside the support are never written; the adjoint reads them
-    // (with zero interpolation weight), so they must hold finite values
-    fill_zero(at(ws, L.wts), (size_t)A.wts_stride * P->w_bytes, stream);
-    if (A.wq) fill_zero(A.wq, (size_t)A.wts_stride * sizeof(float), stream);
     if (!P->lds_img) {
         A.gimg = at(ws, L.gimg);
         pack(P, A.src, nullptr, at(ws, L.gimg), 1, nullptr, stream);
@@ -892,7 +934,7 @@ pget_status pget_jvp(const pget_plan* P, const float* f, const float* mu, const 
     A.wq = P->t.resp ? reinterpret_cast<const float*>(at(ws, L.wq)) : nullptr;
     A.far_off = L.far_off;
     A.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
-    A.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
+    A.wts_stride = P->support;
     A.out = jv;
     A.angles_per_block = sh.apb;
     if (!P->jvp_lds) {
@@ -930,7 +972,7 @@ pget_status pget_vjp(const pget_plan* P, const float* f, const float* mu, const 
     V.far_off = L.far_off;
     V.wt = wt;
     V.sino_stride = (long long)P->g.n_angles * P->g.n_bins;
-    V.wts_stride = (long long)P->g.n_angles * P->g.n_t * P->g.n_bins;
+    V.wts_stride = P->support;
     const long long n2 = (long long)P->g.n * P->g.n;
     V.gpart = reinterpret_cast<float*>(at(ws, L.gpart_cg));
     V.gpart_group_stride = 2 * n2;
@@ -1027,7 +1069,7 @@ void setup(Solve& S)
     const Geo& g = P->g;
     const long long n2 = (long long)g.n * g.n;
     const long long sino = (long long)g.n_angles * g.n_bins;
-    const long long lat = (long long)g.n_angles * g.n_t * g.n_bins;
+    const long long lat = P->support;   // compacted per-sample arrays
     void* ws = S.ws;
     double* part = reinterpret_cast<double*>(at(ws, S.L.part));
     float* u = reinterpret_cast<float*>(at(ws, S.L.u));
@@ -1470,8 +1512,6 @@ void enqueue_group(Group& G, hipStream_t s)
     SS.stream = s;
     const int B = SS.B;
     hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, s, SS.V.st, SS.V.prm, B);
-    fill_zero(SS.lin.wts, (size_t)B * SS.lin.wts_stride * SS.P->w_bytes, s);
-    if (SS.lin.wq) fill_zero(SS.lin.wq, (size_t)B * SS.lin.wts_stride * sizeof(float), s);
     for (int k = 0; k < G.max_outer; ++k) {
         enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false, G.trace, false, G.sgp);
         enqueue_commit(SS);
@@ -1514,8 +1554,6 @@ pget_status solve_groups(std::vector<Group>& groups, pget_refine_fn hook, void* 
         Solve& S = G.S;
         const int B = S.B;
         hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, stream, S.V.st, S.V.prm, B);
-        fill_zero(S.lin.wts, (size_t)B * S.lin.wts_stride * S.P->w_bytes, stream);
-        if (S.lin.wq) fill_zero(S.lin.wq, (size_t)B * S.lin.wts_stride * sizeof(float), stream);
         for (int k = 0; k < G.max_outer; ++k) {
             enqueue_iteration(S, k, G.n_cg, G.need_beta0, true, G.trace, false, G.sgp);
             pget_status rc = run_hook(S, hook, hook_user);
@@ -1906,13 +1944,14 @@ pget_status pget_lm_pool_create(const pget_plan* plan, int32_t capacity, int32_t
     Q->prm.assign(capacity, LMParamsDev{});
     Q->loaded.assign(capacity, 0);
     report_arrays(S, max_outer, n_cg, Q->rep);
-    // weights outside the support are never written and must read as zero;
-    // every slot starts free (finished)
-    fill_zero(S.lin.wts, (size_t)capacity * S.lin.wts_stride * plan->w_bytes, stream);
-    if (S.lin.wq) fill_zero(S.lin.wq, (size_t)capacity * S.lin.wts_stride * sizeof(float), stream);
+    // every slot starts free (finished), with zeroed parameters: the report
+    // kernels of a step (k_final_reg reads a slot's prior pointers) also run
+    // over free slots
+    bool ok = hipMemcpyAsync(const_cast<LMParamsDev*>(S.V.prm), Q->prm.data(), capacity * sizeof(LMParamsDev),
+                             hipMemcpyHostToDevice, stream) == hipSuccess;
     hipLaunchKernelGGL(k_pool_clear, dim3((capacity + 63) / 64), dim3(64), 0, stream, S.V.st, capacity);
     hipLaunchKernelGGL(k_pool_flags, dim3((capacity + 63) / 64), dim3(64), 0, stream, S.V.st, Q->flags, capacity);
-    bool ok = hipMemcpyAsync(S.V.rep, Q->rep.data(), capacity * sizeof(ReportDev), hipMemcpyHostToDevice, stream) ==
+    ok = ok && hipMemcpyAsync(S.V.rep, Q->rep.data(), capacity * sizeof(ReportDev), hipMemcpyHostToDevice, stream) ==
                   hipSuccess &&
               hipStreamSynchronize(stream) == hipSuccess && hipGetLastError() == hipSuccess;
     if (!ok) {
@@ -1992,6 +2031,11 @@ pget_status pget_lm_pool_fetch(pget_lm_pool* Q, int32_t slot, float* f_out, floa
     if (report) copy_report(Q->rep[slot], report, Q->prm[slot].max_outer, Q->n_cg, stream);
     hipLaunchKernelGGL(k_pool_release, dim3(1), dim3(64), 0, stream, S.V.st, slot);
     HIP_TRY(hipGetLastError());
+    // zeroed parameters: the freed slot's prior and trace pointers belong to
+    // the caller and may not outlive the fetch
+    Q->prm[slot] = LMParamsDev{};
+    HIP_TRY(hipMemcpyAsync(const_cast<LMParamsDev*>(S.V.prm) + slot, &Q->prm[slot], sizeof(LMParamsDev),
+                           hipMemcpyHostToDevice, stream));
     Q->loaded[slot] = 0;
     return PGET_OK;
 }

@@ -52,6 +52,13 @@ struct Tables {
     const int2* clip;     // [n_angles][n_bins]: samples [lo, hi] inside the support; lo > hi if none
     const int2* grange;   // [n_angles][n_groups]: union of the group's clip ranges
     const float* taps;    // [2K + 1]
+    const int* roff;      // [n_angles][n_bins]: offset of the ray's first in-support sample in the
+                          // compacted per-sample arrays (a ray's samples lo..hi contiguous)
+    const int2* gcol;     // [n_angles][n_bins]: the adjoint's column table (lo | len << 16,
+                          // b = roff - lo; (0, 0) for an empty ray): sample i of the ray sits
+                          // at b + i; in paired geometry the mirror ray (range the reflection
+                          // of [lo, hi]) is stored right after it, its sample at the same
+                          // point at b + 2 hi + 1 - i
     const float* depth;   // [n_t]: depth factor of the attenuation path per sample, or nullptr (1)
     const float* resp;    // [n_t]: weight alpha_i of the far collimator response per sample, or
                           // nullptr (the response is taps at every depth)
@@ -263,7 +270,7 @@ template <typename S>
 __global__ void k_pack(Geo g, PairSrc s, const double* part, void* out, long long out_stride,
                        const LMState* st);
 __global__ void k_psf(Geo g, const float* taps_g, const float* in, float* out);
-template <typename S, bool QUAD> __global__ void k_vjp_lin(VjpArgs A, const float4* trig);
+template <typename S, bool QUAD> __global__ void k_vjp_lin(VjpArgs A, const float4* trig, const int2* gcol);
 __global__ void k_fill_zero(float4* p, long long n4);
 __global__ void k_sum_groups(int n2, int groups, int gfold, const float* gpart, long long group_stride,
                              float* gf, float* gm);

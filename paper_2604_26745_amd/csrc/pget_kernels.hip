@@ -61,12 +61,15 @@ __device__ __forceinline__ float quad_sum(float x)
     return x;
 }
 
-// Sum over the lanes of one ray (4: the quad; 2: lane pairs within it).
+// Sum over the LANES consecutive lanes of one ray (a power of two <= 64),
+// returned to all of them: quad permutes, then butterflies across quads.
 template <int LANES>
 __device__ __forceinline__ float ray_sum(float x)
 {
     x += qperm<QP_SWAP1>(x);
-    if (LANES == 4) x += qperm<QP_SWAP2>(x);
+    if (LANES >= 4) x += qperm<QP_SWAP2>(x);
+#pragma unroll
+    for (int o = 4; o < LANES; o <<= 1) x += __shfl_xor(x, o, 64);
     return x;
 }
 
@@ -130,7 +133,11 @@ struct F32S {
     using w_t = float2;
     static constexpr bool DR = false;     // no depth-dependent collimator response
     static constexpr int VJP_WAVES = 3;   // gather waves per SIMD (register budget 168)
-    static constexpr int JVP_SPL = 4;     // Jacobian product: lanes per ray (16 rays x 8 B = a 128 B row)
+    // Jacobian product: lanes per ray (8 samples x 8 B = 64 B per ray and
+    // load), and loads in flight per lane and ray.  Eight rays per wave keep
+    // the trip count close to each ray's length.
+    static constexpr int JVP_SPL = 8;
+    static constexpr int JVP_JU = 8;
     static __device__ __forceinline__ float2 px(px_t v) { return v; }
     static __device__ __forceinline__ px_t to_px(float2 v) { return v; }
     static __device__ __forceinline__ float2 w(w_t v) { return v; }
@@ -142,7 +149,8 @@ struct BF16S {
     using w_t = uint32_t;
     static constexpr bool DR = false;
     static constexpr int VJP_WAVES = 4;   // half the staged weight registers (budget 128)
-    static constexpr int JVP_SPL = 2;     // 32 rays x 4 B: a full 128 B row per load
+    static constexpr int JVP_SPL = 8;     // 8 samples x 4 B = 32 B per ray and load
+    static constexpr int JVP_JU = 8;
     static __device__ __forceinline__ float2 px(px_t v)
     {
         return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
@@ -159,6 +167,7 @@ struct BF16S {
 struct F32DR : F32S {
     static constexpr bool DR = true;
     static constexpr int VJP_WAVES = 2;   // the far sums double the staged registers
+    static constexpr int JVP_JU = 2;      // the far sums take the registers of two more trips
 };
 
 // Bilinear sample of the zero-bordered interleaved map pair at (col, row)
@@ -313,9 +322,11 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
             const bool ray_ok = j < g.n_bins;
             int2 cl = make_int2(1, 0);
             float2 rb = make_float2(0.0f, 0.0f);
+            long long ray0 = 0;   // compacted index of the ray's sample 0 (its samples lo..hi stored there)
             if (ray_ok) {
                 cl = A.t.clip[(size_t)a * g.n_bins + j];
                 rb = A.t.rbase[(size_t)a * g.n_bins + j];
+                ray0 = (long long)A.t.roff[(size_t)a * g.n_bins + j] - cl.x;
             }
             const int2 gr = A.t.grange[(size_t)a * g.n_groups + grp];
             float carry_mu = 0.0f, carry_le = 0.0f, carry_dle = 0.0f;
@@ -323,11 +334,13 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
             // near and the far response (lambda E and, for the Jacobian, d lambda E)
             float carry_lf = 0.0f, carry_dn = 0.0f, carry_df = 0.0f;
             const float* depth = A.t.depth;   // per-sample factor of the attenuation path, or none
-            w_t* wrow = nullptr;
-            float* qrow = nullptr;
+            // compacted per-sample arrays of the slice: sample i of this ray
+            // at ray0 + i (written only inside the ray's support)
+            w_t* wsl = nullptr;
+            float* qsl = nullptr;
             if (MODE == MARCH_LIN) {
-                wrow = static_cast<w_t*>(A.wts) + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
-                if (S::DR) qrow = A.wq + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
+                wsl = static_cast<w_t*>(A.wts) + (size_t)slice * A.wts_stride;
+                if (S::DR) qsl = A.wq + (size_t)slice * A.wts_stride;
             }
             for (int i0 = gr.y; i0 >= gr.x; i0 -= SPL) {
                 const int i = i0 - q;
@@ -366,8 +379,8 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                         quad_scan(dfv, q, dfincl, dftot);
                     }
                     if (MODE == MARCH_LIN && act) {
-                        wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, carry_dn + (dnincl - hs * dn));
-                        qrow[(size_t)i * g.n_bins + j] = carry_df + (dfincl - hs * dfv);
+                        wsl[ray0 + i] = S::to_w(g.step * E, carry_dn + (dnincl - hs * dn));
+                        qsl[ray0 + i] = carry_df + (dfincl - hs * dfv);
                     }
                     carry_lf += ftot;
                     carry_dn += dntot;
@@ -378,7 +391,7 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                     quad_scan(le, q, lincl, ltot);
                     if (MODE == MARCH_LIN && act) {
                         const float rprime = carry_le + (lincl - hs * le);
-                        wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, rprime);
+                        wsl[ray0 + i] = S::to_w(g.step * E, rprime);
                     }
                 } else {
                     // E_i = exp(-c d_i B_i); the ray sum needs lam E, the
@@ -391,7 +404,7 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
                     quad_scan(dle, q, dincl, dtot);
                     if (MODE == MARCH_LIN && act) {
                         const float rprime = carry_dle + (dincl - hs * dle);
-                        wrow[(size_t)i * g.n_bins + j] = S::to_w(g.step * E, rprime);
+                        wsl[ray0 + i] = S::to_w(g.step * E, rprime);
                     }
                     carry_dle += dtot;
                 }
@@ -490,22 +503,24 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const px_t* img = LDS_IMG ? simg : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
     __syncthreads();
 
-    // A wave covers JR consecutive rays with JSPL lanes per ray, so that one
-    // load instruction reads whole 128-byte rows of the weight array (16 rays
-    // of FP32 pairs or 32 rays of BF16 pairs).
+    // A wave covers JR consecutive rays with JSPL lanes per ray; the weights
+    // of a ray's in-support samples are contiguous (compacted arrays), so one
+    // load instruction reads JSPL consecutive samples of each of its rays.
+    // The mirror ray holds the same points in reverse order (sample i of this
+    // ray is sample n_t - 1 - i of the mirror), stored right after the ray.
     constexpr int JSPL = S::JVP_SPL;
     constexpr int JR = 64 / JSPL;
-    constexpr int GPI = JR / RG;            // ray groups of the plan tables per item
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int q = lane & (JSPL - 1), jj = lane / JSPL;
     const w_t* wslice = static_cast<const w_t*>(A.wts) + (size_t)slice * A.wts_stride;
+    const float* qslice = S::DR ? A.wq + (size_t)slice * A.wts_stride : nullptr;
     const float* tslice = A.tsum + (size_t)slice * A.sino_stride;
     // Items are taken from a block-wide counter (dynamic balance), longest
     // first: ray groups ordered from the middle of the detector outward.
     __shared__ int next_item;
     if (threadIdx.x == 0) next_item = nwaves;
     __syncthreads();
-    const int n_ig = (g.n_groups + GPI - 1) / GPI;
+    const int n_ig = (g.n_bins + JR - 1) / JR;
     const int n_items = nslot * n_ig;
     const int gc = n_ig / 2;
     for (int item = wave; item < n_items;) {
@@ -517,67 +532,75 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         const int j = grp * JR + jj;
         const int jm = g.n_bins - 1 - j;
         const bool ray_ok = j < g.n_bins;
-        int2 cl = make_int2(1, 0);
+        int2 cl = make_int2(1, 0), clm = make_int2(1, 0);
         float2 rb = make_float2(0.0f, 0.0f);
         float T = 0.0f, Tm = 0.0f, Tf = 0.0f, Tfm = 0.0f;
+        long long off = 0, offm = 0;   // compacted index of the ray's first in-support sample
         if (ray_ok) {
             cl = A.t.clip[(size_t)a * g.n_bins + j];
             rb = A.t.rbase[(size_t)a * g.n_bins + j];
+            off = A.t.roff[(size_t)a * g.n_bins + j];
             T = tslice[(size_t)a * g.n_bins + j];
-            if (g.paired) Tm = tslice[(size_t)am * g.n_bins + jm];
+            if (g.paired) {
+                clm = A.t.clip[(size_t)am * g.n_bins + jm];
+                offm = A.t.roff[(size_t)am * g.n_bins + jm];
+                Tm = tslice[(size_t)am * g.n_bins + jm];
+            }
             if (S::DR) {
                 Tf = tslice[A.far_off + (size_t)a * g.n_bins + j];
                 if (g.paired) Tfm = tslice[A.far_off + (size_t)am * g.n_bins + jm];
             }
         }
-        int2 gr = A.t.grange[(size_t)a * g.n_groups + grp * GPI];
+        const int len = cl.y - cl.x + 1;   // <= 0 without support
+        // trips of the item: the longest of its rays (wave-uniform)
+        int tmax = len;
 #pragma unroll
-        for (int h = 1; h < GPI; ++h) {     // union with the item's other plan groups
-            if (grp * GPI + h < g.n_groups) {
-                const int2 gh = A.t.grange[(size_t)a * g.n_groups + grp * GPI + h];
-                gr = make_int2(min(gr.x, gh.x), max(gr.y, gh.y));
-            }
-        }
-        const w_t* wrow = wslice + (size_t)a * g.n_t * g.n_bins;
-        const w_t* wrowm = wslice + (size_t)am * g.n_t * g.n_bins;
-        const float* qrow = S::DR ? A.wq + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins : nullptr;
-        const float* qrowm = S::DR ? A.wq + (size_t)slice * A.wts_stride + (size_t)am * g.n_t * g.n_bins : nullptr;
+        for (int o = JSPL; o < 64; o <<= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
+        tmax = __builtin_amdgcn_readfirstlane(tmax);
         float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
         // depth response: accf / accq collect the near parts, these the far
         float accff = 0.0f, accqf = 0.0f, accffm = 0.0f, accqfm = 0.0f;
         // The sample loop is software-pipelined: the weights of trip t+1 (JU
         // samples per lane) are loaded while trip t is computed; they stay in
-        // their storage format until used.  Lanes outside their ray's support
-        // load nothing and use (0, T), which makes both terms vanish.
-        constexpr int JU = S::DR ? 2 : 4;   // the far sums take the registers of two more trips
+        // their storage format until used.  Lanes past their ray's support
+        // load nothing and use (0, T), which makes both terms vanish.  Sample
+        // c of the trip pattern is the ray's sample lo + c; the mirror holds it
+        // at its own sample n_t - 1 - i (inside the mirror's support, which
+        // equals this ray's reversed).
+        constexpr int JU = S::JVP_JU;
         constexpr int STEP = JU * JSPL;
         constexpr int QU = S::DR ? JU : 1;
         w_t wa[JU], wma[JU], wb[JU], wmb[JU];
         float qa[QU], qma[QU], qb[QU], qmb[QU];
-        auto load = [&](int i0, w_t* w, w_t* wm, float* qv, float* qm) {
+        // sub-steps past the item's longest ray are skipped (wave-uniform)
+        auto load = [&](int c0, w_t* w, w_t* wm, float* qv, float* qm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
-                const int i = i0 - u * JSPL - q;
-                const bool ok = (i >= cl.x) && (i <= cl.y);
-                w[u] = ok ? wrow[(size_t)i * g.n_bins + j] : w_t{};
-                if (g.paired) wm[u] = ok ? wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : w_t{};
+                if (u > 0 && c0 + u * JSPL >= tmax) break;
+                const int c = c0 + u * JSPL + q;
+                const bool ok = c < len;
+                const int i = cl.x + c;
+                const long long cm = (long long)(g.n_t - 1 - i - clm.x);
+                w[u] = ok ? wslice[off + c] : w_t{};
+                if (g.paired) wm[u] = ok ? wslice[offm + cm] : w_t{};
                 if constexpr (S::DR) {
-                    qv[u] = ok ? qrow[(size_t)i * g.n_bins + j] : 0.0f;
-                    if (g.paired) qm[u] = ok ? qrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm] : 0.0f;
+                    qv[u] = ok ? qslice[off + c] : 0.0f;
+                    if (g.paired) qm[u] = ok ? qslice[offm + cm] : 0.0f;
                 }
             }
         };
-        auto compute = [&](int i0, const w_t* w, const w_t* wm, const float* qv, const float* qm) {
+        auto compute = [&](int c0, const w_t* w, const w_t* wm, const float* qv, const float* qm) {
 #pragma unroll
             for (int u = 0; u < JU; ++u) {
-                const int i = i0 - u * JSPL - q;
-                const bool ok = (i >= cl.x) && (i <= cl.y);
+                if (u > 0 && c0 + u * JSPL >= tmax) break;
+                const int c = c0 + u * JSPL + q;
+                const bool ok = c < len;
+                const int i = cl.x + c;
                 const float ti = (float)i - g.t_off;
                 const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
                 const float2 v = bilerp<S>(img, g.pitch, g.n, col, row);
                 const float2 wv = S::w(w[u]);
                 if constexpr (S::DR) {
-                    // sample i of this ray is sample n_t - 1 - i of the mirror ray
                     const float al = ok ? alpha[i] : 0.0f;
                     const float ef = wv.x * v.x;
                     accf = fmaf(1.0f - al, ef, accf);
@@ -604,17 +627,17 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                 }
             }
         };
-        int i0 = gr.y;
-        if (i0 >= gr.x) load(i0, wa, wma, qa, qma);
-        while (i0 >= gr.x) {
-            const int i1 = i0 - STEP;
-            if (i1 >= gr.x) load(i1, wb, wmb, qb, qmb);
-            compute(i0, wa, wma, qa, qma);
-            if (i1 < gr.x) break;
-            const int i2 = i1 - STEP;
-            if (i2 >= gr.x) load(i2, wa, wma, qa, qma);
-            compute(i1, wb, wmb, qb, qmb);
-            i0 = i2;
+        int c0 = 0;
+        if (c0 < tmax) load(c0, wa, wma, qa, qma);
+        while (c0 < tmax) {
+            const int c1 = c0 + STEP;
+            if (c1 < tmax) load(c1, wb, wmb, qb, qmb);
+            compute(c0, wa, wma, qa, qma);
+            if (c1 >= tmax) break;
+            const int c2 = c1 + STEP;
+            if (c2 < tmax) load(c2, wa, wma, qa, qma);
+            compute(c1, wb, wmb, qb, qmb);
+            c0 = c2;
         }
         accf = ray_sum<JSPL>(accf);
         accq = ray_sum<JSPL>(accq);
@@ -721,6 +744,11 @@ __device__ __forceinline__ Window tile_window(const Geo& g, float4 tr, int tr0, 
     // last candidate is floor(max - sqrt2) + 3; one more column of margin
     w.wj = min(VFP, (int)floorf(umax - SQ2) + 5 - w.jlo);
     w.wi = min(VFP, (int)floorf(vmax - SQ2) + 5 - w.ilo);
+    // wave-uniform: held in scalar registers
+    w.jlo = __builtin_amdgcn_readfirstlane(w.jlo);
+    w.ilo = __builtin_amdgcn_readfirstlane(w.ilo);
+    w.wj = __builtin_amdgcn_readfirstlane(w.wj);
+    w.wi = __builtin_amdgcn_readfirstlane(w.wi);
     return w;
 }
 
@@ -738,161 +766,223 @@ __device__ __forceinline__ Window rot_window(const Geo& g, const Window& W)
     return r;
 }
 
-// Window rows per wave: the block's 4 waves take rows w, w+4, ...; lane =
-// window column.  No integer division in the staging index math.
-constexpr int VROWS = (VFP + 3) / 4;
+// Window columns per wave: the block's 4 waves take columns (rays) w, w+4,
+// ...; lane = window row (sample).  A ray's in-support samples are
+// contiguous in the compacted per-sample arrays, so each load reads
+// consecutive samples of one ray.
+constexpr int VCOLS = (VFP + 3) / 4;
 // LDS row pitch of the staged window (odd in float2 pairs' halves: the
 // transposed adds of the rotated angles spread over the banks)
 constexpr int LP = VFP + 1;
 
-// One angle's window in registers: weight pair per point (rows wave + 4k,
-// column lane) and the blurred cotangent and ray total of the lane's column,
-// with the same for the mirror angle when the geometry is paired.  The
-// weights stay in their storage format until they are staged in LDS, so
-// that no conversion waits on a load while the previous angle is gathered.
+// One angle's window in registers: the weight pair of every point (row
+// lane, columns wave + 4k) with the mirror angle's at the same points, and,
+// for the LDS column table, the blurred cotangent and ray total of the
+// lane's column (lane = column there) and its mirror's.  The weights stay
+// in their storage format until they are staged in LDS, so that no
+// conversion waits on a load while the previous angle is gathered.
 template <typename SP>
 struct Stage {
-    typename SP::w_t w[VROWS];
-    typename SP::w_t wm[VROWS];   // mirror angle, same points (paired geometry)
-    float wt, t, wtm, tm;
-    // depth response: R' of the far response per point, the far cotangent
-    // and total of the lane's column, and alpha of window row `lane` for the
-    // angle and its mirror (a staged row takes its value by readlane: rows
-    // are wave-uniform)
-    static constexpr int QR = SP::DR ? VROWS : 1;
+    typename SP::w_t w[VCOLS];
+    typename SP::w_t wm[VCOLS];   // mirror angle, same points (paired geometry)
+    float4 cv;                    // (wt, T, wt of the mirror, T of the mirror) of column `lane`
+    // depth response: R' of the far response per point, the far planes of
+    // the column values, and alpha of row `lane` for the angle and its mirror
+    static constexpr int QR = SP::DR ? VCOLS : 1;
     float q[QR], qm[QR];
-    float wtf, tf, wtfm, tfm;
+    float4 cvf;
     float al, alm;
+    // column table (lo | len << 16, base) of the next angle this stage loads
+    // (lane = column): read one angle ahead, so that the weight loads never
+    // wait on a dependent load
+    int2 ct;
 };
 
-// Loads of one angle's window into registers (weight pair per point, and the
-// blurred cotangent and ray total of the lane's column).  Rows past the
-// window or off the lattice are skipped (wave-uniform tests) and read as zero;
-// lanes whose column is off the window or the detector read zero.
+// Column-table entries of angle a for window W's columns (lane = column);
+// columns off the window or the detector read as empty rays.
+__device__ __forceinline__ int2 col_table(const Geo& g, const int2* __restrict__ gcol, int a, const Window& W)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = W.jlo + lane;
+    return (lane < W.wj && j >= 0 && j < g.n_bins) ? gcol[(size_t)a * g.n_bins + j] : make_int2(0, 0);
+}
+
+// The weights of one window column (rows = lanes) of a stage: zero, then,
+// where row i lies in the ray's support [lo, lo + len), the sample and (PAIRED)
+// the mirror ray's sample at the same point.  b: element offset of the ray's
+// sample 0 (negative when the ray's first sample opens the array), bm: of
+// the mirror's sample at sample 0's point (the mirror's range is the
+// reflection of the ray's, its samples stored right after it, so its sample
+// at row i sits at b + 2 hi + 1 - i).  Byte offsets are formed in 32-bit
+// unsigned arithmetic, modulo 2^32: b + i and bm - i lie in [0, 2^29), so
+// (b + i) * size is exact whatever the sign of b; iw = i * sizeof(w_t),
+// iq = 4 i.
+template <typename SP, bool PAIRED>
+__device__ __forceinline__ void stage_column(Stage<SP>& S, int k, const char* wb, const char* qb, int i, int lo,
+                                             unsigned len, unsigned b, unsigned bm, unsigned iw, unsigned iq)
+{
+    using w_t = typename SP::w_t;
+    constexpr unsigned WB = sizeof(w_t);
+    S.w[k] = w_t{};                 // zero in either format
+    if (PAIRED) S.wm[k] = w_t{};
+    if constexpr (SP::DR) {
+        S.q[k] = 0.0f;
+        if (PAIRED) S.qm[k] = 0.0f;
+    }
+    if ((unsigned)(i - lo) < len) {
+        S.w[k] = *reinterpret_cast<const w_t*>(wb + (b * WB + iw));
+        if (PAIRED) S.wm[k] = *reinterpret_cast<const w_t*>(wb + (bm * WB - iw));
+        if constexpr (SP::DR) {
+            S.q[k] = *reinterpret_cast<const float*>(qb + (b * 4u + iq));
+            if (PAIRED) S.qm[k] = *reinterpret_cast<const float*>(qb + (bm * 4u - iq));
+        }
+    }
+}
+
+// Loads of one angle's window into registers, by the column table read by
+// the previous call (S.ct); then reads the table of angle `an` over window
+// Wnx for the next call (has_next).  Rows outside a column's support and
+// columns off the window or the detector stage zero weights; rows past the
+// window (lanes >= W.wi) stage their points' true weights, which the gather
+// meets only with a tent weight of exactly zero.
 template <typename SP>
 __device__ __forceinline__ void stage_load(Stage<SP>& S, const VjpArgs& A, const typename SP::w_t* wbase,
-                                           int slice, int a, const Window& W)
+                                           const float* qbase, int slice, int a, const Window& W, bool has_next,
+                                           int an, const Window& Wnx, const int2* __restrict__ gcol)
 {
     const Geo& g = A.g;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int am = a + g.n_angles / 2;
-    const typename SP::w_t* wrow = wbase + (size_t)a * g.n_t * g.n_bins;
-    const typename SP::w_t* wrowm = wbase + (size_t)am * g.n_t * g.n_bins;
     const size_t sbase = (size_t)slice * A.sino_stride + (size_t)a * g.n_bins;
     const size_t sbasem = (size_t)slice * A.sino_stride + (size_t)am * g.n_bins;
-    const int j = W.jlo + lane;
-    const int jm = g.n_bins - 1 - j;
-    const bool jok = lane < W.wj && j >= 0 && j < g.n_bins;
-    S.wt = jok ? A.wt[sbase + j] : 0.0f;
-    S.t = jok ? A.tsum[sbase + j] : 0.0f;
-    S.wtm = (jok && g.paired) ? A.wt[sbasem + jm] : 0.0f;
-    S.tm = (jok && g.paired) ? A.tsum[sbasem + jm] : 0.0f;
-#pragma unroll
-    for (int k = 0; k < VROWS; ++k) {
-        S.w[k] = typename SP::w_t{};     // zero in either format
-        S.wm[k] = typename SP::w_t{};
+    const int2 cur = S.ct;
+    // column values (lane = column)
+    {
+        const int j = W.jlo + lane;
+        const int jm = g.n_bins - 1 - j;
+        const bool jok = lane < W.wj && j >= 0 && j < g.n_bins;
+        S.cv = make_float4(jok ? A.wt[sbase + j] : 0.0f, jok ? A.tsum[sbase + j] : 0.0f,
+                           (jok && g.paired) ? A.wt[sbasem + jm] : 0.0f,
+                           (jok && g.paired) ? A.tsum[sbasem + jm] : 0.0f);
+        if constexpr (SP::DR)
+            S.cvf = make_float4(jok ? A.wt[A.far_off + sbase + j] : 0.0f, jok ? A.tsum[A.far_off + sbase + j] : 0.0f,
+                                (jok && g.paired) ? A.wt[A.far_off + sbasem + jm] : 0.0f,
+                                (jok && g.paired) ? A.tsum[A.far_off + sbasem + jm] : 0.0f);
     }
-    const float* qrow = nullptr;
-    const float* qrowm = nullptr;
+    // weights (lane = row, sample i)
+    const int i = W.ilo + lane;
     if constexpr (SP::DR) {
-        S.wtf = jok ? A.wt[A.far_off + sbase + j] : 0.0f;
-        S.tf = jok ? A.tsum[A.far_off + sbase + j] : 0.0f;
-        S.wtfm = (jok && g.paired) ? A.wt[A.far_off + sbasem + jm] : 0.0f;
-        S.tfm = (jok && g.paired) ? A.tsum[A.far_off + sbasem + jm] : 0.0f;
-        qrow = A.wq + (size_t)slice * A.wts_stride + (size_t)a * g.n_t * g.n_bins;
-        qrowm = A.wq + (size_t)slice * A.wts_stride + (size_t)am * g.n_t * g.n_bins;
-#pragma unroll
-        for (int k = 0; k < VROWS; ++k) {
-            S.q[k] = 0.0f;
-            S.qm[k] = 0.0f;
-        }
         // sample i of the angle is sample n_t - 1 - i of its mirror; rows off
         // the lattice hold zero weights, any alpha serves them
-        const int i = min(max(W.ilo + lane, 0), g.n_t - 1);
-        S.al = A.t.resp[i];
-        S.alm = A.t.resp[g.n_t - 1 - i];
+        const int ic = min(max(i, 0), g.n_t - 1);
+        S.al = A.t.resp[ic];
+        S.alm = A.t.resp[g.n_t - 1 - ic];
     }
-    if (jok) {
+    const char* wb = reinterpret_cast<const char*>(wbase);
+    const char* qb = reinterpret_cast<const char*>(qbase);
+    const unsigned iw = (unsigned)i * (unsigned)sizeof(typename SP::w_t), iq = (unsigned)i * 4u;
+    // entry (lo | len << 16, b): sample i of the ray at b + i
+#define PGET_STAGE_COLUMNS(PAIRED)                                                              \
+    _Pragma("unroll") for (int k = 0; k < VCOLS; ++k) {                                        \
+        const int jj = wave + 4 * k; /* < VFP <= 64: a lane of the table */                    \
+        const int ll = __builtin_amdgcn_readlane(cur.x, jj);                                   \
+        const int b = __builtin_amdgcn_readlane(cur.y, jj);                                    \
+        const int lo = ll & 0xffff, len = ll >> 16;                                            \
+        stage_column<SP, PAIRED>(S, k, wb, qb, i, lo, (unsigned)len, (unsigned)b,              \
+                                 (unsigned)(b + 2 * (lo + len) - 1), iw, iq);                  \
+    }
+    if (g.paired) {
+        PGET_STAGE_COLUMNS(true)
+    } else {
+        PGET_STAGE_COLUMNS(false)
 #pragma unroll
-        for (int k = 0; k < VROWS; ++k) {
-            const int ii = wave + 4 * k;
-            const int i = W.ilo + ii;
-            if (ii < W.wi && i >= 0 && i < g.n_t) {
-                S.w[k] = wrow[(size_t)i * g.n_bins + j];
-                if (g.paired) S.wm[k] = wrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm];
-                if constexpr (SP::DR) {
-                    S.q[k] = qrow[(size_t)i * g.n_bins + j];
-                    if (g.paired) S.qm[k] = qrowm[(size_t)(g.n_t - 1 - i) * g.n_bins + jm];
-                }
-            }
+        for (int k = 0; k < VCOLS; ++k) {
+            S.wm[k] = typename SP::w_t{};
+            if constexpr (SP::DR) S.qm[k] = 0.0f;
         }
     }
+#undef PGET_STAGE_COLUMNS
+    if (has_next) S.ct = col_table(g, gcol, an, Wnx);
 }
 
 // Coefficients of f and mu that a staged point spreads: step*E*wt and
 // kq*(T - R')*wt, plus those of the mirror angle's sample at the same point
 // when the geometry is paired.  With a depth response the f coefficient sees
 // the cotangent blended between the near and far planes by the sample's
-// alpha, and the mu coefficient adds the far plane's term.
+// alpha, and the mu coefficient adds the far plane's term.  cv (and cvf):
+// the point's column values.
 template <typename SP>
-__device__ __forceinline__ float2 stage_coef(const Stage<SP>& S, int k, float kq)
+__device__ __forceinline__ float2 stage_coef(const Stage<SP>& S, int k, float kq, float4 cv, float4 cvf)
 {
     const float2 w = SP::w(S.w[k]), wm = SP::w(S.wm[k]);
+    const float wt = cv.x, t = cv.y, wtm = cv.z, tm = cv.w;
     if constexpr (SP::DR) {
-        const int row = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) + 4 * k;
-        const float al = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(S.al), row));
-        const float alm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(S.alm), row));
-        const float ct = fmaf(al, S.wtf - S.wt, S.wt);
-        const float ctm = fmaf(alm, S.wtfm - S.wtm, S.wtm);
+        const float wtf = cvf.x, tf = cvf.y, wtfm = cvf.z, tfm = cvf.w;
+        const float ct = fmaf(S.al, wtf - wt, wt);
+        const float ctm = fmaf(S.alm, wtfm - wtm, wtm);
         const float cf = fmaf(wm.x, ctm, w.x * ct);
-        float sm = S.wt * (S.t - w.y);
-        sm = fmaf(S.wtf, S.tf - S.q[k], sm);
-        sm = fmaf(S.wtm, S.tm - wm.y, sm);
-        sm = fmaf(S.wtfm, S.tfm - S.qm[k], sm);
+        float sm = wt * (t - w.y);
+        sm = fmaf(wtf, tf - S.q[k], sm);
+        sm = fmaf(wtm, tm - wm.y, sm);
+        sm = fmaf(wtfm, tfm - S.qm[k], sm);
         return make_float2(cf, kq * sm);
     } else {
-        const float kw = kq * S.wt, kwm = kq * S.wtm;
-        const float cf = fmaf(wm.x, S.wtm, w.x * S.wt);
-        const float cm = fmaf(kwm, S.tm - wm.y, kw * (S.t - w.y));
+        const float kw = kq * wt, kwm = kq * wtm;
+        const float cf = fmaf(wm.x, wtm, w.x * wt);
+        const float cm = fmaf(kwm, tm - wm.y, kw * (t - w.y));
         return make_float2(cf, cm);
+    }
+}
+
+// Column values of a stage into the LDS column table (by the first wave).
+template <typename SP>
+__device__ __forceinline__ void stage_columns(float4* colv, float4* colvf, const Stage<SP>& S)
+{
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64 && lane < VFP) {
+        colv[lane] = S.cv;
+        if constexpr (SP::DR) colvf[lane] = S.cvf;
     }
 }
 
 // Staged value of every lattice point of the window (stage_coef).
 template <typename SP>
-__device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, float kq)
+__device__ __forceinline__ void stage_store(float2* lat, const Stage<SP>& S, float kq, const float4* colv,
+                                            const float4* colvf)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (lane >= VFP) return;
 #pragma unroll
-    for (int k = 0; k < VROWS; ++k) {
-        const int ii = wave + 4 * k;
-        if (ii < VFP) lat[ii * LP + lane] = stage_coef(S, k, kq);
+    for (int k = 0; k < VCOLS; ++k) {
+        const int jj = wave + 4 * k;
+        if (jj < VFP)
+            lat[lane * LP + jj] = stage_coef(S, k, kq, colv[jj], SP::DR ? colvf[jj] : make_float4(0, 0, 0, 0));
     }
 }
 
 // Adds the staged coefficients of the rotated pair (a + n_angles/4 and its
 // mirror, loaded over rot_window(W)) to the points of W they coincide with:
-// rotated column lane is W's row W.wi - 1 - lane, rotated row ii is W's column
-// ii.  Every point has one owner thread.
+// point (row ii, column jj) of the rotated window is W's point (row
+// W.wi - 1 - jj, column ii).  Every point has one owner thread.
 template <typename SP>
-__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, float kq, const Window& W)
+__device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, float kq, const Window& W,
+                                              const float4* colv, const float4* colvf)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (lane >= W.wi) return;
-    float2* row = lat + (W.wi - 1 - lane) * LP;
+    if (lane >= W.wj) return;   // rows of the rotated window
 #pragma unroll
-    for (int k = 0; k < VROWS; ++k) {
-        const int ii = wave + 4 * k;
-        if (ii < W.wj) {
-            const float2 c = stage_coef(S, k, kq);
-            float2 v = row[ii];
+    for (int k = 0; k < VCOLS; ++k) {
+        const int jj = wave + 4 * k;
+        if (jj < W.wi) {
+            const float2 c = stage_coef(S, k, kq, colv[jj], SP::DR ? colvf[jj] : make_float4(0, 0, 0, 0));
+            float2* p = lat + (W.wi - 1 - jj) * LP + lane;
+            float2 v = *p;
             v.x += c.x;
             v.y += c.y;
-            row[ii] = v;
+            *p = v;
         }
     }
 }
@@ -918,9 +1008,13 @@ __device__ __forceinline__ float tent(float d)
 
 template <typename SP, bool QUAD>
 __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_eu(SP::VJP_WAVES))) k_vjp_lin(VjpArgs A,
-                                                                      const float4* __restrict__ trig)
+                                                                      const float4* __restrict__ trig,
+                                                                      const int2* __restrict__ gcol)
 {
     __shared__ float2 lat[VFP * LP];
+    // column values of the staged windows (the angle's, the rotated pair's)
+    __shared__ float4 colv[2][VFP];
+    __shared__ float4 colvf[SP::DR ? 2 : 1][SP::DR ? VFP : 1];
     const Geo& g = A.g;
     // Workgroups go to the XCDs round-robin by linear id; give each XCD a
     // contiguous run of (slice, group, tile) items so that neighbouring tiles
@@ -955,6 +1049,7 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
     const float SQ2 = 1.41421356f;
     const float inv_ds = 1.0f / g.bin_size, inv_dt = 1.0f / g.step;
     const typename SP::w_t* wbase = static_cast<const typename SP::w_t*>(A.wts) + (size_t)slice * A.wts_stride;
+    const float* qbase = SP::DR ? A.wq + (size_t)slice * A.wts_stride : nullptr;
 
     // End of fine group fg: its sum (this thread's 4 pixels, both maps) goes
     // either to its own partial image or, when the block runs whole super
@@ -1013,25 +1108,37 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
         }
     };
 
-    // `trig` is the plan's angle table (A.t.trig) as a restrict argument: the
-    // compiler may then keep its loads scalar despite the partial-image
-    // stores inside the loop (a vector load here would wait for the next
-    // angle's weight loads in flight).
+    // `trig`, `clip` and `roff` are the plan's tables (A.t.*) as restrict
+    // arguments: the compiler may then keep their loads scalar despite the
+    // partial-image stores inside the loop (a vector load here would wait
+    // for the next angle's weight loads in flight).
+    // Wn: the window of the next angle to gather, Wnn: of the one after
+    // (whose column table is read one angle ahead).
     Stage<SP> S, R;
-    Window Wn = {0, 0, 0, 0};
+    Window Wn = {0, 0, 0, 0}, Wnn = Wn;
     if (a_begin < a_end) {
         Wn = tile_window(g, trig[a_begin], tr0, tc0);
-        stage_load<SP>(S, A, wbase, slice, a_begin, Wn);
-        if (QUAD) stage_load<SP>(R, A, wbase, slice, a_begin + qa, rot_window(g, Wn));
+        const bool nx = a_begin + 1 < a_end;
+        Wnn = nx ? tile_window(g, trig[a_begin + 1], tr0, tc0) : Wn;
+        S.ct = col_table(g, gcol, a_begin, Wn);
+        if (QUAD) R.ct = col_table(g, gcol, a_begin + qa, rot_window(g, Wn));
+        stage_load<SP>(S, A, wbase, qbase, slice, a_begin, Wn, nx, a_begin + 1, Wnn, gcol);
+        if (QUAD)
+            stage_load<SP>(R, A, wbase, qbase, slice, a_begin + qa, rot_window(g, Wn), nx, a_begin + 1 + qa,
+                           rot_window(g, Wnn), gcol);
     }
     int fg = f_begin, left = A.spf;   // fine group being summed, its slots still to come
     for (int a = a_begin; a < a_end; ++a) {
         const Window W = Wn;
-        __syncthreads();   // the previous angle's gather is done with lat
-        stage_store(lat, S, g.kq);
+        // no wave reads the column tables after the previous iteration's
+        // staging barriers
+        stage_columns(colv[0], colvf[0], S);
+        if (QUAD) stage_columns(colv[1], colvf[SP::DR ? 1 : 0], R);
+        __syncthreads();   // the previous angle's gather is done with lat; columns visible
+        stage_store(lat, S, g.kq, colv[0], colvf[0]);
         if (QUAD) {
             __syncthreads();
-            stage_add_rot(lat, R, g.kq, W);
+            stage_add_rot(lat, R, g.kq, W, colv[1], colvf[SP::DR ? 1 : 0]);
         }
         __syncthreads();
         // the previous fine group is complete: write it out here, where the
@@ -1041,9 +1148,13 @@ __global__ void __launch_bounds__(VJP_THREADS) __attribute__((amdgpu_waves_per_e
             left = A.spf;
         }
         if (a + 1 < a_end) {   // next angle's loads fly during this gather
-            Wn = tile_window(g, trig[a + 1], tr0, tc0);
-            stage_load<SP>(S, A, wbase, slice, a + 1, Wn);
-            if (QUAD) stage_load<SP>(R, A, wbase, slice, a + 1 + qa, rot_window(g, Wn));
+            Wn = Wnn;
+            const bool nx = a + 2 < a_end;
+            if (nx) Wnn = tile_window(g, trig[a + 2], tr0, tc0);
+            stage_load<SP>(S, A, wbase, qbase, slice, a + 1, Wn, nx, a + 2, Wnn, gcol);
+            if (QUAD)
+                stage_load<SP>(R, A, wbase, qbase, slice, a + 1 + qa, rot_window(g, Wn), nx, a + 2 + qa,
+                               rot_window(g, Wnn), gcol);
         }
         const float4 tr = trig[a];
         const float cs = tr.z, sn = tr.w;
@@ -1888,13 +1999,13 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
     INST_MARCH(false, MARCH_TRIAL, S)                                                         \
     INST_JVP(true, JVP_PLAIN, S) INST_JVP(true, JVP_NORMAL, S) INST_JVP(true, JVP_SQNORM, S)  \
     INST_JVP(false, JVP_PLAIN, S) INST_JVP(false, JVP_NORMAL, S) INST_JVP(false, JVP_SQNORM, S) \
-    template __global__ void k_vjp_lin<S, false>(VjpArgs, const float4*);                                    \
+    template __global__ void k_vjp_lin<S, false>(VjpArgs, const float4*, const int2*);                                    \
     template __global__ void k_pack<S>(Geo, PairSrc, const double*, void*, long long, const LMState*);
 INST_ALL(F32S)
 INST_ALL(BF16S)
 INST_ALL(F32DR)
 // the quarter-turn fold; not with a depth response (one staged angle only)
-template __global__ void k_vjp_lin<F32S, true>(VjpArgs, const float4*);
-template __global__ void k_vjp_lin<BF16S, true>(VjpArgs, const float4*);
+template __global__ void k_vjp_lin<F32S, true>(VjpArgs, const float4*, const int2*);
+template __global__ void k_vjp_lin<BF16S, true>(VjpArgs, const float4*, const int2*);
 
 }  // namespace pget
