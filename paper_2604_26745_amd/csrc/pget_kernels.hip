@@ -281,13 +281,36 @@ __device__ __forceinline__ float psf_at(const float* x, const float* taps, int K
 // ------------------------------------------------------------------ march
 
 
+// Logical work item of workgroup `lin` (linear id) among `total`: the
+// hardware places workgroup lin on XCD lin % N_XCD, so XCD x runs items
+// [x * per, (x + 1) * per) in order.  The tail beyond a multiple of N_XCD
+// keeps its own ids.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_item(int lin, int total)
+{
+    const int per = total / N_XCD;
+    if (lin >= per * N_XCD) return lin;
+    return (lin % N_XCD) * per + lin / N_XCD;
+}
+
+// The (slice, block of angles) pair of a product or march workgroup: each
+// XCD runs a contiguous run of them, so that the blocks of one slice share
+// the L2 that holds its staged maps.
+__device__ __forceinline__ int2 slice_block()
+{
+    const int item = xcd_item(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int slice = item / gridDim.x;
+    return make_int2(slice, item - slice * gridDim.x);
+}
+
 template <bool LDS_IMG, int MODE, typename S>
 __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 {
     extern __shared__ float4 smem_raw[];
     __shared__ float taps[MAX_TAPS];
     const Geo& g = A.g;
-    const int slice = blockIdx.y;
+    const int2 sb = slice_block();
+    const int slice = sb.x;
     if (A.st) {
         if (A.st[slice].done) return;
         if (MODE == MARCH_LIN && !A.st[slice].dirty) return;
@@ -314,7 +337,7 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
     const int q = lane & (SPL - 1), jj = lane >> 2;
     const float hs = 0.5f;
     for (int ab = 0; ab < A.angles_per_block; ++ab) {
-        const int a = blockIdx.x * A.angles_per_block + ab;
+        const int a = sb.y * A.angles_per_block + ab;
         if (a >= g.n_angles) break;
         const float4 tr = A.t.trig[a];
         for (int grp = wave; grp < g.n_groups; grp += nwaves) {
@@ -473,12 +496,13 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     __shared__ double sh[16];
     __shared__ float taps[MAX_TAPS];
     const Geo& g = A.g;
-    const int slice = blockIdx.y;
+    const int2 sb = slice_block();
+    const int slice = sb.x;
     if (A.st && A.st[slice].done) return;
     if (A.only_k0 && A.st && A.st[slice].k != 0) return;   // initial-damping probe of a slot pool
     const int per_slot = g.paired ? 2 : 1;
     const int n_slots = g.paired ? g.n_angles / 2 : g.n_angles;
-    const int slot0 = blockIdx.x * A.angles_per_block;
+    const int slot0 = sb.y * A.angles_per_block;
     const int nslot = min(A.angles_per_block, n_slots - slot0);
     const int nrows = nslot * per_slot;   // sinogram rows produced by this block
     using px_t = typename S::px_t;
@@ -985,18 +1009,6 @@ __device__ __forceinline__ void stage_add_rot(float2* lat, const Stage<SP>& S, f
             *p = v;
         }
     }
-}
-
-// Logical work item of workgroup `lin` (linear id) among `total`: the
-// hardware places workgroup lin on XCD lin % N_XCD, so XCD x runs items
-// [x * per, (x + 1) * per) in order.  The tail beyond a multiple of N_XCD
-// keeps its own ids.
-constexpr int N_XCD = 8;
-__device__ __forceinline__ int xcd_item(int lin, int total)
-{
-    const int per = total / N_XCD;
-    if (lin >= per * N_XCD) return lin;
-    return (lin % N_XCD) * per + lin / N_XCD;
 }
 
 // tent(d) = max(0, 1 - |d|); med3 against [0, 1] lets the compiler fold it
