@@ -362,6 +362,29 @@ def run_mixed(args, torch, np, inputs, pget):
     plain = n / el1
     reps = [r.to_report() for r in rbs]
     assert all(r.status == 0 for r in reps)
+    # each size group alone, as a same-size batch: what the concurrent groups
+    # of the mixed call would take one after another
+    alone = {}
+    for nn, plan in plans.items():
+        idx = [s for s in range(n) if cfgs[s].n == nn]
+        sub = lambda v: [v[s] for s in idx]
+        plan.lm_solve_batched(sub(ys), sub(f0s), sub(m0s), sub(prm))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.lm_solve_batched(sub(ys), sub(f0s), sub(m0s), sub(prm))
+        torch.cuda.synchronize()
+        alone[nn] = (time.perf_counter() - t2) / args.steps
+    seq_ms = 1e3 * sum(alone.values())
+    # work: in-support lattice samples x outer iterations x CG steps (each CG
+    # step streams every sample through one product and one adjoint)
+    work = sum(plans[c.n].support_samples * c.max_outer * c.n_cg for c in cfgs)
+    groups = {str(nn): {"slices": counts[nn], "alone_ms": round(1e3 * t, 2),
+                        "gsamples_per_s": round(counts[nn] * plans[nn].support_samples * args.outer * args.cg
+                                                / t / 1e9, 2)}
+              for nn, t in sorted(alone.items())}
+    print("bench: mixed step %.1f ms; groups alone %s ms, sequential sum %.1f ms" % (
+        1e3 * el / args.steps, {k: v["alone_ms"] for k, v in groups.items()}, seq_ms), file=sys.stderr, flush=True)
     out = {
         "metric": "LM reconstructions/s, mixed grid sizes {64..256}^2 x 360 angles (FP32)",
         "value": round(value, 4), "unit": "reconstructions/s", "n_gpus": 1, "steps": args.steps,
@@ -374,6 +397,10 @@ def run_mixed(args, torch, np, inputs, pget):
                    "tuned_shapes": {str(k): p.tuned_shape(counts[k]) for k, p in plans.items()}},
         "plain_per_slice": {"value": round(plain, 4), "unit": "reconstructions/s",
                             "speedup": round(value / plain, 3)},
+        "size_groups": {"alone": groups, "sequential_sum_ms": round(seq_ms, 2),
+                        "concurrent_over_sequential": round(seq_ms / (1e3 * el / args.steps), 3),
+                        "work_gsamples_per_s": round(work * args.steps / el / 1e9, 2),
+                        "work_unit": "in-support samples x outer iterations x CG steps"},
     }
     print(json.dumps(out), flush=True)
 

@@ -1506,21 +1506,39 @@ pget_status group_prepare(Group& G, const pget_plan* P, int B, void* ws, hipStre
 }
 
 // The whole device-resident solve of one group (no hook).
-void enqueue_group(Group& G, hipStream_t s)
+void group_begin(Group& G, hipStream_t s)
+{
+    const int B = G.S.B;
+    hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, s, G.S.V.st, G.S.V.prm, B);
+}
+
+void group_iteration(Group& G, hipStream_t s, int k)
 {
     Solve SS = G.S;
     SS.stream = s;
-    const int B = SS.B;
-    hipLaunchKernelGGL(k_lm_init, dim3((B + 63) / 64), dim3(64), 0, s, SS.V.st, SS.V.prm, B);
-    for (int k = 0; k < G.max_outer; ++k) {
-        enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false, G.trace, false, G.sgp);
-        enqueue_commit(SS);
-    }
-    hipLaunchKernelGGL(k_final_reg, dim3(SS.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, s, SS.V);
-    hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, s, SS.V);
+    enqueue_iteration(SS, k, G.n_cg, G.need_beta0, false, G.trace, false, G.sgp);
+    enqueue_commit(SS);
+}
+
+void group_end(Group& G, hipStream_t s)
+{
+    const int B = G.S.B;
+    hipLaunchKernelGGL(k_final_reg, dim3(G.S.sh.n_ew_blocks, B), dim3(EW_THREADS), 0, s, G.S.V);
+    hipLaunchKernelGGL(k_finish, dim3(B), dim3(256), 0, s, G.S.V);
+}
+
+void enqueue_group(Group& G, hipStream_t s)
+{
+    group_begin(G, s);
+    for (int k = 0; k < G.max_outer; ++k) group_iteration(G, s, k);
+    group_end(G, s);
 }
 
 // All groups forked from `origin` onto their own streams and joined back.
+// The groups' launches are enqueued interleaved, one outer iteration of
+// every group in turn: a captured graph keeps that order, so every group
+// starts at once instead of each waiting until the launches of the groups
+// before it have been submitted.
 pget_status enqueue_forked(std::vector<Group>& groups, hipStream_t origin, size_t stream_base)
 {
     if (groups.size() == 1) {
@@ -1530,14 +1548,23 @@ pget_status enqueue_forked(std::vector<Group>& groups, hipStream_t origin, size_
     hipEvent_t fork = g_pool.event(0);
     if (!fork) return PGET_ERR_HIP;
     HIP_TRY(hipEventRecord(fork, origin));
+    std::vector<hipStream_t> st(groups.size());
+    int kmax = 0;
     for (size_t k = 0; k < groups.size(); ++k) {
-        hipStream_t sk = g_pool.get(stream_base + k);
-        if (!sk) return PGET_ERR_HIP;
-        HIP_TRY(hipStreamWaitEvent(sk, fork, 0));
-        enqueue_group(groups[k], sk);
+        st[k] = g_pool.get(stream_base + k);
+        if (!st[k]) return PGET_ERR_HIP;
+        HIP_TRY(hipStreamWaitEvent(st[k], fork, 0));
+        group_begin(groups[k], st[k]);
+        kmax = std::max(kmax, groups[k].max_outer);
+    }
+    for (int it = 0; it < kmax; ++it)
+        for (size_t k = 0; k < groups.size(); ++k)
+            if (it < groups[k].max_outer) group_iteration(groups[k], st[k], it);
+    for (size_t k = 0; k < groups.size(); ++k) {
+        group_end(groups[k], st[k]);
         hipEvent_t done = g_pool.event(1 + k);
         if (!done) return PGET_ERR_HIP;
-        HIP_TRY(hipEventRecord(done, sk));
+        HIP_TRY(hipEventRecord(done, st[k]));
         HIP_TRY(hipStreamWaitEvent(origin, done, 0));
     }
     return PGET_OK;
