@@ -22,10 +22,12 @@ Measured alongside:
   same workload.
 
 * the serving half of the metric: a 10 s Poisson trace (30 requests/s)
-  over the mixed grid sizes {64..256}^2 through the iteration-level
-  continuous-batching server, with p50/p99 latency, the plain per-slice
-  solver on the same trace, and a bitwise check of served results against
-  the same slices solved alone.
+  over the mixed grid sizes {64..256}^2 through the continuous-batching
+  server (whole batched solves on concurrent streams), with p50/p99
+  latency, the plain per-slice solver on the same trace, and a bitwise
+  check of served results against the same slices solved alone; the same
+  trace through the iteration-level server (per-size slot pools admitting
+  at every outer iteration) beside it.
 
 Other workloads (--workload): mixed grid sizes, serving alone (rate and
 server selectable), the scanner geometry, and the safeguarded Deep
@@ -676,9 +678,17 @@ def serving_measure(torch, pget, rate, duration, pool_n, outer, cg, solver, serv
           flush=True)
     st = serve.run_trace(srv, reqs)
     print("bench: served %s" % st, file=sys.stderr, flush=True)
+    step_stats = None
     if server == "iter":
         for gp in pools.values():
             outputs.update(gp.outputs)
+        # per size: outer-iteration steps taken, and their mean device and
+        # host (launch to retirement) times
+        step_stats = {str(n): {"steps": gp.step_stats["steps"],
+                               "gpu_ms": round(gp.step_stats["gpu_ms"] / max(gp.step_stats["steps"], 1), 2),
+                               "wall_ms": round(gp.step_stats["wall_ms"] / max(gp.step_stats["steps"], 1), 2)}
+                      for n, gp in sorted(pools.items())}
+        print("bench: pool steps %s" % step_stats, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     picks = np.random.default_rng([0, 7]).choice(len(reqs), size=min(check, len(reqs)), replace=False)
     worst, bitwise = [0.0, 0.0], 0
@@ -709,6 +719,7 @@ def serving_measure(torch, pget, rate, duration, pool_n, outer, cg, solver, serv
         "workspace_gb": round(st["peak_in_flight_gb"], 3),
         "plain_per_slice": {"recon_per_s": round(pl["recon_per_s"], 3), "p50_ms": round(pl["p50_ms"], 1),
                             "p99_ms": round(pl["p99_ms"], 1)},
+        **({"pool_steps": step_stats} if step_stats else {}),
         "check_vs_alone": {"requests": int(len(picks)), "bitwise_equal": bitwise,
                            "max_rel_l2_f": float("%.3g" % worst[0]), "max_rel_l2_mu": float("%.3g" % worst[1])},
         "config": {"solver": dict({"name": solver}, **SOLVER_OPTIONS[solver]), "pool": pool_n, "tol": 1e-4,
@@ -855,13 +866,17 @@ def main():
         del plan_b
 
     # the serving half of the metric: a Poisson trace over the mixed sizes
-    # through the iteration-level continuous-batching server, beside the
-    # plain per-slice solver on the same trace
     serving = None
     if args.serve_rate > 0 and args.grid == 128 and args.storage == "fp32":
+        # both servers on the same trace: whole batched solves on concurrent
+        # streams (the headline, with the plain per-slice solver beside it)
+        # and per-size slot pools admitting at every outer iteration
         serving = serving_measure(torch, pget, args.serve_rate, args.serve_duration, args.pool, args.outer,
-                                  args.cg, args.solver, server="iter", capacity=args.capacity,
+                                  args.cg, args.solver, server="batch", streams=args.streams,
                                   hbm_budget_gb=args.hbm_budget_gb)
+        serving["iteration_level"] = serving_measure(
+            torch, pget, args.serve_rate, args.serve_duration, args.pool, args.outer, args.cg, args.solver,
+            server="iter", capacity=args.capacity, hbm_budget_gb=args.hbm_budget_gb, plain=False, check=4)
 
     cpu = None
     if not args.no_cpu_baseline:

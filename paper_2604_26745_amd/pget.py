@@ -641,13 +641,14 @@ class LMPool:
         _check(self.lib.pget_lm_pool_load(self.handle, slot, _ptr(y), _ptr(f0), _ptr(mu0), ctypes.byref(prm),
                                           self.stream.cuda_stream), "pget_lm_pool_load")
 
-    def step(self):
+    def step(self, timing: bool = False):
         """Enqueue one outer iteration; returns an event recorded after it
-        (the `finished` flags are valid once it has completed)."""
+        (the `finished` flags are valid once it has completed; with timing,
+        the event can measure elapsed time)."""
         torch = _torch()
         _check(self.lib.pget_lm_pool_step(self.handle, ctypes.c_void_p(self.finished.data_ptr()),
                                           self.stream.cuda_stream), "pget_lm_pool_step")
-        ev = torch.cuda.Event()
+        ev = torch.cuda.Event(enable_timing=timing)
         ev.record(self.stream)
         return ev
 

@@ -298,16 +298,32 @@ class GpuPool:
         self.nbytes = int(self.p.ws.numel())
         self.outputs: Dict[int, tuple] = {}   # rid -> (f, mu) of served requests (kept if keep_outputs)
         self.keep_outputs = False
+        # per step: device time (events around it) and host time from launch
+        # to the poll that saw it complete
+        self.step_stats = {"steps": 0, "gpu_ms": 0.0, "wall_ms": 0.0}
+        self._t = None
 
     def load(self, slot: int, req: Request):
         sl = self.pool[req.slot]
         self.p.load(slot, sl.y, sl.f0, sl.mu0, self.params)
 
     def step(self):
-        return self.p.step()
+        start = self.torch.cuda.Event(enable_timing=True)
+        start.record(self.stream)
+        end = self.p.step(timing=True)
+        self._t = (start, end, time.perf_counter())
+        return end
 
     def done(self, handle) -> bool:
-        return handle.query()
+        if not handle.query():
+            return False
+        if self._t is not None and self._t[1] is handle:
+            start, end, t0 = self._t
+            self.step_stats["steps"] += 1
+            self.step_stats["gpu_ms"] += start.elapsed_time(end)
+            self.step_stats["wall_ms"] += 1e3 * (time.perf_counter() - t0)
+            self._t = None
+        return True
 
     def finished(self) -> List[int]:
         return self.p.finished.tolist()
