@@ -75,7 +75,7 @@ typedef enum { PGET_FP32 = 0, PGET_BF16 = 1 } pget_storage;
 typedef struct {
     int32_t n;          /* N, 2 <= N <= 512                                  */
     int32_t n_angles;   /* 1 .. 1024                                         */
-    int32_t n_bins;     /* >= 1                                              */
+    int32_t n_bins;     /* 1 .. 8192                                         */
     int32_t psf_radius; /* taps per side; < 0 -> ceil(3*psf_sigma); <= 32   */
     double angle0;      /* radians                                           */
     double arc;         /* radians, e.g. 2*pi for a full turn                */
@@ -93,8 +93,16 @@ enum { PGET_OP_FORWARD = 0, PGET_OP_JVP = 1, PGET_OP_VJP = 2, PGET_OP_LM = 3 };
 /*
  * Build the geometry tables of one slice shape on the current HIP device.
  * *out receives an opaque plan to release with pget_plan_destroy.
- * Errors: INVALID_ARG (null pointer, size out of range), UNSUPPORTED,
- * HIP (device allocation of the tables failed).
+ * The plan holds, per ray, the range of its samples inside the support and
+ * their offset in the compacted per-sample arrays of a workspace (a ray's
+ * in-support samples contiguous; with a full turn and an even angle count
+ * the mirror ray right after it).
+ * Errors: INVALID_ARG (null pointer, size out of range), UNSUPPORTED
+ * (storage other than FP32 / BF16; more than 2^29 in-support samples per
+ * slice, since the adjoint forms 32-bit byte offsets into a slice's weights;
+ * detector rows that overflow the kernels' LDS rows; a device index beyond
+ * the library's per-device tables), HIP (device allocation of the tables
+ * failed).
  */
 pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pget_plan** out);
 void pget_plan_destroy(pget_plan* plan);
