@@ -31,6 +31,8 @@ struct pget_plan {
     size_t op_lds_bytes; // dynamic LDS of k_march
     int op_threads;      // threads per block of k_march
     size_t img_lds;      // LDS bytes of the staged map pair (0 if not staged)
+    int jvp_bands;       // k_jvp_lin stages the pair in this many bands of rows (1: whole)
+    int jvp_band_h;      // top bordered rows per band
     int max_japb;        // most angle slots per k_jvp_lin block that fit in LDS
     int max_japb_dr;     // the same with a depth response (three rows per slot)
     int vjp_resident_dr; // k_vjp_lin blocks per compute unit with a depth response
@@ -378,7 +380,7 @@ void march(const pget_plan* P, const MarchArgs& A, int blocks, int batch, hipStr
     if (P->lds_img) launch_march<true, M>(P, A, blocks, batch, s);
     else launch_march<false, M>(P, A, blocks, batch, s);
 }
-template <bool LDS, int M>
+template <int LDS, int M>
 void launch_jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
     Timed t(PGET_KC_JVP, s);
@@ -395,8 +397,9 @@ void launch_jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batc
 template <int M>
 void jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
-    if (P->jvp_lds) launch_jvp<true, M>(P, A, sh, batch, s);
-    else launch_jvp<false, M>(P, A, sh, batch, s);
+    if (!P->jvp_lds) launch_jvp<IMG_HBM, M>(P, A, sh, batch, s);
+    else if (P->jvp_bands > 1) launch_jvp<IMG_BANDS, M>(P, A, sh, batch, s);
+    else launch_jvp<IMG_LDS, M>(P, A, sh, batch, s);
 }
 
 // The grid is (tiles * V.groups, batch): the kernel decodes (slice, group,
@@ -654,6 +657,27 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         const size_t per_slot = 2 * (size_t)(g.paired ? 2 : 1) * nb * sizeof(float);
         P->jvp_lds = jimg_bytes + per_slot <= lds_budget;
         P->img_lds = P->jvp_lds ? jimg_bytes : 0;
+        P->jvp_bands = 1;
+        P->jvp_band_h = g.n + 1;
+        if (!P->jvp_lds) {
+            // the pair in bands of bordered rows, leaving room for the rows
+            // of four angle slots (three rows per slot with a depth
+            // response, and its alpha table)
+            const size_t row_px = (size_t)g.pitch * P->px_bytes;
+            const size_t keep = 4 * (per_slot / 2 * 3) + (size_t)nt * sizeof(float);
+            if (lds_budget > keep + 9 * row_px) {
+                const int h = (int)((lds_budget - keep) / row_px) - 1;   // staged rows h + 1
+                const int bands = (g.n + 1 + h - 1) / h;
+                // every band runs the block's items again: past 8 bands the
+                // HBM copy read through the caches is kept
+                if (bands <= 8) {
+                    P->jvp_bands = bands;
+                    P->jvp_band_h = (g.n + 1 + bands - 1) / bands;
+                    P->jvp_lds = true;
+                    P->img_lds = (size_t)(P->jvp_band_h + 1) * row_px;
+                }
+            }
+        }
         P->max_japb = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / per_slot);
         const size_t alpha_bytes = (size_t)nt * sizeof(float);
         P->max_japb_dr = lds_budget >= P->img_lds + alpha_bytes
@@ -928,6 +952,8 @@ pget_status pget_jvp(const pget_plan* P, const float* f, const float* mu, const 
     JvpArgs A = {};
     A.g = P->g;
     A.t = P->t;
+    A.bands = P->jvp_bands;
+    A.band_h = P->jvp_band_h;
     A.src = planar_src(vf, vmu, 0);
     A.wts = at(ws, L.wts);
     A.tsum = reinterpret_cast<float*>(at(ws, L.tsum));
@@ -1118,6 +1144,8 @@ void setup(Solve& S)
     J.t = P->t;
     J.gimg = S.gimg;
     J.gimg_stride = (long long)g.pitch * g.pitch;
+    J.bands = P->jvp_bands;
+    J.band_h = P->jvp_band_h;
     J.wts = wts;
     J.tsum = tsum;
     J.wq = wq;

@@ -207,6 +207,8 @@ struct JvpArgs {
     const LMState* st;
     int only_k0;            // initial-damping probe of a slot pool: only slices at iteration 0
     int angles_per_block;   // angle slots per block (a slot is an angle pair when paired)
+    int bands;              // staged map in row bands (IMG_BANDS): their count
+    int band_h;             // ... and the top bordered rows per band
 };
 
 struct VjpArgs {
@@ -265,7 +267,11 @@ struct F32S;
 struct BF16S;
 struct F32DR;   // FP32 with a depth-dependent collimator response
 template <bool LDS_IMG, int MODE, typename S> __global__ void k_march(MarchArgs A);
-template <bool LDS_IMG, int MODE, typename S> __global__ void k_jvp_lin(JvpArgs A);
+// Where k_jvp_lin reads the direction: a bordered copy in HBM, the whole
+// bordered pair staged in LDS, or the pair staged in LDS one band of rows at
+// a time.
+enum { IMG_HBM = 0, IMG_LDS = 1, IMG_BANDS = 2 };
+template <int IMG, int MODE, typename S> __global__ void k_jvp_lin(JvpArgs A);
 template <typename S>
 __global__ void k_pack(Geo g, PairSrc s, const double* part, void* out, long long out_stride,
                        const LMState* st);

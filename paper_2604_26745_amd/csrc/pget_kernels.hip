@@ -246,6 +246,34 @@ __device__ void stage_image(typename S::px_t* dst, const PairSrc& s, int slice, 
     }
 }
 
+// Bordered rows [r0, r0 + rows) of the map pair (rows past the bordered
+// pair are left unwritten; nothing reads them).
+template <typename S>
+__device__ void stage_rows(typename S::px_t* dst, const PairSrc& s, int slice, int n, int pitch, float beta,
+                           int r0, int rows)
+{
+    const int total = min(rows, pitch - r0) * pitch;
+    const float2 w = src_scale(s, slice);
+    constexpr int U = 4;
+    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+        float2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            const int br = idx / pitch;
+            const int rr = r0 + br - 1, cc = idx - br * pitch - 1;
+            v[u] = make_float2(0.0f, 0.0f);
+            if (idx < total && rr >= 0 && rr < n && cc >= 0 && cc < n)
+                v[u] = src_value(s, slice, rr * n + cc, beta, w);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) dst[idx] = S::to_px(v[u]);
+        }
+    }
+}
+
 // Global bordered copy for maps too large for LDS.
 template <typename SP>
 __global__ void __launch_bounds__(256) k_pack(Geo g, PairSrc s, const double* part, void* out_v,
@@ -489,9 +517,17 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 // a' = a + n_angles/2: ray j of a and ray n_bins-1-j of a' visit the same
 // points (sample i of one is sample n_t-1-i of the other), so one bilinear
 // sample of the direction serves both rays.
-template <bool LDS_IMG, int MODE, typename S>
+//
+// IMG_BANDS (maps whose bordered pair does not fit in LDS): the block stages
+// bands of bordered rows in turn and runs its items once per band, each
+// sample in the band that holds its bilinear footprint's top row; a ray's
+// partial sums are added to its row value in band order, so the result
+// depends on the plan only.
+template <int IMG, int MODE, typename S>
 __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
 {
+    constexpr bool LDS_IMG = IMG != IMG_HBM;
+    constexpr bool BANDS = IMG == IMG_BANDS;
     extern __shared__ float4 smem_raw[];
     __shared__ double sh[16];
     __shared__ float taps[MAX_TAPS];
@@ -508,7 +544,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     using px_t = typename S::px_t;
     using w_t = typename S::w_t;
     px_t* simg = reinterpret_cast<px_t*>(smem_raw);
-    const int img_elems = LDS_IMG ? g.pitch * g.pitch : 0;
+    const int img_elems = LDS_IMG ? (BANDS ? (A.band_h + 1) * g.pitch : g.pitch * g.pitch) : 0;
     float* rowz = reinterpret_cast<float*>(simg + img_elems);   // [nrows][n_bins]
     float* rowy = rowz + A.angles_per_block * per_slot * g.n_bins;
     float* rowzf = rowy + A.angles_per_block * per_slot * g.n_bins;   // depth response: far part of z
@@ -520,12 +556,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     }
     if (S::DR)
         for (int i = threadIdx.x; i < g.n_t; i += blockDim.x) alpha[i] = A.t.resp[i];
-    if (LDS_IMG) {
-        const float beta = resolve_beta(A.src, A.part, slice, sh);
-        stage_image<S>(simg, A.src, slice, g.n, g.pitch, beta);
-    }
-    const px_t* img = LDS_IMG ? simg : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
-    __syncthreads();
+    const float beta = LDS_IMG ? resolve_beta(A.src, A.part, slice, sh) : 0.0f;
 
     // A wave covers JR consecutive rays with JSPL lanes per ray; the weights
     // of a ray's in-support samples are contiguous (compacted arrays), so one
@@ -542,11 +573,24 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     // Items are taken from a block-wide counter (dynamic balance), longest
     // first: ray groups ordered from the middle of the detector outward.
     __shared__ int next_item;
-    if (threadIdx.x == 0) next_item = nwaves;
-    __syncthreads();
     const int n_ig = (g.n_bins + JR - 1) / JR;
     const int n_items = nslot * n_ig;
     const int gc = n_ig / 2;
+    const int nbands = BANDS ? A.bands : 1;
+    for (int band = 0; band < nbands; ++band) {
+    // top bordered rows [B0, B1) of this band's samples
+    const int B0 = BANDS ? band * A.band_h : 0;
+    const int B1 = BANDS ? min(B0 + A.band_h, g.n + 1) : g.n + 1;
+    if (BANDS && band > 0) __syncthreads();   // every wave is done with the previous band's rows
+    if (LDS_IMG) {
+        if (BANDS) stage_rows<S>(simg, A.src, slice, g.n, g.pitch, beta, B0, A.band_h + 1);
+        else stage_image<S>(simg, A.src, slice, g.n, g.pitch, beta);
+    }
+    // bordered row r of the map pair at img[r * pitch]
+    const px_t* img = LDS_IMG ? simg - (BANDS ? (ptrdiff_t)B0 * g.pitch : 0)
+                              : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
+    if (threadIdx.x == 0) next_item = nwaves;
+    __syncthreads();
     for (int item = wave; item < n_items;) {
         const int rank = item / nslot, sl = item - rank * nslot;
         const int grp = (rank & 1) ? gc - (rank + 1) / 2 : gc + rank / 2;
@@ -576,11 +620,42 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             }
         }
         const int len = cl.y - cl.x + 1;   // <= 0 without support
-        // trips of the item: the longest of its rays (wave-uniform)
-        int tmax = len;
+        // The ray's samples this pass visits: all of its support, or with
+        // bands a superset of those whose top bilinear row lies in [B0, B1)
+        // (from the row's slope along the ray, two samples of margin; rays
+        // nearly along the rows keep them all), tested exactly per sample.
+        int c_lo = 0, c_hi = len;
+        if (BANDS && len > 0 && fabsf(tr.y) >= 0.01f) {
+            const float base = (float)cl.x - g.t_off;
+            const float ca = ((float)(B0 - 1) - rb.y) / tr.y - base;
+            const float cb = ((float)(B1 - 1) - rb.y) / tr.y - base;
+            const float lo_f = fminf(fmaxf(fminf(ca, cb), -4.0f), (float)len + 4.0f);
+            const float hi_f = fminf(fmaxf(fmaxf(ca, cb), -4.0f), (float)len + 4.0f);
+            c_lo = max(0, (int)floorf(lo_f) - 2);
+            c_hi = min(len, (int)ceilf(hi_f) + 2);
+        }
+        // trips of the item: from the first to the last sample any of its
+        // rays visits (wave-uniform; without bands from 0 to the longest ray)
+        int tlo = 0, tmax = len;
+        if constexpr (BANDS) {
+            const bool any = len > 0 && c_hi > c_lo;
+            tlo = any ? c_lo : 0x3fffffff;
+            tmax = any ? c_hi : 0;
+#pragma unroll
+            for (int o = JSPL; o < 64; o <<= 1) tlo = min(tlo, __shfl_xor(tlo, o, 64));
+            tlo = __builtin_amdgcn_readfirstlane(tlo);
+        }
 #pragma unroll
         for (int o = JSPL; o < 64; o <<= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
         tmax = __builtin_amdgcn_readfirstlane(tmax);
+        // sample c in this pass's band (the top row as the bilinear lookup
+        // computes it)
+        auto in_band = [&](int c) -> bool {
+            if (!BANDS) return true;
+            const float row = fmaf((float)(cl.x + c) - g.t_off, tr.y, rb.y);
+            const int rt = min(max((int)floorf(row), -1), g.n - 1) + 1;
+            return rt >= B0 && rt < B1;
+        };
         float accf = 0.0f, accq = 0.0f, accfm = 0.0f, accqm = 0.0f;
         // depth response: accf / accq collect the near parts, these the far
         float accff = 0.0f, accqf = 0.0f, accffm = 0.0f, accqfm = 0.0f;
@@ -602,7 +677,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             for (int u = 0; u < JU; ++u) {
                 if (u > 0 && c0 + u * JSPL >= tmax) break;
                 const int c = c0 + u * JSPL + q;
-                const bool ok = c < len;
+                const bool ok = c < len && in_band(c);
                 const int i = cl.x + c;
                 const long long cm = (long long)(g.n_t - 1 - i - clm.x);
                 w[u] = ok ? wslice[off + c] : w_t{};
@@ -618,11 +693,13 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             for (int u = 0; u < JU; ++u) {
                 if (u > 0 && c0 + u * JSPL >= tmax) break;
                 const int c = c0 + u * JSPL + q;
-                const bool ok = c < len;
+                const bool ok = c < len && in_band(c);
                 const int i = cl.x + c;
                 const float ti = (float)i - g.t_off;
                 const float col = fmaf(ti, tr.x, rb.x), row = fmaf(ti, tr.y, rb.y);
-                const float2 v = bilerp<S>(img, g.pitch, g.n, col, row);
+                // with bands, lanes whose sample is not in this band look up a
+                // row of the band (their value is discarded)
+                const float2 v = bilerp<S>(img, g.pitch, g.n, col, (BANDS && !ok) ? (float)B0 - 0.5f : row);
                 const float2 wv = S::w(w[u]);
                 if constexpr (S::DR) {
                     const float al = ok ? alpha[i] : 0.0f;
@@ -651,7 +728,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
                 }
             }
         };
-        int c0 = 0;
+        int c0 = tlo;
         if (c0 < tmax) load(c0, wa, wma, qa, qma);
         while (c0 < tmax) {
             const int c1 = c0 + STEP;
@@ -663,28 +740,31 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             compute(c1, wb, wmb, qb, qmb);
             c0 = c2;
         }
+        // a ray's value: this pass's sum, added in band order with bands
+        auto put = [&](float* dst, float v) { *dst = (BANDS && band > 0) ? *dst + v : v; };
         accf = ray_sum<JSPL>(accf);
         accq = ray_sum<JSPL>(accq);
-        if (ray_ok && q == 0) rowz[sl * g.n_bins + j] = fmaf(g.kq, accq, accf);
+        if (ray_ok && q == 0) put(&rowz[sl * g.n_bins + j], fmaf(g.kq, accq, accf));
         if (S::DR) {
             accff = ray_sum<JSPL>(accff);
             accqf = ray_sum<JSPL>(accqf);
-            if (ray_ok && q == 0) rowzf[sl * g.n_bins + j] = fmaf(g.kq, accqf, accff);
+            if (ray_ok && q == 0) put(&rowzf[sl * g.n_bins + j], fmaf(g.kq, accqf, accff));
         }
         if (g.paired) {
             accfm = ray_sum<JSPL>(accfm);
             accqm = ray_sum<JSPL>(accqm);
-            if (ray_ok && q == 0) rowz[(nslot + sl) * g.n_bins + jm] = fmaf(g.kq, accqm, accfm);
+            if (ray_ok && q == 0) put(&rowz[(nslot + sl) * g.n_bins + jm], fmaf(g.kq, accqm, accfm));
             if (S::DR) {
                 accffm = ray_sum<JSPL>(accffm);
                 accqfm = ray_sum<JSPL>(accqfm);
-                if (ray_ok && q == 0) rowzf[(nslot + sl) * g.n_bins + jm] = fmaf(g.kq, accqfm, accffm);
+                if (ray_ok && q == 0) put(&rowzf[(nslot + sl) * g.n_bins + jm], fmaf(g.kq, accqfm, accffm));
             }
         }
         int nxt = 0;
         if (lane == 0) nxt = atomicAdd(&next_item, 1);
         item = __shfl(nxt, 0, 64);
     }
+    }   // bands
     __syncthreads();
     // collimator epilogue over every (row, bin) of the block; row r < nslot is
     // angle slot0 + r, row nslot + r its mirror
@@ -2005,12 +2085,12 @@ __global__ void __launch_bounds__(256) k_finish(VecArgs V)
 // (host-callable wrappers used by the runtime; grid shapes are set there)
 #define INST_MARCH(L, M, S) template __global__ void k_march<L, M, S>(MarchArgs);
 #define INST_JVP(L, M, S) template __global__ void k_jvp_lin<L, M, S>(JvpArgs);
+#define INST_JVP3(M, S) INST_JVP(IMG_HBM, M, S) INST_JVP(IMG_LDS, M, S) INST_JVP(IMG_BANDS, M, S)
 #define INST_ALL(S)                                                                           \
     INST_MARCH(true, MARCH_FWD, S) INST_MARCH(true, MARCH_LIN, S) INST_MARCH(true, MARCH_TRIAL, S) \
     INST_MARCH(false, MARCH_FWD, S) INST_MARCH(false, MARCH_LIN, S)                           \
     INST_MARCH(false, MARCH_TRIAL, S)                                                         \
-    INST_JVP(true, JVP_PLAIN, S) INST_JVP(true, JVP_NORMAL, S) INST_JVP(true, JVP_SQNORM, S)  \
-    INST_JVP(false, JVP_PLAIN, S) INST_JVP(false, JVP_NORMAL, S) INST_JVP(false, JVP_SQNORM, S) \
+    INST_JVP3(JVP_PLAIN, S) INST_JVP3(JVP_NORMAL, S) INST_JVP3(JVP_SQNORM, S)                  \
     template __global__ void k_vjp_lin<S, false>(VjpArgs, const float4*, const int2*);                                    \
     template __global__ void k_pack<S>(Geo, PairSrc, const double*, void*, long long, const LMState*);
 INST_ALL(F32S)
