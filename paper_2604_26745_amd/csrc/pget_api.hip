@@ -661,10 +661,10 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
         P->jvp_band_h = g.n + 1;
         if (!P->jvp_lds) {
             // the pair in bands of bordered rows, leaving room for the rows
-            // of four angle slots (three rows per slot with a depth
-            // response, and its alpha table)
+            // of four angle slots and a depth response's alpha table (with
+            // a depth response, three rows per slot: fewer slots per block)
             const size_t row_px = (size_t)g.pitch * P->px_bytes;
-            const size_t keep = 4 * (per_slot / 2 * 3) + (size_t)nt * sizeof(float);
+            const size_t keep = 4 * per_slot + (size_t)nt * sizeof(float);
             if (lds_budget > keep + 9 * row_px) {
                 const int h = (int)((lds_budget - keep) / row_px) - 1;   // staged rows h + 1
                 const int bands = (g.n + 1 + h - 1) / h;
