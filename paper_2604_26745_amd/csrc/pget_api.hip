@@ -128,13 +128,21 @@ int half_width(const pget_geometry* g)
 // Dynamic LDS of a k_jvp_lin block of `japb` angle slots: the staged map
 // pair, and per sinogram row z and K z (plus, with a depth response, the far
 // part of z, and alpha per sample).
-size_t jvp_lds_for(const pget_plan* P, int japb)
+size_t jvp_lds_for(const pget_plan* P, int japb, int img)
 {
     const size_t rows = P->t.resp ? 3 : 2;
     const size_t alpha = P->t.resp ? (size_t)P->g.n_t * sizeof(float) : 0;
-    return P->img_lds + rows * (size_t)japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float) + alpha;
+    return (img == IMG_HBM ? 0 : P->img_lds) + rows * (size_t)japb * (P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float) +
+           alpha;
 }
 int max_japb_of(const pget_plan* P) { return P->t.resp ? P->max_japb_dr : P->max_japb; }
+
+// Fewest angle slots per product block for which staging the map pair in
+// bands pays: every block stages all its bands, so with fewer slots the
+// bordered copy in HBM, read through the caches, is cheaper (measured at
+// 256^2: 5 slots per block, batch 15, 1052 ms per solve with bands against
+// 1017 from HBM; 6 slots, batch 64, 3.05 against 3.37 ms per product).
+constexpr int BAND_MIN_SLOTS = 6;
 
 // Launch shapes for a batch of `batch` slices.
 struct Shapes {
@@ -144,6 +152,7 @@ struct Shapes {
     int n_jvp_blocks; // blocks per slice of k_jvp_lin
     int jvp_threads;
     size_t jvp_lds;
+    int jvp_img;      // where k_jvp_lin reads the direction (IMG_*)
     int groups;       // blocks per tile and slice of the adjoint gather
     int fine;         // fine angle groups of the gather (plan only)
     int spf;          // angle slots per fine group
@@ -228,6 +237,17 @@ void set_fpb(Shapes& s, int fpb)
     s.gfold = s.super_out ? 1 : s.gs;
 }
 
+// Product shape of `japb` angle slots per block.
+void set_japb(const pget_plan* P, Shapes& s, int japb)
+{
+    const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
+    s.japb = std::max(1, std::min(max_japb_of(P), japb));
+    s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
+    s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
+    s.jvp_img = !P->jvp_lds ? IMG_HBM : P->jvp_bands == 1 ? IMG_LDS : s.japb >= BAND_MIN_SLOTS ? IMG_BANDS : IMG_HBM;
+    s.jvp_lds = jvp_lds_for(P, s.japb, s.jvp_img);
+}
+
 Shapes shapes_for(const pget_plan* P, int batch)
 {
     Shapes s;
@@ -238,11 +258,7 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.apb = std::min(8, want);
     s.n_op_blocks = (P->g.n_angles + s.apb - 1) / s.apb;
     const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
-    int jwant = std::max(1, (slots * batch) / (2 * cus));
-    s.japb = std::max(1, std::min(max_japb_of(P), jwant));
-    s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
-    s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
-    s.jvp_lds = jvp_lds_for(P, s.japb);
+    set_japb(P, s, std::max(1, (slots * batch) / (2 * cus)));
     // blocks of the gather: the fewest launch rounds times the work of one
     // block (its angle slots plus about one slot of fixed cost), counted
     // against the resident blocks.  Small batches run one fine group per
@@ -257,10 +273,7 @@ Shapes shapes_for(const pget_plan* P, int batch)
     }
     for (const auto& t : P->tuned)
         if (t[0] == batch) {
-            s.japb = std::max(1, std::min(max_japb_of(P), t[1]));
-            s.n_jvp_blocks = (slots + s.japb - 1) / s.japb;
-            s.jvp_threads = std::min(16, s.japb * P->g.n_groups) * WAVE;
-            s.jvp_lds = jvp_lds_for(P, s.japb);
+            set_japb(P, s, t[1]);
             fpb = t[2];
         }
     set_fpb(s, fpb);
@@ -299,7 +312,9 @@ Layout layout_for(const pget_plan* P, int op, int batch, const Shapes& sh, int m
     }
     L.sino_a = take(planes * B * sino * sizeof(float));
     L.sino_b = take(planes * B * sino * sizeof(float));
-    L.gimg = (P->lds_img && P->jvp_lds) ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
+    // the bordered copy in HBM: for the march or for a product that does not
+    // stage the whole pair in LDS
+    L.gimg = (P->lds_img && P->jvp_lds && P->jvp_bands == 1) ? 0 : take(B * (size_t)g.pitch * g.pitch * sizeof(float2));
     L.part = take(B * (size_t)N_SLOTS * SLOT_WIDTH * sizeof(double));
     if (op == PGET_OP_VJP || op == PGET_OP_LM) L.gpart_cg = take((size_t)sh.fine * B * 2 * n2 * sizeof(float));
     if (op == PGET_OP_LM) {
@@ -397,8 +412,8 @@ void launch_jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batc
 template <int M>
 void jvp(const pget_plan* P, const JvpArgs& A, const Shapes& sh, int batch, hipStream_t s)
 {
-    if (!P->jvp_lds) launch_jvp<IMG_HBM, M>(P, A, sh, batch, s);
-    else if (P->jvp_bands > 1) launch_jvp<IMG_BANDS, M>(P, A, sh, batch, s);
+    if (sh.jvp_img == IMG_HBM) launch_jvp<IMG_HBM, M>(P, A, sh, batch, s);
+    else if (sh.jvp_img == IMG_BANDS) launch_jvp<IMG_BANDS, M>(P, A, sh, batch, s);
     else launch_jvp<IMG_LDS, M>(P, A, sh, batch, s);
 }
 
@@ -963,7 +978,7 @@ pget_status pget_jvp(const pget_plan* P, const float* f, const float* mu, const 
     A.wts_stride = P->support;
     A.out = jv;
     A.angles_per_block = sh.apb;
-    if (!P->jvp_lds) {
+    if (sh.jvp_img == IMG_HBM) {
         A.gimg = at(ws, L.gimg);
         pack(P, A.src, nullptr, at(ws, L.gimg), 1, nullptr, stream, true);
     }
@@ -1107,7 +1122,7 @@ void setup(Solve& S)
     float* wt_res = reinterpret_cast<float*>(at(ws, S.L.sino_a));   // K (A(u) - y)
     float* wt_cg = reinterpret_cast<float*>(at(ws, S.L.sino_b));    // K K J p
     const float* ymeas = reinterpret_cast<float*>(at(ws, S.L.ymeas));
-    S.gimg = (P->lds_img && P->jvp_lds) ? nullptr : at(ws, S.L.gimg);
+    S.gimg = (P->lds_img && P->jvp_lds && P->jvp_bands == 1) ? nullptr : at(ws, S.L.gimg);
 
     MarchArgs& M = S.lin;
     M = MarchArgs{};
@@ -1242,7 +1257,7 @@ void enqueue_march(Solve& S, const MarchArgs& A, int mode)
 // A Jacobian product over every slice of the solve (the same fallback).
 void enqueue_jvp(Solve& S, const JvpArgs& A, int mode)
 {
-    if (!S.P->jvp_lds) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream, true);
+    if (S.sh.jvp_img == IMG_HBM) pack(S.P, A.src, A.part, S.gimg, S.B, A.st, S.stream, true);
     if (mode == JVP_NORMAL) jvp<JVP_NORMAL>(S.P, A, S.sh, S.B, S.stream);
     else jvp<JVP_SQNORM>(S.P, A, S.sh, S.B, S.stream);
 }
@@ -1838,16 +1853,13 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
     setup(S);
     for (int japb = 1; japb <= max_japb_of(P); japb *= 2) {
         Shapes sh = S.sh;
-        sh.japb = japb;
-        sh.n_jvp_blocks = (slots + japb - 1) / japb;
-        sh.jvp_threads = std::min(16, japb * P->g.n_groups) * WAVE;
-        sh.jvp_lds = jvp_lds_for(P, japb);
+        set_japb(P, sh, japb);
         JvpArgs J = S.jcg;
         J.src = planar_src(S.V.u, S.V.u + (size_t)P->g.n * P->g.n, 2LL * P->g.n * P->g.n);
         J.st = nullptr;
         J.angles_per_block = japb;
         const float t = time_it([&] {
-            if (!P->jvp_lds) pack(P, J.src, nullptr, S.gimg, batch, nullptr, stream, true);
+            if (sh.jvp_img == IMG_HBM) pack(P, J.src, nullptr, S.gimg, batch, nullptr, stream, true);
             jvp<JVP_NORMAL>(P, J, sh, batch, stream);
         });
         if (t < best_j) { best_j = t; best_japb = japb; }
