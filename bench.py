@@ -55,6 +55,9 @@ LANE_OPS_PER_SAMPLE = {"vjp": 70.0, "gradient": 70.0, "jvp": 50.0, "march": 30.0
 # 256 CUs x 64 lanes x 2.4 GHz, one lane-operation (an FMA counts once) per lane and clock.
 PEAK_VALU_TLANEOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
+# Plans solved in batches of at least this many slices turn band staging on
+# (maps whose bordered pair does not fit in LDS: 256^2, the 165^2 scanner grid)
+BAND_STAGING_MIN_BATCH = 32
 
 
 def parse():
@@ -428,6 +431,8 @@ def run_scanner(args, torch, np, inputs, pget):
         ys_ = d.pop("y_scale")
         n = d.pop("n")
         pl = pget.Plan(n, d.pop("n_angles"), d.pop("n_bins"), storage=args.storage, **d)
+        if o == 1:
+            pl.set_band_staging(args.batch >= BAND_STAGING_MIN_BATCH)
         if full:
             dep, al, far = inputs.scanner_full_model(cfg, pl.n_samples)
             pl.set_depth_factor(dep)
@@ -477,6 +482,7 @@ def run_scanner(args, torch, np, inputs, pget):
         d = inputs.scanner_geometry(cfg, 1, full_model=True)
         d.pop("y_scale")
         p0 = pget.Plan(d.pop("n"), d.pop("n_angles"), d.pop("n_bins"), **d)
+        p0.set_band_staging(args.batch >= BAND_STAGING_MIN_BATCH)
         fs0, ms0, _ = p0.lm_solve_batched(ys, f0s, m0s, prm)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -500,6 +506,7 @@ def run_scanner(args, torch, np, inputs, pget):
         "dtype": "f32" if args.storage == "fp32" else "bf16-storage/f32-compute",
         "data": "synthetic: 9x9 assemblies on a 1 mm grid, 2% Gaussian noise",
         "config": {"workload": wl,
+                   "map_bands": int(plan.lib.pget_plan_jvp_bands(plan.handle)),
                    "outer": cfg.max_outer, "cg": cfg.n_cg,
                    "pixel_mm": cfg.pixel_mm, "bin_mm": cfg.bin_mm, "oversample": cfg.oversample,
                    "solver": dict({"name": args.solver, "prior_gamma": args.prior}, **opts),
@@ -783,6 +790,8 @@ def main():
     cfg = inputs.scaled(base, max_outer=args.outer, n_cg=args.cg)
     plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, storage=args.storage)
     B = args.batch
+    # maps too large for LDS (256^2): band staging pays for large batches
+    bands = plan.set_band_staging(B >= BAND_STAGING_MIN_BATCH)
     if args.autotune:
         print("bench: autotune %s" % plan.autotune(B), file=sys.stderr, flush=True)
     ys, f0s, m0s = make_inputs(plan, cfg, B, torch, inputs, np)
@@ -850,6 +859,7 @@ def main():
     bf16 = None
     if args.storage == "fp32" and not args.no_bf16_variant:
         plan_b = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, storage="bf16")
+        plan_b.set_band_staging(B >= BAND_STAGING_MIN_BATCH)
         for _ in range(max(1, args.warmup)):
             plan_b.lm_solve_batched(ys, f0s, m0s, prm)
         torch.cuda.synchronize()
@@ -901,6 +911,7 @@ def main():
         "config": {
             "workload": workload,
             "storage": args.storage,
+            "map_bands": bands,
             "slices_per_step": B,
             "grid": cfg.n, "angles": cfg.n_angles, "bins": cfg.n_bins, "psf_sigma": cfg.psf_sigma,
             "outer": cfg.max_outer, "cg": cfg.n_cg, "alpha": cfg.alpha,

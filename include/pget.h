@@ -115,6 +115,26 @@ int32_t pget_plan_psf_half_width(const pget_plan* plan);
 int64_t pget_plan_support_samples(const pget_plan* plan);
 
 /*
+ * Band staging for maps whose bordered pair does not fit in LDS (FP32 above
+ * 138^2, BF16 above about 196^2 at 1.5 bins per pixel; up to 8 bands of
+ * rows): off by default, so
+ * the Jacobian product reads such a map from a bordered copy in HBM in one
+ * pass.  On, the product walks the map in the plan's bands of rows: blocks
+ * of at least 6 angle slots (large batches) stage each band in LDS, smaller
+ * ones read the same bands from the HBM copy; each ray's per-band sums are
+ * added in band order, so every launch shape gives the same bits.  It pays
+ * for plans solved in large batches and costs small ones.  Switching
+ * changes the plan's results at the FP32 rounding level, drops its captured
+ * solver graphs and tuned shapes; call it between solves.  A plan whose map
+ * fits in LDS, or needs more than 8 bands, ignores it.  Errors:
+ * INVALID_ARG (null plan), UNSUPPORTED (a depth response set on the plan
+ * would no longer fit an angle slot per block; the setting is unchanged).
+ * pget_plan_jvp_bands: the bands the product walks (1: none).
+ */
+pget_status pget_plan_set_band_staging(pget_plan* plan, int32_t enable);
+int32_t pget_plan_jvp_bands(const pget_plan* plan);
+
+/*
  * Depth factor of the attenuation path (the vertical correction c_{m,n} >= 1
  * of the discrete model, Sec. 2.1 eq. d_fwd_model: an emitter farther from
  * the detector reaches it along a steeper path through the medium).  The
@@ -421,6 +441,20 @@ pget_status pget_lm_solve_multi(int32_t n_slices, const pget_plan* const* plans,
  */
 pget_status pget_autotune(pget_plan* plan, int32_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
 int32_t pget_tuned_shape(const pget_plan* plan, int32_t batch, int32_t* japb, int32_t* vjp_groups);
+
+/*
+ * Fix the launch shapes of solves of `batch` slices by hand, as the
+ * autotuner would: japb angle slots per Jacobian-product block (1 ..
+ * the plan's limit; 0 keeps the default) and fine_per_block fine angle groups
+ * per gather block (a multiple of the plan's super group or all of them,
+ * else one; 0 keeps the default).  With band staging on
+ * (pget_plan_set_band_staging), product blocks of at least 6 angle slots
+ * stage the map in bands of rows and smaller ones read the same bands from
+ * the HBM copy: like every shape, this changes no result bit.  Errors:
+ * INVALID_ARG (null plan, batch < 1, negative values, japb above the
+ * plan's limit).
+ */
+pget_status pget_set_shape(pget_plan* plan, int32_t batch, int32_t japb, int32_t fine_per_block);
 
 /*
  * Slot pools: continuous batching at outer-iteration boundaries (Sec. 2.2's

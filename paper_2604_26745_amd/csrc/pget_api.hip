@@ -31,8 +31,12 @@ struct pget_plan {
     size_t op_lds_bytes; // dynamic LDS of k_march
     int op_threads;      // threads per block of k_march
     size_t img_lds;      // LDS bytes of the staged map pair (0 if not staged)
-    int jvp_bands;       // k_jvp_lin stages the pair in this many bands of rows (1: whole)
+    int jvp_bands;       // k_jvp_lin walks the pair in this many bands of rows (1: none)
     int jvp_band_h;      // top bordered rows per band
+    int band_cand;       // bands the pair would take when staged in LDS (1: whole pair fits or none)
+    int band_h_cand;
+    size_t band_img_lds; // LDS bytes of one staged band
+    bool band_staging;   // set by pget_plan_set_band_staging
     int max_japb;        // most angle slots per k_jvp_lin block that fit in LDS
     int max_japb_dr;     // the same with a depth response (three rows per slot)
     int vjp_resident_dr; // k_vjp_lin blocks per compute unit with a depth response
@@ -480,6 +484,27 @@ PairSrc planar_src(const float* f, const float* mu, long long stride)
     return s;
 }
 
+// Where the Jacobian product reads the direction, and the LDS limits that
+// follow: the whole bordered pair staged in LDS when it fits; else, with
+// band staging on and bands possible, the plan's bands (staged by blocks of
+// enough angle slots, walked from the HBM copy by the others); else the HBM
+// copy in one pass.
+void apply_jvp_lds(pget_plan* P, size_t jimg_bytes, size_t per_slot)
+{
+    const size_t lds_budget = 160 * 1024 - 2048;
+    const bool whole = jimg_bytes + per_slot <= lds_budget;
+    const bool bands = !whole && P->band_staging && P->band_cand > 1;
+    P->jvp_lds = whole || bands;
+    P->img_lds = whole ? jimg_bytes : bands ? P->band_img_lds : 0;
+    P->jvp_bands = bands ? P->band_cand : 1;
+    P->jvp_band_h = bands ? P->band_h_cand : P->g.n + 1;
+    P->max_japb = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / per_slot);
+    const size_t alpha_bytes = (size_t)P->g.n_t * sizeof(float);
+    P->max_japb_dr = lds_budget >= P->img_lds + alpha_bytes
+                         ? (int)std::min<size_t>(16, (lds_budget - P->img_lds - alpha_bytes) / (per_slot / 2 * 3))
+                         : 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -670,11 +695,11 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
     P->op_threads = std::min(ng, 16) * WAVE;
     {
         const size_t per_slot = 2 * (size_t)(g.paired ? 2 : 1) * nb * sizeof(float);
-        P->jvp_lds = jimg_bytes + per_slot <= lds_budget;
-        P->img_lds = P->jvp_lds ? jimg_bytes : 0;
-        P->jvp_bands = 1;
-        P->jvp_band_h = g.n + 1;
-        if (!P->jvp_lds) {
+        P->band_cand = 1;
+        P->band_h_cand = g.n + 1;
+        P->band_img_lds = 0;
+        P->band_staging = false;
+        if (jimg_bytes + per_slot > lds_budget) {
             // the pair in bands of bordered rows, leaving room for the rows
             // of four angle slots and a depth response's alpha table (with
             // a depth response, three rows per slot: fewer slots per block)
@@ -686,18 +711,13 @@ pget_status pget_plan_create(const pget_geometry* geom, pget_storage storage, pg
                 // every band runs the block's items again: past 8 bands the
                 // HBM copy read through the caches is kept
                 if (bands <= 8) {
-                    P->jvp_bands = bands;
-                    P->jvp_band_h = (g.n + 1 + bands - 1) / bands;
-                    P->jvp_lds = true;
-                    P->img_lds = (size_t)(P->jvp_band_h + 1) * row_px;
+                    P->band_cand = bands;
+                    P->band_h_cand = (g.n + 1 + bands - 1) / bands;
+                    P->band_img_lds = (size_t)(P->band_h_cand + 1) * row_px;
                 }
             }
         }
-        P->max_japb = (int)std::min<size_t>(16, (lds_budget - P->img_lds) / per_slot);
-        const size_t alpha_bytes = (size_t)nt * sizeof(float);
-        P->max_japb_dr = lds_budget >= P->img_lds + alpha_bytes
-                             ? (int)std::min<size_t>(16, (lds_budget - P->img_lds - alpha_bytes) / (per_slot / 2 * 3))
-                             : 0;
+        apply_jvp_lds(P, jimg_bytes, per_slot);
         if (P->max_japb < 1) {
             (void)hipFree(P->table_mem);
             delete P;
@@ -872,6 +892,28 @@ pget_status pget_plan_set_depth_factor(pget_plan* plan, const double* depth, int
 int32_t pget_plan_n_samples(const pget_plan* plan) { return plan ? plan->g.n_t : -1; }
 int32_t pget_plan_psf_half_width(const pget_plan* plan) { return plan ? plan->g.K : -1; }
 int64_t pget_plan_support_samples(const pget_plan* plan) { return plan ? plan->support : -1; }
+
+pget_status pget_plan_set_band_staging(pget_plan* P, int32_t enable)
+{
+    if (!P) return PGET_ERR_INVALID_ARG;
+    const bool on = enable != 0 && P->band_cand > 1;
+    if (on == P->band_staging) return PGET_OK;
+    const size_t jimg_bytes = (size_t)P->g.pitch * P->g.pitch * P->px_bytes;
+    const size_t per_slot = 2 * (size_t)(P->g.paired ? 2 : 1) * P->g.n_bins * sizeof(float);
+    P->band_staging = on;
+    apply_jvp_lds(P, jimg_bytes, per_slot);
+    if (P->max_japb < 1 || (P->t.resp && P->max_japb_dr < 1)) {
+        P->band_staging = !on;
+        apply_jvp_lds(P, jimg_bytes, per_slot);
+        return PGET_ERR_UNSUPPORTED;
+    }
+    // captured solver sequences and tuned shapes assumed the old limits
+    drop_graphs(P);
+    P->tuned.clear();
+    return PGET_OK;
+}
+
+int32_t pget_plan_jvp_bands(const pget_plan* P) { return P ? P->jvp_bands : -1; }
 
 size_t pget_workspace_bytes(const pget_plan* plan, int32_t op, int32_t batch)
 {
@@ -1880,6 +1922,22 @@ pget_status pget_autotune(pget_plan* P, int32_t batch, void* ws, size_t ws_bytes
     (void)hipEventDestroy(e1);
     P->tuned.push_back({batch, best_japb, best_groups});
     return hipGetLastError() == hipSuccess ? PGET_OK : PGET_ERR_HIP;
+}
+
+pget_status pget_set_shape(pget_plan* P, int32_t batch, int32_t japb, int32_t fine_per_block)
+{
+    if (!P || batch < 1 || japb < 0 || fine_per_block < 0) return PGET_ERR_INVALID_ARG;
+    if (japb > max_japb_of(P)) return PGET_ERR_INVALID_ARG;
+    const Shapes def = shapes_for(P, batch);
+    // captured solver sequences of this plan used the old shapes
+    drop_graphs(P);
+    for (size_t k = 0; k < P->tuned.size(); ++k)
+        if (P->tuned[k][0] == batch) {
+            P->tuned.erase(P->tuned.begin() + k);
+            break;
+        }
+    P->tuned.push_back({batch, japb > 0 ? japb : def.japb, fine_per_block > 0 ? fine_per_block : def.fpb});
+    return PGET_OK;
 }
 
 int32_t pget_tuned_shape(const pget_plan* P, int32_t batch, int32_t* japb, int32_t* vjp_groups)

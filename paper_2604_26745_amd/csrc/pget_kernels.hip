@@ -518,16 +518,25 @@ __global__ void __launch_bounds__(1024) k_march(MarchArgs A)
 // points (sample i of one is sample n_t-1-i of the other), so one bilinear
 // sample of the direction serves both rays.
 //
-// IMG_BANDS (maps whose bordered pair does not fit in LDS): the block stages
-// bands of bordered rows in turn and runs its items once per band, each
-// sample in the band that holds its bilinear footprint's top row; a ray's
-// partial sums are added to its row value in band order, so the result
-// depends on the plan only.
+// Maps whose bordered pair does not fit in LDS are walked in the plan's
+// bands of rows (A.bands > 1): the block runs its items once per band, each
+// sample in the band that holds its bilinear footprint's top row, and a
+// ray's partial sums are added to its row value in band order.  IMG_BANDS
+// stages each band in LDS; IMG_HBM reads the same samples from the bordered
+// copy in the same order, so the two give the same bits and the choice
+// between them (by the block's angle slots) is a launch shape only.
 template <int IMG, int MODE, typename S>
 __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
 {
     constexpr bool LDS_IMG = IMG != IMG_HBM;
-    constexpr bool BANDS = IMG == IMG_BANDS;
+    constexpr bool STAGE_BANDS = IMG == IMG_BANDS;
+    // The band walk: always when staging bands (bands outside the items: each
+    // band staged once per block), never with the whole pair in LDS, and
+    // from the HBM copy when the plan has bands (bands inside each item: its
+    // set-up done once, the per-band values added in band order in
+    // registers).  Block-uniform.
+    const bool INNER = IMG == IMG_HBM && A.bands > 1;
+    const bool BANDS = STAGE_BANDS || INNER;
     extern __shared__ float4 smem_raw[];
     __shared__ double sh[16];
     __shared__ float taps[MAX_TAPS];
@@ -544,7 +553,7 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     using px_t = typename S::px_t;
     using w_t = typename S::w_t;
     px_t* simg = reinterpret_cast<px_t*>(smem_raw);
-    const int img_elems = LDS_IMG ? (BANDS ? (A.band_h + 1) * g.pitch : g.pitch * g.pitch) : 0;
+    const int img_elems = LDS_IMG ? (STAGE_BANDS ? (A.band_h + 1) * g.pitch : g.pitch * g.pitch) : 0;
     float* rowz = reinterpret_cast<float*>(simg + img_elems);   // [nrows][n_bins]
     float* rowy = rowz + A.angles_per_block * per_slot * g.n_bins;
     float* rowzf = rowy + A.angles_per_block * per_slot * g.n_bins;   // depth response: far part of z
@@ -576,18 +585,20 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
     const int n_ig = (g.n_bins + JR - 1) / JR;
     const int n_items = nslot * n_ig;
     const int gc = n_ig / 2;
-    const int nbands = BANDS ? A.bands : 1;
-    for (int band = 0; band < nbands; ++band) {
-    // top bordered rows [B0, B1) of this band's samples
-    const int B0 = BANDS ? band * A.band_h : 0;
-    const int B1 = BANDS ? min(B0 + A.band_h, g.n + 1) : g.n + 1;
-    if (BANDS && band > 0) __syncthreads();   // every wave is done with the previous band's rows
+    const int n_outer = STAGE_BANDS ? A.bands : 1;
+    const int n_inner = INNER ? A.bands : 1;
+    for (int band = 0; band < n_outer; ++band) {
+    // top bordered rows [SB0, ...) of the staged band
+    const int SB0 = STAGE_BANDS ? band * A.band_h : 0;
+    // every wave is done with the previous band's items (their counter is
+    // reset below) and its staged rows
+    if (STAGE_BANDS && band > 0) __syncthreads();
     if (LDS_IMG) {
-        if (BANDS) stage_rows<S>(simg, A.src, slice, g.n, g.pitch, beta, B0, A.band_h + 1);
+        if (STAGE_BANDS) stage_rows<S>(simg, A.src, slice, g.n, g.pitch, beta, SB0, A.band_h + 1);
         else stage_image<S>(simg, A.src, slice, g.n, g.pitch, beta);
     }
     // bordered row r of the map pair at img[r * pitch]
-    const px_t* img = LDS_IMG ? simg - (BANDS ? (ptrdiff_t)B0 * g.pitch : 0)
+    const px_t* img = LDS_IMG ? simg - (STAGE_BANDS ? (ptrdiff_t)SB0 * g.pitch : 0)
                               : static_cast<const px_t*>(A.gimg) + (size_t)slice * A.gimg_stride;
     if (threadIdx.x == 0) next_item = nwaves;
     __syncthreads();
@@ -620,6 +631,13 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             }
         }
         const int len = cl.y - cl.x + 1;   // <= 0 without support
+        // with bands inside the item: the running sum of its per-band values
+        float tz = 0.0f, tzm = 0.0f, tzf = 0.0f, tzfm = 0.0f;
+        for (int ib = 0; ib < n_inner; ++ib) {
+        // top bordered rows [B0, B1) of this pass's samples
+        const int bidx = STAGE_BANDS ? band : ib;
+        const int B0 = BANDS ? bidx * A.band_h : 0;
+        const int B1 = BANDS ? min(B0 + A.band_h, g.n + 1) : g.n + 1;
         // The ray's samples this pass visits: all of its support, or with
         // bands a superset of those whose top bilinear row lies in [B0, B1)
         // (from the row's slope along the ray, two samples of margin; rays
@@ -637,13 +655,15 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
         // trips of the item: from the first to the last sample any of its
         // rays visits (wave-uniform; without bands from 0 to the longest ray)
         int tlo = 0, tmax = len;
-        if constexpr (BANDS) {
+        if (BANDS) {
             const bool any = len > 0 && c_hi > c_lo;
             tlo = any ? c_lo : 0x3fffffff;
             tmax = any ? c_hi : 0;
 #pragma unroll
             for (int o = JSPL; o < 64; o <<= 1) tlo = min(tlo, __shfl_xor(tlo, o, 64));
-            tlo = __builtin_amdgcn_readfirstlane(tlo);
+            // from a multiple of JSPL: sample c on lane c mod JSPL in every
+            // band and launch shape
+            tlo = __builtin_amdgcn_readfirstlane(tlo) / JSPL * JSPL;
         }
 #pragma unroll
         for (int o = JSPL; o < 64; o <<= 1) tmax = max(tmax, __shfl_xor(tmax, o, 64));
@@ -741,23 +761,37 @@ __global__ void __launch_bounds__(1024) k_jvp_lin(JvpArgs A)
             c0 = c2;
         }
         // a ray's value: this pass's sum, added in band order with bands
-        auto put = [&](float* dst, float v) { *dst = (BANDS && band > 0) ? *dst + v : v; };
+        // (in the row value when the bands are staged, in registers when
+        // they run inside the item: the same additions)
+        auto put = [&](float* dst, float& tot, float v) {
+            if (INNER) tot = ib > 0 ? tot + v : v;
+            else if (ray_ok && q == 0) *dst = (STAGE_BANDS && band > 0) ? *dst + v : v;
+        };
         accf = ray_sum<JSPL>(accf);
         accq = ray_sum<JSPL>(accq);
-        if (ray_ok && q == 0) put(&rowz[sl * g.n_bins + j], fmaf(g.kq, accq, accf));
+        put(&rowz[sl * g.n_bins + j], tz, fmaf(g.kq, accq, accf));
         if (S::DR) {
             accff = ray_sum<JSPL>(accff);
             accqf = ray_sum<JSPL>(accqf);
-            if (ray_ok && q == 0) put(&rowzf[sl * g.n_bins + j], fmaf(g.kq, accqf, accff));
+            put(&rowzf[sl * g.n_bins + j], tzf, fmaf(g.kq, accqf, accff));
         }
         if (g.paired) {
             accfm = ray_sum<JSPL>(accfm);
             accqm = ray_sum<JSPL>(accqm);
-            if (ray_ok && q == 0) put(&rowz[(nslot + sl) * g.n_bins + jm], fmaf(g.kq, accqm, accfm));
+            put(&rowz[(nslot + sl) * g.n_bins + jm], tzm, fmaf(g.kq, accqm, accfm));
             if (S::DR) {
                 accffm = ray_sum<JSPL>(accffm);
                 accqfm = ray_sum<JSPL>(accqfm);
-                if (ray_ok && q == 0) put(&rowzf[(nslot + sl) * g.n_bins + jm], fmaf(g.kq, accqfm, accffm));
+                put(&rowzf[(nslot + sl) * g.n_bins + jm], tzfm, fmaf(g.kq, accqfm, accffm));
+            }
+        }
+        }   // bands inside the item
+        if (INNER && ray_ok && q == 0) {
+            rowz[sl * g.n_bins + j] = tz;
+            if (S::DR) rowzf[sl * g.n_bins + j] = tzf;
+            if (g.paired) {
+                rowz[(nslot + sl) * g.n_bins + jm] = tzm;
+                if (S::DR) rowzf[(nslot + sl) * g.n_bins + jm] = tzfm;
             }
         }
         int nxt = 0;

@@ -110,6 +110,12 @@ def load_library():
     lib.pget_autotune.restype = ctypes.c_int
     lib.pget_tuned_shape.argtypes = [V, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
     lib.pget_tuned_shape.restype = ctypes.c_int32
+    lib.pget_set_shape.argtypes = [V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.pget_set_shape.restype = ctypes.c_int
+    lib.pget_plan_set_band_staging.argtypes = [V, ctypes.c_int32]
+    lib.pget_plan_set_band_staging.restype = ctypes.c_int
+    lib.pget_plan_jvp_bands.argtypes = [V]
+    lib.pget_plan_jvp_bands.restype = ctypes.c_int32
     lib.pget_workspace_bytes_multi.argtypes = [ctypes.c_int32, P(V)]
     lib.pget_workspace_bytes_multi.restype = ctypes.c_size_t
     lib.pget_lm_solve_multi.argtypes = [ctypes.c_int32, P(V), P(V), P(V), P(V), P(LMParams),
@@ -462,6 +468,19 @@ class Plan:
         ws = self.workspace(OP_LM, batch)
         _check(self.lib.pget_autotune(self.handle, batch, _ptr(ws), ws.numel(), _stream()),
                "pget_autotune")
+        return self.tuned_shape(batch)
+
+    def set_band_staging(self, enable: bool = True) -> int:
+        """Band staging of maps too large for LDS (pget_plan_set_band_staging):
+        for plans solved in large batches.  Returns the bands the product
+        walks (1: none)."""
+        _check(self.lib.pget_plan_set_band_staging(self.handle, int(bool(enable))), "pget_plan_set_band_staging")
+        self._ws.clear()
+        return int(self.lib.pget_plan_jvp_bands(self.handle))
+
+    def set_shape(self, batch: int = 1, jvp_angle_slots: int = 0, vjp_fine_groups: int = 0):
+        """Fix the launch shapes of solves of `batch` slices (0 keeps a default)."""
+        _check(self.lib.pget_set_shape(self.handle, batch, jvp_angle_slots, vjp_fine_groups), "pget_set_shape")
         return self.tuned_shape(batch)
 
     def tuned_shape(self, batch: int = 1):

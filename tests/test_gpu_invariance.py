@@ -167,3 +167,41 @@ def test_iteration_level_served_requests_equal_alone(mixed_pool):
             alone[r.slot] = plans[r.size].lm_solve(sl.y, sl.f0, sl.mu0, prm)
         f, m = outputs[r.rid]
         assert torch.equal(f, alone[r.slot][0]) and torch.equal(m, alone[r.slot][1]), r.rid
+
+
+@pytest.mark.parametrize("depth_response", [False, True], ids=["plain", "depth_response"])
+def test_band_staging_keeps_every_bit(depth_response):
+    """With band staging on, a map whose bordered pair does not fit in LDS
+    (150^2 at 60 x 220: two bands of rows) is walked band by band in every
+    launch shape: product blocks of at least 6 angle slots stage each band in
+    LDS, smaller ones read the bordered copy in HBM over the same bands in
+    the same order.  A Jacobian product and a solve give the same bits
+    either way."""
+    import numpy as np
+    n, na, nb = 150, 60, 220
+    plan = pget.Plan(n, na, nb)
+    assert plan.set_band_staging(True) == 2
+    if depth_response:
+        n_t, K = plan.n_samples, plan.psf_half_width
+        _, far = inputs.collimator_depth_response(n_t, K, 3.0)
+        plan.set_depth_response(np.linspace(0.0, 1.0, n_t), far)
+    cfg = inputs.SliceConfig("lattice5_n150", n, na, nb, n_rods=5, rod_radius=4.0, pitch=24.0, can_half=66.0,
+                             n_empty=2)
+    T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+    f_true, mu_true = inputs.rod_lattice(cfg, 0)
+    y = T(inputs.poisson_counts(plan.forward(T(f_true), T(mu_true)).double().cpu().numpy(), 1e4, 0))
+    f0 = torch.full((n, n), float(f_true.mean()), device="cuda")
+    m0 = torch.zeros((n, n), device="cuda")
+    rng = np.random.default_rng(3)
+    vf, vm = T(rng.standard_normal((n, n))), T(0.05 * rng.standard_normal((n, n)))
+    prm = pget.SolverParams(max_outer=3, n_cg=8, **SCALED)
+    runs = []
+    for slots in (1, 8):
+        shape = plan.set_shape(1, jvp_angle_slots=slots)
+        log("150^2 (%s): product %s" % ("depth response" if depth_response else "plain", shape))
+        assert shape["jvp_angle_slots"] == slots and shape["tuned"]
+        jv = plan.jvp(f0, T(0.02 * f_true), vf, vm)
+        runs.append((jv, plan.lm_solve(y, f0, m0, prm)))
+    (jv1, (f1, m1, r1)), (jv2, (f2, m2, r2)) = runs
+    assert torch.equal(jv1, jv2)
+    assert torch.equal(f1, f2) and torch.equal(m1, m2) and same_report(r1, r2)
