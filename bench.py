@@ -768,6 +768,12 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "mixed":
         run_mixed(args, torch, np, inputs, pget)
         return
@@ -780,12 +786,6 @@ def main():
     if args.workload == "serve":
         run_serve(args, torch, pget)
         return
-    if args.calibrate_copy:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     base = {64: inputs.SMALL_64, 128: inputs.MAIN_128, 256: inputs.LARGE_256}[args.grid]
     cfg = inputs.scaled(base, max_outer=args.outer, n_cg=args.cg)
     plan = pget.Plan(cfg.n, cfg.n_angles, cfg.n_bins, psf_sigma=cfg.psf_sigma, storage=args.storage)
