@@ -117,19 +117,18 @@ int64_t pget_plan_support_samples(const pget_plan* plan);
 /*
  * Band staging for maps whose bordered pair does not fit in LDS (FP32 above
  * 138^2, BF16 above about 196^2 at 1.5 bins per pixel; up to 8 bands of
- * rows): off by default, so
- * the Jacobian product reads such a map from a bordered copy in HBM in one
- * pass.  On, the product walks the map in the plan's bands of rows: blocks
- * of at least 6 angle slots (large batches) stage each band in LDS, smaller
- * ones read the same bands from the HBM copy; each ray's per-band sums are
- * added in band order, so every launch shape gives the same bits.  It pays
- * for plans solved in large batches and costs small ones.  Switching
- * changes the plan's results at the FP32 rounding level, drops its captured
- * solver graphs and tuned shapes; call it between solves.  A plan whose map
- * fits in LDS, or needs more than 8 bands, ignores it.  Errors:
- * INVALID_ARG (null plan), UNSUPPORTED (a depth response set on the plan
- * would no longer fit an angle slot per block; the setting is unchanged).
- * pget_plan_jvp_bands: the bands the product walks (1: none).
+ * rows).  Off by default: the Jacobian product reads such a map from a
+ * bordered copy in HBM in one pass.  On, it walks the map in the plan's
+ * bands of rows: blocks of at least 6 angle slots (large batches) stage each
+ * band in LDS, smaller ones read the same bands from the HBM copy; each
+ * ray's per-band sums are added in band order, so every launch shape gives
+ * the same bits.  It pays for plans solved in large batches and costs small
+ * ones.  Switching changes the plan's results at the FP32 rounding level and
+ * drops its captured solver graphs and tuned shapes; call it between solves.
+ * A plan whose map fits in LDS, or needs more than 8 bands, ignores it.
+ * Errors: INVALID_ARG (null plan), UNSUPPORTED (a depth response set on the
+ * plan would no longer fit an angle slot per block; the setting is
+ * unchanged).  pget_plan_jvp_bands: the bands the product walks (1: none).
  */
 pget_status pget_plan_set_band_staging(pget_plan* plan, int32_t enable);
 int32_t pget_plan_jvp_bands(const pget_plan* plan);
