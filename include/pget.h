@@ -124,8 +124,10 @@ int64_t pget_plan_support_samples(const pget_plan* plan);
  * ray's per-band sums are added in band order, so every launch shape gives
  * the same bits.  It pays for plans solved in large batches and costs small
  * ones.  Switching changes the plan's results at the FP32 rounding level and
- * drops its captured solver graphs and tuned shapes; call it between solves.
- * A plan whose map fits in LDS, or needs more than 8 bands, ignores it.
+ * drops its captured solver graphs and tuned shapes; call it between solves
+ * (slot pools created before the switch keep the setting they were created
+ * with; workspace sizes do not change).  A plan whose map fits in LDS, or
+ * needs more than 8 bands, ignores it.
  * Errors: INVALID_ARG (null plan), UNSUPPORTED (a depth response set on the
  * plan would no longer fit an angle slot per block; the setting is
  * unchanged).  pget_plan_jvp_bands: the bands the product walks (1: none).
