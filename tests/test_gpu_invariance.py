@@ -169,24 +169,26 @@ def test_iteration_level_served_requests_equal_alone(mixed_pool):
         assert torch.equal(f, alone[r.slot][0]) and torch.equal(m, alone[r.slot][1]), r.rid
 
 
-@pytest.mark.parametrize("depth_response", [False, True], ids=["plain", "depth_response"])
-def test_band_staging_keeps_every_bit(depth_response):
+@pytest.mark.parametrize("storage,depth_response", [("fp32", False), ("fp32", True), ("bf16", False)],
+                         ids=["plain", "depth_response", "bf16"])
+def test_band_staging_keeps_every_bit(storage, depth_response):
     """With band staging on, a map whose bordered pair does not fit in LDS
-    (150^2 at 60 x 220: two bands of rows) is walked band by band in every
-    launch shape: product blocks of at least 6 angle slots stage each band in
-    LDS, smaller ones read the bordered copy in HBM over the same bands in
-    the same order.  A Jacobian product and a solve give the same bits
-    either way."""
+    (FP32 150^2 at 60 x 220, BF16 210^2 at 60 x 300: two bands of rows) is
+    walked band by band in every launch shape: product blocks of at least 6
+    angle slots stage each band in LDS, smaller ones read the bordered copy
+    in HBM over the same bands in the same order.  A Jacobian product and a
+    solve give the same bits either way."""
     import numpy as np
-    n, na, nb = 150, 60, 220
-    plan = pget.Plan(n, na, nb)
+    n, na, nb = (150, 60, 220) if storage == "fp32" else (210, 60, 300)
+    plan = pget.Plan(n, na, nb, storage=storage)
     assert plan.set_band_staging(True) == 2
     if depth_response:
         n_t, K = plan.n_samples, plan.psf_half_width
         _, far = inputs.collimator_depth_response(n_t, K, 3.0)
         plan.set_depth_response(np.linspace(0.0, 1.0, n_t), far)
-    cfg = inputs.SliceConfig("lattice5_n150", n, na, nb, n_rods=5, rod_radius=4.0, pitch=24.0, can_half=66.0,
-                             n_empty=2)
+    k = n / 150.0
+    cfg = inputs.SliceConfig("lattice5_n%d" % n, n, na, nb, n_rods=5, rod_radius=4.0 * k, pitch=24.0 * k,
+                             can_half=66.0 * k, n_empty=2)
     T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
     f_true, mu_true = inputs.rod_lattice(cfg, 0)
     y = T(inputs.poisson_counts(plan.forward(T(f_true), T(mu_true)).double().cpu().numpy(), 1e4, 0))
@@ -198,7 +200,7 @@ def test_band_staging_keeps_every_bit(depth_response):
     runs = []
     for slots in (1, 8):
         shape = plan.set_shape(1, jvp_angle_slots=slots)
-        log("150^2 (%s): product %s" % ("depth response" if depth_response else "plain", shape))
+        log("%d^2 %s (%s): product %s" % (n, storage, "depth response" if depth_response else "plain", shape))
         assert shape["jvp_angle_slots"] == slots and shape["tuned"]
         jv = plan.jvp(f0, T(0.02 * f_true), vf, vm)
         runs.append((jv, plan.lm_solve(y, f0, m0, prm)))
