@@ -262,7 +262,30 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.apb = std::min(8, want);
     s.n_op_blocks = (P->g.n_angles + s.apb - 1) / s.apb;
     const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
-    set_japb(P, s, std::max(1, (slots * batch) / (2 * cus)));
+    int japb = std::max(1, (slots * batch) / (2 * cus));
+    if (P->jvp_lds && P->jvp_bands == 1) {
+        // The whole map pair in LDS: one product block per CU at a time (a
+        // second one sharing the CU gains nothing), so a launch takes about
+        // ceil(blocks / CUs) rounds of (slots per block + 2) slot times, the
+        // 2 for staging the map and the epilogue; the fewest slots that
+        // reach the fewest rounds win.  Measured (LM solve of 15 x 30, slots
+        // per block from blocks enough to fill the chip twice -> this rule):
+        // 64^2 x 12 slices 61.3 -> 51.3 ms (4 -> 9 slots), 96^2 x 13
+        // 130.0 -> 113.9 (4 -> 10), 128^2 x 13 220.5 -> 207.7 (4 -> 5),
+        // 128^2 x 8 137.2 -> 121.4 (2 -> 6), 128^2 x 4 84.3 -> 64.4 (1 -> 3),
+        // 64^2 x 64 at 120 angles (15 x 20) 67.5 -> 60.0 (7 -> 15); every
+        // other shape tried was slower.  128^2 x 64 and one slice keep theirs.
+        double best = 1e30;
+        for (int j = 1; j <= max_japb_of(P); ++j) {
+            const long long blocks = (long long)batch * ((slots + j - 1) / j);
+            const double cost = (double)((blocks + cus - 1) / cus) * (j + 2);
+            if (cost < best * (1.0 - 1e-9)) {
+                best = cost;
+                japb = j;
+            }
+        }
+    }
+    set_japb(P, s, japb);
     // blocks of the gather: the fewest launch rounds times the work of one
     // block (its angle slots plus about one slot of fixed cost), counted
     // against the resident blocks.  Small batches run one fine group per
