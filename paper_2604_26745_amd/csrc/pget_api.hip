@@ -264,8 +264,8 @@ Shapes shapes_for(const pget_plan* P, int batch)
     const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
     int japb = std::max(1, (slots * batch) / (2 * cus));
     if (P->jvp_lds && P->jvp_bands == 1) {
-        // The whole map pair in LDS: one product block per CU at a time (a
-        // second one sharing the CU gains nothing), so a launch takes about
+        // The whole map pair in LDS: a product block gains nothing from a
+        // second one sharing its CU (measured), so a launch takes about
         // ceil(blocks / CUs) rounds of (slots per block + 2) slot times, the
         // 2 for staging the map and the epilogue; the fewest slots that
         // reach the fewest rounds win.  Measured (LM solve of 15 x 30, slots
