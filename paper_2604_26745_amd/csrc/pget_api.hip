@@ -263,22 +263,28 @@ Shapes shapes_for(const pget_plan* P, int batch)
     s.n_op_blocks = (P->g.n_angles + s.apb - 1) / s.apb;
     const int slots = P->g.paired ? P->g.n_angles / 2 : P->g.n_angles;
     int japb = std::max(1, (slots * batch) / (2 * cus));
-    if (P->jvp_lds && P->jvp_bands == 1) {
-        // The whole map pair in LDS: a product block gains nothing from a
-        // second one sharing its CU (measured), so a launch takes about
-        // ceil(blocks / CUs) rounds of (slots per block + 2) slot times, the
-        // 2 for staging the map and the epilogue; the fewest slots that
-        // reach the fewest rounds win.  Measured (LM solve of 15 x 30, slots
-        // per block from blocks enough to fill the chip twice -> this rule):
-        // 64^2 x 12 slices 61.3 -> 51.3 ms (4 -> 9 slots), 96^2 x 13
-        // 130.0 -> 113.9 (4 -> 10), 128^2 x 13 220.5 -> 207.7 (4 -> 5),
-        // 128^2 x 8 137.2 -> 121.4 (2 -> 6), 128^2 x 4 84.3 -> 64.4 (1 -> 3),
-        // 64^2 x 64 at 120 angles (15 x 20) 67.5 -> 60.0 (7 -> 15); every
-        // other shape tried was slower.  128^2 x 64 and one slice keep theirs.
+    if (P->jvp_bands == 1) {
+        // The map pair read whole, from LDS or from the bordered HBM copy: a
+        // product block gains nothing from a second one sharing its CU
+        // (measured), so a launch takes about ceil(blocks / CUs) rounds of
+        // (slots per block + c0) slot times, c0 the per-block cost of staging
+        // the map (2 slot times) or, reading the HBM copy, of the epilogue
+        // (0.5); the fewest slots that reach the lowest cost win.  Measured
+        // (LM solve of 15 x 30, slots per block from blocks enough to fill
+        // the chip twice -> this rule): in LDS, 64^2 x 12 slices 61.3 -> 51.3
+        // ms (4 -> 9 slots), 96^2 x 13 130.0 -> 113.9 (4 -> 10), 128^2 x 13
+        // 220.5 -> 207.7 (4 -> 5), 128^2 x 8 137.2 -> 121.4 (2 -> 6), 128^2 x
+        // 4 84.3 -> 64.4 (1 -> 3), 64^2 x 64 at 120 angles (15 x 20) 67.5 ->
+        // 60.0 (7 -> 15), 128^2 x 64 and one slice unchanged; from the HBM
+        // copy, 256^2 x 15 1026 -> 918 (5 -> 11), 192^2 x 11 417 -> 400 (3 ->
+        // 8), 192^2 x 4 163 -> 156 and 256^2 x 4 257 -> 254 (1 -> 3), 64
+        // slices of 192^2 2172 -> 2105 and of 256^2 3724 -> 3619 (16 -> 15).
+        // Plans with band staging keep the chip-twice rule.
+        const double c0 = P->jvp_lds ? 2.0 : 0.5;
         double best = 1e30;
         for (int j = 1; j <= max_japb_of(P); ++j) {
             const long long blocks = (long long)batch * ((slots + j - 1) / j);
-            const double cost = (double)((blocks + cus - 1) / cus) * (j + 2);
+            const double cost = (double)((blocks + cus - 1) / cus) * (j + c0);
             if (cost < best * (1.0 - 1e-9)) {
                 best = cost;
                 japb = j;
