@@ -19,8 +19,7 @@ Measured alongside:
 * the reconstruction error against the phantoms;
 * a single slice's latency;
 * the FP64 CPU oracle, timed on the host cores on a bounded sample of the
-  same workload.
-
+  same workload;
 * the serving half of the metric: a 10 s Poisson trace (30 requests/s)
   over the mixed grid sizes {64..256}^2 through the continuous-batching
   server (whole batched solves on concurrent streams), with p50/p99
