@@ -62,3 +62,30 @@ def test_product_slots_map_in_hbm(cus, n, na, nb, batch, pick):
     if cus == 256:
         assert got["jvp_angle_slots"] == pick
 
+
+
+def test_widest_blocks_keep_every_bit():
+    """The 64^2 x 120-angle plan at 15 angle slots per block (the default for
+    64 slices) gives the same bits as one slot per block: a Jacobian product
+    and a short solve."""
+    import numpy as np
+    from paper_2604_26745_amd import inputs
+    n, na, nb = 64, 120, 96
+    plan = pget.Plan(n, na, nb)
+    cfg = inputs.SMALL_64
+    T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+    f_true, mu_true = inputs.rod_lattice(cfg, 1)
+    y = T(inputs.poisson_counts(plan.forward(T(f_true), T(mu_true)).double().cpu().numpy(), 1e4, 1))
+    f0 = torch.full((n, n), float(f_true.mean()), device="cuda")
+    m0 = torch.zeros((n, n), device="cuda")
+    rng = np.random.default_rng(4)
+    vf, vm = T(rng.standard_normal((n, n))), T(0.05 * rng.standard_normal((n, n)))
+    prm = pget.SolverParams(max_outer=3, n_cg=8, w_mu=0.05 ** 2, d_mu=1 / 0.05 ** 2, active_set=1)
+    runs = []
+    for slots in (1, 15):
+        assert plan.set_shape(1, jvp_angle_slots=slots)["jvp_angle_slots"] == slots
+        jv = plan.jvp(f0, T(0.02 * f_true), vf, vm)
+        runs.append((jv, plan.lm_solve(y, f0, m0, prm)))
+    (jv1, (f1, m1, _)), (jv2, (f2, m2, _)) = runs
+    assert torch.equal(jv1, jv2)
+    assert torch.equal(f1, f2) and torch.equal(m1, m2)
